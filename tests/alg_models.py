@@ -1,0 +1,177 @@
+"""Executable models of the paper's bottom-up constructions (test helpers).
+
+These run the steps of Alg. 3 (Apetrei's original bottom-up pass, Sec. 3.2)
+and Alg. 4 (the modified pass that keeps Karras' node order and installs the
+skip-connections, Sec. 4) on the CPU, one Python generator per leaf.  Each
+generator yields right before its compare-and-swap on ``store``, so a
+scheduler can interleave the leaves in any order; the CAS itself and the code
+up to the next CAS run without interruption, which is what an atomic CAS
+guarantees.  They exist to check, under adversarial schedules, that the
+paper's procedure reaches the same tree as the oracle's top-down definition.
+
+Readings used (each one is also listed with the oracle):
+  * delta* is the rank of the highest differing bit of the augmented keys,
+    with delta*(-1) = delta*(n-1) = +inf;
+  * Alg. 4's left-child line is read as: the left child of the parent is leaf
+    p if range_left == p, else internal node p, where p is the split (the
+    Apetrei index).  Sec. 4 states that the children of a parent with split
+    gamma are gamma and gamma+1; the printed condition compares against q and
+    names the child by i, which on the worked example gives wrong children;
+  * the boxes, omitted from both listings, are merged by the second thread
+    to arrive: it reads the sibling's box, written before the sibling's CAS.
+"""
+
+from __future__ import annotations
+
+import random
+
+INF = 1 << 30
+SENTINEL = -1
+
+
+class _Delta:
+    def __init__(self, delta, n):
+        self.d = list(int(x) for x in delta)
+        self.n = n
+
+    def __call__(self, i):
+        if i < 0 or i >= self.n - 1:
+            return INF
+        return self.d[i]
+
+
+def _schedule(gens, policy, rng):
+    """Drive generators to completion.  policy: 'random', 'left' (always the
+    lowest live leaf first) or 'right' (the highest first)."""
+    live = list(range(len(gens)))
+    while live:
+        if policy == "random":
+            k = rng.randrange(len(live))
+        elif policy == "left":
+            k = 0
+        else:
+            k = len(live) - 1
+        g = live[k]
+        try:
+            next(gens[g])
+        except StopIteration:
+            live.pop(k)
+
+
+def alg4(delta, n, leaf_boxes=None, policy="random", seed=0):
+    """Modified Apetrei with ropes (Alg. 4) plus box merging.
+
+    Returns (left[n-1], rope[2n-1], boxes[2n-1] or None) in unified ids
+    (internal k -> k, leaf k -> n-1+k, sentinel -1)."""
+    D = _Delta(delta, n)
+    ni = n - 1
+    left = [None] * max(ni, 0)
+    rope = [None] * max(2 * n - 1, 0)
+    boxes = [None] * max(2 * n - 1, 0) if leaf_boxes is not None else None
+    store = [None] * max(ni, 0)   # None plays the 'invalid' marker
+
+    def leaf(k):
+        return ni + k
+
+    def union(a, b):
+        return tuple(min(a[x], b[x]) for x in range(3)) + tuple(max(a[3 + x], b[3 + x]) for x in range(3))
+
+    def run(i):
+        rl = rr = i
+        dl, dr = D(i - 1), D(i)
+        if i == n - 1:
+            rope[leaf(i)] = SENTINEL
+        else:
+            rope[leaf(i)] = leaf(i + 1) if dr < D(i + 1) else i + 1
+        cur = leaf(i)
+        if boxes is not None:
+            boxes[cur] = tuple(leaf_boxes[i])
+        if n == 1:
+            return
+        while True:
+            if dr < dl:                      # left child of its parent
+                p = rr
+                yield
+                old = store[p]
+                if old is None:
+                    store[p] = rl
+                    return
+                rr = old
+                dr = D(rr)
+                sib = leaf(p + 1) if p + 1 == rr else p + 1
+            else:                            # right child of its parent
+                p = rl - 1
+                yield
+                old = store[p]
+                if old is None:
+                    store[p] = rr
+                    return
+                rl = old
+                dl = D(rl - 1)
+                sib = leaf(p) if rl == p else p
+            q = rr if dr < dl else rl        # Karras index of the parent
+            left[q] = leaf(p) if rl == p else p
+            if rr == n - 1:
+                rope[q] = SENTINEL
+            else:
+                r = rr + 1
+                rope[q] = leaf(r) if dr < D(r) else r
+            if boxes is not None:
+                boxes[q] = union(boxes[cur], boxes[sib])
+            cur = q
+            if q == 0:
+                return
+
+    rng = random.Random(seed)
+    _schedule([run(i) for i in range(n)], policy, rng)
+    return left, rope, boxes
+
+
+def alg3(delta, n, policy="random", seed=0):
+    """Apetrei's original bottom-up pass (Alg. 3), nodes indexed by split.
+
+    Returns (children: dict p -> [left, right] with entries ('L', k) or
+    ('I', p'), ranges: dict p -> (lo, hi), root p).  The loop stops when a
+    thread's range is the whole [0, n-1]."""
+    D = _Delta(delta, n)
+    children = {}
+    ranges = {}
+    store = [None] * max(n - 1, 0)
+    root = [None]
+
+    def run(i):
+        rl = rr = i
+        dl, dr = D(i - 1), D(i)
+        cur = ("L", i)
+        while True:
+            if dr < dl:
+                p = rr
+                children.setdefault(p, [None, None])[0] = cur
+                yield
+                old = store[p]
+                if old is None:
+                    store[p] = rl
+                    return
+                rr = old
+                dr = D(rr)
+            else:
+                p = rl - 1
+                children.setdefault(p, [None, None])[1] = cur
+                yield
+                old = store[p]
+                if old is None:
+                    store[p] = rr
+                    return
+                rl = old
+                dl = D(rl - 1)
+            cur = ("I", p)
+            ranges[p] = (rl, rr)
+            if rl == 0 and rr == n - 1:
+                root[0] = p
+                return
+
+    if n == 1:
+        return {}, {}, None
+    rng = random.Random(seed)
+    _schedule([run(i) for i in range(n)], policy, rng)
+    return children, ranges, root[0]

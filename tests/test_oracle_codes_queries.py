@@ -1,0 +1,227 @@
+"""Pins of the oracle's scene box, Morton codes, sort and range queries.
+
+Morton codes have no printed example in the paper (Sec. 3.1 only names the
+step), so they are pinned by closed forms: dyadic grids where every float32
+operation is exact and the expected code can be spelled out bit by bit as a
+string, the scene corners, axis order, flat axes, monotonicity, and agreement
+with an exact float64 computation away from cell boundaries.  The sort is
+pinned by numpy's stable argsort; queries by brute force, by a stack-based
+depth-first walk and by float64 distances away from the sphere surface.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+
+def string_interleave(qx, qy, qz, b):
+    bx, by, bz = (format(q, f"0{b}b") for q in (qx, qy, qz))
+    return int("".join(x + y + z for x, y, z in zip(bx, by, bz)), 2)
+
+
+def deinterleave(code, b):
+    q = [0, 0, 0]
+    for k in range(b):
+        for a in range(3):
+            q[a] |= ((int(code) >> (3 * k + 2 - a)) & 1) << k
+    return q
+
+
+# ------------------------------------------------------------ scene / sort
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_scene_box_is_min_max(kind):
+    rng = np.random.default_rng(3)
+    if kind == 0:
+        p = rng.normal(size=(1000, 3)).astype(np.float32)
+        ref = np.concatenate([p.min(0), p.max(0)])
+    else:
+        c = rng.normal(size=(1000, 3))
+        p = np.concatenate([c - 0.1, c + 0.3], 1).astype(np.float32)
+        ref = np.concatenate([p[:, :3].min(0), p[:, 3:].max(0)])
+    assert np.array_equal(oracle.scene_box(kind, p), ref)
+
+
+def test_sort_is_stable_argsort():
+    rng = np.random.default_rng(4)
+    codes = rng.integers(0, 50, size=5000).astype(np.uint64)
+    s, perm = oracle.sort(codes)
+    ref = np.argsort(codes, kind="stable")
+    assert np.array_equal(perm, ref) and np.array_equal(s, codes[ref])
+
+
+# ----------------------------------------------------------------- Morton
+
+@pytest.mark.parametrize("bits", [30, 63])
+def test_morton_dyadic_grid_exact(bits):
+    """Scene [0,1]^3: scale = 2^b exactly, c = k/2^b gives q = k exactly."""
+    b = bits // 3
+    rng = np.random.default_rng(bits)
+    k = rng.integers(0, 1 << b, size=(500, 3))
+    pts = (k / float(1 << b)).astype(np.float32)
+    pts = np.concatenate([pts, [[0, 0, 0], [1, 1, 1]]]).astype(np.float32)
+    codes = oracle.morton(0, pts, bits)
+    for j in range(500):
+        assert int(codes[j]) == string_interleave(*map(int, k[j]), b)
+    assert int(codes[500]) == 0
+    assert int(codes[501]) == (1 << (3 * b)) - 1          # upper corner clamps
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+def test_morton_just_below_cell_boundary(bits):
+    b = bits // 3
+    k = np.array([1, 7, 1 << (b - 1)], np.float64)
+    c = np.nextafter((k / float(1 << b)).astype(np.float32), np.float32(0))
+    pts = np.stack([c, np.zeros(3, np.float32), np.zeros(3, np.float32)], 1)
+    pts = np.concatenate([pts, [[1, 1, 1], [0, 0, 0]]]).astype(np.float32)
+    codes = oracle.morton(0, pts, bits)
+    for j in range(3):
+        assert deinterleave(codes[j], b)[0] == int(k[j]) - 1
+
+
+def test_morton_axis_order_and_flat_axis():
+    pts = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, 0]], np.float32)
+    codes = oracle.morton(0, pts, 30)
+    x_bits = sum(1 << (3 * k + 2) for k in range(10))
+    assert int(codes[0]) == x_bits
+    assert int(codes[1]) == x_bits >> 1
+    assert int(codes[2]) == x_bits >> 2
+    flat = np.array([[0, 0, 5], [1, 1, 5], [0.5, 0.25, 5]], np.float32)
+    c = oracle.morton(0, flat, 63)
+    assert all(deinterleave(v, 21)[2] == 0 for v in c)
+
+
+def test_morton_box_centroid():
+    lo = np.array([[0.25, 0.5, 0.0]], np.float32)
+    hi = np.array([[0.75, 0.5, 0.5]], np.float32)
+    boxes = np.concatenate([np.concatenate([lo, hi], 1), [[0, 0, 0, 0, 0, 0], [1, 1, 1, 1, 1, 1]]]).astype(np.float32)
+    pts = np.array([[0.5, 0.5, 0.25], [0, 0, 0], [1, 1, 1]], np.float32)
+    assert oracle.morton(1, boxes, 30)[0] == oracle.morton(0, pts, 30)[0]
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+def test_morton_monotone_and_range(bits):
+    b = bits // 3
+    x = np.sort(np.random.default_rng(5).random(3000).astype(np.float32))
+    pts = np.stack([x, np.full_like(x, 0.3), np.full_like(x, 0.7)], 1)
+    pts = np.concatenate([pts, [[0, 0, 0], [1, 1, 1]]]).astype(np.float32)
+    codes = oracle.morton(0, pts, bits)
+    qx = [deinterleave(c, b)[0] for c in codes[:-2]]
+    assert all(a <= c for a, c in zip(qx, qx[1:]))
+    assert int(codes.max()) < (1 << bits)
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+def test_morton_matches_exact_arithmetic_off_boundaries(bits):
+    """Away from cell boundaries the float32 quantisation must agree with the
+    exact real-number value floor((c - lo) * 2^b / extent).  Three float32
+    roundings (subtract, divide, multiply) put t within 3u|t| of the exact
+    value, u = 2^-24; samples closer than 4u|t| to an integer are skipped."""
+    b = bits // 3
+    rng = np.random.default_rng(6)
+    p = (rng.random((4000, 3)) * 3.0 - 1.0).astype(np.float32)
+    scene = oracle.scene_box(0, p)
+    codes = oracle.morton(0, p, bits)
+    lo, hi = scene[:3].astype(np.float64), scene[3:].astype(np.float64)
+    t = (p.astype(np.float64) - lo) * (1 << b) / (hi - lo)
+    frac = t - np.floor(t)
+    margin = 4.0 * 2.0 ** -24 * np.abs(t) + 1e-12
+    ok = (np.minimum(frac, 1 - frac) > margin) & (t < (1 << b) - 1)
+    q = np.array([deinterleave(c, b) for c in codes])
+    assert ok.sum() > 3000
+    assert np.array_equal(q[ok], np.floor(t[ok]).astype(np.int64))
+
+
+# ----------------------------------------------------------------- queries
+
+def test_sphere_predicate_special_cases():
+    box = np.array([3, 4, 0, 3, 4, 0], np.float32)
+    assert oracle.pred_sphere(box, [0, 0, 0, 5])
+    assert not oracle.pred_sphere(box, [0, 0, 0, np.nextafter(np.float32(5), np.float32(0))])
+    unit = np.array([0, 0, 0, 1, 1, 1], np.float32)
+    assert oracle.pred_sphere(unit, [0.5, 0.5, 0.5, 0])          # centre inside
+    assert oracle.pred_sphere(unit, [2, 0.5, 0.5, 1])            # touches face
+    assert not oracle.pred_sphere(unit, [2, 2, 0.5, 1])          # corner at sqrt 2
+    assert oracle.pred_sphere(np.array([1, 1, 1, 1, 1, 1], np.float32), [0, 0, 0, 2])
+
+
+def test_box_predicate_closed():
+    unit = np.array([0, 0, 0, 1, 1, 1], np.float32)
+    assert oracle.pred_box(unit, [1, 1, 1, 2, 2, 2])             # corner touch
+    assert not oracle.pred_box(unit, [1, 1, np.nextafter(np.float32(1), np.float32(2)), 2, 2, 2])
+    assert oracle.pred_box(unit, [0.2, 0.2, 0.2, 0.3, 0.3, 0.3])  # inside
+    assert oracle.pred_box(unit, [-1, -1, -1, 2, 2, 2])          # contains
+
+
+def test_sphere_predicate_matches_exact_distance():
+    rng = np.random.default_rng(9)
+    boxes = rng.random((3000, 6)).astype(np.float32)
+    boxes[:, 3:] = boxes[:, :3] + np.abs(boxes[:, 3:]) * 0.1
+    q = np.array([0.5, 0.5, 0.5, 0.3], np.float32)
+    b64, q64 = boxes.astype(np.float64), q.astype(np.float64)
+    d = np.maximum(np.maximum(b64[:, :3] - q64[:3], q64[:3] - b64[:, 3:]), 0)
+    dist = np.sqrt((d * d).sum(1))
+    clear = np.abs(dist - q64[3]) > 1e-5
+    got = np.array([oracle.pred_sphere(b, q) for b in boxes])
+    assert np.array_equal(got[clear], (dist <= q64[3])[clear])
+
+
+def stack_dfs(t, qkind, q):
+    """Classic stack-based traversal with both children (no ropes)."""
+    pred = oracle.pred_sphere if qkind == 0 else oracle.pred_box
+    out, st, ni = [], [0], t.n - 1
+    while st:
+        v = st.pop()
+        if not pred(t.aabb[v], q):
+            continue
+        if v >= ni:
+            out.append(int(t.perm[v - ni]))
+        else:
+            st.append(int(t.right[v]))
+            st.append(int(t.left[v]))
+    return out
+
+
+def numpy_brute(kind, prims, perm, qkind, q):
+    full = prims if kind == 1 else np.concatenate([prims, prims], 1)
+    b = full[perm]
+    if qkind == 0:
+        d = np.maximum(np.maximum(b[:, :3] - q[:3], q[:3] - b[:, 3:]), np.float32(0))
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        hit = d2 <= q[3] * q[3]
+    else:
+        hit = np.all((q[:3] <= b[:, 3:]) & (b[:, :3] <= q[3:]), axis=1)
+    return perm[hit].tolist()
+
+
+@pytest.mark.parametrize("name,scale", [("small_points", 0.25), ("large_points", 1 / 2048),
+                                        ("clustered_boxes", 1 / 256)])
+def test_traversal_equals_brute_force(name, scale):
+    w = workloads.by_name(name, scale)
+    t = oracle.build(w.kind, w.prims, w.code_bits)
+    off, idx, visits = oracle.query_traverse(w.qkind, w.queries, t)
+    assert visits > 0
+    check = range(w.m) if w.m <= 300 else np.random.default_rng(1).choice(w.m, 300, replace=False)
+    hits = 0
+    for j in check:
+        got = idx[off[j]:off[j + 1]].tolist()
+        brute = oracle.query_brute(w.qkind, w.queries, int(j), w.kind, w.prims, t.perm).tolist()
+        assert got == brute
+        assert got == numpy_brute(w.kind, w.prims, t.perm, w.qkind, w.queries[j])
+        hits += len(got)
+    assert hits > 0
+    for j in list(check)[:40]:
+        assert idx[off[j]:off[j + 1]].tolist() == stack_dfs(t, w.qkind, w.queries[j])
+
+
+def test_queries_on_empty_and_single():
+    t0 = oracle.build(0, np.zeros((0, 3), np.float32), 30)
+    q = np.array([[0, 0, 0, 1]], np.float32)
+    off, idx, _ = oracle.query_traverse(0, q, t0)
+    assert off.tolist() == [0, 0] and idx.size == 0
+    t1 = oracle.build(0, np.array([[0.5, 0.5, 0.5]], np.float32), 30)
+    assert t1.rope.tolist() == [-1] and np.array_equal(t1.aabb[0], [0.5] * 6)
+    off, idx, _ = oracle.query_traverse(0, np.array([[0.5, 0.5, 0.5, 0], [9, 9, 9, 1]], np.float32), t1)
+    assert off.tolist() == [0, 1, 1] and idx.tolist() == [0]
