@@ -1,0 +1,186 @@
+/*
+ * lbvh.h - C ABI of the MI355X (gfx950) rope-LBVH library.
+ *
+ * Builds the linear bounding volume hierarchy of Prokopenko & Lebrun-Grandie,
+ * "Revising Apetrei's bounding volume hierarchy construction algorithm to
+ * allow stackless traversal" (arXiv 2402.00665), and answers range queries
+ * with the stackless traversal that its skip-connections ("ropes") enable.
+ *
+ * Memory and ownership
+ *   Every array argument is a DEVICE pointer owned by the caller, except the
+ *   lbvh_tree descriptor itself, which is host memory.  The library never
+ *   allocates device memory: scratch space comes in through a caller-owned
+ *   workspace whose size the *_workspace_bytes functions return (that size
+ *   is also the build's exact device-memory footprint beyond inputs and
+ *   outputs).  All work is enqueued asynchronously on the given HIP stream
+ *   (a hipStream_t passed as void*; NULL means the null stream).  Inputs must
+ *   stay alive and unmodified, and outputs untouched, until the stream has
+ *   passed the call.  Two calls that share a workspace must be ordered on
+ *   one stream.
+ *
+ * Errors
+ *   Functions return LBVH_OK (0) or a negative status; lbvh_strerror()
+ *   names it.  Arguments are validated before anything is enqueued, so a
+ *   call that returns LBVH_EINVAL or LBVH_ENOSPACE has no effect.
+ *   LBVH_EHIP reports a failed kernel launch.  Faults inside kernels
+ *   surface, as usual for HIP, at the next synchronising call.
+ *
+ * Node ids
+ *   A tree over n >= 1 primitives has n-1 internal nodes and n leaves,
+ *   stored in one array of 2n-1 lbvh_node records: internal node k (Karras
+ *   order) is record k, leaf k (k-th primitive in Morton order) is record
+ *   n-1+k, and -1 is the sentinel that ends a traversal.  Record 0 is the
+ *   root (for n = 1 it is the single leaf).
+ */
+#ifndef LBVH_H
+#define LBVH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ constants */
+
+#define LBVH_OK 0
+#define LBVH_EINVAL (-1)     /* bad argument: null pointer, size, code_bits */
+#define LBVH_ENOSPACE (-2)   /* workspace smaller than *_workspace_bytes */
+#define LBVH_EHIP (-3)       /* a HIP launch or runtime call failed */
+#define LBVH_EDEVICE (-4)    /* a kernel flagged an internal error */
+
+#define LBVH_POINTS 0        /* primitives: float [n][3] = x, y, z */
+#define LBVH_BOXES 1         /* primitives: float [n][6] = lo.xyz, hi.xyz */
+
+#define LBVH_MAX_PRIMS ((int64_t)(1 << 30) - 1)
+
+/* --------------------------------------------------------------- types */
+
+/* One node of the hierarchy, 32 bytes, 16-byte aligned.
+ *   lo, hi : the node's axis-aligned bounding box.  A leaf holds its
+ *            primitive's box (a point p gives lo = hi = p); an internal node
+ *            holds the componentwise min of its children's lo and max of
+ *            their hi, exact in binary32.
+ *   left   : internal node: id of its left child (Karras order: the children
+ *            of a node split at gamma are gamma and gamma+1, Sec. 3.1);
+ *            leaf: index of its primitive in the caller's input array.
+ *   rope   : skip-connection (escape index, Sec. 2): where a traversal goes
+ *            when this node's test fails or after a leaf; -1 = sentinel. */
+typedef struct lbvh_node {
+    float lo[3];
+    int32_t left;
+    float hi[3];
+    int32_t rope;
+} lbvh_node;
+
+/* A built tree.  The caller allocates both arrays and sets the pointers;
+ * the build fills n, code_bits and kind and writes the arrays.
+ *   nodes : device, 2n-1 records (nothing for n = 0).
+ *   codes : device, n Morton codes in ascending order (uint32 for 30-bit
+ *           codes, uint64 for 63-bit); the build also uses it as sort
+ *           scratch.  Queries do not read it. */
+typedef struct lbvh_tree {
+    int64_t n;
+    int32_t code_bits;
+    int32_t kind;
+    lbvh_node *nodes;
+    void *codes;
+} lbvh_tree;
+
+/* ---------------------------------------------------------------- build */
+
+/* Workspace bytes that lbvh_build needs for n primitives of the given kind
+ * (LBVH_POINTS / LBVH_BOXES) and code_bits (30 or 63).  Returns a negative
+ * status for invalid arguments. */
+int64_t lbvh_build_workspace_bytes(int64_t n, int32_t code_bits, int32_t kind);
+
+/* Build the rope-LBVH of n primitives.
+ *   Steps (Sec. 3.1 and Alg. 4): scene box (min/max of all primitive
+ *   boxes); Morton code of each centroid (b = code_bits/3 bits per axis,
+ *   x in the most significant bit of each 3-bit group); stable radix sort of
+ *   (code, input index); one bottom-up pass that merges ranges with a
+ *   compare-and-swap per internal node, names each parent by its Karras
+ *   index, and writes its left child, rope and box.
+ *   prims      : device, float [n][3] (points) or [n][6] (boxes), finite,
+ *                lo <= hi per axis for boxes.
+ *   n          : 0 <= n <= LBVH_MAX_PRIMS.  n = 0 gives an empty tree.
+ *   code_bits  : 30 (uint32 codes) or 63 (uint64 codes).
+ *   tree       : host descriptor with nodes/codes set (non-NULL if n > 0).
+ *   workspace  : device, at least lbvh_build_workspace_bytes(...) bytes,
+ *                256-byte aligned; contents on entry are ignored.
+ * Equal Morton codes are ordered by input index and the keys are made
+ * distinct by the sorted position, so the tree is unique. */
+int lbvh_build(int32_t kind, const float *prims, int64_t n, int32_t code_bits,
+               lbvh_tree *tree, void *workspace, int64_t workspace_bytes,
+               void *stream);
+
+/* lbvh_build with kind = LBVH_POINTS; xyz is float [n][3]. */
+int lbvh_build_points(const float *xyz, int64_t n, int32_t code_bits,
+                      lbvh_tree *tree, void *workspace, int64_t workspace_bytes,
+                      void *stream);
+
+/* lbvh_build with kind = LBVH_BOXES; lohi is float [n][6]. */
+int lbvh_build_boxes(const float *lohi, int64_t n, int32_t code_bits,
+                     lbvh_tree *tree, void *workspace, int64_t workspace_bytes,
+                     void *stream);
+
+/* Synchronise the stream and report an internal error that a build's
+ * kernels flagged in the workspace (LBVH_EDEVICE), else LBVH_OK.  For tests
+ * and debugging; the build itself never synchronises. */
+int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits,
+                     int32_t kind, void *stream);
+
+/* ------------------------------------------------------------- queries */
+
+/* Workspace bytes for a count call over m queries. */
+int64_t lbvh_query_workspace_bytes(int64_t m);
+
+/* Range queries, first of two passes (Alg. 1 per query).
+ * Sphere j is xyzr[j] = (x, y, z, r), r >= 0: a node or primitive box B
+ * matches if d = per-axis max(B.lo - c, c - B.hi, 0) gives
+ * (dx*dx + dy*dy) + dz*dz <= r*r in binary32 (closed ball, no fused
+ * multiply-add).  Box j is lohi[j] = (lo.xyz, hi.xyz): B matches if
+ * lo <= B.hi and B.lo <= hi on every axis (closed boxes).
+ *   offsets : device int64 [m+1]; receives the CSR offsets, offsets[0] = 0
+ *             and offsets[m] = total number of hits.
+ *   workspace: device, at least lbvh_query_workspace_bytes(m) bytes.
+ * The caller reads offsets[m] (the one device-to-host copy), allocates the
+ * index array and calls the matching *_fill. */
+int lbvh_query_spheres_count(const lbvh_tree *tree, const float *xyzr, int64_t m,
+                             int64_t *offsets, void *workspace,
+                             int64_t workspace_bytes, void *stream);
+int lbvh_query_boxes_count(const lbvh_tree *tree, const float *lohi, int64_t m,
+                           int64_t *offsets, void *workspace,
+                           int64_t workspace_bytes, void *stream);
+
+/* Second pass: repeat the traversal and write, for query j, the input
+ * indices of the matching primitives into indices[offsets[j] .. offsets[j+1])
+ * in traversal order (ascending Morton-order position).
+ *   offsets : device int64 [m+1] from the count call.
+ *   indices : device int32 [offsets[m]]. */
+int lbvh_query_spheres_fill(const lbvh_tree *tree, const float *xyzr, int64_t m,
+                            const int64_t *offsets, int32_t *indices, void *stream);
+int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
+                          const int64_t *offsets, int32_t *indices, void *stream);
+
+/* ------------------------------------------------------------ utilities */
+
+/* Human-readable name of a status code (static string). */
+const char *lbvh_strerror(int status);
+
+/* Per-kernel timing.  While enabled, every launch the library makes is
+ * bracketed by HIP events recorded on the launch's own stream.
+ * lbvh_profile_read synchronises those events and returns, for the kernel
+ * named `kernel`, the summed duration in milliseconds and the number of
+ * launches since the last reset.  Names: "bounds", "bounds_final",
+ * "morton", "sort_pass", "bottomup", "query_count", "query_fill",
+ * "scan".  Returns LBVH_EINVAL for an unknown name. */
+int lbvh_profile_enable(int32_t on);
+int lbvh_profile_reset(void);
+int lbvh_profile_read(const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBVH_H */

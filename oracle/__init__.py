@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check in
 (``paper_2402_00665_amd``) never imports it.
 
 Thin ctypes wrapper over ``lbvh_oracle.c`` (plain, single-threaded C built by
-``oracle/build.py``).  Each function states the definition it follows; the C
+``oracle/make_lib.py``).  Each function states the definition it follows; the C
 file's header lists the readings taken where the paper is silent.
 """
 
@@ -30,8 +30,8 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            from . import build as _b
-            _b.build()
+            from . import make_lib
+            make_lib.build()
         lib = C.CDLL(_LIB_PATH)
         P = C.c_void_p
         i64, i32 = C.c_int64, C.c_int

@@ -1,0 +1,291 @@
+"""Python binding of the MI355X rope-LBVH library (``liblbvh.so``).
+
+Two layers, both argument marshalling only (every step of the build and of
+the queries runs in the library's HIP kernels):
+
+* ``lbvh_*`` functions with the names and arguments of the C ABI in
+  ``include/lbvh.h`` (device pointers as ints, the tree descriptor as a
+  ctypes structure, the stream as a hipStream_t int);
+* ``build`` / ``query`` / ``Tree``: the same calls with torch tensors for
+  device memory and torch's current stream.
+
+The shared library must have been built (``python -m
+paper_2402_00665_amd.build_lib`` or ``__graft_entry__.build()``); there is
+no fallback of any kind.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbvh.so")
+
+LBVH_OK, LBVH_EINVAL, LBVH_ENOSPACE, LBVH_EHIP, LBVH_EDEVICE = 0, -1, -2, -3, -4
+LBVH_POINTS, LBVH_BOXES = 0, 1
+SPHERES, QBOXES = 0, 1
+LBVH_MAX_PRIMS = (1 << 30) - 1
+NODE_BYTES = 32
+
+
+class LbvhError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {lbvh_strerror(status)} ({status})")
+        self.status = status
+
+
+class lbvh_tree(C.Structure):
+    _fields_ = [("n", C.c_int64), ("code_bits", C.c_int32), ("kind", C.c_int32),
+                ("nodes", C.c_void_p), ("codes", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2402_00665_amd.build_lib`")
+        L = C.CDLL(LIB_PATH)
+        P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        T = C.POINTER(lbvh_tree)
+        sig = {
+            "lbvh_build_workspace_bytes": (i64, [i64, i32, i32]),
+            "lbvh_build": (C.c_int, [i32, P, i64, i32, T, P, i64, P]),
+            "lbvh_build_points": (C.c_int, [P, i64, i32, T, P, i64, P]),
+            "lbvh_build_boxes": (C.c_int, [P, i64, i32, T, P, i64, P]),
+            "lbvh_build_check": (C.c_int, [P, i64, i32, i32, P]),
+            "lbvh_query_workspace_bytes": (i64, [i64]),
+            "lbvh_query_spheres_count": (C.c_int, [T, P, i64, P, P, i64, P]),
+            "lbvh_query_boxes_count": (C.c_int, [T, P, i64, P, P, i64, P]),
+            "lbvh_query_spheres_fill": (C.c_int, [T, P, i64, P, P, P]),
+            "lbvh_query_boxes_fill": (C.c_int, [T, P, i64, P, P, P]),
+            "lbvh_strerror": (C.c_char_p, [C.c_int]),
+            "lbvh_profile_enable": (C.c_int, [i32]),
+            "lbvh_profile_reset": (C.c_int, []),
+            "lbvh_profile_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype, f.argtypes = res, args
+        _lib = L
+    return _lib
+
+
+# --------------------------------------------------------- C-ABI names
+
+def lbvh_strerror(status: int) -> str:
+    return lib().lbvh_strerror(status).decode()
+
+
+def lbvh_build_workspace_bytes(n: int, code_bits: int, kind: int) -> int:
+    return lib().lbvh_build_workspace_bytes(n, code_bits, kind)
+
+
+def lbvh_build(kind, prims_ptr, n, code_bits, tree: lbvh_tree, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_build(kind, prims_ptr, n, code_bits, C.byref(tree), ws_ptr, ws_bytes, stream)
+
+
+def lbvh_build_points(xyz_ptr, n, code_bits, tree: lbvh_tree, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_build_points(xyz_ptr, n, code_bits, C.byref(tree), ws_ptr, ws_bytes, stream)
+
+
+def lbvh_build_boxes(lohi_ptr, n, code_bits, tree: lbvh_tree, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_build_boxes(lohi_ptr, n, code_bits, C.byref(tree), ws_ptr, ws_bytes, stream)
+
+
+def lbvh_build_check(ws_ptr, n, code_bits, kind, stream) -> int:
+    return lib().lbvh_build_check(ws_ptr, n, code_bits, kind, stream)
+
+
+def lbvh_query_workspace_bytes(m: int) -> int:
+    return lib().lbvh_query_workspace_bytes(m)
+
+
+def lbvh_query_spheres_count(tree, q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_spheres_count(C.byref(tree), q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_query_boxes_count(tree, q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_boxes_count(C.byref(tree), q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_query_spheres_fill(tree, q_ptr, m, offsets_ptr, idx_ptr, stream) -> int:
+    return lib().lbvh_query_spheres_fill(C.byref(tree), q_ptr, m, offsets_ptr, idx_ptr, stream)
+
+
+def lbvh_query_boxes_fill(tree, q_ptr, m, offsets_ptr, idx_ptr, stream) -> int:
+    return lib().lbvh_query_boxes_fill(C.byref(tree), q_ptr, m, offsets_ptr, idx_ptr, stream)
+
+
+def lbvh_profile_enable(on: bool) -> int:
+    return lib().lbvh_profile_enable(1 if on else 0)
+
+
+def lbvh_profile_reset() -> int:
+    return lib().lbvh_profile_reset()
+
+
+def lbvh_profile_read(kernel: str):
+    ms, cnt = C.c_double(0.0), C.c_int64(0)
+    rc = lib().lbvh_profile_read(kernel.encode(), C.byref(ms), C.byref(cnt))
+    if rc != LBVH_OK:
+        raise LbvhError(rc, f"lbvh_profile_read({kernel})")
+    return ms.value, cnt.value
+
+
+# ------------------------------------------------------- torch layer
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != LBVH_OK:
+        raise LbvhError(rc, what)
+
+
+def _dev_f32(t, width, what):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32):
+        raise TypeError(f"{what} must be a float32 CUDA tensor")
+    if t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous [n, {width}] tensor")
+    return t
+
+
+@dataclass
+class Tree:
+    """A built tree: ``nodes`` is int32 [2n-1, 8] (lo.xyz, left, hi.xyz,
+    rope; the float fields are stored by bit pattern), ``codes`` the sorted
+    Morton codes (int32 storage for 30-bit codes, int64 for 63-bit)."""
+    n: int
+    code_bits: int
+    kind: int
+    nodes: object
+    codes: object
+    desc: lbvh_tree
+
+    @property
+    def lo(self):
+        return self.nodes[:, 0:3].view(_torch().float32)
+
+    @property
+    def hi(self):
+        return self.nodes[:, 4:7].view(_torch().float32)
+
+    @property
+    def left(self):
+        """Left-child ids of the internal nodes, [n-1]."""
+        return self.nodes[: max(self.n - 1, 0), 3]
+
+    @property
+    def rope(self):
+        return self.nodes[:, 7]
+
+    @property
+    def perm(self):
+        """Leaf k -> input index of its primitive, [n]."""
+        return self.nodes[max(self.n - 1, 0):, 3]
+
+
+class Workspace:
+    """Grow-only device scratch buffer (a torch uint8 tensor)."""
+
+    def __init__(self, device=None):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device or "cuda")
+        return self.buf
+
+
+def alloc_tree(n: int, code_bits: int, device="cuda") -> Tree:
+    torch = _torch()
+    nodes = torch.empty((max(2 * n - 1, 0), 8), dtype=torch.int32, device=device)
+    codes = torch.empty(max(n, 1), dtype=torch.int32 if code_bits == 30 else torch.int64, device=device)
+    desc = lbvh_tree(n, code_bits, 0, nodes.data_ptr() if n > 0 else None, codes.data_ptr())
+    return Tree(n, code_bits, 0, nodes, codes, desc)
+
+
+def build(prims, code_bits: int, kind: int | None = None, workspace: Workspace | None = None,
+          tree: Tree | None = None, stream=None) -> Tree:
+    """Build the rope-LBVH of ``prims`` (float32 CUDA [n,3] points or [n,6]
+    boxes) on the current stream; asynchronous."""
+    if kind is None:
+        kind = LBVH_POINTS if prims.shape[1] == 3 else LBVH_BOXES
+    prims = _dev_f32(prims, 3 if kind == LBVH_POINTS else 6, "prims")
+    n = int(prims.shape[0])
+    if tree is None or tree.n != n or tree.code_bits != code_bits:
+        tree = alloc_tree(n, code_bits, prims.device)
+    ws_bytes = lbvh_build_workspace_bytes(n, code_bits, kind)
+    _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_build_workspace_bytes")
+    ws = (workspace or Workspace(prims.device)).get(ws_bytes)
+    rc = lbvh_build(kind, prims.data_ptr() if n else None, n, code_bits, tree.desc,
+                    ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(rc, "lbvh_build")
+    tree.kind = kind
+    tree.last_workspace = ws
+    return tree
+
+
+def check_build(tree: Tree, stream=None):
+    """Synchronise and raise if the last build on this tree flagged an error."""
+    ws = getattr(tree, "last_workspace", None)
+    if ws is None or tree.n == 0:
+        return
+    _check(lbvh_build_check(ws.data_ptr(), tree.n, tree.code_bits, tree.kind, _stream(stream)),
+           "lbvh_build_check")
+
+
+def query_count(tree: Tree, queries, qkind: int, offsets=None, workspace: Workspace | None = None,
+                stream=None):
+    torch = _torch()
+    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    m = int(q.shape[0])
+    if offsets is None:
+        offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
+    ws_bytes = lbvh_query_workspace_bytes(m)
+    _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_query_workspace_bytes")
+    ws = (workspace or Workspace(q.device)).get(ws_bytes)
+    f = lbvh_query_spheres_count if qkind == SPHERES else lbvh_query_boxes_count
+    _check(f(tree.desc, q.data_ptr() if m else None, m, offsets.data_ptr(), ws.data_ptr(),
+             ws.numel(), _stream(stream)), "query count")
+    return offsets
+
+
+def query_fill(tree: Tree, queries, qkind: int, offsets, indices, stream=None):
+    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    m = int(q.shape[0])
+    f = lbvh_query_spheres_fill if qkind == SPHERES else lbvh_query_boxes_fill
+    _check(f(tree.desc, q.data_ptr() if m else None, m, offsets.data_ptr(),
+             indices.data_ptr(), _stream(stream)), "query fill")
+    return indices
+
+
+def query(tree: Tree, queries, qkind: int, workspace: Workspace | None = None, stream=None):
+    """Count, read the total (one 8-byte device-to-host copy), fill.
+    Returns (offsets int64 [m+1], indices int32 [total]) on the device."""
+    torch = _torch()
+    offsets = query_count(tree, queries, qkind, workspace=workspace, stream=stream)
+    total = int(offsets[-1].item())
+    # at least one element so the device pointer is never null
+    buf = torch.empty(max(total, 1), dtype=torch.int32, device=queries.device)
+    query_fill(tree, queries, qkind, offsets, buf, stream=stream)
+    return offsets, buf[:total]

@@ -1,0 +1,289 @@
+// C ABI of the rope-LBVH library: argument checks, workspace layout,
+// launch sequencing on the caller's stream, per-kernel event timing.
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "lbvh_internal.hpp"
+
+namespace lbvh {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+BuildLayout build_layout(int64_t n, int code_bits)
+{
+    BuildLayout L{};
+    const size_t kb = (size_t)key_bytes(code_bits);
+    L.passes = radix_passes(code_bits);
+    L.ntiles = (n + kTile - 1) / kTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+    L.scene = take(3 * sizeof(float4));
+    L.partials = take((size_t)kBoundsBlocksMax * 8 * sizeof(float));
+    L.ctrl = take(kCtrlWords * sizeof(uint32_t));
+    L.hist = take((size_t)L.passes * kRadix * sizeof(uint32_t));
+    L.status[0] = take((size_t)L.ntiles * kRadix * sizeof(uint32_t));
+    L.status[1] = take((size_t)L.ntiles * kRadix * sizeof(uint32_t));
+    L.keys_alt = take((size_t)n * kb);
+    L.vals[0] = take((size_t)n * sizeof(int32_t));
+    L.vals[1] = take((size_t)n * sizeof(int32_t));
+    L.store = take((size_t)(n > 1 ? n - 1 : 1) * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+QueryLayout query_layout(int64_t m)
+{
+    QueryLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+    L.counts = take((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    L.partials = take((size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------- timing
+
+namespace {
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    hipEvent_t open[K_NUM] = {};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[K_NUM];
+    double ms[K_NUM] = {};
+    int64_t launches[K_NUM] = {};
+    std::vector<hipEvent_t> pool;
+
+    hipEvent_t get()
+    {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void drain(int id)
+    {
+        for (auto &pr : pending[id]) {
+            float t = 0.0f;
+            if (hipEventSynchronize(pr.second) == hipSuccess &&
+                hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) {
+                ms[id] += t;
+                launches[id] += 1;
+            }
+            pool.push_back(pr.first);
+            pool.push_back(pr.second);
+        }
+        pending[id].clear();
+    }
+};
+Profiler &prof()
+{
+    static Profiler p;
+    return p;
+}
+const char *kNames[K_NUM] = {"bounds", "bounds_final", "morton", "sort_pass",
+                             "bottomup", "query_count", "query_fill", "scan"};
+}  // namespace
+
+void prof_begin(int id, hipStream_t s)
+{
+    Profiler &P = prof();
+    if (!P.on) return;
+    std::lock_guard<std::mutex> g(P.mu);
+    hipEvent_t e = P.get();
+    if (e && hipEventRecord(e, s) == hipSuccess) P.open[id] = e;
+}
+
+void prof_end(int id, hipStream_t s)
+{
+    Profiler &P = prof();
+    if (!P.on) return;
+    std::lock_guard<std::mutex> g(P.mu);
+    hipEvent_t e = P.get();
+    if (!e || !P.open[id]) return;
+    if (hipEventRecord(e, s) == hipSuccess) P.pending[id].push_back({P.open[id], e});
+    P.open[id] = nullptr;
+}
+
+}  // namespace lbvh
+
+using namespace lbvh;
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+extern "C" {
+
+const char *lbvh_strerror(int status)
+{
+    switch (status) {
+    case LBVH_OK: return "ok";
+    case LBVH_EINVAL: return "invalid argument";
+    case LBVH_ENOSPACE: return "workspace too small";
+    case LBVH_EHIP: return "HIP launch or runtime error";
+    case LBVH_EDEVICE: return "device-side error flagged by a kernel";
+    default: return "unknown status";
+    }
+}
+
+int64_t lbvh_build_workspace_bytes(int64_t n, int32_t code_bits, int32_t kind)
+{
+    if (n < 0 || n > LBVH_MAX_PRIMS || (code_bits != 30 && code_bits != 63) ||
+        (kind != LBVH_POINTS && kind != LBVH_BOXES))
+        return LBVH_EINVAL;
+    return (int64_t)build_layout(n, code_bits).total;
+}
+
+int lbvh_build(int32_t kind, const float *prims, int64_t n, int32_t code_bits, lbvh_tree *tree,
+               void *workspace, int64_t workspace_bytes, void *stream)
+{
+    if (!tree || n < 0 || n > LBVH_MAX_PRIMS || (code_bits != 30 && code_bits != 63) ||
+        (kind != LBVH_POINTS && kind != LBVH_BOXES))
+        return LBVH_EINVAL;
+    if (n == 0) {
+        tree->n = 0;
+        tree->code_bits = code_bits;
+        tree->kind = kind;
+        return LBVH_OK;
+    }
+    if (!prims || !tree->nodes || !tree->codes || !workspace || !aligned(prims, 16) ||
+        !aligned(tree->nodes, 16) || !aligned(tree->codes, 16) || !aligned(workspace, 256))
+        return LBVH_EINVAL;
+    const BuildLayout L = build_layout(n, code_bits);
+    if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
+    tree->n = n;
+    tree->code_bits = code_bits;
+    tree->kind = kind;
+    hipError_t e = launch_build(kind, prims, (int)n, code_bits, tree->nodes, tree->codes,
+                                static_cast<char *>(workspace), L, (hipStream_t)stream);
+    return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
+}
+
+int lbvh_build_points(const float *xyz, int64_t n, int32_t code_bits, lbvh_tree *tree,
+                      void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return lbvh_build(LBVH_POINTS, xyz, n, code_bits, tree, workspace, workspace_bytes, stream);
+}
+
+int lbvh_build_boxes(const float *lohi, int64_t n, int32_t code_bits, lbvh_tree *tree,
+                     void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return lbvh_build(LBVH_BOXES, lohi, n, code_bits, tree, workspace, workspace_bytes, stream);
+}
+
+int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits, int32_t kind,
+                     void *stream)
+{
+    if (lbvh_build_workspace_bytes(n, code_bits, kind) < 0 || !workspace) return LBVH_EINVAL;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return LBVH_EHIP;
+    if (n == 0) return LBVH_OK;
+    const BuildLayout L = build_layout(n, code_bits);
+    uint32_t flag = 0;
+    if (hipMemcpy(&flag, static_cast<const char *>(workspace) + L.ctrl + kCtrlError * sizeof(uint32_t),
+                  sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess)
+        return LBVH_EHIP;
+    return flag ? LBVH_EDEVICE : LBVH_OK;
+}
+
+int64_t lbvh_query_workspace_bytes(int64_t m)
+{
+    if (m < 0 || m > INT32_MAX) return LBVH_EINVAL;
+    return (int64_t)query_layout(m).total;
+}
+
+static int query_count(int qkind, const lbvh_tree *tree, const float *q, int64_t m, int64_t *offsets,
+                       void *workspace, int64_t workspace_bytes, void *stream)
+{
+    if (!tree || m < 0 || m > INT32_MAX || tree->n < 0 || tree->n > LBVH_MAX_PRIMS || !offsets ||
+        !aligned(offsets, 8))
+        return LBVH_EINVAL;
+    if (m > 0 && (!q || !aligned(q, 16))) return LBVH_EINVAL;
+    if (tree->n > 0 && (!tree->nodes || !aligned(tree->nodes, 16))) return LBVH_EINVAL;
+    const QueryLayout L = query_layout(m);
+    if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
+    if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
+    hipError_t e = launch_query(qkind, tree->nodes, (int)tree->n, q, (int)m, offsets, nullptr, false,
+                                static_cast<char *>(workspace), L, (hipStream_t)stream);
+    return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
+}
+
+static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t m,
+                      const int64_t *offsets, int32_t *indices, void *stream)
+{
+    if (!tree || m < 0 || m > INT32_MAX || tree->n < 0 || tree->n > LBVH_MAX_PRIMS || !offsets ||
+        !aligned(offsets, 8))
+        return LBVH_EINVAL;
+    if (m > 0 && (!q || !aligned(q, 16))) return LBVH_EINVAL;
+    if (tree->n > 0 && m > 0 && (!tree->nodes || !indices || !aligned(tree->nodes, 16)))
+        return LBVH_EINVAL;
+    const QueryLayout L = query_layout(0);
+    hipError_t e = launch_query(qkind, tree->nodes, (int)tree->n, q, (int)m,
+                                const_cast<int64_t *>(offsets), indices, true, nullptr, L,
+                                (hipStream_t)stream);
+    return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
+}
+
+int lbvh_query_spheres_count(const lbvh_tree *tree, const float *xyzr, int64_t m, int64_t *offsets,
+                             void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return query_count(0, tree, xyzr, m, offsets, workspace, workspace_bytes, stream);
+}
+
+int lbvh_query_boxes_count(const lbvh_tree *tree, const float *lohi, int64_t m, int64_t *offsets,
+                           void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return query_count(1, tree, lohi, m, offsets, workspace, workspace_bytes, stream);
+}
+
+int lbvh_query_spheres_fill(const lbvh_tree *tree, const float *xyzr, int64_t m,
+                            const int64_t *offsets, int32_t *indices, void *stream)
+{
+    return query_fill(0, tree, xyzr, m, offsets, indices, stream);
+}
+
+int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
+                          const int64_t *offsets, int32_t *indices, void *stream)
+{
+    return query_fill(1, tree, lohi, m, offsets, indices, stream);
+}
+
+int lbvh_profile_enable(int32_t on)
+{
+    Profiler &P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.on = on != 0;
+    return LBVH_OK;
+}
+
+int lbvh_profile_reset(void)
+{
+    Profiler &P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (int k = 0; k < K_NUM; ++k) {
+        P.drain(k);
+        P.ms[k] = 0.0;
+        P.launches[k] = 0;
+    }
+    return LBVH_OK;
+}
+
+int lbvh_profile_read(const char *kernel, double *total_ms, int64_t *launches)
+{
+    if (!kernel) return LBVH_EINVAL;
+    Profiler &P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (int k = 0; k < K_NUM; ++k) {
+        if (strcmp(kernel, kNames[k]) == 0) {
+            P.drain(k);
+            if (total_ms) *total_ms = P.ms[k];
+            if (launches) *launches = P.launches[k];
+            return LBVH_OK;
+        }
+    }
+    return LBVH_EINVAL;
+}
+
+}  // extern "C"

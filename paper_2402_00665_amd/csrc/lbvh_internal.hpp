@@ -1,0 +1,89 @@
+// Internal declarations shared by the library's HIP translation units:
+// workspace layout, tuning constants, launcher prototypes and the
+// per-kernel timing hooks.  Not part of the public C ABI (include/lbvh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbvh.h"
+
+namespace lbvh {
+
+// ------------------------------------------------------------ constants
+
+constexpr int kBlock = 256;           // threads per block of the simple kernels
+constexpr int kRadixBits = 8;         // digit width of the LSD radix sort
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;     // 4 waves of 64
+constexpr int kSortItems = 16;        // keys per thread
+constexpr int kTile = kSortThreads * kSortItems;
+constexpr int kBoundsBlocksMax = 1024;
+constexpr int kMortonBlocksMax = 2048;
+constexpr int kScanItems = 8;         // values per thread in the query scan
+constexpr int kScanTile = kBlock * kScanItems;
+
+// ctrl words at the start of the build workspace
+constexpr int kCtrlTileCounter = 0;   // [0, 8): one per sort pass
+constexpr int kCtrlError = 8;         // non-zero: a kernel flagged an error
+constexpr int kCtrlWords = 64;
+
+// look-back status word: 2 flag bits over a 30-bit count
+constexpr uint32_t kFlagAggregate = 1u << 30;
+constexpr uint32_t kFlagInclusive = 2u << 30;
+constexpr uint32_t kValueMask = (1u << 30) - 1u;
+
+inline int radix_passes(int code_bits) { return (code_bits + kRadixBits - 1) / kRadixBits; }
+inline int key_bytes(int code_bits) { return code_bits <= 32 ? 4 : 8; }
+
+// --------------------------------------------------- workspace layout
+
+struct BuildLayout {
+    size_t scene;      // float4 lo, hi, scale (48 B)
+    size_t partials;   // kBoundsBlocksMax x 8 floats
+    size_t ctrl;       // kCtrlWords uint32
+    size_t hist;       // passes x kRadix uint32 (global digit counts)
+    size_t status[2];  // ntiles x kRadix uint32 each (ping-pong look-back)
+    size_t keys_alt;   // n keys (sort ping-pong partner of tree->codes)
+    size_t vals[2];    // n int32 each (sort values: input indices)
+    size_t store;      // n-1 int32 (Alg. 4 arrival flags / parked range ends)
+    size_t total;
+    int passes;
+    int64_t ntiles;
+};
+
+BuildLayout build_layout(int64_t n, int code_bits);
+
+struct QueryLayout {
+    size_t counts;     // m int32
+    size_t partials;   // ceil(m / kScanTile) int64
+    size_t total;
+};
+
+QueryLayout query_layout(int64_t m);
+
+// ------------------------------------------------------------ timing
+
+enum KernelId {
+    K_BOUNDS = 0, K_BOUNDS_FINAL, K_MORTON, K_SORT, K_BOTTOMUP,
+    K_QCOUNT, K_QFILL, K_SCAN, K_NUM
+};
+
+void prof_begin(int id, hipStream_t s);
+void prof_end(int id, hipStream_t s);
+
+// ---------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.  Arguments are already
+// validated by the C ABI layer.
+
+hipError_t launch_build(int kind, const float *prims, int n, int code_bits,
+                        lbvh_node *nodes, void *codes, char *ws,
+                        const BuildLayout &L, hipStream_t s);
+
+hipError_t launch_query(int qkind, const lbvh_node *nodes, int n,
+                        const float *q, int m, int64_t *offsets,
+                        int32_t *indices, bool fill, char *ws,
+                        const QueryLayout &L, hipStream_t s);
+
+}  // namespace lbvh

@@ -1,0 +1,152 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every build output (sorted Morton codes, leaf permutation, left children,
+ropes, node boxes) and every query result (CSR offsets and indices, in
+order) must be identical to the oracle's: integers bit for bit, binary32
+boxes exactly (tolerance 0).  The oracle's query answers are themselves
+pinned to brute force by the CPU tests.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import (assert_query_equal, assert_tree_equal, gpu_build, gpu_query, host_tree,
+                      say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ws():
+    import paper_2402_00665_amd as lb
+    return lb.Workspace()
+
+
+def _parity(w: workloads.Workload, ws, queries=True):
+    say(f"case {w.name}: n={w.n} m={w.m} bits={w.code_bits} kind={w.kind}")
+    ref = oracle.build(w.kind, w.prims, w.code_bits)
+    tree, _ = gpu_build(w.prims, w.kind, w.code_bits, ws)
+    assert_tree_equal(tree, ref)
+    if queries:
+        roff, ridx, _ = oracle.query_traverse(w.qkind, w.queries, ref)
+        off, idx = gpu_query(tree, w.queries, w.qkind, ws)
+        assert_query_equal(off, idx, roff, ridx)
+        return int(roff[-1])
+    return None
+
+
+def test_small_points_full_size(ws):
+    hits = _parity(workloads.small_points(), ws)
+    assert hits > 0
+
+
+@pytest.mark.parametrize("name,scale", [("large_points", 1 / 64), ("clustered_boxes", 1 / 64),
+                                        ("large_points", 1 / 1000), ("clustered_boxes", 1 / 1000)])
+def test_reduced_workloads(name, scale, ws):
+    _parity(workloads.by_name(name, scale), ws)
+
+
+SIZES = [1, 2, 3, 5, 63, 64, 65, 127, 4095, 4096, 4097, 12289, 100003]
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_sizes_kinds_bits(kind, bits, ws):
+    rng = np.random.default_rng([11, kind, bits])
+    for n in SIZES:
+        if kind == 0:
+            prims = rng.random((n, 3), dtype=np.float32)
+        else:
+            c = rng.random((n, 3))
+            s = rng.random((n, 3)) * 0.02
+            prims = np.concatenate([c - s, c + s], 1).astype(np.float32)
+        q = workloads.spheres(rng.random((97, 3), dtype=np.float32), np.float32(0.1))
+        _parity(workloads.Workload(f"sizes_{n}", kind, prims, bits, 0, q), ws)
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+def test_degenerate_inputs(bits, ws):
+    rng = np.random.default_rng([12, bits])
+    n = 5000
+    cases = {
+        "all_equal": np.full((n, 3), 0.25, np.float32),
+        "plane": np.concatenate([rng.random((n, 2), dtype=np.float32), np.full((n, 1), 3.0, np.float32)], 1),
+        "line": np.stack([rng.random(n, dtype=np.float32)] * 3, 1),
+        "grid_dups": (rng.integers(0, 4, size=(n, 3)) / 3.0).astype(np.float32),
+        "negative_wide": (rng.normal(size=(n, 3)) * 1e4).astype(np.float32),
+        "filled_cube": workloads.filled_cube(n, rng),
+        "hollow_cube": workloads.hollow_cube(n, rng),
+    }
+    for name, p in cases.items():
+        lo, hi = p.min(0), p.max(0)
+        c = (lo + (hi - lo) * rng.random((64, 3))).astype(np.float32)
+        q = workloads.spheres(c, np.float32(0.05 * float(np.max(hi - lo)) + 0.01))
+        _parity(workloads.Workload(name, 0, np.ascontiguousarray(p), bits, 0, q), ws)
+
+
+def test_query_edge_cases(ws):
+    rng = np.random.default_rng(13)
+    p = rng.random((3000, 3), dtype=np.float32)
+    ref = oracle.build(0, p, 30)
+    tree, _ = gpu_build(p, 0, 30, ws)
+    qs = {
+        "r0_on_points": workloads.spheres(p[:50], np.float32(0.0)),
+        "huge": workloads.spheres(rng.random((5, 3), dtype=np.float32), np.float32(10.0)),
+        "far": workloads.spheres(rng.random((5, 3), dtype=np.float32) + 5, np.float32(0.5)),
+        "empty": np.zeros((0, 4), np.float32),
+    }
+    for name, q in qs.items():
+        say(f"query case {name}")
+        roff, ridx, _ = oracle.query_traverse(0, q, ref)
+        off, idx = gpu_query(tree, q, 0, ws)
+        assert_query_equal(off, idx, roff, ridx)
+    boxes = np.concatenate([p[:20] - 0.01, p[:20] + 0.01], 1).astype(np.float32)
+    roff, ridx, _ = oracle.query_traverse(1, boxes, ref)
+    off, idx = gpu_query(tree, boxes, 1, ws)
+    assert_query_equal(off, idx, roff, ridx)
+    assert off[1] >= 1
+
+
+def test_empty_tree(ws):
+    import torch
+    import paper_2402_00665_amd as lb
+    tree = lb.build(torch.zeros((0, 3), dtype=torch.float32, device="cuda"), 30, workspace=ws)
+    assert tree.n == 0
+    q = workloads.spheres(np.random.default_rng(1).random((10, 3), dtype=np.float32), np.float32(1))
+    off, idx = gpu_query(tree, q, 0, ws)
+    assert off.tolist() == [0] * 11 and idx.size == 0
+
+
+def test_repeated_builds_are_identical(ws):
+    """Alg. 4's schedule differs run to run; the tree must not."""
+    w = workloads.clustered(1 << 17, 1)
+    tree, dev = gpu_build(w.prims, w.kind, w.code_bits, ws)
+    first = tree.nodes.clone()
+    import paper_2402_00665_amd as lb
+    import torch
+    for r in range(20):
+        tree = lb.build(dev, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
+        torch.cuda.synchronize()
+        assert torch.equal(tree.nodes, first), f"build {r} differs"
+    lb.check_build(tree)
+
+
+def test_workspace_reuse_across_sizes(ws):
+    rng = np.random.default_rng(14)
+    for n in (70000, 1000, 33333):
+        p = rng.random((n, 3), dtype=np.float32)
+        ref = oracle.build(0, p, 63)
+        tree, _ = gpu_build(p, 0, 63, ws)
+        assert_tree_equal(tree, ref)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["large_points", "clustered_boxes"])
+def test_full_size(name, ws):
+    """Full-size workloads in the configuration the benchmark times: every
+    build output and every query result."""
+    say(f"full-size {name}: generating")
+    w = workloads.by_name(name)
+    _parity(w, ws)
