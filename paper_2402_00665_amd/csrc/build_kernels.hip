@@ -6,9 +6,10 @@
 //   k_morton                   Morton code per primitive + the digit
 //                              histograms of every radix pass
 //   k_onesweep (x passes)      LSD radix pass with decoupled look-back
-//   k_bottomup                 Alg. 4: leaves up, one CAS per internal node,
-//                              Karras-ordered parents with left child, rope
-//                              and box written by the second thread to arrive
+//   k_bottomup_l0 / _up        Alg. 4 in levels of blocks: leaves up, one
+//                              CAS per internal node, Karras-ordered parents
+//                              with left child, rope and box written by the
+//                              second thread to arrive
 //
 // Floating point follows binary32 with no contraction (the library is built
 // with -ffp-contract=off and the pragma below repeats it), no fast-math and
@@ -227,15 +228,14 @@ __device__ __forceinline__ K code_of(const float lo[3], const float hi[3], float
 }
 
 // Codes in input order, LDS digit histograms of every radix pass folded
-// into the global ones, and two side jobs that must precede the sort and
-// the bottom-up pass: clear the look-back status of the first sort pass and
-// set every Alg. 4 arrival flag to "empty" (-1).
+// into the global ones, and one side job that must precede the sort: clear
+// the look-back status of the first sort pass.
 template <int KIND, typename K>
 __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ prims, int n,
                                                    const float4 *__restrict__ scene,
                                                    K *__restrict__ codes, uint32_t *__restrict__ hist,
                                                    int passes, uint32_t *__restrict__ status0,
-                                                   int64_t status_words, int32_t *__restrict__ store)
+                                                   int64_t status_words)
 {
     using P = Prims<KIND>;
     __shared__ uint32_t lh[8 * kRadix];
@@ -244,7 +244,6 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     for (int64_t j = tid; j < status_words; j += stride) status0[j] = 0u;
-    for (int64_t j = tid; j < n - 1; j += stride) store[j] = -1;
     __syncthreads();
 
     const float4 slo = scene[0], sc = scene[2];
@@ -440,6 +439,25 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
 }
 
 // ------------------------------------------------------------ Alg. 4
+//
+// Alg. 4 runs in levels of blocks so that every compare-and-swap on `store`
+// has all of its possible participants inside one workgroup and needs only
+// workgroup-scope ordering (an agent-scope acquire-release CAS per tree
+// level would write back and invalidate the XCD's L2 every time):
+//   level 0   block b takes the kChunk leaves [A, B) = [b*kChunk, ...):
+//             leaf records, then the climb with `store` and every box of
+//             the chunk in LDS;
+//   level L   block b takes the kFanout level-(L-1) blocks under its span
+//             [A, B) and resumes their handed-over threads, with `store` and
+//             the node records in global memory.
+// A block owns the boundaries strictly inside [A, B).  A thread whose next
+// parent is split at A-1 or B-1 stops and hands its state (node, range) to
+// the level above; that parent's other child cannot be finished inside this
+// block.  Parents split inside [A, B) meet their two children either inside
+// the block or in a later launch, and launches on one stream see all writes
+// of earlier ones.  The top level is one block owning [0, n), so the climb
+// always reaches the root.  Every internal node is still written once, by
+// the second thread to arrive, exactly as in Alg. 4.
 
 // delta*(i): rank of the highest differing bit of the augmented keys
 // (code, sorted position) of leaves i and i+1; codes that differ rank
@@ -461,82 +479,190 @@ __device__ __forceinline__ void store_node(float4 *nodes, int id, const float lo
     p[1] = make_float4(hi[0], hi[1], hi[2], __int_as_float(rope));
 }
 
-// One thread per leaf i (Morton order).  The leaf's rope follows Alg. 2
-// with the leaf's own range [i, i].  Going up, the thread parks its range
-// end in store[p] (p = the parent's split, the Apetrei index) with a CAS;
-// the first thread to arrive leaves, the second one owns the parent: it
-// learns the full range, names the parent by its Karras index q (the range
-// bound with the smaller adjacent delta*), sets the left child (leaf p if
-// the range starts at p, else internal p), the rope (Alg. 2 from the right
-// bound) and the box (own box united with the sibling's, which the sibling
-// wrote before its CAS), and continues from q until the root (q = 0).
-// The CAS is acquire-release at agent scope so the sibling's node record,
-// written with ordinary stores, is visible across XCDs.
+// A path has at most one node per distinct delta* rank (<= 64 + 31), so a
+// climb ends well within this cap; it only guards against corrupted input.
+constexpr int kMaxDepth = 256;
+
 template <int KIND, typename K>
-__global__ __launch_bounds__(kBlock) void k_bottomup(const K *__restrict__ codes,
-                                                     const int32_t *__restrict__ perm,
-                                                     const float *__restrict__ prims, int n,
-                                                     int32_t *store, float4 *nodes, uint32_t *err)
+__global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict__ codes,
+                                                             const int32_t *__restrict__ perm,
+                                                             const float *__restrict__ prims,
+                                                             int n, int32_t *__restrict__ store,
+                                                             float4 *__restrict__ nodes,
+                                                             int4 *__restrict__ pend,
+                                                             uint32_t *err)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int leaf0 = n - 1;   // id of leaf 0
+    __shared__ K s_codes[kChunk + 3];        // codes[A-1 .. B+1]
+    __shared__ int32_t s_store[kChunk];      // store[A .. B-1]
+    __shared__ float s_box[6][2 * kChunk];   // internal A.. then leaves A..
+    __shared__ int4 s_pend[2];
 
-    const int prim = perm[i];
-    float lo[3], hi[3];
-    Prims<KIND>::one(prims, prim, lo, hi);
+    const int A = blockIdx.x * kChunk;
+    const int B = min(A + kChunk, n);
+    const int cn = B - A;
+    const int leaf0 = n - 1;
 
-    int dl = delta_rank(codes, i - 1, n);
-    int dr = delta_rank(codes, i, n);
-    int rope;
-    if (i == n - 1) rope = -1;
-    else rope = dr < delta_rank(codes, i + 1, n) ? leaf0 + i + 1 : i + 1;
-    store_node(nodes, leaf0 + i, lo, prim, hi, rope);
-    if (n == 1) return;
-
-    int rl = i, rr = i;
-    // A path has at most one node per distinct delta* rank (<= 64 + 31), so
-    // the climb ends well within kMaxDepth; the cap only guards against a
-    // corrupted input order.
-    constexpr int kMaxDepth = 256;
-    for (int level = 0;; ++level) {
-        if (level == kMaxDepth) {
-            __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
-        int p, sib;
-        if (dr < dl) {                     // left child of its parent
-            p = rr;
-            int other = -1;
-            if (__hip_atomic_compare_exchange_strong(&store[p], &other, rl, __ATOMIC_ACQ_REL,
-                                                     __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT))
-                return;                    // first to arrive
-            rr = other;
-            dr = delta_rank(codes, rr, n);
-            sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
-        } else {                           // right child of its parent
-            p = rl - 1;
-            int other = -1;
-            if (__hip_atomic_compare_exchange_strong(&store[p], &other, rr, __ATOMIC_ACQ_REL,
-                                                     __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT))
-                return;
-            rl = other;
-            dl = delta_rank(codes, rl - 1, n);
-            sib = (rl == p) ? leaf0 + p : p;
-        }
-        const float4 *s = nodes + 2 * (int64_t)sib;
-        const float4 s0 = s[0], s1 = s[1];
-        lo[0] = fminf(lo[0], s0.x); lo[1] = fminf(lo[1], s0.y); lo[2] = fminf(lo[2], s0.z);
-        hi[0] = fmaxf(hi[0], s1.x); hi[1] = fmaxf(hi[1], s1.y); hi[2] = fmaxf(hi[2], s1.z);
-
-        const int q = dr < dl ? rr : rl;   // Karras index of the parent
-        const int left = (rl == p) ? leaf0 + p : p;
-        int qrope;
-        if (rr == n - 1) qrope = -1;
-        else qrope = dr < delta_rank(codes, rr + 1, n) ? leaf0 + rr + 1 : rr + 1;
-        store_node(nodes, q, lo, left, hi, qrope);
-        if (q == 0) return;
+    for (int t = threadIdx.x; t < cn + 3; t += kBU0Threads) {
+        const int g = A - 1 + t;
+        s_codes[t] = (g >= 0 && g < n) ? codes[g] : (K)0;
     }
+    for (int t = threadIdx.x; t < kChunk; t += kBU0Threads) s_store[t] = -1;
+    if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
+    __syncthreads();
+
+    // delta*(g) for g in [A-1, B]
+    auto delta = [&](int g) -> int {
+        if (g < 0 || g >= n - 1) return 255;
+        const K x = s_codes[g - A + 1] ^ s_codes[g - A + 2];
+        if (x) return 64 + highest_bit(x);
+        return highest_bit((uint32_t)(g ^ (g + 1)));
+    };
+
+    // leaves: box, primitive id, rope (Alg. 2 on the range [i, i])
+    for (int i = A + threadIdx.x; i < B; i += kBU0Threads) {
+        const int prim = perm[i];
+        float lo[3], hi[3];
+        Prims<KIND>::one(prims, prim, lo, hi);
+        const int dr = delta(i);
+        const int rope = (i == n - 1) ? -1 : (dr < delta(i + 1) ? leaf0 + i + 1 : i + 1);
+        store_node(nodes, leaf0 + i, lo, prim, hi, rope);
+        const int sl = kChunk + (i - A);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { s_box[a][sl] = lo[a]; s_box[3 + a][sl] = hi[a]; }
+    }
+    __syncthreads();
+
+    if (n > 1) {
+        for (int i = A + threadIdx.x; i < B; i += kBU0Threads) {
+            int rl = i, rr = i, cur = leaf0 + i;
+            int dl = delta(i - 1), dr = delta(i);
+            float lo[3], hi[3];
+            const int sl = kChunk + (i - A);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { lo[a] = s_box[a][sl]; hi[a] = s_box[3 + a][sl]; }
+            for (int level = 0;; ++level) {
+                if (level == kMaxDepth) {
+                    __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                int p, sib;
+                if (dr < dl) {                 // left child of its parent
+                    p = rr;
+                    if (p == B - 1) { s_pend[1] = make_int4(cur, rl, rr, 0); break; }
+                    int other = -1;
+                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, rl,
+                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;                 // first to arrive
+                    rr = other;
+                    dr = delta(rr);
+                    sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
+                } else {                       // right child of its parent
+                    p = rl - 1;
+                    if (p == A - 1) { s_pend[0] = make_int4(cur, rl, rr, 0); break; }
+                    int other = -1;
+                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, rr,
+                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;
+                    rl = other;
+                    dl = delta(rl - 1);
+                    sib = (rl == p) ? leaf0 + p : p;
+                }
+                const int ss = sib >= leaf0 ? kChunk + (sib - leaf0 - A) : sib - A;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], s_box[a][ss]);
+                    hi[a] = fmaxf(hi[a], s_box[3 + a][ss]);
+                }
+                const int q = dr < dl ? rr : rl;   // Karras index of the parent
+                const int left = (rl == p) ? leaf0 + p : p;
+                int qrope;
+                if (rr == n - 1) qrope = -1;
+                else qrope = dr < delta(rr + 1) ? leaf0 + rr + 1 : rr + 1;
+                store_node(nodes, q, lo, left, hi, qrope);
+                const int qs = q - A;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
+                cur = q;
+                if (q == 0) break;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn; t += kBU0Threads) store[A + t] = s_store[t];
+    if (threadIdx.x < 2) pend[2 * blockIdx.x + threadIdx.x] = s_pend[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict__ codes, int n,
+                                                            int64_t child_span, int64_t span,
+                                                            int32_t *store, float4 *nodes,
+                                                            const int4 *__restrict__ pend_in,
+                                                            int4 *__restrict__ pend_out,
+                                                            uint32_t *err)
+{
+    __shared__ int4 s_pend[2];
+    const int64_t A = (int64_t)blockIdx.x * span;
+    const int64_t B = A + span < n ? A + span : n;
+    const int64_t j0 = A / child_span, j1 = (B + child_span - 1) / child_span;
+    const int leaf0 = n - 1;
+    if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
+    __syncthreads();
+
+    for (int64_t slot = 2 * j0 + threadIdx.x; slot < 2 * j1; slot += kBUThreads) {
+        const int4 P = pend_in[slot];
+        if (P.x < 0) continue;
+        int cur = P.x, rl = P.y, rr = P.z;
+        const float4 *own = nodes + 2 * (int64_t)cur;
+        const float4 o0 = own[0], o1 = own[1];
+        float lo[3] = {o0.x, o0.y, o0.z}, hi[3] = {o1.x, o1.y, o1.z};
+        int dl = delta_rank(codes, rl - 1, n), dr = delta_rank(codes, rr, n);
+        for (int level = 0;; ++level) {
+            if (level == kMaxDepth) {
+                __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            int p, sib;
+            if (dr < dl) {
+                p = rr;
+                if (p == B - 1) { s_pend[1] = make_int4(cur, rl, rr, 0); break; }
+                int other = -1;
+                if (__hip_atomic_compare_exchange_strong(&store[p], &other, rl, __ATOMIC_ACQ_REL,
+                                                         __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                rr = other;
+                dr = delta_rank(codes, rr, n);
+                sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
+            } else {
+                p = rl - 1;
+                if (p == A - 1) { s_pend[0] = make_int4(cur, rl, rr, 0); break; }
+                int other = -1;
+                if (__hip_atomic_compare_exchange_strong(&store[p], &other, rr, __ATOMIC_ACQ_REL,
+                                                         __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                rl = other;
+                dl = delta_rank(codes, rl - 1, n);
+                sib = (rl == p) ? leaf0 + p : p;
+            }
+            const float4 *sp = nodes + 2 * (int64_t)sib;
+            const float4 s0 = sp[0], s1 = sp[1];
+            lo[0] = fminf(lo[0], s0.x); lo[1] = fminf(lo[1], s0.y); lo[2] = fminf(lo[2], s0.z);
+            hi[0] = fmaxf(hi[0], s1.x); hi[1] = fmaxf(hi[1], s1.y); hi[2] = fmaxf(hi[2], s1.z);
+            const int q = dr < dl ? rr : rl;
+            const int left = (rl == p) ? leaf0 + p : p;
+            int qrope;
+            if (rr == n - 1) qrope = -1;
+            else qrope = dr < delta_rank(codes, rr + 1, n) ? leaf0 + rr + 1 : rr + 1;
+            store_node(nodes, q, lo, left, hi, qrope);
+            cur = q;
+            if (q == 0) break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) pend_out[2 * blockIdx.x + threadIdx.x] = s_pend[threadIdx.x];
 }
 
 template <int KIND, typename K>
@@ -572,7 +698,7 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     nm = nm < 1 ? 1 : (nm > kMortonBlocksMax ? kMortonBlocksMax : nm);
     prof_begin(K_MORTON, s);
     hipLaunchKernelGGL((k_morton<KIND, K>), dim3(nm), dim3(kBlock), 0, s, prims, n, scene, codes,
-                       hist, passes, status[0], L.ntiles * kRadix, store);
+                       hist, passes, status[0], L.ntiles * kRadix);
     prof_end(K_MORTON, s);
 
     // ping-pong: even passes read tree->codes, odd passes write it back;
@@ -592,8 +718,21 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     }
 
     prof_begin(K_BOTTOMUP, s);
-    hipLaunchKernelGGL((k_bottomup<KIND, K>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       codes, vals[(passes - 1) & 1], prims, n, store, nodes, ctrl + kCtrlError);
+    int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
+    int nbu = (n + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
+                       vals[(passes - 1) & 1], prims, n, store, nodes, pend[0], ctrl + kCtrlError);
+    int64_t span = kChunk;
+    int in = 0;
+    while (nbu > 1) {
+        const int64_t next = span * kFanout;
+        const int nbn = (int)((n + next - 1) / next);
+        hipLaunchKernelGGL((k_bottomup_up<K>), dim3(nbn), dim3(kBUThreads), 0, s, codes, n, span,
+                           next, store, nodes, pend[in], pend[in ^ 1], ctrl + kCtrlError);
+        in ^= 1;
+        span = next;
+        nbu = nbn;
+    }
     prof_end(K_BOTTOMUP, s);
     return hipGetLastError();
 }

@@ -30,7 +30,11 @@ BuildLayout build_layout(int64_t n, int code_bits)
     L.keys_alt = take((size_t)n * kb);
     L.vals[0] = take((size_t)n * sizeof(int32_t));
     L.vals[1] = take((size_t)n * sizeof(int32_t));
-    L.store = take((size_t)(n > 1 ? n - 1 : 1) * sizeof(int32_t));
+    L.store = take((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    const int64_t nb0 = (n + kChunk - 1) / kChunk;
+    const int64_t nb1 = (n + (int64_t)kChunk * kFanout - 1) / ((int64_t)kChunk * kFanout);
+    L.pend[0] = take((size_t)(2 * nb0 + 2) * 16);
+    L.pend[1] = take((size_t)(2 * nb1 + 2) * 16);
     L.total = off;
     return L;
 }

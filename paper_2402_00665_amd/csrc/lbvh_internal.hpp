@@ -21,6 +21,10 @@ constexpr int kSortItems = 16;        // keys per thread
 constexpr int kTile = kSortThreads * kSortItems;
 constexpr int kBoundsBlocksMax = 1024;
 constexpr int kMortonBlocksMax = 2048;
+constexpr int kChunk = 1024;          // leaves per level-0 block of the bottom-up pass
+constexpr int kBU0Threads = 256;
+constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
+constexpr int kBUThreads = 256;
 constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kScanTile = kBlock * kScanItems;
 
@@ -47,7 +51,8 @@ struct BuildLayout {
     size_t status[2];  // ntiles x kRadix uint32 each (ping-pong look-back)
     size_t keys_alt;   // n keys (sort ping-pong partner of tree->codes)
     size_t vals[2];    // n int32 each (sort values: input indices)
-    size_t store;      // n-1 int32 (Alg. 4 arrival flags / parked range ends)
+    size_t store;      // n int32 (Alg. 4 arrival flags / parked range ends)
+    size_t pend[2];    // handed-over climb states between bottom-up levels (int4)
     size_t total;
     int passes;
     int64_t ntiles;

@@ -127,6 +127,107 @@ def alg4(delta, n, leaf_boxes=None, policy="random", seed=0):
     return left, rope, boxes
 
 
+def alg4_blocked(delta, n, chunk, fanout, leaf_boxes=None, policy="random", seed=0):
+    """Alg. 4 run the way the GPU kernels run it: by levels of blocks.
+
+    Level 0 gives each block `chunk` consecutive leaves; level L >= 1 gives
+    each block `fanout` consecutive blocks of level L-1.  A block owns the
+    boundaries strictly inside its leaf span [A, B).  Its threads climb as in
+    Alg. 4, but a thread whose parent's split p is a boundary of the span
+    (p = A-1 or p = B-1) stops and hands its state (node, range) to the
+    level above.  Blocks of one level run one after another here (they touch
+    disjoint parts of `store`); threads inside a block interleave under the
+    given schedule.  Returns (left, rope, boxes) like ``alg4``."""
+    D = _Delta(delta, n)
+    ni = n - 1
+    left = [None] * max(ni, 0)
+    rope = [None] * max(2 * n - 1, 0)
+    boxes = [None] * max(2 * n - 1, 0) if leaf_boxes is not None else None
+    store = [None] * max(ni, 0)
+
+    def leaf(k):
+        return ni + k
+
+    def union(a, b):
+        return tuple(min(a[x], b[x]) for x in range(3)) + tuple(max(a[3 + x], b[3 + x]) for x in range(3))
+
+    def climb(cur, rl, rr, A, B, out):
+        dl, dr = D(rl - 1), D(rr)
+        while True:
+            if dr < dl:
+                p = rr
+                if p == B - 1:
+                    out[1] = (cur, rl, rr)
+                    return
+                yield
+                old = store[p]
+                if old is None:
+                    store[p] = rl
+                    return
+                rr = old
+                dr = D(rr)
+                sib = leaf(p + 1) if p + 1 == rr else p + 1
+            else:
+                p = rl - 1
+                if p == A - 1:
+                    out[0] = (cur, rl, rr)
+                    return
+                yield
+                old = store[p]
+                if old is None:
+                    store[p] = rr
+                    return
+                rl = old
+                dl = D(rl - 1)
+                sib = leaf(p) if rl == p else p
+            q = rr if dr < dl else rl
+            left[q] = leaf(p) if rl == p else p
+            if rr == n - 1:
+                rope[q] = SENTINEL
+            else:
+                r = rr + 1
+                rope[q] = leaf(r) if dr < D(r) else r
+            if boxes is not None:
+                boxes[q] = union(boxes[cur], boxes[sib])
+            cur = q
+            if q == 0:
+                return
+
+    rng = random.Random(seed)
+    for i in range(n):                       # leaf records (Alg. 4 leaf part)
+        rope[leaf(i)] = SENTINEL if i == n - 1 else (leaf(i + 1) if D(i) < D(i + 1) else i + 1)
+        if boxes is not None:
+            boxes[leaf(i)] = tuple(leaf_boxes[i])
+    if n == 1:
+        return left, rope, boxes
+
+    span = chunk
+    nb = (n + span - 1) // span
+    pend = []
+    for b in range(nb):                      # level 0
+        A, B = b * span, min((b + 1) * span, n)
+        out = [None, None]
+        _schedule([climb(leaf(i), i, i, A, B, out) for i in range(A, B)], policy, rng)
+        pend.append(out)
+    levels = 0
+    while nb > 1:                            # levels >= 1
+        levels += 1
+        child_span, span = span, span * fanout
+        nb_next = (n + span - 1) // span
+        nxt = []
+        for b in range(nb_next):
+            A, B = b * span, min((b + 1) * span, n)
+            j0, j1 = A // child_span, (B + child_span - 1) // child_span
+            out = [None, None]
+            gens = [climb(s[0], s[1], s[2], A, B, out)
+                    for j in range(j0, j1) for s in pend[j] if s is not None]
+            _schedule(gens, policy, rng)
+            nxt.append(out)
+        pend, nb = nxt, nb_next
+    assert all(s is None for s in pend[0]), "the top level must finish the tree"
+    return left, rope, boxes
+
+
 def alg3(delta, n, policy="random", seed=0):
     """Apetrei's original bottom-up pass (Alg. 3), nodes indexed by split.
 

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 
 import oracle
-from alg_models import alg3, alg4
+from alg_models import alg3, alg4, alg4_blocked
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
 
@@ -343,3 +343,35 @@ def test_alg4_boxes_match_oracle(seed):
     for pol in ("left", "right", "random"):
         left, rope, boxes = alg4(t.delta, n, leaf_boxes, pol, seed)
         assert np.array_equal(np.array(boxes, np.float32), t.aabb)
+
+
+# ------------------------------------------------ blocked (level) schedule
+
+@pytest.mark.parametrize("chunk,fanout", [(1, 2), (2, 2), (3, 2), (4, 3), (8, 2), (16, 4)])
+def test_alg4_blocked_exhaustive(chunk, fanout):
+    """Alg. 4 split into levels of blocks (the GPU kernels' schedule) gives
+    the oracle tree for every sorted multiset of <= 6 keys over 3-bit codes."""
+    k = 0
+    for n in range(1, 7):
+        for keys in itertools.combinations_with_replacement(range(8), n):
+            t = oracle.tree_from_sorted(np.array(keys, np.uint64))
+            for pol in ("left", "right", "random"):
+                left, rope, _ = alg4_blocked(t.delta, n, chunk, fanout, None, pol, k)
+                assert list(left) == [int(x) for x in t.left]
+                assert list(rope) == [int(x) for x in t.rope]
+            k += 1
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_alg4_blocked_random_with_boxes(seed):
+    rng = np.random.default_rng([15, seed])
+    n = int(rng.integers(2, 1500))
+    prims = (rng.integers(0, 6, size=(n, 3)) / 5).astype(np.float32)
+    t = oracle.build(oracle.POINTS, prims, 30)
+    leaf_boxes = np.concatenate([prims, prims], 1)[t.perm]
+    chunk = int(rng.choice([1, 3, 16, 64, 1024]))
+    fanout = int(rng.choice([2, 3, 256]))
+    left, rope, boxes = alg4_blocked(t.delta, n, chunk, fanout, leaf_boxes, "random", seed)
+    assert list(left) == [int(x) for x in t.left]
+    assert list(rope) == [int(x) for x in t.rope]
+    assert np.array_equal(np.array(boxes, np.float32), t.aabb)
