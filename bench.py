@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--workload", default="clustered_boxes",
                     choices=["clustered_boxes", "large_points", "small_points"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--build-only", action="store_true",
+                    help="time the build alone (no queries in the step)")
     ap.add_argument("--cpu-sample", type=float, default=0.5,
                     help="fraction of the workload the oracle baseline runs on")
     return ap.parse_args()
@@ -96,7 +98,7 @@ def main():
         lb.build(prims, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
         if ev:
             ev[1].record(stream)
-        off, idx = lb.query(tree, queries, w.qkind, workspace=qws)
+        off, idx = (None, None) if args.build_only else lb.query(tree, queries, w.qkind, workspace=qws)
         if ev:
             ev[2].record(stream)
         return off, idx
@@ -115,7 +117,7 @@ def main():
     hits = 0
     for k in range(args.steps):
         off, idx = step(evs[k])
-        hits = int(idx.numel())
+        hits = int(idx.numel()) if idx is not None else 0
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     lb.lbvh_profile_enable(False)
@@ -128,8 +130,8 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
 
     kernels = {}
-    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "query_count",
-                 "scan", "query_fill"]:
+    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "query_split",
+                 "query_count", "scan", "query_fill"]:
         tot, cnt = lb.lbvh_profile_read(name)
         if cnt:
             kernels[name] = {"ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
@@ -212,8 +214,9 @@ def main():
                    "code_bits": w.code_bits, "m": w.m,
                    "queries": "spheres" if w.qkind == 0 else "boxes"},
         "build_ms": round(mean_build, 4),
-        "queries": {"mqueries_per_s": round(w.m / (mean_query * 1e-3) / 1e6, 2),
-                    "ms": round(mean_query, 4), "hits": hits},
+        "queries": None if args.build_only else {
+            "mqueries_per_s": round(w.m / (mean_query * 1e-3) / 1e6, 2),
+            "ms": round(mean_query, 4), "hits": hits},
         "build_model_bytes": int(model_bytes),
         "build_model_gbps": round(model_bytes / (mean_build * 1e-3) / 1e9, 1),
         "copy_gbps": round(copy_gbps, 1),

@@ -132,20 +132,25 @@ int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits,
 
 /* ------------------------------------------------------------- queries */
 
-/* Workspace bytes for a count call over m queries. */
+/* Workspace bytes for the count and fill calls over m queries. */
 int64_t lbvh_query_workspace_bytes(int64_t m);
 
-/* Range queries, first of two passes (Alg. 1 per query).
+/* Range queries, first of two calls: Alg. 1 per query, counting hits.
  * Sphere j is xyzr[j] = (x, y, z, r), r >= 0: a node or primitive box B
  * matches if d = per-axis max(B.lo - c, c - B.hi, 0) gives
  * (dx*dx + dy*dy) + dz*dz <= r*r in binary32 (closed ball, no fused
  * multiply-add).  Box j is lohi[j] = (lo.xyz, hi.xyz): B matches if
  * lo <= B.hi and B.lo <= hi on every axis (closed boxes).
- *   offsets : device int64 [m+1]; receives the CSR offsets, offsets[0] = 0
- *             and offsets[m] = total number of hits.
- *   workspace: device, at least lbvh_query_workspace_bytes(m) bytes.
+ * Each query's walk is run as independent pieces over aligned blocks of
+ * leaves (same nodes, same order); the pieces and their hit offsets are
+ * kept in the workspace for the fill call.
+ *   xyzr / lohi : device, float [m][4] / [m][6], 16-byte aligned.
+ *   offsets     : device int64 [m+1]; receives the CSR offsets,
+ *                 offsets[0] = 0 and offsets[m] = total number of hits.
+ *   workspace   : device, at least lbvh_query_workspace_bytes(m) bytes,
+ *                 256-byte aligned.
  * The caller reads offsets[m] (the one device-to-host copy), allocates the
- * index array and calls the matching *_fill. */
+ * index array and calls the matching *_fill with the same workspace. */
 int lbvh_query_spheres_count(const lbvh_tree *tree, const float *xyzr, int64_t m,
                              int64_t *offsets, void *workspace,
                              int64_t workspace_bytes, void *stream);
@@ -153,15 +158,19 @@ int lbvh_query_boxes_count(const lbvh_tree *tree, const float *lohi, int64_t m,
                            int64_t *offsets, void *workspace,
                            int64_t workspace_bytes, void *stream);
 
-/* Second pass: repeat the traversal and write, for query j, the input
- * indices of the matching primitives into indices[offsets[j] .. offsets[j+1])
- * in traversal order (ascending Morton-order position).
- *   offsets : device int64 [m+1] from the count call.
- *   indices : device int32 [offsets[m]]. */
+/* Second call: write, for query j, the input indices of the matching
+ * primitives into indices[offsets[j] .. offsets[j+1]) in traversal order
+ * (ascending Morton-order position).
+ *   indices   : device int32 [offsets[m]] (non-NULL even when empty).
+ *   workspace : the workspace of the preceding count call on the same tree
+ *               and queries, untouched since (enqueue both on one stream or
+ *               order the streams). */
 int lbvh_query_spheres_fill(const lbvh_tree *tree, const float *xyzr, int64_t m,
-                            const int64_t *offsets, int32_t *indices, void *stream);
+                            int32_t *indices, const void *workspace,
+                            int64_t workspace_bytes, void *stream);
 int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
-                          const int64_t *offsets, int32_t *indices, void *stream);
+                          int32_t *indices, const void *workspace,
+                          int64_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------ utilities */
 
@@ -173,8 +182,9 @@ const char *lbvh_strerror(int status);
  * lbvh_profile_read synchronises those events and returns, for the kernel
  * named `kernel`, the summed duration in milliseconds and the number of
  * launches since the last reset.  Names: "bounds", "bounds_final",
- * "morton", "sort_pass", "bottomup", "query_count", "query_fill",
- * "scan".  Returns LBVH_EINVAL for an unknown name. */
+ * "morton", "sort_pass", "bottomup" (all its levels), "query_split",
+ * "query_count", "query_fill", "scan" (scans and offset bookkeeping).
+ * Returns LBVH_EINVAL for an unknown name. */
 int lbvh_profile_enable(int32_t on);
 int lbvh_profile_reset(void);
 int lbvh_profile_read(const char *kernel, double *total_ms, int64_t *launches);

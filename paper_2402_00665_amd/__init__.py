@@ -63,8 +63,8 @@ def lib() -> C.CDLL:
             "lbvh_query_workspace_bytes": (i64, [i64]),
             "lbvh_query_spheres_count": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_query_boxes_count": (C.c_int, [T, P, i64, P, P, i64, P]),
-            "lbvh_query_spheres_fill": (C.c_int, [T, P, i64, P, P, P]),
-            "lbvh_query_boxes_fill": (C.c_int, [T, P, i64, P, P, P]),
+            "lbvh_query_spheres_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
+            "lbvh_query_boxes_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_strerror": (C.c_char_p, [C.c_int]),
             "lbvh_profile_enable": (C.c_int, [i32]),
             "lbvh_profile_reset": (C.c_int, []),
@@ -115,12 +115,12 @@ def lbvh_query_boxes_count(tree, q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream
     return lib().lbvh_query_boxes_count(C.byref(tree), q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream)
 
 
-def lbvh_query_spheres_fill(tree, q_ptr, m, offsets_ptr, idx_ptr, stream) -> int:
-    return lib().lbvh_query_spheres_fill(C.byref(tree), q_ptr, m, offsets_ptr, idx_ptr, stream)
+def lbvh_query_spheres_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_spheres_fill(C.byref(tree), q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream)
 
 
-def lbvh_query_boxes_fill(tree, q_ptr, m, offsets_ptr, idx_ptr, stream) -> int:
-    return lib().lbvh_query_boxes_fill(C.byref(tree), q_ptr, m, offsets_ptr, idx_ptr, stream)
+def lbvh_query_boxes_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_boxes_fill(C.byref(tree), q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream)
 
 
 def lbvh_profile_enable(on: bool) -> int:
@@ -254,8 +254,9 @@ def check_build(tree: Tree, stream=None):
            "lbvh_build_check")
 
 
-def query_count(tree: Tree, queries, qkind: int, offsets=None, workspace: Workspace | None = None,
-                stream=None):
+def query_count(tree: Tree, queries, qkind: int, workspace: Workspace, offsets=None, stream=None):
+    """First call: CSR offsets (int64 [m+1]) on the device; the workspace
+    keeps what the fill call needs."""
     torch = _torch()
     q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
     m = int(q.shape[0])
@@ -263,19 +264,21 @@ def query_count(tree: Tree, queries, qkind: int, offsets=None, workspace: Worksp
         offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
     ws_bytes = lbvh_query_workspace_bytes(m)
     _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_query_workspace_bytes")
-    ws = (workspace or Workspace(q.device)).get(ws_bytes)
+    ws = workspace.get(ws_bytes)
     f = lbvh_query_spheres_count if qkind == SPHERES else lbvh_query_boxes_count
     _check(f(tree.desc, q.data_ptr() if m else None, m, offsets.data_ptr(), ws.data_ptr(),
              ws.numel(), _stream(stream)), "query count")
     return offsets
 
 
-def query_fill(tree: Tree, queries, qkind: int, offsets, indices, stream=None):
+def query_fill(tree: Tree, queries, qkind: int, indices, workspace: Workspace, stream=None):
+    """Second call, with the count call's workspace."""
     q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
     m = int(q.shape[0])
+    ws = workspace.buf
     f = lbvh_query_spheres_fill if qkind == SPHERES else lbvh_query_boxes_fill
-    _check(f(tree.desc, q.data_ptr() if m else None, m, offsets.data_ptr(),
-             indices.data_ptr(), _stream(stream)), "query fill")
+    _check(f(tree.desc, q.data_ptr() if m else None, m, indices.data_ptr(), ws.data_ptr(),
+             ws.numel(), _stream(stream)), "query fill")
     return indices
 
 
@@ -283,9 +286,10 @@ def query(tree: Tree, queries, qkind: int, workspace: Workspace | None = None, s
     """Count, read the total (one 8-byte device-to-host copy), fill.
     Returns (offsets int64 [m+1], indices int32 [total]) on the device."""
     torch = _torch()
-    offsets = query_count(tree, queries, qkind, workspace=workspace, stream=stream)
+    workspace = workspace or Workspace(queries.device)
+    offsets = query_count(tree, queries, qkind, workspace, stream=stream)
     total = int(offsets[-1].item())
     # at least one element so the device pointer is never null
     buf = torch.empty(max(total, 1), dtype=torch.int32, device=queries.device)
-    query_fill(tree, queries, qkind, offsets, buf, stream=stream)
+    query_fill(tree, queries, qkind, buf, workspace, stream=stream)
     return offsets, buf[:total]

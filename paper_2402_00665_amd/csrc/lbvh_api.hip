@@ -42,10 +42,20 @@ BuildLayout build_layout(int64_t n, int code_bits)
 QueryLayout query_layout(int64_t m)
 {
     QueryLayout L{};
+    L.cap1 = 2 * m + 1024;
+    L.cap2 = 6 * m + 4096;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
-    L.counts = take((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
-    L.partials = take((size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+    L.cnt1 = take((size_t)(m + 1) * sizeof(int32_t));
+    L.off1 = take((size_t)(m + 1) * sizeof(int64_t));
+    L.items1 = take((size_t)L.cap1 * 16);
+    L.cnt2 = take((size_t)L.cap1 * sizeof(int32_t));
+    L.off2 = take((size_t)(L.cap1 + 1) * sizeof(int64_t));
+    L.items2 = take((size_t)L.cap2 * 16);
+    L.hcnt = take((size_t)L.cap2 * sizeof(int32_t));
+    L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
+    L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+    L.ctrl = take(128);
     L.total = off;
     return L;
 }
@@ -89,8 +99,8 @@ Profiler &prof()
     static Profiler p;
     return p;
 }
-const char *kNames[K_NUM] = {"bounds", "bounds_final", "morton", "sort_pass",
-                             "bottomup", "query_count", "query_fill", "scan"};
+const char *kNames[K_NUM] = {"bounds", "bounds_final", "morton", "sort_pass", "bottomup",
+                             "query_count", "query_fill", "scan", "query_split"};
 }  // namespace
 
 void prof_begin(int id, hipStream_t s)
@@ -214,18 +224,19 @@ static int query_count(int qkind, const lbvh_tree *tree, const float *q, int64_t
     return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
 }
 
-static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t m,
-                      const int64_t *offsets, int32_t *indices, void *stream)
+static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t m, int32_t *indices,
+                      const void *workspace, int64_t workspace_bytes, void *stream)
 {
-    if (!tree || m < 0 || m > INT32_MAX || tree->n < 0 || tree->n > LBVH_MAX_PRIMS || !offsets ||
-        !aligned(offsets, 8))
+    if (!tree || m < 0 || m > INT32_MAX || tree->n < 0 || tree->n > LBVH_MAX_PRIMS)
         return LBVH_EINVAL;
     if (m > 0 && (!q || !aligned(q, 16))) return LBVH_EINVAL;
     if (tree->n > 0 && m > 0 && (!tree->nodes || !indices || !aligned(tree->nodes, 16)))
         return LBVH_EINVAL;
-    const QueryLayout L = query_layout(0);
-    hipError_t e = launch_query(qkind, tree->nodes, (int)tree->n, q, (int)m,
-                                const_cast<int64_t *>(offsets), indices, true, nullptr, L,
+    const QueryLayout L = query_layout(m);
+    if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
+    if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
+    hipError_t e = launch_query(qkind, tree->nodes, (int)tree->n, q, (int)m, nullptr, indices, true,
+                                static_cast<char *>(const_cast<void *>(workspace)), L,
                                 (hipStream_t)stream);
     return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
 }
@@ -242,16 +253,16 @@ int lbvh_query_boxes_count(const lbvh_tree *tree, const float *lohi, int64_t m, 
     return query_count(1, tree, lohi, m, offsets, workspace, workspace_bytes, stream);
 }
 
-int lbvh_query_spheres_fill(const lbvh_tree *tree, const float *xyzr, int64_t m,
-                            const int64_t *offsets, int32_t *indices, void *stream)
+int lbvh_query_spheres_fill(const lbvh_tree *tree, const float *xyzr, int64_t m, int32_t *indices,
+                            const void *workspace, int64_t workspace_bytes, void *stream)
 {
-    return query_fill(0, tree, xyzr, m, offsets, indices, stream);
+    return query_fill(0, tree, xyzr, m, indices, workspace, workspace_bytes, stream);
 }
 
-int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
-                          const int64_t *offsets, int32_t *indices, void *stream)
+int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m, int32_t *indices,
+                          const void *workspace, int64_t workspace_bytes, void *stream)
 {
-    return query_fill(1, tree, lohi, m, offsets, indices, stream);
+    return query_fill(1, tree, lohi, m, indices, workspace, workspace_bytes, stream);
 }
 
 int lbvh_profile_enable(int32_t on)

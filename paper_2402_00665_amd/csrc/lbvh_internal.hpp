@@ -22,10 +22,13 @@ constexpr int kTile = kSortThreads * kSortItems;
 constexpr int kBoundsBlocksMax = 1024;
 constexpr int kMortonBlocksMax = 2048;
 constexpr int kChunk = 1024;          // leaves per level-0 block of the bottom-up pass
-constexpr int kBU0Threads = 256;
+constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
 constexpr int kBUThreads = 256;
 constexpr int kScanItems = 8;         // values per thread in the query scan
+constexpr int kSplit1 = 12;           // query walks cut by aligned blocks of 2^12 leaves
+constexpr int kSplit2 = 7;            // ... then by blocks of 2^7 leaves
+constexpr int kQueryGridMax = 8192;   // blocks of the grid-stride query kernels
 constexpr int kScanTile = kBlock * kScanItems;
 
 // ctrl words at the start of the build workspace
@@ -61,8 +64,17 @@ struct BuildLayout {
 BuildLayout build_layout(int64_t n, int code_bits);
 
 struct QueryLayout {
-    size_t counts;     // m int32
-    size_t partials;   // ceil(m / kScanTile) int64
+    int64_t cap1, cap2;  // capacities of level-1 and level-2 pieces
+    size_t cnt1;       // m int32: level-1 pieces per query
+    size_t off1;       // m+1 int64
+    size_t items1;     // cap1 int4 (query, node, left bound, range end)
+    size_t cnt2;       // cap1 int32: level-2 pieces per level-1 piece
+    size_t off2;       // cap1+1 int64
+    size_t items2;     // cap2 int4
+    size_t hcnt;       // cap2 int32: hits per level-2 piece
+    size_t hoff;       // cap2+1 int64
+    size_t partials;   // scan tile sums
+    size_t ctrl;       // overflow flags and piece counts
     size_t total;
 };
 
@@ -72,7 +84,7 @@ QueryLayout query_layout(int64_t m);
 
 enum KernelId {
     K_BOUNDS = 0, K_BOUNDS_FINAL, K_MORTON, K_SORT, K_BOTTOMUP,
-    K_QCOUNT, K_QFILL, K_SCAN, K_NUM
+    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_NUM
 };
 
 void prof_begin(int id, hipStream_t s);

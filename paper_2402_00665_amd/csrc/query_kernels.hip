@@ -1,11 +1,29 @@
-// Stackless range queries on gfx950 (Alg. 1) and the CSR offset scan.
+// Stackless range queries on gfx950 (Alg. 1) and their CSR output.
 //
-// One thread per query walks the tree from the root: a node whose box
-// passes the test sends the walk to its left child (internal node) or
-// reports the primitive (leaf) and follows the rope; a node that fails sends
-// it along the rope.  The walk ends at the sentinel -1.  The same walk runs
-// twice: the count pass stores hits per query, a three-kernel scan turns the
-// counts into int64 offsets, the fill pass writes the primitive indices.
+// Alg. 1 walks the tree in preorder from the root: a node whose box passes
+// the test sends the walk to its left child (internal node) or reports the
+// primitive (leaf) and follows the rope; a node that fails sends it along
+// the rope; the sentinel -1 ends it.  One thread per query makes the
+// heaviest query the critical path (a query can hit 10^5 primitives, each a
+// dependent node load), so each query's walk is cut into independent pieces
+// by aligned blocks of leaves, without changing what is visited in order:
+//
+// * During a walk the current node's leaf range [i, j] is known for free:
+//   i stays when descending left, and a rope leads to a node whose Karras
+//   index is its left bound, so i = index(rope target); j = index(rope) - 1
+//   (n - 1 at the sentinel).
+// * A split walk covers the leaf range [i, hi) of its piece; at the first
+//   passing node inside an aligned block of 2^S leaves it emits a piece
+//   (node, i, block end) and jumps to the largest node starting at the next
+//   block: internal node r if it is a right child (its split >= r), else
+//   leaf r.  Everything it skips lies inside the emitted block.
+// * Level 1 splits each query's whole walk by 2^kSplit1 leaves, level 2
+//   splits each level-1 piece by 2^kSplit2 leaves, and the leaf walk runs
+//   each level-2 piece as plain Alg. 1 restricted to its leaf range.
+// Pieces are emitted in walk order, so concatenating their hits gives the
+// plain walk's hits in the plain walk's order.  Each level is a count pass,
+// a scan and a fill pass; a level whose pieces would exceed the workspace
+// capacity passes its pieces through unsplit (same results, less parallel).
 // No contraction: the sphere test is evaluated exactly as written.
 #pragma clang fp contract(off)
 
@@ -44,39 +62,123 @@ struct QBox {
     }
 };
 
-template <class Q, bool FILL>
-__global__ __launch_bounds__(kBlock) void k_query(const float4 *__restrict__ nodes, int n,
-                                                  const float *__restrict__ queries, int m,
-                                                  int32_t *__restrict__ counts,
-                                                  const int64_t *__restrict__ offsets,
-                                                  int32_t *__restrict__ out)
-{
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= m) return;
-    Q q;
-    q.load(queries, j);
-    const int first_leaf = n - 1;
-    int64_t pos = FILL ? offsets[j] : 0;
-    int cnt = 0;
-    int id = 0;
-    // ropes only point forward in preorder, so a walk visits each of the
-    // 2n-1 nodes at most once; the cap only guards against a corrupt tree
-    int64_t budget = 2 * (int64_t)n;
-    do {
-        if (--budget < 0) break;
-        const float4 a = nodes[2 * (int64_t)id];
-        const float4 b = nodes[2 * (int64_t)id + 1];
-        const bool hit = q.test(a, b);
-        const int left = __float_as_int(a.w);
-        const int rope = __float_as_int(b.w);
-        const bool leaf = id >= first_leaf;
-        if (hit && leaf) {
-            if (FILL) out[pos++] = left;   // a leaf's `left` is its primitive
-            else ++cnt;
+struct Tree {
+    const float4 *nodes;
+    int n;
+    __device__ int leaf0() const { return n - 1; }
+    __device__ int index(int v) const { return v >= n - 1 ? v - (n - 1) : v; }
+    __device__ void load(int v, float4 &a, float4 &b) const
+    {
+        const float4 *p = nodes + 2 * (int64_t)v;
+        a = p[0];
+        b = p[1];
+    }
+    // right bound of node v whose record half `b` holds the rope
+    __device__ int right_bound(float4 b) const
+    {
+        const int r = __float_as_int(b.w);
+        return r == -1 ? n - 1 : index(r) - 1;
+    }
+    // largest node whose range starts at leaf r (r <= n-1)
+    __device__ int first_at(int r) const
+    {
+        if (r <= n - 2) {
+            const int l = __float_as_int(nodes[2 * (int64_t)r].w);
+            if (index(l) >= r) return r;   // internal r is a right child
         }
-        id = (hit && !leaf) ? left : rope;
-    } while (id != -1);
-    if (!FILL) counts[j] = cnt;
+        return n - 1 + r;
+    }
+};
+
+// A piece: query, start node, left bound of the start node, end (exclusive)
+// of the leaf range the walk covers.
+__device__ __forceinline__ int4 piece(int q, int v, int i, int hi) { return make_int4(q, v, i, hi); }
+
+template <class Q, bool FILL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restrict__ queries, int m,
+                                                  const int4 *__restrict__ in, const int64_t *in_count,
+                                                  int shift, int32_t *__restrict__ counts,
+                                                  const int64_t *__restrict__ out_off,
+                                                  const int32_t *__restrict__ overflow,
+                                                  int4 *__restrict__ out)
+{
+    const int64_t T = FIRST ? (int64_t)m : *in_count;
+    const bool pass_through = FILL && *overflow;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
+        if (pass_through) { out[t] = it; continue; }
+        Q q;
+        q.load(queries, it.x);
+        int64_t pos = FILL ? out_off[t] : 0;
+        int cnt = 0;
+        int v = it.y, i = it.z;
+        const int hi = it.w;
+        int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
+        while (v != -1 && i < hi && --budget >= 0) {
+            float4 a, b;
+            tr.load(v, a, b);
+            const int j = tr.right_bound(b);
+            if (!q.test(a, b)) {
+                v = __float_as_int(b.w);
+                i = j + 1;
+                continue;
+            }
+            if ((i >> shift) == (j >> shift)) {
+                const int r = ((i >> shift) + 1) << shift;   // next block start
+                const int end = r < hi ? r : hi;
+                if (FILL) out[pos++] = piece(it.x, v, i, end);
+                else ++cnt;
+                if (r >= hi || r > tr.n - 1) break;
+                v = tr.first_at(r);
+                i = r;
+                continue;
+            }
+            v = __float_as_int(a.w);   // multi-block node: descend
+        }
+        if (!FILL) counts[t] = cnt;
+    }
+}
+
+template <class Q, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_leafwalk(Tree tr, const float *__restrict__ queries,
+                                                     const int4 *__restrict__ in,
+                                                     const int64_t *in_count,
+                                                     int32_t *__restrict__ counts,
+                                                     const int64_t *__restrict__ hit_off,
+                                                     int32_t *__restrict__ out)
+{
+    const int64_t T = *in_count;
+    const int leaf0 = tr.leaf0();
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int4 it = in[t];
+        Q q;
+        q.load(queries, it.x);
+        int64_t pos = FILL ? hit_off[t] : 0;
+        int cnt = 0;
+        int v = it.y, i = it.z;
+        const int hi = it.w;
+        int64_t budget = 2 * (int64_t)tr.n;
+        while (v != -1 && i < hi && --budget >= 0) {
+            float4 a, b;
+            tr.load(v, a, b);
+            const bool hit = q.test(a, b);
+            const int left = __float_as_int(a.w);
+            const int rope = __float_as_int(b.w);
+            if (hit && v < leaf0) {
+                v = left;
+                continue;
+            }
+            if (hit) {   // leaf: `left` holds its primitive
+                if (FILL) out[pos++] = left;
+                else ++cnt;
+            }
+            i = tr.right_bound(b) + 1;
+            v = rope;
+        }
+        if (!FILL) counts[t] = cnt;
+    }
 }
 
 __global__ void k_zero_i64(int64_t *p, int64_t count)
@@ -86,6 +188,10 @@ __global__ void k_zero_i64(int64_t *p, int64_t count)
 }
 
 // -------------------------------------------------------------- scan
+//
+// Exclusive scan of `m` int32 counts into int64 offsets[0..m] (offsets[m] =
+// total).  The count is either a host value (m_dev == nullptr) or read on
+// the device; grids are sized for `cap`, the largest count possible.
 
 template <typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T *sh /* [kBlock/64] */, T *block_total)
@@ -108,12 +214,18 @@ __device__ __forceinline__ T block_excl_scan(T v, T *sh /* [kBlock/64] */, T *bl
     return before + x - v;
 }
 
-// Sum of each tile of kScanTile counts.
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ counts, int m,
-                                                        int64_t *__restrict__ partials)
+__device__ __forceinline__ int64_t count_of(int64_t cap, const int64_t *m_dev)
+{
+    return m_dev ? *m_dev : cap;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ counts, int64_t cap,
+                                                        const int64_t *m_dev, int64_t *__restrict__ partials)
 {
     __shared__ int64_t sh[kBlock / 64];
+    const int64_t m = count_of(cap, m_dev);
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    if ((int64_t)blockIdx.x * kScanTile >= m) return;   // whole block past the end
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k)
@@ -123,13 +235,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restric
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// Exclusive scan of the tile sums, in place, by one block.
-__global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t *partials, int nb)
+__global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t *partials, int64_t cap,
+                                                          const int64_t *m_dev)
 {
     __shared__ int64_t sh[kBlock / 64];
+    const int64_t m = count_of(cap, m_dev);
+    const int64_t nb = (m + kScanTile - 1) / kScanTile;
     int64_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += kBlock) {
-        const int b = b0 + threadIdx.x;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const int64_t b = b0 + threadIdx.x;
         const int64_t v = b < nb ? partials[b] : 0;
         int64_t total;
         const int64_t e = block_excl_scan<int64_t>(v, sh, &total);
@@ -139,12 +253,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t *partials, int
     }
 }
 
-// offsets[j] = sum of counts before j; offsets[m] = total.
-__global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t *__restrict__ counts, int m,
+__global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t *__restrict__ counts, int64_t cap,
+                                                       const int64_t *m_dev,
                                                        const int64_t *__restrict__ partials,
                                                        int64_t *__restrict__ offsets)
 {
     __shared__ int64_t sh[kBlock / 64];
+    const int64_t m = count_of(cap, m_dev);
+    if (m == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
+        return;
+    }
+    if ((int64_t)blockIdx.x * kScanTile >= m) return;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t c[kScanItems];
     int64_t s = 0;
@@ -163,38 +283,133 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t *__restrict
     }
 }
 
-template <class Q>
-hipError_t run_query(const lbvh_node *nodes_, int n, const float *q, int m, int64_t *offsets,
-                     int32_t *indices, bool fill, char *ws, const QueryLayout &L, hipStream_t s)
+// After a level's scan: does the number of pieces fit?  If not, the level
+// passes its parents through unchanged.
+__global__ void k_level_check(const int64_t *__restrict__ off, const int64_t *parent_dev,
+                              int64_t parent_host, int64_t cap, int32_t *__restrict__ overflow,
+                              int64_t *__restrict__ count)
 {
-    const float4 *nodes = reinterpret_cast<const float4 *>(nodes_);
-    int32_t *counts = reinterpret_cast<int32_t *>(ws + L.counts);
-    int64_t *partials = reinterpret_cast<int64_t *>(ws + L.partials);
-    const unsigned gq = (unsigned)((m + kBlock - 1) / kBlock);
-    if (fill) {
-        if (n == 0 || m == 0) return hipSuccess;
-        prof_begin(K_QFILL, s);
-        hipLaunchKernelGGL((k_query<Q, true>), dim3(gq), dim3(kBlock), 0, s, nodes, n, q, m, nullptr,
-                           offsets, indices);
-        prof_end(K_QFILL, s);
-        return hipGetLastError();
-    }
-    if (n == 0 || m == 0) {
-        const int64_t cnt = (int64_t)m + 1;
-        hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, offsets, cnt);
-        return hipGetLastError();
-    }
-    prof_begin(K_QCOUNT, s);
-    hipLaunchKernelGGL((k_query<Q, false>), dim3(gq), dim3(kBlock), 0, s, nodes, n, q, m, counts,
-                       nullptr, nullptr);
-    prof_end(K_QCOUNT, s);
-    const int nb = (int)((m + kScanTile - 1) / kScanTile);
+    const int64_t parents = parent_dev ? *parent_dev : parent_host;
+    const int64_t total = off[parents];
+    const bool over = total > cap;
+    *overflow = over ? 1 : 0;
+    *count = over ? parents : total;
+}
+
+// offsets[q] = hit offset of query q's first leaf-walk piece.
+__global__ __launch_bounds__(kBlock) void k_compose(const int64_t *__restrict__ off1,
+                                                    const int32_t *__restrict__ ovf1,
+                                                    const int64_t *__restrict__ off2,
+                                                    const int32_t *__restrict__ ovf2,
+                                                    const int64_t *__restrict__ hit_off, int m,
+                                                    int64_t *__restrict__ offsets)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q > m) return;
+    const int64_t p1 = *ovf1 ? q : off1[q];
+    const int64_t p2 = *ovf2 ? p1 : off2[p1];
+    offsets[q] = hit_off[p2];
+}
+
+struct Scratch {
+    int32_t *cnt1, *cnt2, *hcnt, *ovf;
+    int64_t *off1, *off2, *hoff, *partials, *count;
+    int4 *items1, *items2;
+};
+
+Scratch carve(char *ws, const QueryLayout &L)
+{
+    Scratch S;
+    S.cnt1 = reinterpret_cast<int32_t *>(ws + L.cnt1);
+    S.off1 = reinterpret_cast<int64_t *>(ws + L.off1);
+    S.items1 = reinterpret_cast<int4 *>(ws + L.items1);
+    S.cnt2 = reinterpret_cast<int32_t *>(ws + L.cnt2);
+    S.off2 = reinterpret_cast<int64_t *>(ws + L.off2);
+    S.items2 = reinterpret_cast<int4 *>(ws + L.items2);
+    S.hcnt = reinterpret_cast<int32_t *>(ws + L.hcnt);
+    S.hoff = reinterpret_cast<int64_t *>(ws + L.hoff);
+    S.partials = reinterpret_cast<int64_t *>(ws + L.partials);
+    S.ovf = reinterpret_cast<int32_t *>(ws + L.ctrl);              // [0] level 1, [1] level 2
+    S.count = reinterpret_cast<int64_t *>(ws + L.ctrl + 64);       // [0] pieces 1, [1] pieces 2
+    return S;
+}
+
+void scan(const int32_t *counts, int64_t cap, const int64_t *m_dev, int64_t *partials,
+          int64_t *offsets, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((cap + kScanTile - 1) / kScanTile);
+    const unsigned g = nb > 0 ? nb : 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(g), dim3(kBlock), 0, s, counts, cap, m_dev, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partials, cap, m_dev);
+    hipLaunchKernelGGL(k_scan_final, dim3(g), dim3(kBlock), 0, s, counts, cap, m_dev, partials,
+                       offsets);
+}
+
+unsigned grid_for(int64_t items)
+{
+    int64_t g = (items + kBlock - 1) / kBlock;
+    if (g > kQueryGridMax) g = kQueryGridMax;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+template <class Q>
+hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, char *ws,
+                     const QueryLayout &L, hipStream_t s)
+{
+    Scratch S = carve(ws, L);
+    const unsigned gm = grid_for(m);
+    // level 1: queries -> pieces of 2^kSplit1 leaves
+    prof_begin(K_QSPLIT, s);
+    hipLaunchKernelGGL((k_split<Q, false, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
+                       nullptr, kSplit1, S.cnt1, nullptr, nullptr, nullptr);
+    prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, counts, m, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partials, nb);
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, counts, m, partials, offsets);
+    scan(S.cnt1, m, nullptr, S.partials, S.off1, s);
+    hipLaunchKernelGGL(k_level_check, dim3(1), dim3(1), 0, s, S.off1, nullptr, (int64_t)m, L.cap1,
+                       S.ovf + 0, S.count + 0);
     prof_end(K_SCAN, s);
+    prof_begin(K_QSPLIT, s);
+    hipLaunchKernelGGL((k_split<Q, true, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
+                       nullptr, kSplit1, nullptr, S.off1, S.ovf + 0, S.items1);
+    prof_end(K_QSPLIT, s);
+    // level 2: pieces -> pieces of 2^kSplit2 leaves
+    const unsigned g1 = grid_for(L.cap1);
+    prof_begin(K_QSPLIT, s);
+    hipLaunchKernelGGL((k_split<Q, false, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m,
+                       S.items1, S.count + 0, kSplit2, S.cnt2, nullptr, nullptr, nullptr);
+    prof_end(K_QSPLIT, s);
+    prof_begin(K_SCAN, s);
+    scan(S.cnt2, L.cap1, S.count + 0, S.partials, S.off2, s);
+    hipLaunchKernelGGL(k_level_check, dim3(1), dim3(1), 0, s, S.off2, S.count + 0, (int64_t)0, L.cap2,
+                       S.ovf + 1, S.count + 1);
+    prof_end(K_SCAN, s);
+    prof_begin(K_QSPLIT, s);
+    hipLaunchKernelGGL((k_split<Q, true, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m, S.items1,
+                       S.count + 0, kSplit2, nullptr, S.off2, S.ovf + 1, S.items2);
+    prof_end(K_QSPLIT, s);
+    // leaf walks: count hits per piece, scan, per-query offsets
+    const unsigned g2 = grid_for(L.cap2);
+    prof_begin(K_QCOUNT, s);
+    hipLaunchKernelGGL((k_leafwalk<Q, false>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                       S.count + 1, S.hcnt, nullptr, nullptr);
+    prof_end(K_QCOUNT, s);
+    prof_begin(K_SCAN, s);
+    scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
+    hipLaunchKernelGGL(k_compose, dim3((unsigned)((m + kBlock) / kBlock)), dim3(kBlock), 0, s, S.off1,
+                       S.ovf + 0, S.off2, S.ovf + 1, S.hoff, m, offsets);
+    prof_end(K_SCAN, s);
+    return hipGetLastError();
+}
+
+template <class Q>
+hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, const QueryLayout &L,
+                    hipStream_t s)
+{
+    Scratch S = carve(ws, L);
+    prof_begin(K_QFILL, s);
+    hipLaunchKernelGGL((k_leafwalk<Q, true>), dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr, q,
+                       S.items2, S.count + 1, nullptr, S.hoff, indices);
+    prof_end(K_QFILL, s);
     return hipGetLastError();
 }
 
@@ -204,8 +419,19 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, int n, const float *q
                         int64_t *offsets, int32_t *indices, bool fill, char *ws,
                         const QueryLayout &L, hipStream_t s)
 {
-    if (qkind == 0) return run_query<Sphere>(nodes, n, q, m, offsets, indices, fill, ws, L, s);
-    return run_query<QBox>(nodes, n, q, m, offsets, indices, fill, ws, L, s);
+    if (n == 0 || m == 0) {
+        if (fill) return hipSuccess;
+        const int64_t cnt = (int64_t)m + 1;
+        hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, offsets, cnt);
+        return hipGetLastError();
+    }
+    Tree tr{reinterpret_cast<const float4 *>(nodes), n};
+    if (fill)
+        return qkind == 0 ? run_fill<Sphere>(tr, q, indices, ws, L, s)
+                          : run_fill<QBox>(tr, q, indices, ws, L, s);
+    return qkind == 0 ? run_count<Sphere>(tr, q, m, offsets, ws, L, s)
+                      : run_count<QBox>(tr, q, m, offsets, ws, L, s);
 }
 
 }  // namespace lbvh

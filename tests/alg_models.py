@@ -276,3 +276,72 @@ def alg3(delta, n, policy="random", seed=0):
     rng = random.Random(seed)
     _schedule([run(i) for i in range(n)], policy, rng)
     return children, ranges, root[0]
+
+
+def split_walk(n, left, rope, perm, test, S1, S2):
+    """A query's Alg. 1 walk cut into independent pieces by aligned leaf
+    blocks, the way the GPU query kernels run it.
+
+    During a walk the leaf range [i, j] of the current node is known without
+    extra data: i is kept (descending left keeps it; a rope leads to the
+    node whose Karras index is the new left bound) and j = index(rope) - 1
+    (n - 1 at the sentinel).  Level 1 walks from the root and emits one
+    piece per aligned block of 2^S1 leaves at the first passing node inside
+    that block, then jumps to the largest node starting at the next block
+    (internal node r if it is a right child, i.e. its split >= r, else leaf
+    r).  Level 2 does the same inside each piece with 2^S2 leaves; the last
+    level is the plain walk restricted to the piece's leaf range.  Returns
+    the hits in order (must equal the plain walk)."""
+    ni = n - 1
+
+    def idx(v):
+        return v - ni if v >= ni else v
+
+    def jend(v):
+        r = rope[v]
+        return n - 1 if r == -1 else idx(r) - 1
+
+    def first_at(r):
+        if r <= n - 2 and idx(left[r]) >= r:
+            return r
+        return ni + r
+
+    def split(v, i, hi, S):
+        out = []
+        while v != -1 and i < hi:
+            j = jend(v)
+            if not test(v):
+                v, i = rope[v], j + 1
+                continue
+            if (i >> S) == (j >> S):
+                blk = i >> S
+                out.append((v, i, min((blk + 1) << S, hi)))
+                r = (blk + 1) << S
+                if r >= hi or r > n - 1:
+                    break
+                v, i = first_at(r), r
+                continue
+            v = left[v]
+        return out
+
+    def walk(v, i, hi):
+        out = []
+        while v != -1 and i < hi:
+            j = jend(v)
+            if test(v):
+                if v >= ni:
+                    out.append(int(perm[v - ni]))
+                    v, i = rope[v], j + 1
+                else:
+                    v = left[v]
+            else:
+                v, i = rope[v], j + 1
+        return out
+
+    if n == 0:
+        return []
+    hits = []
+    for (a, i, hi) in split(0, 0, n, S1):
+        for (b, i2, hi2) in split(a, i, hi, S2):
+            hits += walk(b, i2, hi2)
+    return hits

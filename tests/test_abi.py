@@ -91,11 +91,14 @@ def test_invalid_arguments_are_rejected_without_side_effects():
     assert lb.lbvh_query_spheres_count(t3, None, -1, 4096, 4096, 1 << 20, None) == lb.LBVH_EINVAL
     assert lb.lbvh_query_boxes_count(t3, None, 4, None, 4096, 1 << 20, None) == lb.LBVH_EINVAL
     assert lb.lbvh_query_boxes_count(t3, 4096, 4, 4096, 4096, 8, None) == lb.LBVH_ENOSPACE
-    assert lb.lbvh_query_spheres_fill(t3, 4100, 4, 4096, 4096, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_spheres_fill(t3, 4100, 4, 4096, 4096, 1 << 30, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_spheres_fill(t3, 4096, 4, 4096, 4096, 8, None) == lb.LBVH_ENOSPACE
 
 
 def test_profile_names():
-    assert lb.lbvh_profile_read("bottomup")[1] >= 0
+    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "query_split",
+                 "query_count", "query_fill", "scan"]:
+        assert lb.lbvh_profile_read(name)[1] >= 0
     with pytest.raises(lb.LbvhError):
         lb.lbvh_profile_read("nope")
 

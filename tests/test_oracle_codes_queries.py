@@ -225,3 +225,36 @@ def test_queries_on_empty_and_single():
     assert t1.rope.tolist() == [-1] and np.array_equal(t1.aabb[0], [0.5] * 6)
     off, idx, _ = oracle.query_traverse(0, np.array([[0.5, 0.5, 0.5, 0], [9, 9, 9, 1]], np.float32), t1)
     assert off.tolist() == [0, 1, 1] and idx.tolist() == [0]
+
+
+@pytest.mark.parametrize("name,scale,S1,S2", [("clustered_boxes", 1 / 128, 9, 5),
+                                              ("large_points", 1 / 512, 8, 3),
+                                              ("small_points", 1.0, 12, 7)])
+def test_split_walk_equals_plain_walk(name, scale, S1, S2):
+    """Cutting Alg. 1 into aligned-block pieces (the GPU query schedule)
+    returns the plain walk's hits in the same order."""
+    from alg_models import split_walk
+    w = workloads.by_name(name, scale)
+    t = oracle.build(w.kind, w.prims, w.code_bits)
+    off, idx, _ = oracle.query_traverse(w.qkind, w.queries, t)
+    pred = oracle.pred_sphere if w.qkind == 0 else oracle.pred_box
+    left = np.concatenate([t.left, t.perm]).tolist()
+    rope = t.rope.tolist()
+    for j in range(min(w.m, 150)):
+        q = w.queries[j]
+        got = split_walk(t.n, left, rope, t.perm, lambda v: pred(t.aabb[v], q), S1, S2)
+        assert got == idx[off[j]:off[j + 1]].tolist()
+
+
+def test_split_walk_degenerate():
+    from alg_models import split_walk
+    for n in [1, 2, 3, 5, 40, 300]:
+        p = np.full((n, 3), 0.5, np.float32)
+        t = oracle.build(0, p, 30)
+        left = np.concatenate([t.left, t.perm]).tolist()
+        for q in ([0.5, 0.5, 0.5, 0.1], [9, 9, 9, 0.1]):
+            q = np.array(q, np.float32)
+            off, idx, _ = oracle.query_traverse(0, q[None], t)
+            got = split_walk(n, left, t.rope.tolist(), t.perm,
+                             lambda v: oracle.pred_sphere(t.aabb[v], q), 3, 1)
+            assert got == idx.tolist()
