@@ -73,18 +73,21 @@ typedef struct lbvh_node {
     int32_t rope;
 } lbvh_node;
 
-/* A built tree.  The caller allocates both arrays and sets the pointers;
+/* A built tree.  The caller allocates the arrays and sets the pointers;
  * the build fills n, code_bits and kind and writes the arrays.
- *   nodes : device, 2n-1 records (nothing for n = 0).
- *   codes : device, n Morton codes in ascending order (uint32 for 30-bit
- *           codes, uint64 for 63-bit); the build also uses it as sort
- *           scratch.  Queries do not read it. */
+ *   nodes     : device, 2n-1 records (nothing for n = 0).
+ *   codes     : device, n Morton codes in ascending order (uint32 for 30-bit
+ *               codes, uint64 for 63-bit); the build also uses it as sort
+ *               scratch.  Queries do not read it.
+ *   leaf_perm : device, int32 [n]: leaf k -> input index of its primitive
+ *               (the same values as the leaves' `left` fields, contiguous). */
 typedef struct lbvh_tree {
     int64_t n;
     int32_t code_bits;
     int32_t kind;
     lbvh_node *nodes;
     void *codes;
+    int32_t *leaf_perm;
 } lbvh_tree;
 
 /* ---------------------------------------------------------------- build */
@@ -105,7 +108,8 @@ int64_t lbvh_build_workspace_bytes(int64_t n, int32_t code_bits, int32_t kind);
  *                lo <= hi per axis for boxes.
  *   n          : 0 <= n <= LBVH_MAX_PRIMS.  n = 0 gives an empty tree.
  *   code_bits  : 30 (uint32 codes) or 63 (uint64 codes).
- *   tree       : host descriptor with nodes/codes set (non-NULL if n > 0).
+ *   tree       : host descriptor with nodes, codes and leaf_perm set
+ *                (non-NULL if n > 0).
  *   workspace  : device, at least lbvh_build_workspace_bytes(...) bytes,
  *                256-byte aligned; contents on entry are ignored.
  * Equal Morton codes are ordered by input index and the keys are made

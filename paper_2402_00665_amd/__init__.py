@@ -38,7 +38,7 @@ class LbvhError(RuntimeError):
 
 class lbvh_tree(C.Structure):
     _fields_ = [("n", C.c_int64), ("code_bits", C.c_int32), ("kind", C.c_int32),
-                ("nodes", C.c_void_p), ("codes", C.c_void_p)]
+                ("nodes", C.c_void_p), ("codes", C.c_void_p), ("leaf_perm", C.c_void_p)]
 
 
 _lib = None
@@ -170,12 +170,14 @@ def _dev_f32(t, width, what):
 class Tree:
     """A built tree: ``nodes`` is int32 [2n-1, 8] (lo.xyz, left, hi.xyz,
     rope; the float fields are stored by bit pattern), ``codes`` the sorted
-    Morton codes (int32 storage for 30-bit codes, int64 for 63-bit)."""
+    Morton codes (int32 storage for 30-bit codes, int64 for 63-bit),
+    ``leaf_perm`` int32 [n] (leaf k -> input index)."""
     n: int
     code_bits: int
     kind: int
     nodes: object
     codes: object
+    leaf_perm: object
     desc: lbvh_tree
 
     @property
@@ -197,7 +199,8 @@ class Tree:
 
     @property
     def perm(self):
-        """Leaf k -> input index of its primitive, [n]."""
+        """Leaf k -> input index of its primitive, [n] (the leaves' `left`
+        fields; ``leaf_perm`` holds the same values contiguously)."""
         return self.nodes[max(self.n - 1, 0):, 3]
 
 
@@ -220,8 +223,10 @@ def alloc_tree(n: int, code_bits: int, device="cuda") -> Tree:
     torch = _torch()
     nodes = torch.empty((max(2 * n - 1, 0), 8), dtype=torch.int32, device=device)
     codes = torch.empty(max(n, 1), dtype=torch.int32 if code_bits == 30 else torch.int64, device=device)
-    desc = lbvh_tree(n, code_bits, 0, nodes.data_ptr() if n > 0 else None, codes.data_ptr())
-    return Tree(n, code_bits, 0, nodes, codes, desc)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    desc = lbvh_tree(n, code_bits, 0, nodes.data_ptr() if n > 0 else None, codes.data_ptr(),
+                     perm.data_ptr())
+    return Tree(n, code_bits, 0, nodes, codes, perm, desc)
 
 
 def build(prims, code_bits: int, kind: int | None = None, workspace: Workspace | None = None,

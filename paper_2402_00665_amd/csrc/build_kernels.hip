@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict_
 
 template <int KIND, typename K>
 hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_, K *codes,
-                     char *ws, const BuildLayout &L, hipStream_t s)
+                     int32_t *leaf_perm, char *ws, const BuildLayout &L, hipStream_t s)
 {
     using P = Prims<KIND>;
     float *partials = reinterpret_cast<float *>(ws + L.partials);
@@ -703,12 +703,12 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
 
     // ping-pong: even passes read tree->codes, odd passes write it back;
     // the pass count is even for both code widths, so the sorted codes end
-    // in tree->codes and the permutation in vals[(passes-1) & 1]
+    // in tree->codes; the last pass writes the permutation to leaf_perm
     for (int p = 0; p < passes; ++p) {
         const K *kin = (p & 1) ? keys_alt : codes;
         K *kout = (p & 1) ? codes : keys_alt;
         const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
-        int32_t *vout = vals[p & 1];
+        int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
         uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
         prof_begin(K_SORT, s);
         hipLaunchKernelGGL((k_onesweep<K>), dim3((unsigned)L.ntiles), dim3(kSortThreads), 0, s, kin,
@@ -721,7 +721,7 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
     int nbu = (n + kChunk - 1) / kChunk;
     hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
-                       vals[(passes - 1) & 1], prims, n, store, nodes, pend[0], ctrl + kCtrlError);
+                       leaf_perm, prims, n, store, nodes, pend[0], ctrl + kCtrlError);
     int64_t span = kChunk;
     int in = 0;
     while (nbu > 1) {
@@ -740,20 +740,23 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
 }  // namespace
 
 hipError_t launch_build(int kind, const float *prims, int n, int code_bits, lbvh_node *nodes,
-                        void *codes, char *ws, const BuildLayout &L, hipStream_t s)
+                        void *codes, int32_t *leaf_perm, char *ws, const BuildLayout &L,
+                        hipStream_t s)
 {
     if (code_bits == 30) {
         if (kind == LBVH_POINTS)
             return run_build<LBVH_POINTS, uint32_t>(prims, n, code_bits, nodes,
-                                                    static_cast<uint32_t *>(codes), ws, L, s);
+                                                    static_cast<uint32_t *>(codes), leaf_perm, ws,
+                                                    L, s);
         return run_build<LBVH_BOXES, uint32_t>(prims, n, code_bits, nodes,
-                                               static_cast<uint32_t *>(codes), ws, L, s);
+                                               static_cast<uint32_t *>(codes), leaf_perm, ws, L, s);
     }
     if (kind == LBVH_POINTS)
         return run_build<LBVH_POINTS, uint64_t>(prims, n, code_bits, nodes,
-                                                static_cast<uint64_t *>(codes), ws, L, s);
+                                                static_cast<uint64_t *>(codes), leaf_perm, ws, L,
+                                                s);
     return run_build<LBVH_BOXES, uint64_t>(prims, n, code_bits, nodes,
-                                           static_cast<uint64_t *>(codes), ws, L, s);
+                                           static_cast<uint64_t *>(codes), leaf_perm, ws, L, s);
 }
 
 }  // namespace lbvh

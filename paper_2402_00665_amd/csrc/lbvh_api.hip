@@ -163,8 +163,9 @@ int lbvh_build(int32_t kind, const float *prims, int64_t n, int32_t code_bits, l
         tree->kind = kind;
         return LBVH_OK;
     }
-    if (!prims || !tree->nodes || !tree->codes || !workspace || !aligned(prims, 16) ||
-        !aligned(tree->nodes, 16) || !aligned(tree->codes, 16) || !aligned(workspace, 256))
+    if (!prims || !tree->nodes || !tree->codes || !tree->leaf_perm || !workspace ||
+        !aligned(prims, 16) || !aligned(tree->nodes, 16) || !aligned(tree->codes, 16) ||
+        !aligned(tree->leaf_perm, 16) || !aligned(workspace, 256))
         return LBVH_EINVAL;
     const BuildLayout L = build_layout(n, code_bits);
     if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
@@ -172,7 +173,8 @@ int lbvh_build(int32_t kind, const float *prims, int64_t n, int32_t code_bits, l
     tree->code_bits = code_bits;
     tree->kind = kind;
     hipError_t e = launch_build(kind, prims, (int)n, code_bits, tree->nodes, tree->codes,
-                                static_cast<char *>(workspace), L, (hipStream_t)stream);
+                                tree->leaf_perm, static_cast<char *>(workspace), L,
+                                (hipStream_t)stream);
     return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
 }
 
@@ -215,11 +217,13 @@ static int query_count(int qkind, const lbvh_tree *tree, const float *q, int64_t
         !aligned(offsets, 8))
         return LBVH_EINVAL;
     if (m > 0 && (!q || !aligned(q, 16))) return LBVH_EINVAL;
-    if (tree->n > 0 && (!tree->nodes || !aligned(tree->nodes, 16))) return LBVH_EINVAL;
+    if (tree->n > 0 && (!tree->nodes || !tree->leaf_perm || !aligned(tree->nodes, 16)))
+        return LBVH_EINVAL;
     const QueryLayout L = query_layout(m);
     if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
     if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
-    hipError_t e = launch_query(qkind, tree->nodes, (int)tree->n, q, (int)m, offsets, nullptr, false,
+    hipError_t e = launch_query(qkind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
+                                offsets, nullptr, false,
                                 static_cast<char *>(workspace), L, (hipStream_t)stream);
     return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
 }
@@ -230,12 +234,14 @@ static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t 
     if (!tree || m < 0 || m > INT32_MAX || tree->n < 0 || tree->n > LBVH_MAX_PRIMS)
         return LBVH_EINVAL;
     if (m > 0 && (!q || !aligned(q, 16))) return LBVH_EINVAL;
-    if (tree->n > 0 && m > 0 && (!tree->nodes || !indices || !aligned(tree->nodes, 16)))
+    if (tree->n > 0 && m > 0 &&
+        (!tree->nodes || !tree->leaf_perm || !indices || !aligned(tree->nodes, 16)))
         return LBVH_EINVAL;
     const QueryLayout L = query_layout(m);
     if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
     if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
-    hipError_t e = launch_query(qkind, tree->nodes, (int)tree->n, q, (int)m, nullptr, indices, true,
+    hipError_t e = launch_query(qkind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
+                                nullptr, indices, true,
                                 static_cast<char *>(const_cast<void *>(workspace)), L,
                                 (hipStream_t)stream);
     return e == hipSuccess ? LBVH_OK : LBVH_EHIP;

@@ -95,10 +95,10 @@ void prof_end(int id, hipStream_t s);
 // validated by the C ABI layer.
 
 hipError_t launch_build(int kind, const float *prims, int n, int code_bits,
-                        lbvh_node *nodes, void *codes, char *ws,
+                        lbvh_node *nodes, void *codes, int32_t *leaf_perm, char *ws,
                         const BuildLayout &L, hipStream_t s);
 
-hipError_t launch_query(int qkind, const lbvh_node *nodes, int n,
+hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_perm, int n,
                         const float *q, int m, int64_t *offsets,
                         int32_t *indices, bool fill, char *ws,
                         const QueryLayout &L, hipStream_t s);

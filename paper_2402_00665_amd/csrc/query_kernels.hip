@@ -20,6 +20,10 @@
 // * Level 1 splits each query's whole walk by 2^kSplit1 leaves, level 2
 //   splits each level-1 piece by 2^kSplit2 leaves, and the leaf walk runs
 //   each level-2 piece as plain Alg. 1 restricted to its leaf range.
+// * A passing node whose box the query contains has only hits below it: its
+//   leaf range [i, j] is reported from leaf_perm without visiting it (as
+//   all-hit pieces in the split levels).  Alg. 1 would visit the same
+//   leaves in the same order and report the same primitives.
 // Pieces are emitted in walk order, so concatenating their hits gives the
 // plain walk's hits in the plain walk's order.  Each level is a count pass,
 // a scan and a fill pass; a level whose pieces would exceed the workspace
@@ -46,6 +50,18 @@ struct Sphere {
         const float dz = fmaxf(fmaxf(lo.z - cz, cz - hi.z), 0.0f);
         return (dx * dx + dy * dy) + dz * dz <= r2;
     }
+    // The box lies inside the ball: its farthest corner passes.  Every box
+    // inside it then passes `test` too, also after rounding: each per-axis
+    // term of `test` for an inner box is <= the corresponding far term here
+    // (rounding is monotone), and squares and sums of non-negative terms
+    // keep the order.
+    __device__ bool contains(float4 lo, float4 hi) const
+    {
+        const float fx = fmaxf(cx - lo.x, hi.x - cx);
+        const float fy = fmaxf(cy - lo.y, hi.y - cy);
+        const float fz = fmaxf(cz - lo.z, hi.z - cz);
+        return (fx * fx + fy * fy) + fz * fz <= r2;
+    }
 };
 
 struct QBox {
@@ -60,10 +76,16 @@ struct QBox {
     {
         return lx <= hi.x && lo.x <= hx && ly <= hi.y && lo.y <= hy && lz <= hi.z && lo.z <= hz;
     }
+    // The box lies inside the query box, so every box inside it overlaps.
+    __device__ bool contains(float4 lo, float4 hi) const
+    {
+        return lx <= lo.x && hi.x <= hx && ly <= lo.y && hi.y <= hy && lz <= lo.z && hi.z <= hz;
+    }
 };
 
 struct Tree {
     const float4 *nodes;
+    const int32_t *perm;   // leaf k -> primitive
     int n;
     __device__ int leaf0() const { return n - 1; }
     __device__ int index(int v) const { return v >= n - 1 ? v - (n - 1) : v; }
@@ -91,7 +113,9 @@ struct Tree {
 };
 
 // A piece: query, start node, left bound of the start node, end (exclusive)
-// of the leaf range the walk covers.
+// of the leaf range the walk covers.  Start node kAllHits marks a range
+// whose leaves all pass (it lies under a node the query contains).
+constexpr int kAllHits = -2;
 __device__ __forceinline__ int4 piece(int q, int v, int i, int hi) { return make_int4(q, v, i, hi); }
 
 template <class Q, bool FILL, bool FIRST>
@@ -108,33 +132,53 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
          t += (int64_t)gridDim.x * kBlock) {
         const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
         if (pass_through) { out[t] = it; continue; }
-        Q q;
-        q.load(queries, it.x);
         int64_t pos = FILL ? out_off[t] : 0;
         int cnt = 0;
-        int v = it.y, i = it.z;
-        const int hi = it.w;
-        int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
-        while (v != -1 && i < hi && --budget >= 0) {
-            float4 a, b;
-            tr.load(v, a, b);
-            const int j = tr.right_bound(b);
-            if (!q.test(a, b)) {
-                v = __float_as_int(b.w);
-                i = j + 1;
-                continue;
-            }
-            if ((i >> shift) == (j >> shift)) {
-                const int r = ((i >> shift) + 1) << shift;   // next block start
-                const int end = r < hi ? r : hi;
-                if (FILL) out[pos++] = piece(it.x, v, i, end);
+        // all-hit range [a, b): one all-hit piece per block it touches
+        auto emit_range = [&](int a, int b) {
+            while (a < b) {
+                const int blk_end = ((a >> shift) + 1) << shift;
+                const int e = blk_end < b ? blk_end : b;
+                if (FILL) out[pos++] = piece(it.x, kAllHits, a, e);
                 else ++cnt;
-                if (r >= hi || r > tr.n - 1) break;
-                v = tr.first_at(r);
-                i = r;
-                continue;
+                a = e;
             }
-            v = __float_as_int(a.w);   // multi-block node: descend
+        };
+        if (it.y == kAllHits) {
+            emit_range(it.z, it.w);
+        } else {
+            Q q;
+            q.load(queries, it.x);
+            int v = it.y, i = it.z;
+            const int hi = it.w;
+            int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
+            while (v != -1 && i < hi && --budget >= 0) {
+                float4 a, b;
+                tr.load(v, a, b);
+                const int j = tr.right_bound(b);
+                if (!q.test(a, b)) {
+                    v = __float_as_int(b.w);
+                    i = j + 1;
+                    continue;
+                }
+                if ((i >> shift) == (j >> shift)) {
+                    const int r = ((i >> shift) + 1) << shift;   // next block start
+                    const int end = r < hi ? r : hi;
+                    if (FILL) out[pos++] = piece(it.x, v, i, end);
+                    else ++cnt;
+                    if (r >= hi || r > tr.n - 1) break;
+                    v = tr.first_at(r);
+                    i = r;
+                    continue;
+                }
+                if (q.contains(a, b)) {   // multi-block node with only hits below
+                    emit_range(i, j + 1 < hi ? j + 1 : hi);
+                    v = __float_as_int(b.w);
+                    i = j + 1;
+                    continue;
+                }
+                v = __float_as_int(a.w);   // multi-block node: descend
+            }
         }
         if (!FILL) counts[t] = cnt;
     }
@@ -153,29 +197,43 @@ __global__ __launch_bounds__(kBlock) void k_leafwalk(Tree tr, const float *__res
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
          t += (int64_t)gridDim.x * kBlock) {
         const int4 it = in[t];
-        Q q;
-        q.load(queries, it.x);
         int64_t pos = FILL ? hit_off[t] : 0;
         int cnt = 0;
-        int v = it.y, i = it.z;
-        const int hi = it.w;
-        int64_t budget = 2 * (int64_t)tr.n;
-        while (v != -1 && i < hi && --budget >= 0) {
-            float4 a, b;
-            tr.load(v, a, b);
-            const bool hit = q.test(a, b);
-            const int left = __float_as_int(a.w);
-            const int rope = __float_as_int(b.w);
-            if (hit && v < leaf0) {
-                v = left;
-                continue;
+        // leaves [a, b) are all hits
+        auto take_range = [&](int a, int b) {
+            if (FILL)
+                for (int k = a; k < b; ++k) out[pos++] = tr.perm[k];
+            else
+                cnt += b - a;
+        };
+        if (it.y == kAllHits) {
+            take_range(it.z, it.w);
+        } else {
+            Q q;
+            q.load(queries, it.x);
+            int v = it.y, i = it.z;
+            const int hi = it.w;
+            int64_t budget = 2 * (int64_t)tr.n;
+            while (v != -1 && i < hi && --budget >= 0) {
+                float4 a, b;
+                tr.load(v, a, b);
+                const int left = __float_as_int(a.w);
+                const int rope = __float_as_int(b.w);
+                const int j = tr.right_bound(b);
+                if (q.test(a, b)) {
+                    if (v >= leaf0) {              // leaf: `left` holds its primitive
+                        if (FILL) out[pos++] = left;
+                        else ++cnt;
+                    } else if (q.contains(a, b)) {
+                        take_range(i, j + 1 < hi ? j + 1 : hi);
+                    } else {
+                        v = left;
+                        continue;
+                    }
+                }
+                v = rope;
+                i = j + 1;
             }
-            if (hit) {   // leaf: `left` holds its primitive
-                if (FILL) out[pos++] = left;
-                else ++cnt;
-            }
-            i = tr.right_bound(b) + 1;
-            v = rope;
         }
         if (!FILL) counts[t] = cnt;
     }
@@ -415,9 +473,9 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
 
 }  // namespace
 
-hipError_t launch_query(int qkind, const lbvh_node *nodes, int n, const float *q, int m,
-                        int64_t *offsets, int32_t *indices, bool fill, char *ws,
-                        const QueryLayout &L, hipStream_t s)
+hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_perm, int n,
+                        const float *q, int m, int64_t *offsets, int32_t *indices, bool fill,
+                        char *ws, const QueryLayout &L, hipStream_t s)
 {
     if (n == 0 || m == 0) {
         if (fill) return hipSuccess;
@@ -426,7 +484,7 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, int n, const float *q
                            s, offsets, cnt);
         return hipGetLastError();
     }
-    Tree tr{reinterpret_cast<const float4 *>(nodes), n};
+    Tree tr{reinterpret_cast<const float4 *>(nodes), leaf_perm, n};
     if (fill)
         return qkind == 0 ? run_fill<Sphere>(tr, q, indices, ws, L, s)
                           : run_fill<QBox>(tr, q, indices, ws, L, s);

@@ -278,7 +278,7 @@ def alg3(delta, n, policy="random", seed=0):
     return children, ranges, root[0]
 
 
-def split_walk(n, left, rope, perm, test, S1, S2):
+def split_walk(n, left, rope, perm, test, S1, S2, contains=None):
     """A query's Alg. 1 walk cut into independent pieces by aligned leaf
     blocks, the way the GPU query kernels run it.
 
@@ -290,8 +290,12 @@ def split_walk(n, left, rope, perm, test, S1, S2):
     that block, then jumps to the largest node starting at the next block
     (internal node r if it is a right child, i.e. its split >= r, else leaf
     r).  Level 2 does the same inside each piece with 2^S2 leaves; the last
-    level is the plain walk restricted to the piece's leaf range.  Returns
-    the hits in order (must equal the plain walk)."""
+    level is the plain walk restricted to the piece's leaf range.  With
+    ``contains`` (node -> the query contains its box), a passing multi-block
+    node that is contained becomes all-hit ranges split at block bounds, and
+    a contained internal node in the last level reports its whole leaf range
+    without being walked.  Returns the hits in order (must equal the plain
+    walk)."""
     ni = n - 1
 
     def idx(v):
@@ -306,7 +310,19 @@ def split_walk(n, left, rope, perm, test, S1, S2):
             return r
         return ni + r
 
+    ALL = -2
+
+    def ranges(a, b, S):
+        out = []
+        while a < b:
+            e = min(((a >> S) + 1) << S, b)
+            out.append((ALL, a, e))
+            a = e
+        return out
+
     def split(v, i, hi, S):
+        if v == ALL:
+            return ranges(i, hi, S)
         out = []
         while v != -1 and i < hi:
             j = jend(v)
@@ -321,21 +337,28 @@ def split_walk(n, left, rope, perm, test, S1, S2):
                     break
                 v, i = first_at(r), r
                 continue
+            if contains is not None and contains(v):
+                out += ranges(i, min(j + 1, hi), S)
+                v, i = rope[v], j + 1
+                continue
             v = left[v]
         return out
 
     def walk(v, i, hi):
+        if v == ALL:
+            return [int(perm[k]) for k in range(i, hi)]
         out = []
         while v != -1 and i < hi:
             j = jend(v)
             if test(v):
                 if v >= ni:
                     out.append(int(perm[v - ni]))
-                    v, i = rope[v], j + 1
+                elif contains is not None and contains(v):
+                    out += [int(perm[k]) for k in range(i, min(j + 1, hi))]
                 else:
                     v = left[v]
-            else:
-                v, i = rope[v], j + 1
+                    continue
+            v, i = rope[v], j + 1
         return out
 
     if n == 0:

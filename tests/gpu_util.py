@@ -37,7 +37,9 @@ def host_tree(tree):
     codes = codes.view(np.uint32 if tree.code_bits == 30 else np.uint64).astype(np.uint64)
     f = nodes.view(np.float32)
     aabb = np.concatenate([f[:, 0:3], f[:, 4:7]], axis=1)
-    return codes, nodes[n - 1:, 3].copy(), nodes[: n - 1, 3].copy(), nodes[:, 7].copy(), aabb
+    perm = nodes[n - 1:, 3].copy()
+    assert np.array_equal(tree.leaf_perm.cpu().numpy()[:n], perm), "leaf_perm != leaf records"
+    return codes, perm, nodes[: n - 1, 3].copy(), nodes[:, 7].copy(), aabb
 
 
 def first_mismatch(a, b):

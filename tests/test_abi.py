@@ -47,7 +47,7 @@ def test_node_record_layout():
     class Node(C.Structure):
         _fields_ = [("lo", C.c_float * 3), ("left", C.c_int32), ("hi", C.c_float * 3), ("rope", C.c_int32)]
     assert C.sizeof(Node) == lb.NODE_BYTES == 32
-    assert C.sizeof(lb.lbvh_tree) == 32
+    assert C.sizeof(lb.lbvh_tree) == 40
 
 
 def test_strerror():
@@ -72,19 +72,19 @@ def test_workspace_bytes(bits, kb):
 
 
 def test_invalid_arguments_are_rejected_without_side_effects():
-    t = lb.lbvh_tree(0, 0, 0, None, None)
+    t = lb.lbvh_tree(0, 0, 0, None, None, None)
     assert lb.lbvh_build(0, None, 10, 31, t, None, 0, None) == lb.LBVH_EINVAL   # code_bits
     assert lb.lbvh_build(2, None, 10, 30, t, None, 0, None) == lb.LBVH_EINVAL   # kind
     assert lb.lbvh_build(0, None, -1, 30, t, None, 0, None) == lb.LBVH_EINVAL   # n < 0
     assert lb.lbvh_build(0, None, 10, 30, t, None, 0, None) == lb.LBVH_EINVAL   # null pointers
     # misaligned pointers (never dereferenced: rejected up front)
-    t2 = lb.lbvh_tree(0, 0, 0, 4096, 4096)
+    t2 = lb.lbvh_tree(0, 0, 0, 4096, 4096, 4096)
     assert lb.lbvh_build(0, 4100, 10, 30, t2, 4096, 1 << 30, None) == lb.LBVH_EINVAL
     assert lb.lbvh_build(0, 4096, 10, 30, t2, 4096 + 16, 1 << 30, None) == lb.LBVH_EINVAL
     # too small a workspace
     assert lb.lbvh_build(0, 4096, 10, 30, t2, 4096, 16, None) == lb.LBVH_ENOSPACE
     # empty build needs nothing and touches nothing
-    t3 = lb.lbvh_tree(5, 0, 0, None, None)
+    t3 = lb.lbvh_tree(5, 0, 0, None, None, None)
     assert lb.lbvh_build(1, None, 0, 63, t3, None, 0, None) == lb.LBVH_OK
     assert (t3.n, t3.code_bits, t3.kind) == (0, 63, 1)
     # queries

@@ -150,3 +150,44 @@ def test_full_size(name, ws):
     say(f"full-size {name}: generating")
     w = workloads.by_name(name)
     _parity(w, ws)
+
+
+def test_large_queries_all_hit_ranges(ws):
+    """Query boxes and spheres big enough to contain whole subtrees spanning
+    many 4096- and 128-leaf blocks (the all-hit pieces)."""
+    rng = np.random.default_rng(16)
+    w = workloads.clustered(1 << 18, 1)
+    ref = oracle.build(w.kind, w.prims, w.code_bits)
+    tree, _ = gpu_build(w.prims, w.kind, w.code_bits, ws)
+    c = rng.random((40, 3))
+    s = rng.random((40, 3)) * 0.4
+    boxes = np.concatenate([c - s, c + s], 1).astype(np.float32)
+    roff, ridx, _ = oracle.query_traverse(1, boxes, ref)
+    off, idx = gpu_query(tree, boxes, 1, ws)
+    assert_query_equal(off, idx, roff, ridx)
+    assert roff[-1] > 1 << 18
+    sph = workloads.spheres(rng.random((40, 3), dtype=np.float32), np.float32(0.3))
+    roff, ridx, _ = oracle.query_traverse(0, sph, ref)
+    off, idx = gpu_query(tree, sph, 0, ws)
+    assert_query_equal(off, idx, roff, ridx)
+
+
+def test_piece_capacity_overflow_passes_through(ws):
+    """16 queries that each cover all 2^20 leaves need more pieces than the
+    workspace holds at both split levels; the levels pass pieces through
+    unsplit and the results stay exact."""
+    rng = np.random.default_rng(17)
+    p = rng.random((1 << 20, 3), dtype=np.float32)
+    ref = oracle.build(0, p, 30)
+    tree, _ = gpu_build(p, 0, 30, ws)
+    q = workloads.spheres(rng.random((16, 3), dtype=np.float32), np.float32(2.0))
+    roff, ridx, _ = oracle.query_traverse(0, q, ref)
+    off, idx = gpu_query(tree, q, 0, ws)
+    assert_query_equal(off, idx, roff, ridx)
+    assert roff[-1] == 16 << 20
+    # a mix: most queries light, a few cover everything
+    q2 = workloads.spheres(rng.random((600, 3), dtype=np.float32), np.float32(0.01))
+    q2[::97, 3] = 2.0
+    roff, ridx, _ = oracle.query_traverse(0, q2, ref)
+    off, idx = gpu_query(tree, q2, 0, ws)
+    assert_query_equal(off, idx, roff, ridx)

@@ -242,8 +242,49 @@ def test_split_walk_equals_plain_walk(name, scale, S1, S2):
     rope = t.rope.tolist()
     for j in range(min(w.m, 150)):
         q = w.queries[j]
+        ref = idx[off[j]:off[j + 1]].tolist()
         got = split_walk(t.n, left, rope, t.perm, lambda v: pred(t.aabb[v], q), S1, S2)
-        assert got == idx[off[j]:off[j + 1]].tolist()
+        assert got == ref
+        got = split_walk(t.n, left, rope, t.perm, lambda v: pred(t.aabb[v], q), S1, S2,
+                         lambda v: contains(w.qkind, t.aabb[v], q))
+        assert got == ref
+
+
+def contains(qkind, box, q):
+    """The query contains the box (float32 arithmetic as in the kernels)."""
+    box = box.astype(np.float32)
+    q = q.astype(np.float32)
+    if qkind == 1:
+        return bool(np.all(q[:3] <= box[:3]) and np.all(box[3:] <= q[3:]))
+    f = np.maximum(q[:3] - box[:3], box[3:] - q[:3])
+    d2 = np.float32(np.float32(f[0] * f[0]) + np.float32(f[1] * f[1])) + np.float32(f[2] * f[2])
+    return bool(d2 <= np.float32(q[3] * q[3]))
+
+
+@pytest.mark.parametrize("qkind", [0, 1])
+def test_containment_implies_every_leaf_passes(qkind):
+    """Exactness of the containment shortcut: whenever the float32
+    containment test accepts a node, the float32 predicate accepts every
+    leaf box below it."""
+    w = workloads.clustered(1 << 13, 64) if qkind == 1 else workloads.small_points(1 << 13, 64)
+    t = oracle.build(w.kind, w.prims, w.code_bits)
+    pred = oracle.pred_sphere if qkind == 0 else oracle.pred_box
+    rng = np.random.default_rng(21)
+    qs = w.queries.copy()
+    if qkind == 0:
+        qs[:, 3] = rng.random(len(qs)).astype(np.float32) * 0.3
+    else:
+        c = rng.random((len(qs), 3)).astype(np.float32)
+        s = rng.random((len(qs), 3)).astype(np.float32) * 0.3
+        qs = np.concatenate([c - s, c + s], 1).astype(np.float32)
+    seen = 0
+    for q in qs:
+        for v in range(t.n - 1):
+            if contains(qkind, t.aabb[v], q):
+                seen += 1
+                for k in range(t.rlo[v], t.rhi[v] + 1):
+                    assert pred(t.aabb[t.n - 1 + k], q)
+    assert seen > 0
 
 
 def test_split_walk_degenerate():
