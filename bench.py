@@ -34,20 +34,57 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic bytes per primitive of each build kernel (P = primitive bytes,
-# K = code bytes, d = radix passes), counting each array element once per
-# kernel that must touch it:
-#   bounds    read P
-#   morton    read P, write code K, write the Alg. 4 flag 4
-#   sort pass read key K (+ value 4 after the first pass), write K + 4
-#   bottomup  read code K, perm 4, primitive P, flag CAS 8, sibling box 24,
-#             write leaf node 32 and internal node 32
+# K = code bytes, d = radix passes): each array element a kernel must move
+# between HBM and the chip, counted once per kernel:
+#   bounds    read the primitive (P)
+#   morton    read the primitive, write its code (P + K)
+#   sort pass read key (+ 4-byte value after the first pass), write key and
+#             value (averaged over the d passes)
+#   bottomup  level 0 of the bottom-up pass: read the code (K), leaf_perm (4)
+#             and the primitive (P, a gather), write the leaf record (32),
+#             the internal record (32) and the store slot (4); sibling boxes
+#             and arrival flags stay in LDS
 def build_bytes_per_prim(P: int, K: int, d: int) -> dict:
     return {
         "bounds": P,
-        "morton": P + K + 4,
+        "morton": P + K,
         "sort_pass": ((2 * K + 4) + (d - 1) * (2 * K + 8)) / d,
-        "bottomup": K + 4 + P + 8 + 24 + 32 + 32,
+        "bottomup": K + 4 + P + 32 + 32 + 4,
     }
+
+
+# The fixed whole-build byte model used for the roofline target
+# (bounds P, Morton P + K, sort 2K + (2d-1)(K+4), bottom-up K + P + 100).
+def build_model_bytes_per_prim(P: int, K: int, d: int) -> float:
+    return P + (P + K) + (2 * K + (2 * d - 1) * (K + 4)) + (K + P + 100)
+
+
+KERNEL_SOURCES = ["paper_2402_00665_amd/csrc/build_kernels.hip",
+                  "paper_2402_00665_amd/csrc/lbvh_internal.hpp"]
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None if there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
 
 
 def parse():
@@ -62,6 +99,10 @@ def parse():
                     help="time the build alone (no queries in the step)")
     ap.add_argument("--cpu-sample", type=float, default=0.5,
                     help="fraction of the workload the oracle baseline runs on")
+    ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="turn rocprofv3 outputs (kernel-trace --stats run, --pmc FETCH_SIZE "
+                         "run, --pmc WRITE_SIZE run) into profiles/ summaries and exit")
+    ap.add_argument("--command", default="", help="with --summarize: the profiled command")
     return ap.parse_args()
 
 
@@ -71,6 +112,9 @@ def log(*a):
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(this path has no multi-GPU form)", file=sys.stderr)
@@ -130,8 +174,8 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
 
     kernels = {}
-    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "query_split",
-                 "query_count", "scan", "query_fill"]:
+    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "bottomup_up",
+                 "query_split", "query_count", "scan", "query_fill"]:
         tot, cnt = lb.lbvh_profile_read(name)
         if cnt:
             kernels[name] = {"ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
@@ -149,6 +193,7 @@ def main():
     build_kernels = {k: v for k, v in kernels.items() if k in bpp}
     dom = max(build_kernels, key=lambda k: build_kernels[k]["ms_per_step"])
     dk = kernels[dom]
+    traffic = measured_traffic(w.name, dom)
     roofline = {
         "kernel": dom,
         "bound": "hbm",
@@ -156,11 +201,11 @@ def main():
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
         "frac": round(dk["achieved_gbps"] / HBM_PEAK_GBPS, 4),
-        "traffic": None,
+        "traffic": None if traffic is None else int(traffic),
         "alg_bytes_per_launch": int(dk["alg_bytes_per_launch"]),
         "ms_per_launch": round(dk["ms_per_launch"], 4),
     }
-    model_bytes = (bpp["bounds"] + bpp["morton"] + d * bpp["sort_pass"] + bpp["bottomup"]) * w.n
+    model_bytes = build_model_bytes_per_prim(P, K, d) * w.n
 
     # stream-copy bandwidth in the same run, for context
     buf = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
@@ -226,6 +271,94 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# --------------------------------------------------------------- profiles
+
+KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name
+    "k_bounds<": "bounds", "k_bounds_final": "bounds_final", "k_morton": "morton",
+    "k_onesweep": "sort_pass", "k_bottomup_l0": "bottomup", "k_bottomup_up": "bottomup_up",
+    "k_split": "query_split", "k_leafwalk<": None, "copyBuffer": "copy",
+}
+
+
+def _group(name: str):
+    for frag, g in KERNEL_GROUPS.items():
+        if frag in name:
+            if frag == "k_leafwalk<":
+                return "query_fill" if "true>" in name.split("k_leafwalk<")[1][:40] else "query_count"
+            return g
+    return None
+
+
+def summarize(args):
+    """Write profiles/<workload> summaries from rocprofv3 CSV outputs: the
+    --kernel-trace --stats table, and per-kernel HBM bytes from the two
+    --pmc runs, each counter scaled by what it reads for the 256 MiB device
+    copy the bench itself runs (a copy of known size)."""
+    import csv
+    import collections
+    import glob
+    stats_dir, fetch_dir, write_dir = args.summarize
+
+    def one(pattern):
+        got = glob.glob(os.path.join(pattern, "**", "*"), recursive=True)
+        return got
+
+    stats = [f for f in one(stats_dir) if f.endswith("kernel_stats.csv")][0]
+    rows = list(csv.DictReader(open(stats)))
+    lines = [f"# Kernel time: {args.workload}", "",
+             f"Command: `{args.command}`", "",
+             "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        nm = r["Name"].replace("lbvh::(anonymous namespace)::", "")
+        nm = nm.split("(")[0].replace("void ", "")
+        lines.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+                     f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} | "
+                     f"{float(r['Percentage']):.2f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"kernels_{args.workload}.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+    def per_dispatch(d, counter):
+        f = [x for x in one(d) if x.endswith("counter_collection.csv")][0]
+        agg = collections.OrderedDict()
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]))
+            agg[key] = agg.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+        return agg
+
+    fetch, write = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    copy_bytes = 1 << 28
+    def calib(agg):
+        vals = [v for (d, nm, g), v in agg.items() if "copyBuffer" in nm and v > copy_bytes / 8]
+        return copy_bytes / (sum(vals) / len(vals))
+    # the copy reads 256 MiB and writes 256 MiB
+    cf, cw = calib(fetch), calib(write)
+    out = collections.defaultdict(lambda: {"fetch": [], "write": []})
+    for (d, nm, g), v in fetch.items():
+        grp = _group(nm)
+        if grp and grp != "copy":
+            out[grp]["fetch"].append(v * cf)
+    for (d, nm, g), v in write.items():
+        grp = _group(nm)
+        if grp and grp != "copy":
+            out[grp]["write"].append(v * cw)
+    kernels = {}
+    for grp, dv in out.items():
+        fb = sum(dv["fetch"]) / max(len(dv["fetch"]), 1)
+        wb = sum(dv["write"]) / max(len(dv["write"]), 1)
+        kernels[grp] = {"fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
+                        "hbm_bytes_per_launch": int(fb + wb), "launches": len(dv["fetch"])}
+    doc = {"workload": args.workload, "command": args.command,
+           "calibration": {"fetch_scale": cf, "write_scale": cw,
+                           "copy_kernel": "__amd_rocclr_copyBuffer, 256 MiB device copy"},
+           "source_sha256": source_hash(), "kernels": kernels}
+    with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"), "w") as f:
+        json.dump(doc, f, indent=1)
+    print(json.dumps(doc, indent=1))
 
 
 if __name__ == "__main__":

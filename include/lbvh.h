@@ -181,12 +181,29 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
 /* Human-readable name of a status code (static string). */
 const char *lbvh_strerror(int status);
 
+/* The HIP runtime's description of the error behind the last LBVH_EHIP
+ * returned on the calling thread ("no error" if none). */
+const char *lbvh_last_hip_error(void);
+
+/* Launch-shape tuning, process-wide (for autotuners and benchmarks).
+ * Sets knob `name` to `value` and returns the previous value; a negative
+ * `value` only reads the knob.  Returns LBVH_EINVAL for an unknown name or
+ * a value out of range.  Knobs:
+ *   "sort_variant32", "sort_variant64": tile shape of the radix passes for
+ *       30-bit / 63-bit codes: 0 = 256 threads x 16 keys, 1 = 256 x 8,
+ *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8
+ *       (defaults 4 and 3).
+ * Results never depend on the knobs; only speed does.  Calls already
+ * enqueued keep the shapes they were enqueued with. */
+int64_t lbvh_tune(const char *name, int64_t value);
+
 /* Per-kernel timing.  While enabled, every launch the library makes is
  * bracketed by HIP events recorded on the launch's own stream.
  * lbvh_profile_read synchronises those events and returns, for the kernel
  * named `kernel`, the summed duration in milliseconds and the number of
  * launches since the last reset.  Names: "bounds", "bounds_final",
- * "morton", "sort_pass", "bottomup" (all its levels), "query_split",
+ * "morton", "sort_pass", "bottomup" (level 0 of the bottom-up pass),
+ * "bottomup_up" (its upper levels), "query_split",
  * "query_count", "query_fill", "scan" (scans and offset bookkeeping).
  * Returns LBVH_EINVAL for an unknown name. */
 int lbvh_profile_enable(int32_t on);

@@ -32,7 +32,10 @@ NODE_BYTES = 32
 
 class LbvhError(RuntimeError):
     def __init__(self, status: int, what: str):
-        super().__init__(f"{what}: {lbvh_strerror(status)} ({status})")
+        msg = f"{what}: {lbvh_strerror(status)} ({status})"
+        if status == LBVH_EHIP:
+            msg += f": {lbvh_last_hip_error()}"
+        super().__init__(msg)
         self.status = status
 
 
@@ -51,6 +54,14 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2402_00665_amd.build_lib`")
+        # torch ships its own HIP runtime under the same soname
+        # (libamdhip64.so.7); importing torch first makes liblbvh bind to
+        # that runtime, so device pointers and streams from torch belong to
+        # the runtime the library launches on (one runtime per process).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
         T = C.POINTER(lbvh_tree)
@@ -66,6 +77,8 @@ def lib() -> C.CDLL:
             "lbvh_query_spheres_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_query_boxes_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_strerror": (C.c_char_p, [C.c_int]),
+            "lbvh_last_hip_error": (C.c_char_p, []),
+            "lbvh_tune": (i64, [C.c_char_p, i64]),
             "lbvh_profile_enable": (C.c_int, [i32]),
             "lbvh_profile_reset": (C.c_int, []),
             "lbvh_profile_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(i64)]),
@@ -81,6 +94,10 @@ def lib() -> C.CDLL:
 
 def lbvh_strerror(status: int) -> str:
     return lib().lbvh_strerror(status).decode()
+
+
+def lbvh_last_hip_error() -> str:
+    return lib().lbvh_last_hip_error().decode()
 
 
 def lbvh_build_workspace_bytes(n: int, code_bits: int, kind: int) -> int:
@@ -121,6 +138,10 @@ def lbvh_query_spheres_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -
 
 def lbvh_query_boxes_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> int:
     return lib().lbvh_query_boxes_fill(C.byref(tree), q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_tune(name: str, value: int = -1) -> int:
+    return lib().lbvh_tune(name.encode(), value)
 
 
 def lbvh_profile_enable(on: bool) -> int:

@@ -278,8 +278,9 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
 
 // ------------------------------------------------------ onesweep pass
 
-// Exclusive scan of one value per thread across the 256-thread block.
-__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *sh /* [4] */)
+// Exclusive scan across the block of one value per thread (THREADS values).
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh /* [THREADS/64] */)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t x = v;
@@ -295,43 +296,45 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t *sh 
     return before + x - v;
 }
 
-// One LSD radix pass over 8-bit digit `shift/8`.  A block takes the next
-// tile id from a counter (so every tile it waits for is already running),
-// ranks its 4096 keys stably with wave64 ballots, publishes its per-digit
-// counts, looks back over earlier tiles for their running totals, and
-// scatters through LDS so that global writes are runs of equal digits.
-// vals_in == nullptr makes the values the input indices.  status_next,
-// when set, is the next pass's look-back buffer, cleared here tile by tile.
-template <typename K>
-__global__ __launch_bounds__(kSortThreads) void k_onesweep(
+// One LSD radix pass over the 8-bit digit at `shift`.  A block takes the
+// next tile id from a counter (so every tile it waits for is already
+// running), ranks its THREADS*ITEMS keys stably with wave64 ballots,
+// publishes its per-digit counts, looks back over earlier tiles for their
+// running totals, and scatters keys, then values, through one LDS buffer so
+// that global writes are runs of equal digits.  vals_in == nullptr makes
+// the values the input indices.  status_next, when set, is the next pass's
+// look-back buffer, cleared here tile by tile.
+template <typename K, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, const int32_t *__restrict__ vals_in,
     int32_t *__restrict__ vals_out, int n, int shift, const uint32_t *__restrict__ hist_pass,
     uint32_t *status, uint32_t *__restrict__ status_next, uint32_t *tile_counter, uint32_t *err)
 {
-    constexpr int W = kSortThreads / 64;
+    static_assert(THREADS >= kRadix && THREADS % 64 == 0, "one thread per digit");
+    constexpr int W = THREADS / 64;
+    constexpr int TILE = THREADS * ITEMS;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wcnt[W][kRadix];
     __shared__ uint32_t s_start[kRadix];     // tile-local start of each digit run
     __shared__ uint32_t s_gbase[kRadix];     // global position of that run
-    __shared__ uint32_t s_scan[2][4];
-    __shared__ K s_keys[kTile];
-    __shared__ int32_t s_vals[kTile];
+    __shared__ uint32_t s_scan[2][W];
+    __shared__ K s_buf[TILE];                // keys, then values
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (int j = tid; j < W * kRadix; j += kSortThreads) (&s_wcnt[0][0])[j] = 0u;
+    for (int j = tid; j < W * kRadix; j += THREADS) (&s_wcnt[0][0])[j] = 0u;
     __syncthreads();
     const uint32_t tile = s_tile;
-    const int64_t base = (int64_t)tile * kTile;
-    if (status_next) status_next[(int64_t)tile * kRadix + tid] = 0u;
+    const int64_t base = (int64_t)tile * TILE;
+    if (status_next && tid < kRadix) status_next[(int64_t)tile * kRadix + tid] = 0u;
 
-    // load: wave w owns keys [base + w*64*ITEMS, ...), item k of lane l is
-    // key base + w*64*ITEMS + k*64 + l, so (item, lane) order is input order
-    K key[kSortItems];
-    int32_t val[kSortItems];
-    const int64_t wbase = base + (int64_t)wave * 64 * kSortItems;
+    // wave w owns keys [base + w*64*ITEMS, ...); item k of lane l is key
+    // base + w*64*ITEMS + k*64 + l, so (item, lane) order is input order
+    K key[ITEMS];
+    int32_t val[ITEMS];
+    const int64_t wbase = base + (int64_t)wave * 64 * ITEMS;
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         const int64_t idx = wbase + k * 64 + lane;
         const bool ok = idx < n;
         key[k] = ok ? keys_in[idx] : (K)0;
@@ -340,9 +343,9 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
 
     // stable rank within the wave: lanes holding the same digit find each
     // other with 8 ballots; the lowest of them advances the wave's counter
-    uint32_t rank[kSortItems];
+    uint32_t rank[ITEMS];
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
+    for (int k = 0; k < ITEMS; ++k) {
         const int64_t idx = wbase + k * 64 + lane;
         const bool ok = idx < n;
         const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
@@ -360,82 +363,91 @@ __global__ __launch_bounds__(kSortThreads) void k_onesweep(
     }
     __syncthreads();
 
-    // thread d: per-wave exclusive offsets of digit d and the tile total
+    // threads d < 256: per-wave exclusive offsets of digit d and the total
     const uint32_t d = tid;
-    uint32_t c[W], total = 0;
+    uint32_t total = 0;
+    if (tid < kRadix) {
+        uint32_t c[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) { c[w] = s_wcnt[w][d]; }
+        for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
 #pragma unroll
-    for (int w = 0; w < W; ++w) { s_wcnt[w][d] = total; total += c[w]; }
-
-    // publish this tile's count for digit d, then look back
-    uint32_t *my = status + (int64_t)tile * kRadix + d;
-    if (tile == 0)
-        __hip_atomic_store(my, kFlagInclusive | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        __hip_atomic_store(my, kFlagAggregate | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
-    const uint32_t start = block_excl_scan256(total, s_scan[0]);
-    const uint32_t hoff = block_excl_scan256(hist_pass[d], s_scan[1]);
-    s_start[d] = start;
-
-    uint32_t excl = 0;
-    if (tile > 0) {
-        int64_t j = (int64_t)tile - 1;
-        uint32_t spins = 0;
-        while (true) {
-            const uint32_t s = __hip_atomic_load(status + j * kRadix + d, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t flag = s & ~kValueMask;
-            if (flag == 0u) {
-                if (++spins > (1u << 24)) {   // never expected: bounded wait
-                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+        for (int w = 0; w < W; ++w) { s_wcnt[w][d] = total; total += c[w]; }
+        uint32_t *my = status + (int64_t)tile * kRadix + d;
+        __hip_atomic_store(my, (tile == 0 ? kFlagInclusive : kFlagAggregate) | total,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t start = block_excl_scan<THREADS>(tid < kRadix ? total : 0u, s_scan[0]);
+    const uint32_t hoff = block_excl_scan<THREADS>(tid < kRadix ? hist_pass[d] : 0u, s_scan[1]);
+    if (tid < kRadix) {
+        s_start[d] = start;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint32_t sv = __hip_atomic_load(status + j * kRadix + d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t flag = sv & ~kValueMask;
+                if (flag == 0u) {
+                    if (++spins > (1u << 24)) {   // never expected: bounded wait
+                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
                 }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
+                excl += sv & kValueMask;
+                if (flag == kFlagInclusive || j == 0) break;
+                --j;
             }
-            excl += s & kValueMask;
-            if (flag == kFlagInclusive || j == 0) break;
-            --j;
+            __hip_atomic_store(status + (int64_t)tile * kRadix + d, kFlagInclusive | (excl + total),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __hip_atomic_store(my, kFlagInclusive | (excl + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        s_gbase[d] = hoff + excl;
     }
-    s_gbase[d] = hoff + excl;
     __syncthreads();
 
-    // scatter into LDS in tile-sorted order
+    uint32_t pos[ITEMS];
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        const int64_t idx = wbase + k * 64 + lane;
-        if (idx < n) {
-            const uint32_t dk = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-            const uint32_t pos = s_start[dk] + s_wcnt[wave][dk] + rank[k];
-            s_keys[pos] = key[k];
-            s_vals[pos] = val[k];
-        }
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t dk = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+        pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
     }
-    __syncthreads();
-
-    // write out: consecutive threads take consecutive sorted slots
     const int64_t rem = (int64_t)n - base;
-    const int valid = rem < kTile ? (int)rem : kTile;
+    const int valid = rem < TILE ? (int)rem : TILE;
+
+    // keys: into LDS in tile-sorted order, then out in runs
 #pragma unroll
-    for (int k = 0; k < kSortItems; ++k) {
-        const int p = k * kSortThreads + tid;
+    for (int k = 0; k < ITEMS; ++k)
+        if (wbase + k * 64 + lane < n) s_buf[pos[k]] = key[k];
+    __syncthreads();
+    int64_t dst[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int p = k * THREADS + tid;
+        dst[k] = -1;
         if (p < valid) {
-            const K kk = s_keys[p];
+            const K kk = s_buf[p];
             const uint32_t dk = (uint32_t)(kk >> shift) & (kRadix - 1);
             const int64_t out = (int64_t)s_gbase[dk] + (p - (int)s_start[dk]);
             if (out >= 0 && out < n) {
                 keys_out[out] = kk;
-                vals_out[out] = s_vals[p];
+                dst[k] = out;
             } else {   // inconsistent histogram: flag it rather than write outside
                 __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
+    __syncthreads();
+    // values: same slots, same destinations
+    int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (wbase + k * 64 + lane < n) s_vals[pos[k]] = val[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (dst[k] >= 0) vals_out[dst[k]] = s_vals[k * THREADS + tid];
 }
 
 // ------------------------------------------------------------ Alg. 4
@@ -665,6 +677,44 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict_
     if (threadIdx.x < 2) pend_out[2 * blockIdx.x + threadIdx.x] = s_pend[threadIdx.x];
 }
 
+// Tile shapes of the radix pass (threads x keys per thread); the tuning
+// knob "sort_variant" picks one (see lbvh_tune).
+struct SortShape { int threads, items; };
+constexpr SortShape kSortShapes[] = {{256, 16}, {256, 8}, {256, 24}, {512, 8}, {512, 16}, {1024, 8}};
+constexpr int kSortShapeCount = sizeof(kSortShapes) / sizeof(kSortShapes[0]);
+
+template <typename K>
+int sort_variant()
+{
+    const int64_t v = tune_get(sizeof(K) == 4 ? TUNE_SORT_VARIANT32 : TUNE_SORT_VARIANT64);
+    return (v >= 0 && v < kSortShapeCount) ? (int)v : 0;
+}
+
+template <typename K, int T, int I>
+void launch_one(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n, int shift,
+                const uint32_t *hist, uint32_t *st, uint32_t *st_next, uint32_t *ctr, uint32_t *err,
+                hipStream_t s)
+{
+    const unsigned tiles = (unsigned)(((int64_t)n + T * I - 1) / (T * I));
+    hipLaunchKernelGGL((k_onesweep<K, T, I>), dim3(tiles), dim3(T), 0, s, kin, kout, vin, vout, n,
+                       shift, hist, st, st_next, ctr, err);
+}
+
+template <typename K>
+void launch_onesweep(int variant, const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n,
+                     int shift, const uint32_t *hist, uint32_t *st, uint32_t *st_next, uint32_t *ctr,
+                     uint32_t *err, hipStream_t s)
+{
+    switch (variant) {
+    case 1: launch_one<K, 256, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    case 2: launch_one<K, 256, 24>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    case 3: launch_one<K, 512, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    case 4: launch_one<K, 512, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    case 5: launch_one<K, 1024, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    default: launch_one<K, 256, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    }
+}
+
 template <int KIND, typename K>
 hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_, K *codes,
                      int32_t *leaf_perm, char *ws, const BuildLayout &L, hipStream_t s)
@@ -711,9 +761,9 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
         int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
         uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
         prof_begin(K_SORT, s);
-        hipLaunchKernelGGL((k_onesweep<K>), dim3((unsigned)L.ntiles), dim3(kSortThreads), 0, s, kin,
-                           kout, vin, vout, n, p * kRadixBits, hist + p * kRadix, status[p & 1],
-                           st_next, ctrl + kCtrlTileCounter + p, ctrl + kCtrlError);
+        launch_onesweep<K>(sort_variant<K>(), kin, kout, vin, vout, n, p * kRadixBits,
+                           hist + p * kRadix, status[p & 1], st_next, ctrl + kCtrlTileCounter + p,
+                           ctrl + kCtrlError, s);
         prof_end(K_SORT, s);
     }
 
@@ -722,18 +772,20 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     int nbu = (n + kChunk - 1) / kChunk;
     hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
                        leaf_perm, prims, n, store, nodes, pend[0], ctrl + kCtrlError);
+    prof_end(K_BOTTOMUP, s);
     int64_t span = kChunk;
     int in = 0;
     while (nbu > 1) {
         const int64_t next = span * kFanout;
         const int nbn = (int)((n + next - 1) / next);
+        prof_begin(K_BOTTOMUP_UP, s);
         hipLaunchKernelGGL((k_bottomup_up<K>), dim3(nbn), dim3(kBUThreads), 0, s, codes, n, span,
                            next, store, nodes, pend[in], pend[in ^ 1], ctrl + kCtrlError);
+        prof_end(K_BOTTOMUP_UP, s);
         in ^= 1;
         span = next;
         nbu = nbn;
     }
-    prof_end(K_BOTTOMUP, s);
     return hipGetLastError();
 }
 

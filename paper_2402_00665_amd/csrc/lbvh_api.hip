@@ -3,6 +3,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -18,7 +19,7 @@ BuildLayout build_layout(int64_t n, int code_bits)
     BuildLayout L{};
     const size_t kb = (size_t)key_bytes(code_bits);
     L.passes = radix_passes(code_bits);
-    L.ntiles = (n + kTile - 1) / kTile;
+    L.ntiles = (n + kMinSortTile - 1) / kMinSortTile;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     L.scene = take(3 * sizeof(float4));
@@ -60,6 +61,17 @@ QueryLayout query_layout(int64_t m)
     return L;
 }
 
+// ---------------------------------------------------------------- tuning
+
+namespace {
+// defaults measured on MI355X: 512 x 16 for 30-bit keys, 512 x 8 for 63-bit
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}};
+const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64"};
+const int64_t kTuneLimit[TUNE_NUM] = {6, 6};   // values are 0 .. limit-1
+}  // namespace
+
+int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
+
 // ---------------------------------------------------------------- timing
 
 namespace {
@@ -100,7 +112,7 @@ Profiler &prof()
     return p;
 }
 const char *kNames[K_NUM] = {"bounds", "bounds_final", "morton", "sort_pass", "bottomup",
-                             "query_count", "query_fill", "scan", "query_split"};
+                             "query_count", "query_fill", "scan", "query_split", "bottomup_up"};
 }  // namespace
 
 void prof_begin(int id, hipStream_t s)
@@ -128,6 +140,16 @@ void prof_end(int id, hipStream_t s)
 using namespace lbvh;
 
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// HIP error behind the last LBVH_EHIP returned on this thread.
+static thread_local hipError_t t_last_hip = hipSuccess;
+
+static int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return LBVH_OK;
+    t_last_hip = e;
+    return LBVH_EHIP;
+}
 
 extern "C" {
 
@@ -175,7 +197,7 @@ int lbvh_build(int32_t kind, const float *prims, int64_t n, int32_t code_bits, l
     hipError_t e = launch_build(kind, prims, (int)n, code_bits, tree->nodes, tree->codes,
                                 tree->leaf_perm, static_cast<char *>(workspace), L,
                                 (hipStream_t)stream);
-    return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
+    return hip_status(e);
 }
 
 int lbvh_build_points(const float *xyz, int64_t n, int32_t code_bits, lbvh_tree *tree,
@@ -194,13 +216,16 @@ int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits, int32_
                      void *stream)
 {
     if (lbvh_build_workspace_bytes(n, code_bits, kind) < 0 || !workspace) return LBVH_EINVAL;
-    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return LBVH_EHIP;
+    if (hipError_t e = hipStreamSynchronize((hipStream_t)stream); e != hipSuccess) return hip_status(e);
     if (n == 0) return LBVH_OK;
     const BuildLayout L = build_layout(n, code_bits);
     uint32_t flag = 0;
-    if (hipMemcpy(&flag, static_cast<const char *>(workspace) + L.ctrl + kCtrlError * sizeof(uint32_t),
-                  sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess)
-        return LBVH_EHIP;
+    if (hipError_t e = hipMemcpy(&flag,
+                                 static_cast<const char *>(workspace) + L.ctrl +
+                                     kCtrlError * sizeof(uint32_t),
+                                 sizeof(flag), hipMemcpyDeviceToHost);
+        e != hipSuccess)
+        return hip_status(e);
     return flag ? LBVH_EDEVICE : LBVH_OK;
 }
 
@@ -225,7 +250,7 @@ static int query_count(int qkind, const lbvh_tree *tree, const float *q, int64_t
     hipError_t e = launch_query(qkind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
                                 offsets, nullptr, false,
                                 static_cast<char *>(workspace), L, (hipStream_t)stream);
-    return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
+    return hip_status(e);
 }
 
 static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t m, int32_t *indices,
@@ -244,7 +269,7 @@ static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t 
                                 nullptr, indices, true,
                                 static_cast<char *>(const_cast<void *>(workspace)), L,
                                 (hipStream_t)stream);
-    return e == hipSuccess ? LBVH_OK : LBVH_EHIP;
+    return hip_status(e);
 }
 
 int lbvh_query_spheres_count(const lbvh_tree *tree, const float *xyzr, int64_t m, int64_t *offsets,
@@ -269,6 +294,21 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m, i
                           const void *workspace, int64_t workspace_bytes, void *stream)
 {
     return query_fill(1, tree, lohi, m, indices, workspace, workspace_bytes, stream);
+}
+
+const char *lbvh_last_hip_error(void) { return hipGetErrorString(t_last_hip); }
+
+int64_t lbvh_tune(const char *name, int64_t value)
+{
+    if (!name) return LBVH_EINVAL;
+    for (int k = 0; k < TUNE_NUM; ++k) {
+        if (strcmp(name, kTuneNames[k]) == 0) {
+            if (value < 0) return g_tune[k].load();
+            if (value >= kTuneLimit[k]) return LBVH_EINVAL;
+            return g_tune[k].exchange(value);
+        }
+    }
+    return LBVH_EINVAL;
 }
 
 int lbvh_profile_enable(int32_t on)

@@ -16,9 +16,7 @@ namespace lbvh {
 constexpr int kBlock = 256;           // threads per block of the simple kernels
 constexpr int kRadixBits = 8;         // digit width of the LSD radix sort
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortThreads = 256;     // 4 waves of 64
-constexpr int kSortItems = 16;        // keys per thread
-constexpr int kTile = kSortThreads * kSortItems;
+constexpr int kMinSortTile = 2048;    // smallest radix tile (sizes the look-back buffers)
 constexpr int kBoundsBlocksMax = 1024;
 constexpr int kMortonBlocksMax = 2048;
 constexpr int kChunk = 1024;          // leaves per level-0 block of the bottom-up pass
@@ -80,11 +78,17 @@ struct QueryLayout {
 
 QueryLayout query_layout(int64_t m);
 
+// ------------------------------------------------------------ tuning
+// Launch-shape knobs read by the launchers; set through lbvh_tune.
+
+enum TuneKnob { TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_NUM };
+int64_t tune_get(int knob);
+
 // ------------------------------------------------------------ timing
 
 enum KernelId {
     K_BOUNDS = 0, K_BOUNDS_FINAL, K_MORTON, K_SORT, K_BOTTOMUP,
-    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_NUM
+    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_BOTTOMUP_UP, K_NUM
 };
 
 void prof_begin(int id, hipStream_t s);

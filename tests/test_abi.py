@@ -96,8 +96,8 @@ def test_invalid_arguments_are_rejected_without_side_effects():
 
 
 def test_profile_names():
-    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "query_split",
-                 "query_count", "query_fill", "scan"]:
+    for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "bottomup_up",
+                 "query_split", "query_count", "query_fill", "scan"]:
         assert lb.lbvh_profile_read(name)[1] >= 0
     with pytest.raises(lb.LbvhError):
         lb.lbvh_profile_read("nope")
@@ -112,3 +112,12 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "lbvh_oracle" not in text, f
+
+
+def test_one_hip_runtime_per_process():
+    """The library binds to the HIP runtime torch loaded (same soname), so
+    torch's pointers and streams are the library's own."""
+    lb.lib()
+    maps = open("/proc/self/maps").read()
+    runtimes = {ln.split()[-1] for ln in maps.splitlines() if "libamdhip64" in ln}
+    assert len(runtimes) == 1, runtimes

@@ -191,3 +191,21 @@ def test_piece_capacity_overflow_passes_through(ws):
     roff, ridx, _ = oracle.query_traverse(0, q2, ref)
     off, idx = gpu_query(tree, q2, 0, ws)
     assert_query_equal(off, idx, roff, ridx)
+
+
+@pytest.mark.parametrize("variant", range(6))
+def test_sort_tile_variants(variant, ws):
+    """Every radix-pass tile shape gives the same tree (tolerance 0)."""
+    import paper_2402_00665_amd as lb
+    rng = np.random.default_rng([18, variant])
+    old32 = lb.lbvh_tune("sort_variant32", variant)
+    old64 = lb.lbvh_tune("sort_variant64", variant)
+    try:
+        for n, bits in [(100003, 30), (100003, 63), (4097, 30), (300, 63), (1 << 18, 30)]:
+            p = rng.random((n, 3), dtype=np.float32)
+            ref = oracle.build(0, p, bits)
+            tree, _ = gpu_build(p, 0, bits, ws)
+            assert_tree_equal(tree, ref)
+    finally:
+        lb.lbvh_tune("sort_variant32", old32)
+        lb.lbvh_tune("sort_variant64", old64)
