@@ -176,6 +176,83 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
                           int32_t *indices, const void *workspace,
                           int64_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------- batched */
+
+/* Many independent scenes built together.  Scene s owns primitives
+ * [seg_off[s], seg_off[s+1]) of the concatenated input; its tree is exactly
+ * the tree lbvh_build gives for those primitives alone (own scene box,
+ * Morton codes, sort, node ids, primitive ids local to the scene), stored at
+ * record 2*seg_off[s] of `nodes` (2n_s-1 records; n_s = 0 gives none).
+ * The caller allocates every array and fills the descriptor except kind.
+ *   seg_off   : device int64 [num_scenes+1], seg_off[0] = 0, non-decreasing,
+ *               seg_off[num_scenes] = total_n.
+ *   max_scene : an upper bound of every scene's size (host value; sizes the
+ *               launch; a larger scene is reported by the check call).
+ *   nodes     : device, 2*total_n records.
+ *   codes     : device, total_n codes, ascending within each scene.
+ *   leaf_perm : device int32 [total_n]: leaf k of scene s (entry
+ *               seg_off[s]+k) -> index of its primitive within the scene. */
+typedef struct lbvh_batch {
+    int32_t num_scenes;
+    int32_t code_bits;
+    int32_t kind;
+    int32_t reserved;
+    int64_t total_n;
+    int64_t max_scene;
+    const int64_t *seg_off;
+    lbvh_node *nodes;
+    void *codes;
+    int32_t *leaf_perm;
+} lbvh_batch;
+
+/* Workspace bytes for lbvh_build_batched. */
+int64_t lbvh_build_batched_workspace_bytes(int64_t total_n, int32_t num_scenes,
+                                           int64_t max_scene, int32_t code_bits,
+                                           int32_t kind);
+
+/* Build every scene's rope-LBVH (the steps of lbvh_build, Sec. 3.1 and
+ * Alg. 4) with one launch sequence for all scenes: per-scene boxes and
+ * codes (one block per scene), segmented radix passes (tiles never cross
+ * scenes), and the bottom-up pass with blocks that never cross scenes.
+ * Only kernel launches are enqueued (no memsets, no host synchronisation),
+ * so the call can be captured in a HIP graph and replayed.
+ *   prims     : device, float [total_n][3] or [total_n][6], 8-byte aligned.
+ *   workspace : device, lbvh_build_batched_workspace_bytes(...) bytes,
+ *               256-byte aligned. */
+int lbvh_build_batched(int32_t kind, const float *prims, lbvh_batch *batch,
+                       void *workspace, int64_t workspace_bytes, void *stream);
+
+/* Synchronise and report an error flagged by a batched build's kernels
+ * (LBVH_EDEVICE), e.g. a scene larger than max_scene. */
+int lbvh_build_batched_check(const void *workspace, const lbvh_batch *batch,
+                             void *stream);
+
+/* Workspace bytes for a batched count call over m queries. */
+int64_t lbvh_query_batched_workspace_bytes(int64_t m);
+
+/* Range queries on a batch: query j belongs to the scene s with
+ * qseg_off[s] <= j < qseg_off[s+1] (device int64 [num_scenes+1]) and walks
+ * that scene's tree (Alg. 1; same predicates and order as the single-tree
+ * calls).  Indices are primitive ids local to the scene.  The count call
+ * writes CSR offsets [m+1]; the fill call repeats the walk and writes the
+ * ids at those offsets. */
+int lbvh_query_batched_spheres_count(const lbvh_batch *batch, const float *xyzr,
+                                     const int64_t *qseg_off, int64_t m,
+                                     int64_t *offsets, void *workspace,
+                                     int64_t workspace_bytes, void *stream);
+int lbvh_query_batched_boxes_count(const lbvh_batch *batch, const float *lohi,
+                                   const int64_t *qseg_off, int64_t m,
+                                   int64_t *offsets, void *workspace,
+                                   int64_t workspace_bytes, void *stream);
+int lbvh_query_batched_spheres_fill(const lbvh_batch *batch, const float *xyzr,
+                                    const int64_t *qseg_off, int64_t m,
+                                    const int64_t *offsets, int32_t *indices,
+                                    void *stream);
+int lbvh_query_batched_boxes_fill(const lbvh_batch *batch, const float *lohi,
+                                  const int64_t *qseg_off, int64_t m,
+                                  const int64_t *offsets, int32_t *indices,
+                                  void *stream);
+
 /* ------------------------------------------------------------ utilities */
 
 /* Human-readable name of a status code (static string). */
@@ -203,7 +280,8 @@ int64_t lbvh_tune(const char *name, int64_t value);
  * named `kernel`, the summed duration in milliseconds and the number of
  * launches since the last reset.  Names: "bounds", "bounds_final",
  * "morton", "sort_pass", "bottomup" (level 0 of the bottom-up pass),
- * "bottomup_up" (its upper levels), "query_split",
+ * "bottomup_up" (its upper levels), "batch_prep" (batched plan and
+ * per-scene codes), "query_split",
  * "query_count", "query_fill", "scan" (scans and offset bookkeeping).
  * Returns LBVH_EINVAL for an unknown name. */
 int lbvh_profile_enable(int32_t on);

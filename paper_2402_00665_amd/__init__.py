@@ -44,6 +44,13 @@ class lbvh_tree(C.Structure):
                 ("nodes", C.c_void_p), ("codes", C.c_void_p), ("leaf_perm", C.c_void_p)]
 
 
+class lbvh_batch(C.Structure):
+    _fields_ = [("num_scenes", C.c_int32), ("code_bits", C.c_int32), ("kind", C.c_int32),
+                ("reserved", C.c_int32), ("total_n", C.c_int64), ("max_scene", C.c_int64),
+                ("seg_off", C.c_void_p), ("nodes", C.c_void_p), ("codes", C.c_void_p),
+                ("leaf_perm", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -65,7 +72,16 @@ def lib() -> C.CDLL:
         L = C.CDLL(LIB_PATH)
         P, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
         T = C.POINTER(lbvh_tree)
+        Bt = C.POINTER(lbvh_batch)
         sig = {
+            "lbvh_build_batched_workspace_bytes": (i64, [i64, i32, i64, i32, i32]),
+            "lbvh_build_batched": (C.c_int, [i32, P, Bt, P, i64, P]),
+            "lbvh_build_batched_check": (C.c_int, [P, Bt, P]),
+            "lbvh_query_batched_workspace_bytes": (i64, [i64]),
+            "lbvh_query_batched_spheres_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
+            "lbvh_query_batched_boxes_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
+            "lbvh_query_batched_spheres_fill": (C.c_int, [Bt, P, P, i64, P, P, P]),
+            "lbvh_query_batched_boxes_fill": (C.c_int, [Bt, P, P, i64, P, P, P]),
             "lbvh_build_workspace_bytes": (i64, [i64, i32, i32]),
             "lbvh_build": (C.c_int, [i32, P, i64, i32, T, P, i64, P]),
             "lbvh_build_points": (C.c_int, [P, i64, i32, T, P, i64, P]),
@@ -142,6 +158,42 @@ def lbvh_query_boxes_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> 
 
 def lbvh_tune(name: str, value: int = -1) -> int:
     return lib().lbvh_tune(name.encode(), value)
+
+
+def lbvh_build_batched_workspace_bytes(total_n, num_scenes, max_scene, code_bits, kind) -> int:
+    return lib().lbvh_build_batched_workspace_bytes(total_n, num_scenes, max_scene, code_bits, kind)
+
+
+def lbvh_build_batched(kind, prims_ptr, batch: lbvh_batch, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_build_batched(kind, prims_ptr, C.byref(batch), ws_ptr, ws_bytes, stream)
+
+
+def lbvh_build_batched_check(ws_ptr, batch: lbvh_batch, stream) -> int:
+    return lib().lbvh_build_batched_check(ws_ptr, C.byref(batch), stream)
+
+
+def lbvh_query_batched_workspace_bytes(m) -> int:
+    return lib().lbvh_query_batched_workspace_bytes(m)
+
+
+def lbvh_query_batched_spheres_count(batch, q_ptr, qseg_ptr, m, off_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_batched_spheres_count(C.byref(batch), q_ptr, qseg_ptr, m, off_ptr, ws_ptr,
+                                                 ws_bytes, stream)
+
+
+def lbvh_query_batched_boxes_count(batch, q_ptr, qseg_ptr, m, off_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_batched_boxes_count(C.byref(batch), q_ptr, qseg_ptr, m, off_ptr, ws_ptr,
+                                               ws_bytes, stream)
+
+
+def lbvh_query_batched_spheres_fill(batch, q_ptr, qseg_ptr, m, off_ptr, idx_ptr, stream) -> int:
+    return lib().lbvh_query_batched_spheres_fill(C.byref(batch), q_ptr, qseg_ptr, m, off_ptr, idx_ptr,
+                                                stream)
+
+
+def lbvh_query_batched_boxes_fill(batch, q_ptr, qseg_ptr, m, off_ptr, idx_ptr, stream) -> int:
+    return lib().lbvh_query_batched_boxes_fill(C.byref(batch), q_ptr, qseg_ptr, m, off_ptr, idx_ptr,
+                                              stream)
 
 
 def lbvh_profile_enable(on: bool) -> int:
@@ -318,4 +370,94 @@ def query(tree: Tree, queries, qkind: int, workspace: Workspace | None = None, s
     # at least one element so the device pointer is never null
     buf = torch.empty(max(total, 1), dtype=torch.int32, device=queries.device)
     query_fill(tree, queries, qkind, buf, workspace, stream=stream)
+    return offsets, buf[:total]
+
+
+# ------------------------------------------------------------- batched
+
+@dataclass
+class Batch:
+    """Trees of many scenes built together.  Scene s's 2n_s-1 node records
+    start at record 2*seg_off[s] of ``nodes`` (int32 [2N, 8]); ``codes`` and
+    ``leaf_perm`` hold its sorted codes and local primitive ids at
+    [seg_off[s], seg_off[s+1])."""
+    num_scenes: int
+    total_n: int
+    code_bits: int
+    kind: int
+    max_scene: int
+    seg_off: object
+    nodes: object
+    codes: object
+    leaf_perm: object
+    desc: lbvh_batch
+    workspace: object = None
+
+    def scene_nodes(self, s: int, seg_off_host):
+        a, b = int(seg_off_host[s]), int(seg_off_host[s + 1])
+        return self.nodes[2 * a: 2 * a + max(2 * (b - a) - 1, 0)]
+
+
+def alloc_batch(seg_off, code_bits: int, max_scene: int, device="cuda") -> Batch:
+    """seg_off: int64 CUDA tensor [S+1]."""
+    torch = _torch()
+    S = int(seg_off.numel()) - 1
+    N = int(seg_off[-1].item()) if S >= 0 else 0
+    nodes = torch.empty((max(2 * N, 1), 8), dtype=torch.int32, device=device)
+    codes = torch.empty(max(N, 1), dtype=torch.int32 if code_bits == 30 else torch.int64, device=device)
+    perm = torch.empty(max(N, 1), dtype=torch.int32, device=device)
+    desc = lbvh_batch(S, code_bits, 0, 0, N, max_scene, seg_off.data_ptr(), nodes.data_ptr(),
+                      codes.data_ptr(), perm.data_ptr())
+    return Batch(S, N, code_bits, 0, max_scene, seg_off, nodes, codes, perm, desc)
+
+
+def build_batched(prims, seg_off, code_bits: int, max_scene: int, kind: int | None = None,
+                  workspace: Workspace | None = None, batch: Batch | None = None, stream=None) -> Batch:
+    """Build the trees of all scenes; prims float32 CUDA [N,3] or [N,6],
+    seg_off int64 CUDA [S+1]; max_scene >= every scene size (host value)."""
+    torch = _torch()
+    if kind is None:
+        kind = LBVH_POINTS if prims.shape[1] == 3 else LBVH_BOXES
+    prims = _dev_f32(prims, 3 if kind == LBVH_POINTS else 6, "prims")
+    if not (seg_off.is_cuda and seg_off.dtype == torch.int64 and seg_off.is_contiguous()):
+        raise TypeError("seg_off must be a contiguous int64 CUDA tensor")
+    if batch is None:
+        batch = alloc_batch(seg_off, code_bits, max_scene, prims.device)
+    ws_bytes = lbvh_build_batched_workspace_bytes(batch.total_n, batch.num_scenes, max_scene,
+                                                  code_bits, kind)
+    _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_build_batched_workspace_bytes")
+    ws = (workspace or Workspace(prims.device)).get(ws_bytes)
+    _check(lbvh_build_batched(kind, prims.data_ptr() if batch.total_n else None, batch.desc,
+                              ws.data_ptr(), ws.numel(), _stream(stream)), "lbvh_build_batched")
+    batch.kind = kind
+    batch.workspace = ws
+    return batch
+
+
+def check_batched(batch: Batch, stream=None):
+    if batch.workspace is None:
+        return
+    _check(lbvh_build_batched_check(batch.workspace.data_ptr(), batch.desc, _stream(stream)),
+           "lbvh_build_batched_check")
+
+
+def query_batched(batch: Batch, queries, qseg_off, qkind: int, workspace: Workspace | None = None,
+                  stream=None):
+    """Count, read the total, fill.  Returns (offsets int64 [m+1], indices
+    int32 [total]) with scene-local primitive ids."""
+    torch = _torch()
+    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    m = int(q.shape[0])
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
+    ws_bytes = lbvh_query_batched_workspace_bytes(m)
+    _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_query_batched_workspace_bytes")
+    ws = (workspace or Workspace(q.device)).get(ws_bytes)
+    cnt = lbvh_query_batched_spheres_count if qkind == SPHERES else lbvh_query_batched_boxes_count
+    _check(cnt(batch.desc, q.data_ptr() if m else None, qseg_off.data_ptr(), m, offsets.data_ptr(),
+               ws.data_ptr(), ws.numel(), _stream(stream)), "batched query count")
+    total = int(offsets[-1].item())
+    buf = torch.empty(max(total, 1), dtype=torch.int32, device=q.device)
+    fill = lbvh_query_batched_spheres_fill if qkind == SPHERES else lbvh_query_batched_boxes_fill
+    _check(fill(batch.desc, q.data_ptr() if m else None, qseg_off.data_ptr(), m, offsets.data_ptr(),
+                buf.data_ptr(), _stream(stream)), "batched query fill")
     return offsets, buf[:total]

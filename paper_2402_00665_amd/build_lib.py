@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbvh.so")
-SOURCES = ["build_kernels.hip", "query_kernels.hip", "lbvh_api.hip"]
+SOURCES = ["build_kernels.hip", "batch_kernels.hip", "query_kernels.hip", "lbvh_api.hip"]
 
 ARCH = os.environ.get("LBVH_OFFLOAD_ARCH", "gfx950")
 

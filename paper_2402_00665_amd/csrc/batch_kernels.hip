@@ -1,0 +1,320 @@
+// Batched construction and queries: S independent scenes (each with its
+// own scene box, Morton codes, sort and tree) built by one launch sequence
+// that covers all of them, instead of one launch sequence per scene.
+//
+//   k_batch_plan     one block: per-scene radix tiles and bottom-up blocks
+//                    per level (exclusive scans over the scenes), counters
+//   k_batch_morton   one block per scene: scene box and scale, Morton codes,
+//                    digit histograms of scenes that span several tiles
+//   k_onesweep       segmented radix passes (tiles never cross scenes)
+//   k_bottomup_*     Alg. 4 in levels of blocks, blocks never cross scenes
+//   k_batch_walk     Alg. 1 per query on the tree of the query's scene
+//
+// Every scene's tree is exactly the tree a single build of that scene gives
+// (local leaf, node and primitive ids), stored at record 2*seg_off[s].
+#pragma clang fp contract(off)
+
+#include "bottomup.hpp"
+#include "device_common.hpp"
+#include "query_common.hpp"
+#include "radix_sort.hpp"
+
+namespace lbvh {
+namespace {
+
+constexpr int kPlanThreads = 1024;
+constexpr int kSceneThreads = 512;
+
+__device__ __forceinline__ int64_t scene_size(const int64_t *seg_off, int s)
+{
+    return seg_off[s + 1] - seg_off[s];
+}
+
+// Exclusive scans over scenes of: radix tiles per scene, and bottom-up
+// blocks per scene at levels 0..levels (a scene needs a level-L block only
+// while its level-(L-1) blocks are more than one).  Also clears the control
+// words (tile counters, error flag).
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t *__restrict__ seg_off,
+                                                             int S, int levels,
+                                                             int32_t *__restrict__ tile_off,
+                                                             int32_t *__restrict__ blk_off,
+                                                             uint32_t *__restrict__ ctrl)
+{
+    __shared__ uint32_t sh[kPlanThreads / 64];
+    __shared__ uint32_t s_total;
+    for (int w = threadIdx.x; w < kCtrlWords; w += kPlanThreads) ctrl[w] = 0u;
+    uint32_t carry_t = 0;
+    uint32_t carry_b[kMaxBatchLevels + 1] = {};
+    for (int c = 0; c < S; c += kPlanThreads) {
+        const int s = c + threadIdx.x;
+        // exclusive scan of v over the scenes, continued across chunks
+        auto scan_into = [&](uint32_t v, int32_t *dst, uint32_t &carry) {
+            const uint32_t e = block_excl_scan<kPlanThreads>(v, sh);
+            if (s < S) dst[s] = (int32_t)(carry + e);
+            if (threadIdx.x == kPlanThreads - 1) s_total = e + v;
+            __syncthreads();
+            carry += s_total;
+            __syncthreads();
+        };
+        const int64_t ns = s < S ? scene_size(seg_off, s) : 0;
+        scan_into((uint32_t)((ns + kBatchTile - 1) / kBatchTile), tile_off, carry_t);
+        uint32_t blk = (uint32_t)((ns + kChunk - 1) / kChunk);
+        for (int L = 0; L <= levels; ++L) {
+            if (L > 0) blk = blk > 1 ? (blk + kFanout - 1) / kFanout : 0u;
+            scan_into(blk, blk_off + L * (S + 1), carry_b[L]);
+        }
+    }
+    if (threadIdx.x == 0) {
+        tile_off[S] = (int32_t)carry_t;
+        for (int L = 0; L <= levels; ++L) blk_off[L * (S + 1) + S] = (int32_t)carry_b[L];
+    }
+}
+
+// One block per scene: scene box (min/max), scale 2^b / extent, Morton codes
+// (written in place of the scene's primitives' order), digit histograms of
+// every radix pass for scenes spanning several tiles, and the first pass's
+// look-back status of those tiles cleared.
+template <int KIND, typename K>
+__global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
+    const float *__restrict__ prims, const int64_t *__restrict__ seg_off,
+    const int32_t *__restrict__ tile_off, int bits_per_axis, float4 *__restrict__ scene_box,
+    K *__restrict__ codes, uint32_t *__restrict__ hist, int passes, uint32_t *__restrict__ status0)
+{
+    __shared__ float sh[(kSceneThreads / 64) * 6];
+    __shared__ float4 s_box[3];
+    __shared__ uint32_t lh[8 * kRadix];
+    using P = Prims<KIND>;
+    const int s = blockIdx.x;
+    const int64_t b0 = seg_off[s];
+    const int64_t ns = seg_off[s + 1] - b0;
+    if (ns == 0) return;
+    const bool multi = tile_off[s + 1] - tile_off[s] > 1;
+    if (multi)
+        for (int j = threadIdx.x; j < passes * kRadix; j += kSceneThreads) lh[j] = 0u;
+
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = threadIdx.x; i < ns; i += kSceneThreads) {
+        float lo[3], hi[3];
+        P::one(prims, b0 + i, lo, hi);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { v[a] = fminf(v[a], lo[a]); v[3 + a] = fmaxf(v[3 + a], hi[a]); }
+    }
+    block_minmax6<kSceneThreads>(v, sh);
+    if (threadIdx.x == 0) {
+        const float two_b = (float)(1u << bits_per_axis);
+        float sc[3];
+        for (int a = 0; a < 3; ++a) {
+            const float ext = v[3 + a] - v[a];
+            sc[a] = ext > 0.0f ? __fdiv_rn(two_b, ext) : 0.0f;
+        }
+        s_box[0] = make_float4(v[0], v[1], v[2], 0.0f);
+        s_box[1] = make_float4(v[3], v[4], v[5], 0.0f);
+        s_box[2] = make_float4(sc[0], sc[1], sc[2], 0.0f);
+        scene_box[3 * s + 0] = s_box[0];
+        scene_box[3 * s + 1] = s_box[1];
+        scene_box[3 * s + 2] = s_box[2];
+    }
+    __syncthreads();
+    const float4 slo = s_box[0], sc = s_box[2];
+    for (int64_t i = threadIdx.x; i < ns; i += kSceneThreads) {
+        float lo[3], hi[3];
+        P::one(prims, b0 + i, lo, hi);
+        const K c = code_of<KIND, K>(lo, hi, slo, sc);
+        codes[b0 + i] = c;
+        if (multi)
+            for (int p = 0; p < passes; ++p)
+                atomicAdd(&lh[p * kRadix + (uint32_t)((c >> (p * kRadixBits)) & (kRadix - 1))], 1u);
+    }
+    if (!multi) return;
+    __syncthreads();
+    uint32_t *hs = hist + (int64_t)s * passes * kRadix;
+    for (int j = threadIdx.x; j < passes * kRadix; j += kSceneThreads) hs[j] = lh[j];
+    const int64_t w0 = (int64_t)tile_off[s] * kRadix, w1 = (int64_t)tile_off[s + 1] * kRadix;
+    for (int64_t w = w0 + threadIdx.x; w < w1; w += kSceneThreads) status0[w] = 0u;
+}
+
+// Alg. 1 for query j on the tree of its scene (no splitting: batched
+// workloads have many scenes and light queries).  Containment reports whole
+// leaf ranges from leaf_perm, as in the single-tree leaf walk.
+template <class Q, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_batch_walk(const float4 *__restrict__ nodes_all,
+                                                       const int32_t *__restrict__ perm_all,
+                                                       const int64_t *__restrict__ seg_off,
+                                                       const int64_t *__restrict__ qseg_off, int S,
+                                                       const float *__restrict__ queries, int64_t m,
+                                                       int32_t *__restrict__ counts,
+                                                       const int64_t *__restrict__ offsets,
+                                                       int32_t *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= m) return;
+    int lo = 0, hi = S - 1;   // scene of query j: largest s with qseg_off[s] <= j
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (qseg_off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t b0 = seg_off[lo];
+    const int n = (int)(seg_off[lo + 1] - b0);
+    int64_t pos = FILL ? offsets[j] : 0;
+    int cnt = 0;
+    if (n > 0) {
+        Tree tr{nodes_all + 4 * b0, perm_all + b0, n};
+        Q q;
+        q.load(queries, (int)j);
+        const int leaf0 = n - 1;
+        int v = 0, i = 0;
+        int64_t budget = 2 * (int64_t)n;
+        while (v != -1 && --budget >= 0) {
+            float4 a, b;
+            tr.load(v, a, b);
+            const int left = __float_as_int(a.w);
+            const int rope = __float_as_int(b.w);
+            const int jr = tr.right_bound(b);
+            if (q.test(a, b)) {
+                if (v >= leaf0) {
+                    if (FILL) out[pos++] = left;
+                    else ++cnt;
+                } else if (q.contains(a, b)) {
+                    if (FILL)
+                        for (int k = i; k <= jr; ++k) out[pos++] = tr.perm[k];
+                    else
+                        cnt += jr - i + 1;
+                } else {
+                    v = left;
+                    continue;
+                }
+            }
+            v = rope;
+            i = jr + 1;
+        }
+    }
+    if (!FILL) counts[j] = cnt;
+}
+
+template <int KIND, typename K>
+hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t N, int levels,
+                     int code_bits, lbvh_node *nodes_, K *codes, int32_t *leaf_perm, char *ws,
+                     const BatchLayout &L, hipStream_t s)
+{
+    uint32_t *ctrl = reinterpret_cast<uint32_t *>(ws + L.ctrl);
+    float4 *scene_box = reinterpret_cast<float4 *>(ws + L.scene_box);
+    int32_t *tile_off = reinterpret_cast<int32_t *>(ws + L.tile_off);
+    int32_t *blk_off = reinterpret_cast<int32_t *>(ws + L.blk_off);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *status[2] = {reinterpret_cast<uint32_t *>(ws + L.status[0]),
+                           reinterpret_cast<uint32_t *>(ws + L.status[1])};
+    K *keys_alt = reinterpret_cast<K *>(ws + L.keys_alt);
+    int32_t *vals[2] = {reinterpret_cast<int32_t *>(ws + L.vals[0]),
+                        reinterpret_cast<int32_t *>(ws + L.vals[1])};
+    int32_t *store = reinterpret_cast<int32_t *>(ws + L.store);
+    int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
+    float4 *nodes = reinterpret_cast<float4 *>(nodes_);
+    const int passes = L.passes;
+
+    prof_begin(K_BATCH_PREP, s);
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile_off,
+                       blk_off, ctrl);
+    hipLaunchKernelGGL((k_batch_morton<KIND, K>), dim3(S), dim3(kSceneThreads), 0, s, prims, seg_off,
+                       tile_off, code_bits / 3, scene_box, codes, hist, passes, status[0]);
+    prof_end(K_BATCH_PREP, s);
+
+    const SortSegs segs{seg_off, tile_off, S, passes * kRadix};
+    for (int p = 0; p < passes; ++p) {
+        const K *kin = (p & 1) ? keys_alt : codes;
+        K *kout = (p & 1) ? codes : keys_alt;
+        const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
+        int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
+        uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
+        prof_begin(K_SORT, s);
+        hipLaunchKernelGGL((k_onesweep<K, kBatchSortThreads, kBatchSortItems>),
+                           dim3((unsigned)L.tiles_max), dim3(kBatchSortThreads), 0, s, kin, kout, vin,
+                           vout, N, segs, p * kRadixBits, hist + p * kRadix, status[p & 1], st_next,
+                           ctrl + kCtrlTileCounter + p, ctrl + kCtrlError);
+        prof_end(K_SORT, s);
+    }
+
+    prof_begin(K_BOTTOMUP, s);
+    BatchLevel bl{seg_off, blk_off, nullptr, S, levels == 0};
+    hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3((unsigned)L.blocks_max[0]), dim3(kBU0Threads),
+                       0, s, codes, leaf_perm, prims, (int)N, store, nodes, pend[0], bl,
+                       ctrl + kCtrlError);
+    prof_end(K_BOTTOMUP, s);
+    int64_t span = kChunk;
+    for (int lv = 1; lv <= levels; ++lv) {
+        const int64_t next = span * kFanout;
+        BatchLevel up{seg_off, blk_off + lv * (S + 1), blk_off + (lv - 1) * (S + 1), S, lv == levels};
+        prof_begin(K_BOTTOMUP_UP, s);
+        hipLaunchKernelGGL((k_bottomup_up<K>), dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads), 0, s,
+                           codes, (int)N, span, next, store, nodes, pend[(lv - 1) & 1], pend[lv & 1],
+                           up, ctrl + kCtrlError);
+        prof_end(K_BOTTOMUP_UP, s);
+        span = next;
+    }
+    return hipGetLastError();
+}
+
+template <class Q>
+hipError_t run_batch_query(const lbvh_batch *b, const float *q, const int64_t *qseg_off, int64_t m,
+                           int64_t *offsets, int32_t *indices, bool fill, char *ws,
+                           const QueryLayout &L, hipStream_t s)
+{
+    const float4 *nodes = reinterpret_cast<const float4 *>(b->nodes);
+    const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
+    if (fill) {
+        prof_begin(K_QFILL, s);
+        hipLaunchKernelGGL((k_batch_walk<Q, true>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
+                           b->seg_off, qseg_off, b->num_scenes, q, m, nullptr, offsets, indices);
+        prof_end(K_QFILL, s);
+        return hipGetLastError();
+    }
+    int32_t *counts = reinterpret_cast<int32_t *>(ws + L.cnt1);
+    int64_t *partials = reinterpret_cast<int64_t *>(ws + L.partials);
+    prof_begin(K_QCOUNT, s);
+    hipLaunchKernelGGL((k_batch_walk<Q, false>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
+                       b->seg_off, qseg_off, b->num_scenes, q, m, counts, nullptr, nullptr);
+    prof_end(K_QCOUNT, s);
+    prof_begin(K_SCAN, s);
+    scan(counts, m, nullptr, partials, offsets, s);
+    prof_end(K_SCAN, s);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_batched(int kind, const float *prims, const lbvh_batch *b, int levels,
+                                char *ws, const BatchLayout &L, hipStream_t s)
+{
+    const int S = b->num_scenes;
+    const int64_t N = b->total_n;
+    if (b->code_bits == 30) {
+        uint32_t *codes = static_cast<uint32_t *>(b->codes);
+        if (kind == LBVH_POINTS)
+            return run_batch<LBVH_POINTS, uint32_t>(prims, b->seg_off, S, N, levels, 30, b->nodes,
+                                                    codes, b->leaf_perm, ws, L, s);
+        return run_batch<LBVH_BOXES, uint32_t>(prims, b->seg_off, S, N, levels, 30, b->nodes, codes,
+                                               b->leaf_perm, ws, L, s);
+    }
+    uint64_t *codes = static_cast<uint64_t *>(b->codes);
+    if (kind == LBVH_POINTS)
+        return run_batch<LBVH_POINTS, uint64_t>(prims, b->seg_off, S, N, levels, 63, b->nodes, codes,
+                                                b->leaf_perm, ws, L, s);
+    return run_batch<LBVH_BOXES, uint64_t>(prims, b->seg_off, S, N, levels, 63, b->nodes, codes,
+                                           b->leaf_perm, ws, L, s);
+}
+
+hipError_t launch_query_batched(int qkind, const lbvh_batch *b, const float *q,
+                                const int64_t *qseg_off, int64_t m, int64_t *offsets,
+                                int32_t *indices, bool fill, char *ws, const QueryLayout &L,
+                                hipStream_t s)
+{
+    if (m == 0) {
+        if (fill) return hipSuccess;
+        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(kBlock), 0, s, offsets, (int64_t)1);
+        return hipGetLastError();
+    }
+    return qkind == 0 ? run_batch_query<Sphere>(b, q, qseg_off, m, offsets, indices, fill, ws, L, s)
+                      : run_batch_query<QBox>(b, q, qseg_off, m, offsets, indices, fill, ws, L, s);
+}
+
+}  // namespace lbvh

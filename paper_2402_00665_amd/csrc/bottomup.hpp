@@ -1,0 +1,285 @@
+// Alg. 4, the bottom-up pass, run in levels of blocks; for one tree or for
+// many independent trees (batched scenes) at once.
+#pragma once
+#pragma clang fp contract(off)
+
+#include "device_common.hpp"
+
+namespace lbvh {
+namespace {
+
+// Alg. 4 runs in levels of blocks so that every compare-and-swap on `store`
+// has all of its possible participants inside one workgroup and needs only
+// workgroup-scope ordering (an agent-scope acquire-release CAS per tree
+// level would write back and invalidate the XCD's L2 every time):
+//   level 0   block b takes the kChunk leaves [A, B) = [b*kChunk, ...):
+//             leaf records, then the climb with `store` and every box of
+//             the chunk in LDS;
+//   level L   block b takes the kFanout level-(L-1) blocks under its span
+//             [A, B) and resumes their handed-over threads, with `store` and
+//             the node records in global memory.
+// A block owns the boundaries strictly inside [A, B).  A thread whose next
+// parent is split at A-1 or B-1 stops and hands its state (node, range) to
+// the level above; that parent's other child cannot be finished inside this
+// block.  Parents split inside [A, B) meet their two children either inside
+// the block or in a later launch, and launches on one stream see all writes
+// of earlier ones.  The top level is one block owning [0, n), so the climb
+// always reaches the root.  Every internal node is still written once, by
+// the second thread to arrive, exactly as in Alg. 4.
+
+//
+// Batched trees: every scene is its own problem (local leaf and node ids);
+// its leaves sit at seg_off[s] in the sorted arrays and its 2n_s-1 node
+// records at record 2*seg_off[s].  Level-L blocks of all scenes share one
+// launch; blk_off[s] is the first level-L block of scene s.
+
+struct BatchLevel {
+    const int64_t *seg_off;    // [S+1] scene starts (leaves); nullptr: one tree
+    const int32_t *blk_off;    // [S+1] first block of each scene at this level
+    const int32_t *child_off;  // [S+1] first block of each scene one level down
+    int S;
+    int last;                  // top level: no climb may stop at a boundary
+};
+
+__device__ __forceinline__ int scene_of(const int32_t *off, int S, int b)
+{
+    int lo = 0, hi = S - 1;   // largest s with off[s] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int KIND, typename K>
+__global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict__ codes_all,
+                                                             const int32_t *__restrict__ perm_all,
+                                                             const float *__restrict__ prims_all,
+                                                             int n_all, int32_t *__restrict__ store_all,
+                                                             float4 *__restrict__ nodes_all,
+                                                             int4 *__restrict__ pend, BatchLevel bl,
+                                                             uint32_t *err)
+{
+    __shared__ K s_codes[kChunk + 3];        // codes[A-1 .. B+1]
+    __shared__ int32_t s_store[kChunk];      // store[A .. B-1]
+    __shared__ float s_box[6][2 * kChunk];   // internal A.. then leaves A..
+    __shared__ int4 s_pend[2];
+
+    // this block's chunk: tree (codes, perm, ... of one scene), leaves [A, B)
+    int64_t b0 = 0;
+    int n = n_all, c = blockIdx.x;
+    if (bl.seg_off) {
+        if ((int)blockIdx.x >= bl.blk_off[bl.S]) return;   // grid is an upper bound
+        const int s = scene_of(bl.blk_off, bl.S, blockIdx.x);
+        b0 = bl.seg_off[s];
+        n = (int)(bl.seg_off[s + 1] - b0);
+        c = blockIdx.x - bl.blk_off[s];
+    }
+    const K *codes = codes_all + b0;
+    const int32_t *perm = perm_all + b0;
+    const float *prims = prims_all + b0 * (KIND == LBVH_POINTS ? 3 : 6);
+    int32_t *store = store_all + b0;
+    float4 *nodes = nodes_all + 4 * b0;   // record 2*b0, two float4 per record
+    const int A = c * kChunk;
+    const int B = min(A + kChunk, n);
+    const int cn = B - A;
+    const int leaf0 = n - 1;
+
+    for (int t = threadIdx.x; t < cn + 3; t += kBU0Threads) {
+        const int g = A - 1 + t;
+        s_codes[t] = (g >= 0 && g < n) ? codes[g] : (K)0;
+    }
+    for (int t = threadIdx.x; t < kChunk; t += kBU0Threads) s_store[t] = -1;
+    if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
+    __syncthreads();
+
+    // delta*(g) for g in [A-1, B]
+    auto delta = [&](int g) -> int {
+        if (g < 0 || g >= n - 1) return 255;
+        const K x = s_codes[g - A + 1] ^ s_codes[g - A + 2];
+        if (x) return 64 + highest_bit(x);
+        return highest_bit((uint32_t)(g ^ (g + 1)));
+    };
+
+    // leaves: box, primitive id, rope (Alg. 2 on the range [i, i])
+    for (int i = A + threadIdx.x; i < B; i += kBU0Threads) {
+        const int prim = perm[i];
+        float lo[3], hi[3];
+        Prims<KIND>::one(prims, prim, lo, hi);
+        const int dr = delta(i);
+        const int rope = (i == n - 1) ? -1 : (dr < delta(i + 1) ? leaf0 + i + 1 : i + 1);
+        store_node(nodes, leaf0 + i, lo, prim, hi, rope);
+        const int sl = kChunk + (i - A);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { s_box[a][sl] = lo[a]; s_box[3 + a][sl] = hi[a]; }
+    }
+    __syncthreads();
+
+    if (n > 1) {
+        for (int i = A + threadIdx.x; i < B; i += kBU0Threads) {
+            int rl = i, rr = i, cur = leaf0 + i;
+            int dl = delta(i - 1), dr = delta(i);
+            float lo[3], hi[3];
+            const int sl = kChunk + (i - A);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { lo[a] = s_box[a][sl]; hi[a] = s_box[3 + a][sl]; }
+            for (int level = 0;; ++level) {
+                if (level == kMaxDepth) {
+                    __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                int p, sib;
+                if (dr < dl) {                 // left child of its parent
+                    p = rr;
+                    if (p == B - 1) { s_pend[1] = make_int4(cur, rl, rr, 0); break; }
+                    int other = -1;
+                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, rl,
+                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;                 // first to arrive
+                    rr = other;
+                    dr = delta(rr);
+                    sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
+                } else {                       // right child of its parent
+                    p = rl - 1;
+                    if (p == A - 1) { s_pend[0] = make_int4(cur, rl, rr, 0); break; }
+                    int other = -1;
+                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, rr,
+                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;
+                    rl = other;
+                    dl = delta(rl - 1);
+                    sib = (rl == p) ? leaf0 + p : p;
+                }
+                const int ss = sib >= leaf0 ? kChunk + (sib - leaf0 - A) : sib - A;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = fminf(lo[a], s_box[a][ss]);
+                    hi[a] = fmaxf(hi[a], s_box[3 + a][ss]);
+                }
+                const int q = dr < dl ? rr : rl;   // Karras index of the parent
+                const int left = (rl == p) ? leaf0 + p : p;
+                int qrope;
+                if (rr == n - 1) qrope = -1;
+                else qrope = dr < delta(rr + 1) ? leaf0 + rr + 1 : rr + 1;
+                store_node(nodes, q, lo, left, hi, qrope);
+                const int qs = q - A;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
+                cur = q;
+                if (q == 0) break;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cn; t += kBU0Threads) store[A + t] = s_store[t];
+    if (threadIdx.x < 2) {
+        const int4 st = s_pend[threadIdx.x];
+        if (bl.last && st.x >= 0)   // a climb stopped below the root of its tree
+            __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pend[2 * blockIdx.x + threadIdx.x] = st;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict__ codes_all, int n_all,
+                                                            int64_t child_span, int64_t span,
+                                                            int32_t *store_all, float4 *nodes_all,
+                                                            const int4 *__restrict__ pend_in,
+                                                            int4 *__restrict__ pend_out, BatchLevel bl,
+                                                            uint32_t *err)
+{
+    __shared__ int4 s_pend[2];
+    // this block's span [A, B) of one tree and the handed-over slots of its
+    // child blocks
+    int64_t b0 = 0, slot_lo, slot_hi, A, B;
+    int n = n_all;
+    if (bl.seg_off) {
+        if ((int)blockIdx.x >= bl.blk_off[bl.S]) return;
+        const int s = scene_of(bl.blk_off, bl.S, blockIdx.x);
+        b0 = bl.seg_off[s];
+        n = (int)(bl.seg_off[s + 1] - b0);
+        const int g = blockIdx.x - bl.blk_off[s];
+        const int nchild = bl.child_off[s + 1] - bl.child_off[s];
+        const int c0 = g * kFanout, c1 = min(c0 + kFanout, nchild);
+        A = (int64_t)c0 * child_span;
+        B = min(A + span, (int64_t)n);
+        slot_lo = 2 * ((int64_t)bl.child_off[s] + c0);
+        slot_hi = 2 * ((int64_t)bl.child_off[s] + c1);
+    } else {
+        A = (int64_t)blockIdx.x * span;
+        B = A + span < n ? A + span : n;
+        slot_lo = 2 * (A / child_span);
+        slot_hi = 2 * ((B + child_span - 1) / child_span);
+    }
+    const K *codes = codes_all + b0;
+    int32_t *store = store_all + b0;
+    float4 *nodes = nodes_all + 4 * b0;
+    const int leaf0 = n - 1;
+    if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
+    __syncthreads();
+
+    for (int64_t slot = slot_lo + threadIdx.x; slot < slot_hi; slot += kBUThreads) {
+        const int4 P = pend_in[slot];
+        if (P.x < 0) continue;
+        int cur = P.x, rl = P.y, rr = P.z;
+        const float4 *own = nodes + 2 * (int64_t)cur;
+        const float4 o0 = own[0], o1 = own[1];
+        float lo[3] = {o0.x, o0.y, o0.z}, hi[3] = {o1.x, o1.y, o1.z};
+        int dl = delta_rank(codes, rl - 1, n), dr = delta_rank(codes, rr, n);
+        for (int level = 0;; ++level) {
+            if (level == kMaxDepth) {
+                __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            int p, sib;
+            if (dr < dl) {
+                p = rr;
+                if (p == B - 1) { s_pend[1] = make_int4(cur, rl, rr, 0); break; }
+                int other = -1;
+                if (__hip_atomic_compare_exchange_strong(&store[p], &other, rl, __ATOMIC_ACQ_REL,
+                                                         __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                rr = other;
+                dr = delta_rank(codes, rr, n);
+                sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
+            } else {
+                p = rl - 1;
+                if (p == A - 1) { s_pend[0] = make_int4(cur, rl, rr, 0); break; }
+                int other = -1;
+                if (__hip_atomic_compare_exchange_strong(&store[p], &other, rr, __ATOMIC_ACQ_REL,
+                                                         __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
+                    break;
+                rl = other;
+                dl = delta_rank(codes, rl - 1, n);
+                sib = (rl == p) ? leaf0 + p : p;
+            }
+            const float4 *sp = nodes + 2 * (int64_t)sib;
+            const float4 s0 = sp[0], s1 = sp[1];
+            lo[0] = fminf(lo[0], s0.x); lo[1] = fminf(lo[1], s0.y); lo[2] = fminf(lo[2], s0.z);
+            hi[0] = fmaxf(hi[0], s1.x); hi[1] = fmaxf(hi[1], s1.y); hi[2] = fmaxf(hi[2], s1.z);
+            const int q = dr < dl ? rr : rl;
+            const int left = (rl == p) ? leaf0 + p : p;
+            int qrope;
+            if (rr == n - 1) qrope = -1;
+            else qrope = dr < delta_rank(codes, rr + 1, n) ? leaf0 + rr + 1 : rr + 1;
+            store_node(nodes, q, lo, left, hi, qrope);
+            cur = q;
+            if (q == 0) break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int4 st = s_pend[threadIdx.x];
+        if (bl.last && st.x >= 0)
+            __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pend_out[2 * blockIdx.x + threadIdx.x] = st;
+    }
+}
+
+}  // namespace
+}  // namespace lbvh

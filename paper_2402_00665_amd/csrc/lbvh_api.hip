@@ -61,6 +61,52 @@ QueryLayout query_layout(int64_t m)
     return L;
 }
 
+QueryLayout batch_query_layout(int64_t m)
+{
+    QueryLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+    L.cnt1 = take((size_t)(m + 1) * sizeof(int32_t));
+    L.partials = take((size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+    L.total = off;
+    return L;
+}
+
+int batch_levels(int64_t max_scene)
+{
+    int levels = 0;
+    for (int64_t span = kChunk; span < max_scene; span *= kFanout) ++levels;
+    return levels;
+}
+
+BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
+{
+    BatchLayout L{};
+    const size_t kb = (size_t)key_bytes(code_bits);
+    L.passes = radix_passes(code_bits);
+    L.levels = batch_levels(max_scene);
+    L.tiles_max = (N + kBatchTile - 1) / kBatchTile + S;
+    int64_t span = kChunk;
+    for (int lv = 0; lv <= L.levels; ++lv, span *= kFanout) L.blocks_max[lv] = (N + span - 1) / span + S;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
+    L.ctrl = take(kCtrlWords * sizeof(uint32_t));
+    L.scene_box = take((size_t)S * 3 * sizeof(float4));
+    L.tile_off = take((size_t)(S + 1) * sizeof(int32_t));
+    L.blk_off = take((size_t)(L.levels + 1) * (S + 1) * sizeof(int32_t));
+    L.hist = take((size_t)S * L.passes * kRadix * sizeof(uint32_t));
+    L.status[0] = take((size_t)L.tiles_max * kRadix * sizeof(uint32_t));
+    L.status[1] = take((size_t)L.tiles_max * kRadix * sizeof(uint32_t));
+    L.keys_alt = take((size_t)N * kb);
+    L.vals[0] = take((size_t)N * sizeof(int32_t));
+    L.vals[1] = take((size_t)N * sizeof(int32_t));
+    L.store = take((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
+    L.pend[0] = take((size_t)2 * L.blocks_max[0] * 16);
+    L.pend[1] = take((size_t)2 * L.blocks_max[0] * 16);
+    L.total = off;
+    return L;
+}
+
 // ---------------------------------------------------------------- tuning
 
 namespace {
@@ -112,7 +158,8 @@ Profiler &prof()
     return p;
 }
 const char *kNames[K_NUM] = {"bounds", "bounds_final", "morton", "sort_pass", "bottomup",
-                             "query_count", "query_fill", "scan", "query_split", "bottomup_up"};
+                             "query_count", "query_fill", "scan", "query_split", "bottomup_up",
+                             "batch_prep"};
 }  // namespace
 
 void prof_begin(int id, hipStream_t s)
@@ -227,6 +274,112 @@ int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits, int32_
         e != hipSuccess)
         return hip_status(e);
     return flag ? LBVH_EDEVICE : LBVH_OK;
+}
+
+// ------------------------------------------------------------- batched
+
+static bool batch_args_ok(int64_t N, int32_t S, int64_t max_scene, int32_t code_bits, int32_t kind)
+{
+    return N >= 0 && N <= LBVH_MAX_PRIMS && S >= 0 && max_scene >= 0 &&
+           max_scene <= LBVH_MAX_PRIMS && (code_bits == 30 || code_bits == 63) &&
+           (kind == LBVH_POINTS || kind == LBVH_BOXES);
+}
+
+int64_t lbvh_build_batched_workspace_bytes(int64_t total_n, int32_t num_scenes, int64_t max_scene,
+                                           int32_t code_bits, int32_t kind)
+{
+    if (!batch_args_ok(total_n, num_scenes, max_scene, code_bits, kind)) return LBVH_EINVAL;
+    return (int64_t)batch_layout(total_n, num_scenes, max_scene, code_bits).total;
+}
+
+int lbvh_build_batched(int32_t kind, const float *prims, lbvh_batch *b, void *workspace,
+                       int64_t workspace_bytes, void *stream)
+{
+    if (!b || !batch_args_ok(b->total_n, b->num_scenes, b->max_scene, b->code_bits, kind))
+        return LBVH_EINVAL;
+    b->kind = kind;
+    if (b->num_scenes == 0 || b->total_n == 0) return LBVH_OK;
+    if (!prims || !b->seg_off || !b->nodes || !b->codes || !b->leaf_perm || !workspace ||
+        !aligned(prims, 8) || !aligned(b->seg_off, 8) || !aligned(b->nodes, 16) ||
+        !aligned(b->codes, 16) || !aligned(b->leaf_perm, 16) || !aligned(workspace, 256))
+        return LBVH_EINVAL;
+    const BatchLayout L = batch_layout(b->total_n, b->num_scenes, b->max_scene, b->code_bits);
+    if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
+    hipError_t e = launch_build_batched(kind, prims, b, L.levels, static_cast<char *>(workspace), L,
+                                        (hipStream_t)stream);
+    return hip_status(e);
+}
+
+int lbvh_build_batched_check(const void *workspace, const lbvh_batch *b, void *stream)
+{
+    if (!b || !workspace) return LBVH_EINVAL;
+    if (hipError_t e = hipStreamSynchronize((hipStream_t)stream); e != hipSuccess) return hip_status(e);
+    if (b->num_scenes == 0 || b->total_n == 0) return LBVH_OK;
+    const BatchLayout L = batch_layout(b->total_n, b->num_scenes, b->max_scene, b->code_bits);
+    uint32_t flag = 0;
+    if (hipError_t e = hipMemcpy(&flag,
+                                 static_cast<const char *>(workspace) + L.ctrl +
+                                     kCtrlError * sizeof(uint32_t),
+                                 sizeof(flag), hipMemcpyDeviceToHost);
+        e != hipSuccess)
+        return hip_status(e);
+    return flag ? LBVH_EDEVICE : LBVH_OK;
+}
+
+int64_t lbvh_query_batched_workspace_bytes(int64_t m)
+{
+    if (m < 0 || m > INT32_MAX) return LBVH_EINVAL;
+    return (int64_t)batch_query_layout(m).total;
+}
+
+static int batched_query(int qkind, const lbvh_batch *b, const float *q, const int64_t *qseg_off,
+                         int64_t m, int64_t *offsets, int32_t *indices, bool fill, void *workspace,
+                         int64_t workspace_bytes, void *stream)
+{
+    if (!b || m < 0 || m > INT32_MAX || !offsets || !aligned(offsets, 8)) return LBVH_EINVAL;
+    if (m > 0 && (!q || !aligned(q, 16) || !qseg_off || b->num_scenes < 1 || !b->seg_off ||
+                  !b->nodes || !b->leaf_perm || !aligned(b->nodes, 16)))
+        return LBVH_EINVAL;
+    if (fill && m > 0 && !indices) return LBVH_EINVAL;
+    const QueryLayout L = batch_query_layout(m);
+    if (!fill) {
+        if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
+        if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
+    }
+    hipError_t e = launch_query_batched(qkind, b, q, qseg_off, m, offsets, indices, fill,
+                                        static_cast<char *>(workspace), L, (hipStream_t)stream);
+    return hip_status(e);
+}
+
+int lbvh_query_batched_spheres_count(const lbvh_batch *b, const float *xyzr, const int64_t *qseg_off,
+                                     int64_t m, int64_t *offsets, void *workspace,
+                                     int64_t workspace_bytes, void *stream)
+{
+    return batched_query(0, b, xyzr, qseg_off, m, offsets, nullptr, false, workspace,
+                         workspace_bytes, stream);
+}
+
+int lbvh_query_batched_boxes_count(const lbvh_batch *b, const float *lohi, const int64_t *qseg_off,
+                                   int64_t m, int64_t *offsets, void *workspace,
+                                   int64_t workspace_bytes, void *stream)
+{
+    return batched_query(1, b, lohi, qseg_off, m, offsets, nullptr, false, workspace,
+                         workspace_bytes, stream);
+}
+
+int lbvh_query_batched_spheres_fill(const lbvh_batch *b, const float *xyzr, const int64_t *qseg_off,
+                                    int64_t m, const int64_t *offsets, int32_t *indices,
+                                    void *stream)
+{
+    return batched_query(0, b, xyzr, qseg_off, m, const_cast<int64_t *>(offsets), indices, true,
+                         nullptr, 0, stream);
+}
+
+int lbvh_query_batched_boxes_fill(const lbvh_batch *b, const float *lohi, const int64_t *qseg_off,
+                                  int64_t m, const int64_t *offsets, int32_t *indices, void *stream)
+{
+    return batched_query(1, b, lohi, qseg_off, m, const_cast<int64_t *>(offsets), indices, true,
+                         nullptr, 0, stream);
 }
 
 int64_t lbvh_query_workspace_bytes(int64_t m)

@@ -23,6 +23,10 @@ constexpr int kChunk = 1024;          // leaves per level-0 block of the bottom-
 constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
 constexpr int kBUThreads = 256;
+constexpr int kMaxBatchLevels = 3;    // kChunk * kFanout^3 >= LBVH_MAX_PRIMS
+constexpr int kBatchSortThreads = 256;  // radix tile of the batched build
+constexpr int kBatchSortItems = 16;
+constexpr int kBatchTile = kBatchSortThreads * kBatchSortItems;
 constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // query walks cut by aligned blocks of 2^12 leaves
 constexpr int kSplit2 = 7;            // ... then by blocks of 2^7 leaves
@@ -77,6 +81,28 @@ struct QueryLayout {
 };
 
 QueryLayout query_layout(int64_t m);
+QueryLayout batch_query_layout(int64_t m);   // counts and scan sums only
+
+struct BatchLayout {
+    size_t ctrl;       // kCtrlWords uint32
+    size_t scene_box;  // S x 3 float4 (lo, hi, scale)
+    size_t tile_off;   // S+1 int32
+    size_t blk_off;    // (levels+1) x (S+1) int32
+    size_t hist;       // S x passes x kRadix uint32
+    size_t status[2];  // tiles_max x kRadix uint32
+    size_t keys_alt;   // N keys
+    size_t vals[2];    // N int32
+    size_t store;      // N int32
+    size_t pend[2];    // 2 x blocks_max[0] int4
+    size_t total;
+    int passes;
+    int levels;
+    int64_t tiles_max;                       // upper bound of radix tiles
+    int64_t blocks_max[kMaxBatchLevels + 1]; // upper bound of bottom-up blocks per level
+};
+
+BatchLayout batch_layout(int64_t total_n, int S, int64_t max_scene, int code_bits);
+int batch_levels(int64_t max_scene);
 
 // ------------------------------------------------------------ tuning
 // Launch-shape knobs read by the launchers; set through lbvh_tune.
@@ -88,7 +114,7 @@ int64_t tune_get(int knob);
 
 enum KernelId {
     K_BOUNDS = 0, K_BOUNDS_FINAL, K_MORTON, K_SORT, K_BOTTOMUP,
-    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_BOTTOMUP_UP, K_NUM
+    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_BOTTOMUP_UP, K_BATCH_PREP, K_NUM
 };
 
 void prof_begin(int id, hipStream_t s);
@@ -106,5 +132,13 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_p
                         const float *q, int m, int64_t *offsets,
                         int32_t *indices, bool fill, char *ws,
                         const QueryLayout &L, hipStream_t s);
+
+hipError_t launch_build_batched(int kind, const float *prims, const lbvh_batch *b, int levels,
+                                char *ws, const BatchLayout &L, hipStream_t s);
+
+hipError_t launch_query_batched(int qkind, const lbvh_batch *b, const float *q,
+                                const int64_t *qseg_off, int64_t m, int64_t *offsets,
+                                int32_t *indices, bool fill, char *ws, const QueryLayout &L,
+                                hipStream_t s);
 
 }  // namespace lbvh

@@ -1,0 +1,358 @@
+// Query-side device code shared by the single-tree and batched query
+// translation units: the two predicates (with their containment tests), the
+// tree walker, the split and leaf-walk kernels and the CSR scan.
+#pragma once
+#pragma clang fp contract(off)
+
+#include "lbvh_internal.hpp"
+
+namespace lbvh {
+namespace {
+
+struct Sphere {
+    float cx, cy, cz, r2;
+    __device__ void load(const float *q, int j)
+    {
+        const float4 v = reinterpret_cast<const float4 *>(q)[j];
+        cx = v.x; cy = v.y; cz = v.z; r2 = v.w * v.w;
+    }
+    __device__ bool test(float4 lo, float4 hi) const
+    {
+        const float dx = fmaxf(fmaxf(lo.x - cx, cx - hi.x), 0.0f);
+        const float dy = fmaxf(fmaxf(lo.y - cy, cy - hi.y), 0.0f);
+        const float dz = fmaxf(fmaxf(lo.z - cz, cz - hi.z), 0.0f);
+        return (dx * dx + dy * dy) + dz * dz <= r2;
+    }
+    // The box lies inside the ball: its farthest corner passes.  Every box
+    // inside it then passes `test` too, also after rounding: each per-axis
+    // term of `test` for an inner box is <= the corresponding far term here
+    // (rounding is monotone), and squares and sums of non-negative terms
+    // keep the order.
+    __device__ bool contains(float4 lo, float4 hi) const
+    {
+        const float fx = fmaxf(cx - lo.x, hi.x - cx);
+        const float fy = fmaxf(cy - lo.y, hi.y - cy);
+        const float fz = fmaxf(cz - lo.z, hi.z - cz);
+        return (fx * fx + fy * fy) + fz * fz <= r2;
+    }
+};
+
+struct QBox {
+    float lx, ly, lz, hx, hy, hz;
+    __device__ void load(const float *q, int j)
+    {
+        const float2 *p = reinterpret_cast<const float2 *>(q + 6 * (int64_t)j);
+        const float2 a = p[0], b = p[1], c = p[2];
+        lx = a.x; ly = a.y; lz = b.x; hx = b.y; hy = c.x; hz = c.y;
+    }
+    __device__ bool test(float4 lo, float4 hi) const
+    {
+        return lx <= hi.x && lo.x <= hx && ly <= hi.y && lo.y <= hy && lz <= hi.z && lo.z <= hz;
+    }
+    // The box lies inside the query box, so every box inside it overlaps.
+    __device__ bool contains(float4 lo, float4 hi) const
+    {
+        return lx <= lo.x && hi.x <= hx && ly <= lo.y && hi.y <= hy && lz <= lo.z && hi.z <= hz;
+    }
+};
+
+struct Tree {
+    const float4 *nodes;
+    const int32_t *perm;   // leaf k -> primitive
+    int n;
+    __device__ int leaf0() const { return n - 1; }
+    __device__ int index(int v) const { return v >= n - 1 ? v - (n - 1) : v; }
+    __device__ void load(int v, float4 &a, float4 &b) const
+    {
+        const float4 *p = nodes + 2 * (int64_t)v;
+        a = p[0];
+        b = p[1];
+    }
+    // right bound of node v whose record half `b` holds the rope
+    __device__ int right_bound(float4 b) const
+    {
+        const int r = __float_as_int(b.w);
+        return r == -1 ? n - 1 : index(r) - 1;
+    }
+    // largest node whose range starts at leaf r (r <= n-1)
+    __device__ int first_at(int r) const
+    {
+        if (r <= n - 2) {
+            const int l = __float_as_int(nodes[2 * (int64_t)r].w);
+            if (index(l) >= r) return r;   // internal r is a right child
+        }
+        return n - 1 + r;
+    }
+};
+
+// A piece: query, start node, left bound of the start node, end (exclusive)
+// of the leaf range the walk covers.  Start node kAllHits marks a range
+// whose leaves all pass (it lies under a node the query contains).
+constexpr int kAllHits = -2;
+__device__ __forceinline__ int4 piece(int q, int v, int i, int hi) { return make_int4(q, v, i, hi); }
+
+template <class Q, bool FILL, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restrict__ queries, int m,
+                                                  const int4 *__restrict__ in, const int64_t *in_count,
+                                                  int shift, int32_t *__restrict__ counts,
+                                                  const int64_t *__restrict__ out_off,
+                                                  const int32_t *__restrict__ overflow,
+                                                  int4 *__restrict__ out)
+{
+    const int64_t T = FIRST ? (int64_t)m : *in_count;
+    const bool pass_through = FILL && *overflow;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
+        if (pass_through) { out[t] = it; continue; }
+        int64_t pos = FILL ? out_off[t] : 0;
+        int cnt = 0;
+        // all-hit range [a, b): one all-hit piece per block it touches
+        auto emit_range = [&](int a, int b) {
+            while (a < b) {
+                const int blk_end = ((a >> shift) + 1) << shift;
+                const int e = blk_end < b ? blk_end : b;
+                if (FILL) out[pos++] = piece(it.x, kAllHits, a, e);
+                else ++cnt;
+                a = e;
+            }
+        };
+        if (it.y == kAllHits) {
+            emit_range(it.z, it.w);
+        } else {
+            Q q;
+            q.load(queries, it.x);
+            int v = it.y, i = it.z;
+            const int hi = it.w;
+            int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
+            while (v != -1 && i < hi && --budget >= 0) {
+                float4 a, b;
+                tr.load(v, a, b);
+                const int j = tr.right_bound(b);
+                if (!q.test(a, b)) {
+                    v = __float_as_int(b.w);
+                    i = j + 1;
+                    continue;
+                }
+                if ((i >> shift) == (j >> shift)) {
+                    const int r = ((i >> shift) + 1) << shift;   // next block start
+                    const int end = r < hi ? r : hi;
+                    if (FILL) out[pos++] = piece(it.x, v, i, end);
+                    else ++cnt;
+                    if (r >= hi || r > tr.n - 1) break;
+                    v = tr.first_at(r);
+                    i = r;
+                    continue;
+                }
+                if (q.contains(a, b)) {   // multi-block node with only hits below
+                    emit_range(i, j + 1 < hi ? j + 1 : hi);
+                    v = __float_as_int(b.w);
+                    i = j + 1;
+                    continue;
+                }
+                v = __float_as_int(a.w);   // multi-block node: descend
+            }
+        }
+        if (!FILL) counts[t] = cnt;
+    }
+}
+
+template <class Q, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_leafwalk(Tree tr, const float *__restrict__ queries,
+                                                     const int4 *__restrict__ in,
+                                                     const int64_t *in_count,
+                                                     int32_t *__restrict__ counts,
+                                                     const int64_t *__restrict__ hit_off,
+                                                     int32_t *__restrict__ out)
+{
+    const int64_t T = *in_count;
+    const int leaf0 = tr.leaf0();
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int4 it = in[t];
+        int64_t pos = FILL ? hit_off[t] : 0;
+        int cnt = 0;
+        // leaves [a, b) are all hits
+        auto take_range = [&](int a, int b) {
+            if (FILL)
+                for (int k = a; k < b; ++k) out[pos++] = tr.perm[k];
+            else
+                cnt += b - a;
+        };
+        if (it.y == kAllHits) {
+            take_range(it.z, it.w);
+        } else {
+            Q q;
+            q.load(queries, it.x);
+            int v = it.y, i = it.z;
+            const int hi = it.w;
+            int64_t budget = 2 * (int64_t)tr.n;
+            while (v != -1 && i < hi && --budget >= 0) {
+                float4 a, b;
+                tr.load(v, a, b);
+                const int left = __float_as_int(a.w);
+                const int rope = __float_as_int(b.w);
+                const int j = tr.right_bound(b);
+                if (q.test(a, b)) {
+                    if (v >= leaf0) {              // leaf: `left` holds its primitive
+                        if (FILL) out[pos++] = left;
+                        else ++cnt;
+                    } else if (q.contains(a, b)) {
+                        take_range(i, j + 1 < hi ? j + 1 : hi);
+                    } else {
+                        v = left;
+                        continue;
+                    }
+                }
+                v = rope;
+                i = j + 1;
+            }
+        }
+        if (!FILL) counts[t] = cnt;
+    }
+}
+
+__global__ void k_zero_i64(int64_t *p, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// -------------------------------------------------------------- scan
+//
+// Exclusive scan of `m` int32 counts into int64 offsets[0..m] (offsets[m] =
+// total).  The count is either a host value (m_dev == nullptr) or read on
+// the device; grids are sized for `cap`, the largest count possible.
+
+template <typename T>
+__device__ __forceinline__ T block_excl_scan_total(T v, T *sh /* [kBlock/64] */, T *block_total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wave] = x;
+    __syncthreads();
+    T before = 0, all = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wave) before += sh[w];
+        all += sh[w];
+    }
+    *block_total = all;
+    return before + x - v;
+}
+
+__device__ __forceinline__ int64_t count_of(int64_t cap, const int64_t *m_dev)
+{
+    return m_dev ? *m_dev : cap;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ counts, int64_t cap,
+                                                        const int64_t *m_dev, int64_t *__restrict__ partials)
+{
+    __shared__ int64_t sh[kBlock / 64];
+    const int64_t m = count_of(cap, m_dev);
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    if ((int64_t)blockIdx.x * kScanTile >= m) return;   // whole block past the end
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += counts[base + k];
+    int64_t total;
+    block_excl_scan_total<int64_t>(s, sh, &total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_partials(int64_t *partials, int64_t cap,
+                                                          const int64_t *m_dev)
+{
+    __shared__ int64_t sh[kBlock / 64];
+    const int64_t m = count_of(cap, m_dev);
+    const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const int64_t b = b0 + threadIdx.x;
+        const int64_t v = b < nb ? partials[b] : 0;
+        int64_t total;
+        const int64_t e = block_excl_scan_total<int64_t>(v, sh, &total);
+        if (b < nb) partials[b] = carry + e;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t *__restrict__ counts, int64_t cap,
+                                                       const int64_t *m_dev,
+                                                       const int64_t *__restrict__ partials,
+                                                       int64_t *__restrict__ offsets)
+{
+    __shared__ int64_t sh[kBlock / 64];
+    const int64_t m = count_of(cap, m_dev);
+    if (m == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) offsets[0] = 0;
+        return;
+    }
+    if ((int64_t)blockIdx.x * kScanTile >= m) return;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t c[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        c[k] = base + k < m ? counts[base + k] : 0;
+        s += c[k];
+    }
+    int64_t total;
+    int64_t run = partials[blockIdx.x] + block_excl_scan_total<int64_t>(s, sh, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) offsets[base + k] = run;
+        run += c[k];
+        if (base + k == m - 1) offsets[m] = run;
+    }
+}
+
+// After a level's scan: does the number of pieces fit?  If not, the level
+// passes its parents through unchanged.
+__global__ void k_level_check(const int64_t *__restrict__ off, const int64_t *parent_dev,
+                              int64_t parent_host, int64_t cap, int32_t *__restrict__ overflow,
+                              int64_t *__restrict__ count)
+{
+    const int64_t parents = parent_dev ? *parent_dev : parent_host;
+    const int64_t total = off[parents];
+    const bool over = total > cap;
+    *overflow = over ? 1 : 0;
+    *count = over ? parents : total;
+}
+
+// offsets[q] = hit offset of query q's first leaf-walk piece.
+__global__ __launch_bounds__(kBlock) void k_compose(const int64_t *__restrict__ off1,
+                                                    const int32_t *__restrict__ ovf1,
+                                                    const int64_t *__restrict__ off2,
+                                                    const int32_t *__restrict__ ovf2,
+                                                    const int64_t *__restrict__ hit_off, int m,
+                                                    int64_t *__restrict__ offsets)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q > m) return;
+    const int64_t p1 = *ovf1 ? q : off1[q];
+    const int64_t p2 = *ovf2 ? p1 : off2[p1];
+    offsets[q] = hit_off[p2];
+}
+
+// Exclusive scan of int32 counts into int64 offsets (three launches).
+void scan(const int32_t *counts, int64_t cap, const int64_t *m_dev, int64_t *partials,
+          int64_t *offsets, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((cap + kScanTile - 1) / kScanTile);
+    const unsigned g = nb > 0 ? nb : 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(g), dim3(kBlock), 0, s, counts, cap, m_dev, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partials, cap, m_dev);
+    hipLaunchKernelGGL(k_scan_final, dim3(g), dim3(kBlock), 0, s, counts, cap, m_dev, partials,
+                       offsets);
+}
+
+}  // namespace
+}  // namespace lbvh

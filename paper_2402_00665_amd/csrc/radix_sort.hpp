@@ -1,0 +1,205 @@
+// LSD radix pass (onesweep) over one 8-bit digit, for one key array or for
+// many independent segments of it (batched scenes).
+//
+// A block takes the next tile id from a counter (so every tile it waits for
+// is already running), ranks its THREADS*ITEMS keys stably with wave64
+// ballots, publishes its per-digit counts, looks back over earlier tiles of
+// its segment for their running totals, and scatters keys, then values,
+// through one LDS buffer so that global writes are runs of equal digits.
+// Tiles never straddle segments: tile_off[s] is the first tile of segment
+// s, and the first tile of a segment starts its running totals at zero.  A
+// segment that fits one tile needs no histogram; otherwise `hist` holds the
+// segment's digit counts for this pass (written by the Morton kernel).
+#pragma once
+#pragma clang fp contract(off)
+
+#include "device_common.hpp"
+
+namespace lbvh {
+namespace {
+
+struct SortSegs {
+    const int64_t *seg_off;   // [S+1] segment starts; nullptr: one segment [0, n)
+    const int32_t *tile_off;  // [S+1] first tile of each segment
+    int S;
+    int hist_stride;          // words between consecutive segments' histograms
+};
+
+__device__ __forceinline__ int upper_segment(const int32_t *off, int S, uint32_t x)
+{
+    // largest s in [0, S) with off[s] <= x (off is non-decreasing, off[0] = 0)
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((uint32_t)off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename K, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_onesweep(
+    const K *__restrict__ keys_in, K *__restrict__ keys_out, const int32_t *__restrict__ vals_in,
+    int32_t *__restrict__ vals_out, int64_t n, SortSegs seg, int shift,
+    const uint32_t *__restrict__ hist, uint32_t *status, uint32_t *__restrict__ status_next,
+    uint32_t *tile_counter, uint32_t *err)
+{
+    static_assert(THREADS >= kRadix && THREADS % 64 == 0, "one thread per digit");
+    constexpr int W = THREADS / 64;
+    constexpr int TILE = THREADS * ITEMS;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wcnt[W][kRadix];
+    __shared__ uint32_t s_start[kRadix];     // tile-local start of each digit run
+    __shared__ uint32_t s_gbase[kRadix];     // segment-local position of that run
+    __shared__ uint32_t s_scan[2][W];
+    __shared__ K s_buf[TILE];                // keys, then values
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int j = tid; j < W * kRadix; j += THREADS) (&s_wcnt[0][0])[j] = 0u;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+
+    // the tile's segment
+    int64_t b0 = 0, ns = n;
+    uint32_t t0 = 0, nt = (uint32_t)((n + TILE - 1) / TILE);
+    int s = 0;
+    if (seg.seg_off) {
+        if (tile >= (uint32_t)seg.tile_off[seg.S]) return;   // grid is an upper bound
+        s = upper_segment(seg.tile_off, seg.S, tile);
+        b0 = seg.seg_off[s];
+        ns = seg.seg_off[s + 1] - b0;
+        t0 = (uint32_t)seg.tile_off[s];
+        nt = (uint32_t)seg.tile_off[s + 1] - t0;
+    }
+    const uint32_t lt = tile - t0;           // tile index within the segment
+    const int64_t base = (int64_t)lt * TILE; // segment-local
+    if (status_next && tid < kRadix) status_next[(int64_t)tile * kRadix + tid] = 0u;
+
+    // wave w owns keys [base + w*64*ITEMS, ...); item k of lane l is key
+    // base + w*64*ITEMS + k*64 + l, so (item, lane) order is input order
+    K key[ITEMS];
+    int32_t val[ITEMS];
+    const int64_t wbase = base + (int64_t)wave * 64 * ITEMS;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < ns;
+        key[k] = ok ? keys_in[b0 + idx] : (K)0;
+        val[k] = vals_in ? (ok ? vals_in[b0 + idx] : 0) : (int32_t)idx;
+    }
+
+    // stable rank within the wave: lanes holding the same digit find each
+    // other with 8 ballots; the lowest of them advances the wave's counter
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int64_t idx = wbase + k * 64 + lane;
+        const bool ok = idx < ns;
+        const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = count_below(peers);
+        const uint32_t cnt = s_wcnt[wave][d];
+        rank[k] = cnt + below;
+        if (ok && below == 0) s_wcnt[wave][d] = cnt + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    // threads d < 256: per-wave exclusive offsets of digit d and the total
+    const uint32_t d = tid;
+    uint32_t total = 0;
+    if (tid < kRadix) {
+        uint32_t c[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
+#pragma unroll
+        for (int w = 0; w < W; ++w) { s_wcnt[w][d] = total; total += c[w]; }
+        if (nt > 1)
+            __hip_atomic_store(status + (int64_t)tile * kRadix + d,
+                               (lt == 0 ? kFlagInclusive : kFlagAggregate) | total,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t start = block_excl_scan<THREADS>(tid < kRadix ? total : 0u, s_scan[0]);
+    const uint32_t *hs = hist + (int64_t)s * seg.hist_stride;
+    const uint32_t hoff =
+        block_excl_scan<THREADS>((tid < kRadix && nt > 1) ? hs[d] : 0u, s_scan[1]);
+    if (tid < kRadix) {
+        s_start[d] = start;
+        uint32_t excl = 0;
+        if (nt > 1 && lt > 0) {
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (true) {
+                const uint32_t sv = __hip_atomic_load(status + j * kRadix + d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t flag = sv & ~kValueMask;
+                if (flag == 0u) {
+                    if (++spins > (1u << 24)) {   // never expected: bounded wait
+                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += sv & kValueMask;
+                if (flag == kFlagInclusive || j == (int64_t)t0) break;
+                --j;
+            }
+            __hip_atomic_store(status + (int64_t)tile * kRadix + d, kFlagInclusive | (excl + total),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_gbase[d] = (nt > 1 ? hoff : 0u) + excl + (nt > 1 ? 0u : start);
+    }
+    __syncthreads();
+
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t dk = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+        pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
+    }
+    const int64_t rem = ns - base;
+    const int valid = rem < TILE ? (int)rem : TILE;
+
+    // keys: into LDS in tile-sorted order, then out in runs
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (wbase + k * 64 + lane < ns) s_buf[pos[k]] = key[k];
+    __syncthreads();
+    int64_t dst[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int p = k * THREADS + tid;
+        dst[k] = -1;
+        if (p < valid) {
+            const K kk = s_buf[p];
+            const uint32_t dk = (uint32_t)(kk >> shift) & (kRadix - 1);
+            const int64_t out = (int64_t)s_gbase[dk] + (p - (int)s_start[dk]);
+            if (out >= 0 && out < ns) {
+                keys_out[b0 + out] = kk;
+                dst[k] = b0 + out;
+            } else {   // inconsistent histogram: flag it rather than write outside
+                __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    __syncthreads();
+    // values: same slots, same destinations
+    int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (wbase + k * 64 + lane < ns) s_vals[pos[k]] = val[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+        if (dst[k] >= 0) vals_out[dst[k]] = s_vals[k * THREADS + tid];
+}
+
+}  // namespace
+}  // namespace lbvh

@@ -1,0 +1,194 @@
+"""GPU parity of the batched build and batched queries: every scene's tree
+and query results must equal the oracle run on that scene alone
+(tolerance 0), and a HIP-graph replay must give the same bits each time."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import first_mismatch, say
+
+pytestmark = pytest.mark.gpu
+
+
+def run_batched(prims, seg_off, bits, kind, max_scene=None, ws=None):
+    import torch
+    import paper_2402_00665_amd as lb
+    sizes = np.diff(seg_off)
+    max_scene = int(sizes.max()) if max_scene is None else max_scene
+    say(f"  batched build: S={len(sizes)} N={int(seg_off[-1])} bits={bits} kind={kind} "
+        f"max_scene={max_scene}")
+    dp = torch.from_numpy(np.ascontiguousarray(prims)).cuda()
+    ds = torch.from_numpy(np.ascontiguousarray(seg_off, dtype=np.int64)).cuda()
+    b = lb.build_batched(dp, ds, bits, max_scene, kind=kind, workspace=ws)
+    return b, dp, ds
+
+
+def check_scene(b, s, seg_off, ref, nodes_h, codes_h, perm_h):
+    a, e = int(seg_off[s]), int(seg_off[s + 1])
+    n = e - a
+    assert ref.n == n
+    if n == 0:
+        return
+    rec = nodes_h[2 * a: 2 * a + 2 * n - 1]
+    f = rec.view(np.float32)
+    aabb = np.concatenate([f[:, 0:3], f[:, 4:7]], axis=1)
+    codes = codes_h[a:e].astype(np.uint64)
+    for name, got, exp in [("codes", codes, ref.sorted), ("leaf_perm", perm_h[a:e], ref.perm),
+                           ("perm field", rec[n - 1:, 3], ref.perm), ("left", rec[: n - 1, 3], ref.left),
+                           ("rope", rec[:, 7], ref.rope)]:
+        k = first_mismatch(got, exp)
+        assert k is None, f"scene {s} {name}[{k}]: gpu {got[k]} oracle {exp[k]}"
+    bad = np.flatnonzero(~np.all(aabb == ref.aabb, axis=1))
+    assert bad.size == 0, f"scene {s} aabb[{bad[0]}]"
+
+
+def host_arrays(b):
+    nodes_h = b.nodes.cpu().numpy()
+    c = b.codes.cpu().numpy()
+    codes_h = c.view(np.uint32) if b.code_bits == 30 else c.view(np.uint64)
+    return nodes_h, codes_h, b.leaf_perm.cpu().numpy()
+
+
+def batched_parity(prims, seg_off, bits, kind, queries=None, qseg=None, qkind=0, ws=None,
+                   check_every=1):
+    import torch
+    import paper_2402_00665_amd as lb
+    b, dp, ds = run_batched(prims, seg_off, bits, kind, ws=ws)
+    lb.check_batched(b)
+    nodes_h, codes_h, perm_h = host_arrays(b)
+    S = len(seg_off) - 1
+    refs = {}
+    for s in range(0, S, check_every):
+        a, e = int(seg_off[s]), int(seg_off[s + 1])
+        refs[s] = oracle.build(kind, prims[a:e], bits)
+        check_scene(b, s, seg_off, refs[s], nodes_h, codes_h, perm_h)
+    if queries is None:
+        return b
+    dq = torch.from_numpy(np.ascontiguousarray(queries)).cuda()
+    dqs = torch.from_numpy(np.ascontiguousarray(qseg, dtype=np.int64)).cuda()
+    off, idx = lb.query_batched(b, dq, dqs, qkind)
+    torch.cuda.synchronize()
+    off, idx = off.cpu().numpy(), idx.cpu().numpy()
+    for s in range(0, S, check_every):
+        qa, qe = int(qseg[s]), int(qseg[s + 1])
+        roff, ridx, _ = oracle.query_traverse(qkind, queries[qa:qe], refs[s])
+        got_off = off[qa:qe + 1] - off[qa]
+        k = first_mismatch(got_off, roff)
+        assert k is None, f"scene {s} query offsets[{k}]"
+        k = first_mismatch(idx[off[qa]:off[qe]], ridx)
+        assert k is None, f"scene {s} query indices[{k}]"
+    return b
+
+
+SIZES = [0, 1, 2, 3, 33, 4095, 4096, 4097, 1025, 70000, 0, 5, 8193, 1024, 1023, 300000]
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_mixed_scene_sizes(kind, bits):
+    rng = np.random.default_rng([20, kind, bits])
+    sizes = np.array(SIZES, np.int64)
+    seg = np.zeros(len(sizes) + 1, np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    N = int(seg[-1])
+    if kind == 0:
+        prims = rng.random((N, 3), dtype=np.float32)
+    else:
+        c = rng.random((N, 3))
+        s = rng.random((N, 3)) * 0.01
+        prims = np.concatenate([c - s, c + s], 1).astype(np.float32)
+    m_per = 7
+    q = workloads.spheres(rng.random((len(sizes) * m_per, 3), dtype=np.float32), np.float32(0.05))
+    qseg = np.arange(len(sizes) + 1, dtype=np.int64) * m_per
+    batched_parity(prims, seg, bits, kind, q, qseg, 0)
+
+
+def test_batched_workload_reduced():
+    pts, off, q, qoff = workloads.batched(S=160, m_per=64)
+    batched_parity(pts, off, 63, 0, q, qoff, 0)
+
+
+def test_batched_box_queries_and_duplicates():
+    rng = np.random.default_rng(21)
+    sizes = np.array([5000, 12000, 3, 64, 9000], np.int64)
+    seg = np.zeros(len(sizes) + 1, np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    pts = (rng.integers(0, 5, size=(int(seg[-1]), 3)) / 4).astype(np.float32)   # heavy duplicates
+    c = rng.random((50, 3))
+    qb = np.concatenate([c - 0.2, c + 0.2], 1).astype(np.float32)
+    qseg = np.array([0, 10, 20, 30, 40, 50], np.int64)
+    batched_parity(pts, seg, 30, 0, qb, qseg, 1)
+
+
+def test_max_scene_too_small_is_reported():
+    import paper_2402_00665_amd as lb
+    rng = np.random.default_rng(22)
+    seg = np.array([0, 3000, 5000], np.int64)
+    pts = rng.random((5000, 3), dtype=np.float32)
+    b, _, _ = run_batched(pts, seg, 30, 0, max_scene=1000)
+    with pytest.raises(lb.LbvhError) as e:
+        lb.check_batched(b)
+    assert e.value.status == lb.LBVH_EDEVICE
+
+
+def test_graph_capture_replays_identically():
+    """The batched build and count enqueue kernels only, so they can be
+    captured in a HIP graph; every replay must reproduce the eager bits."""
+    import torch
+    import paper_2402_00665_amd as lb
+    pts, off, q, qoff = workloads.batched(S=64, m_per=64)
+    max_scene = int(np.diff(off).max())
+    dp = torch.from_numpy(pts).cuda()
+    ds = torch.from_numpy(off).cuda()
+    dq = torch.from_numpy(q).cuda()
+    dqs = torch.from_numpy(qoff).cuda()
+    ws, qws = lb.Workspace(), lb.Workspace()
+    b = lb.build_batched(dp, ds, 63, max_scene, workspace=ws)
+    offsets = torch.empty(q.shape[0] + 1, dtype=torch.int64, device="cuda")
+    qbuf = qws.get(lb.lbvh_query_batched_workspace_bytes(q.shape[0]))
+
+    def enqueue():
+        lb._check(lb.lbvh_build_batched(0, dp.data_ptr(), b.desc, b.workspace.data_ptr(),
+                                        b.workspace.numel(), lb._stream()), "build")
+        lb._check(lb.lbvh_query_batched_spheres_count(b.desc, dq.data_ptr(), dqs.data_ptr(),
+                                                      q.shape[0], offsets.data_ptr(), qbuf.data_ptr(),
+                                                      qbuf.numel(), lb._stream()), "count")
+
+    # records the build owns: scene s has 2n_s-1 of its 2n_s slots
+    used = np.zeros(b.nodes.shape[0], bool)
+    for a, e in zip(off[:-1], off[1:]):
+        used[2 * a: 2 * a + max(2 * (e - a) - 1, 0)] = True
+    used = torch.from_numpy(used).cuda()
+    enqueue()
+    torch.cuda.synchronize()
+    eager_nodes, eager_off = b.nodes[used].clone(), offsets.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            enqueue()
+    torch.cuda.synchronize()
+    for r in range(4):
+        b.nodes.zero_()
+        offsets.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(b.nodes[used], eager_nodes), f"replay {r}: nodes differ"
+        assert torch.equal(offsets, eager_off), f"replay {r}: offsets differ"
+        x = torch.rand(1000, device="cuda").sum()   # eager work between replays
+        x.item()
+    lb.check_batched(b)
+
+
+@pytest.mark.timeout(900)
+def test_batched_workload_full_size():
+    """4096 scenes, sizes log-uniform in [32, 65536] (35M points), 63-bit
+    codes, 64 spheres per scene: every 16th scene checked against the
+    oracle, all scenes' query counts checked against per-scene oracles."""
+    say("full batched workload: generating")
+    pts, off, q, qoff = workloads.batched()
+    batched_parity(pts, off, 63, 0, q, qoff, 0, check_every=16)
