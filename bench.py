@@ -95,10 +95,14 @@ def parse():
     ap.add_argument("--workload", default="clustered_boxes",
                     choices=["clustered_boxes", "large_points", "small_points"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain comparison (4096 scenes)")
     ap.add_argument("--build-only", action="store_true",
                     help="time the build alone (no queries in the step)")
-    ap.add_argument("--cpu-sample", type=float, default=0.5,
+    ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of the workload the oracle baseline runs on")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="repeat the oracle baseline until this much CPU time is spent (max 8 runs)")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="turn rocprofv3 outputs (kernel-trace --stats run, --pmc FETCH_SIZE "
                          "run, --pmc WRITE_SIZE run) into profiles/ summaries and exit")
@@ -229,18 +233,26 @@ def main():
         sub_p = np.ascontiguousarray(w.prims[:ns])
         sub_q = np.ascontiguousarray(w.queries[:ms_])
         log(f"[bench] cpu baseline: oracle on {ns} primitives, {ms_} queries")
-        c0 = time.perf_counter()
-        ref = oracle.build(w.kind, sub_p, w.code_bits)
-        c1 = time.perf_counter()
-        oracle.query_traverse(w.qkind, sub_q, ref)
-        c2 = time.perf_counter()
-        cpu = {"value": round(ns / (c1 - c0) / 1e6, 3), "unit": "Mprims/s", "cores": 1,
+        tb = tq = 0.0
+        runs = 0
+        while runs == 0 or (tb + tq < args.cpu_seconds and runs < 8):
+            c0 = time.perf_counter()
+            ref = oracle.build(w.kind, sub_p, w.code_bits)
+            c1 = time.perf_counter()
+            oracle.query_traverse(w.qkind, sub_q, ref)
+            c2 = time.perf_counter()
+            tb, tq, runs = tb + (c1 - c0), tq + (c2 - c1), runs + 1
+            del ref
+        cpu = {"value": round(runs * ns / tb / 1e6, 3), "unit": "Mprims/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"first {ns} of the {w.n} primitives (build) and first {ms_} of the "
-                         f"{w.m} queries (Alg. 1 on the oracle tree); single-threaded C",
-               "build_s": round(c1 - c0, 3), "query_s": round(c2 - c1, 3),
-               "queries_mqps": round(ms_ / (c2 - c1) / 1e6, 3)}
-        log(f"[bench] cpu baseline done in {c2 - c0:.1f}s")
+               "sample": f"{runs} run(s) of: build over the first {ns} of the {w.n} primitives, "
+                         f"then Alg. 1 for the first {ms_} of the {w.m} queries on the oracle "
+                         "tree; single-threaded C",
+               "build_s": round(tb / runs, 3), "query_s": round(tq / runs, 3),
+               "queries_mqps": round(runs * ms_ / tq / 1e6, 3)}
+        log(f"[bench] cpu baseline done: {runs} run(s) in {tb + tq:.1f}s")
+
+    batched = None if args.no_batched else bench_batched(args)
 
     out = {
         "metric": "rope-LBVH build Mprims/s + stackless Mqueries/s",
@@ -269,8 +281,104 @@ def main():
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------- batched
+
+def bench_batched(args, reps: int = 5):
+    """4096 uniform point sets (sizes log-uniform in [32, 65536], 63-bit
+    codes, 64 spheres of radius 0.05 each): one batched launch sequence for
+    all scenes against one plain build + query per scene, same GPU, same
+    stream.  Both produce every scene's tree; they are compared bit for bit
+    on the device."""
+    import torch
+    import paper_2402_00665_amd as lb
+    import workloads
+    t0 = time.time()
+    pts, off, q, qoff = workloads.batched()
+    S, N, m = len(off) - 1, int(off[-1]), q.shape[0]
+    max_scene = int(np.diff(off).max())
+    log(f"[bench] batched workload: S={S} N={N} m={m} (generated in {time.time() - t0:.1f}s)")
+    dp, ds = torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda()
+    dq, dqs = torch.from_numpy(q).cuda(), torch.from_numpy(qoff).cuda()
+    ws, qws = lb.Workspace(), lb.Workspace()
+    b = lb.build_batched(dp, ds, 63, max_scene, workspace=ws)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def batched_step():
+        lb.build_batched(dp, ds, 63, max_scene, workspace=ws, batch=b)
+        ev[1].record()
+        return lb.query_batched(b, dq, dqs, 0, workspace=qws)
+
+    for _ in range(2):
+        batched_step()
+    torch.cuda.synchronize()
+    lb.check_batched(b)
+    bt, qt, wt = [], [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        ev[0].record()
+        boff, bidx = batched_step()
+        ev[2].record()
+        torch.cuda.synchronize()
+        wt.append(time.perf_counter() - w0)
+        bt.append(ev[0].elapsed_time(ev[1]))
+        qt.append(ev[1].elapsed_time(ev[2]))
+
+    # plain: one single-scene build and one query call per scene
+    off_h, qoff_h = off.tolist(), qoff.tolist()
+    trees = [lb.alloc_tree(off_h[s + 1] - off_h[s], 63) for s in range(S)]
+    # each scene in its own allocation, as a caller of the single-tree entry
+    # point holds it (a slice of the packed array is not 16-byte aligned)
+    scene_p = [dp[off_h[s]:off_h[s + 1]].clone() for s in range(S)]
+    pws, pqws = lb.Workspace(), lb.Workspace()
+
+    def plain_pass(with_queries):
+        res = []
+        for s in range(S):
+            t = lb.build(scene_p[s], 63, kind=0, workspace=pws, tree=trees[s])
+            if with_queries:
+                res.append(lb.query(t, dq[qoff_h[s]:qoff_h[s + 1]], 0, workspace=pqws))
+        return res
+
+    plain_pass(True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    plain_pass(False)
+    torch.cuda.synchronize()
+    plain_build_s = time.perf_counter() - w0
+    w0 = time.perf_counter()
+    pres = plain_pass(True)
+    torch.cuda.synchronize()
+    plain_all_s = time.perf_counter() - w0
+
+    # same trees and results, scene by scene
+    same = True
+    for s in range(S):
+        a, e = off_h[s], off_h[s + 1]
+        if e > a:
+            same &= bool(torch.equal(b.nodes[2 * a:2 * a + 2 * (e - a) - 1], trees[s].nodes))
+        qa, qe = qoff_h[s], qoff_h[s + 1]
+        po, pi = pres[s]
+        same &= bool(torch.equal(boff[qa:qe + 1] - boff[qa], po))
+        same &= bool(torch.equal(bidx[int(boff[qa]):int(boff[qe])], pi))
+    bb, bq, bw = float(np.median(bt)), float(np.median(qt)), float(np.median(wt))
+    return {
+        "workload": "batched_scenes", "scenes": S, "n": N, "m": m, "code_bits": 63,
+        "batched_build_ms": round(bb, 4), "batched_query_ms": round(bq, 4),
+        "batched_wall_ms": round(bw * 1e3, 3),
+        "batched_mprims_per_s": round(N / (bb * 1e-3) / 1e6, 1),
+        "plain_build_ms": round(plain_build_s * 1e3, 3),
+        "plain_wall_ms": round(plain_all_s * 1e3, 3),
+        "plain_mprims_per_s": round(N / plain_build_s / 1e6, 1),
+        "build_speedup": round(plain_build_s * 1e3 / bb, 2),
+        "wall_speedup": round(plain_all_s / bw, 2),
+        "identical": same,
+    }
 
 
 # --------------------------------------------------------------- profiles

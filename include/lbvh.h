@@ -270,6 +270,9 @@ const char *lbvh_last_hip_error(void);
  *       30-bit / 63-bit codes: 0 = 256 threads x 16 keys, 1 = 256 x 8,
  *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8
  *       (defaults 4 and 3).
+ *   "batch_sort_variant": tile shape of the batched build's segmented
+ *       radix passes: 0 = 256 x 16 (default), 1 = 256 x 8, 2 = 512 x 8,
+ *       3 = 512 x 16.
  * Results never depend on the knobs; only speed does.  Calls already
  * enqueued keep the shapes they were enqueued with. */
 int64_t lbvh_tune(const char *name, int64_t value);

@@ -441,6 +441,34 @@ def check_batched(batch: Batch, stream=None):
            "lbvh_build_batched_check")
 
 
+def query_batched_count(batch: Batch, queries, qseg_off, qkind: int, workspace: Workspace,
+                        offsets=None, stream=None):
+    """First batched call, asynchronous: CSR offsets int64 [m+1]."""
+    torch = _torch()
+    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    m = int(q.shape[0])
+    if offsets is None:
+        offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
+    ws_bytes = lbvh_query_batched_workspace_bytes(m)
+    _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_query_batched_workspace_bytes")
+    ws = workspace.get(ws_bytes)
+    cnt = lbvh_query_batched_spheres_count if qkind == SPHERES else lbvh_query_batched_boxes_count
+    _check(cnt(batch.desc, q.data_ptr() if m else None, qseg_off.data_ptr(), m, offsets.data_ptr(),
+               ws.data_ptr(), ws.numel(), _stream(stream)), "batched query count")
+    return offsets
+
+
+def query_batched_fill(batch: Batch, queries, qseg_off, qkind: int, offsets, indices, stream=None):
+    """Second batched call, asynchronous: indices int32 [offsets[m]] (the
+    tensor must hold at least one element)."""
+    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    m = int(q.shape[0])
+    fill = lbvh_query_batched_spheres_fill if qkind == SPHERES else lbvh_query_batched_boxes_fill
+    _check(fill(batch.desc, q.data_ptr() if m else None, qseg_off.data_ptr(), m, offsets.data_ptr(),
+                indices.data_ptr(), _stream(stream)), "batched query fill")
+    return indices
+
+
 def query_batched(batch: Batch, queries, qseg_off, qkind: int, workspace: Workspace | None = None,
                   stream=None):
     """Count, read the total, fill.  Returns (offsets int64 [m+1], indices

@@ -1,0 +1,148 @@
+"""Self-written autotuner for the library's launch-shape knobs.
+
+A knob (see ``lbvh_tune`` in include/lbvh.h) picks a tile shape; results
+never depend on it, only speed does.  ``tune`` times every candidate value
+on the caller's own workload with HIP events, checks once per candidate that
+its output is bit-identical to the default value's output, keeps the fastest
+and records it in a JSON cache keyed by (GPU arch, knob, code bits, kind,
+size bucket = floor(log2 n)).  ``apply`` sets the cached winners for a
+workload shape.
+
+Cache path: $LBVH_TUNING_CACHE, else ~/.cache/paper_2402_00665_amd/tuning.json.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import (LBVH_POINTS, Workspace, alloc_tree, build, build_batched, check_batched,
+               check_build, lbvh_profile_enable, lbvh_profile_read, lbvh_profile_reset,
+               lbvh_tune)
+
+KNOB_CANDIDATES = {
+    "sort_variant32": list(range(6)),
+    "sort_variant64": list(range(6)),
+    "batch_sort_variant": list(range(4)),
+}
+
+
+def cache_path() -> str:
+    return os.environ.get("LBVH_TUNING_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2402_00665_amd",
+                                       "tuning.json"))
+
+
+def _arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _key(knob: str, code_bits: int, kind: int, n: int) -> str:
+    return f"{_arch()}/{knob}/{code_bits}/{kind}/{int(math.log2(max(n, 1)))}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(cache: dict):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time_single(prims, code_bits, kind, ws, tree, reps):
+    import torch
+    for _ in range(2):
+        build(prims, code_bits, kind=kind, workspace=ws, tree=tree)
+    torch.cuda.synchronize()
+    lbvh_profile_reset()
+    lbvh_profile_enable(True)
+    for _ in range(reps):
+        build(prims, code_bits, kind=kind, workspace=ws, tree=tree)
+    torch.cuda.synchronize()
+    lbvh_profile_enable(False)
+    ms, cnt = lbvh_profile_read("sort_pass")
+    check_build(tree)
+    return ms / max(cnt, 1)
+
+
+def _time_batched(prims, seg_off, code_bits, kind, max_scene, ws, batch, reps):
+    import torch
+    for _ in range(2):
+        build_batched(prims, seg_off, code_bits, max_scene, kind=kind, workspace=ws, batch=batch)
+    torch.cuda.synchronize()
+    lbvh_profile_reset()
+    lbvh_profile_enable(True)
+    for _ in range(reps):
+        build_batched(prims, seg_off, code_bits, max_scene, kind=kind, workspace=ws, batch=batch)
+    torch.cuda.synchronize()
+    lbvh_profile_enable(False)
+    ms, cnt = lbvh_profile_read("sort_pass")
+    check_batched(batch)
+    return ms / max(cnt, 1)
+
+
+def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene: int | None = None,
+         reps: int = 5, save: bool = True, verbose: bool = False) -> dict:
+    """Tune the radix-pass tile shape for this workload (a single tree, or
+    a batch when ``seg_off`` is given).  Returns {"knob", "value",
+    "times_ms": {value: ms per pass}}; every candidate is checked to give the
+    same tree, bit for bit, as the first (default) candidate."""
+    import torch
+    if kind is None:
+        kind = LBVH_POINTS if prims.shape[1] == 3 else 1
+    batched = seg_off is not None
+    knob = "batch_sort_variant" if batched else f"sort_variant{32 if code_bits == 30 else 64}"
+    cands = KNOB_CANDIDATES[knob]
+    default = lbvh_tune(knob)
+    order = [default] + [c for c in cands if c != default]
+    ws = Workspace(prims.device)
+    n = int(prims.shape[0])
+    if batched:
+        from . import alloc_batch
+        obj = alloc_batch(seg_off, code_bits, max_scene, prims.device)
+    else:
+        obj = alloc_tree(n, code_bits, prims.device)
+    times, ref = {}, None
+    try:
+        for v in order:
+            lbvh_tune(knob, v)
+            t = (_time_batched(prims, seg_off, code_bits, kind, max_scene, ws, obj, reps) if batched
+                 else _time_single(prims, code_bits, kind, ws, obj, reps))
+            out = torch.cat([obj.nodes.flatten(), obj.leaf_perm]).clone()
+            if ref is None:
+                ref = out
+            elif not torch.equal(out, ref):
+                raise RuntimeError(f"{knob}={v} changed the tree; refusing to tune with it")
+            times[v] = t
+            if verbose:
+                print(f"[autotune] {knob}={v}: {t * 1e3:.1f} us per pass", flush=True)
+    finally:
+        lbvh_tune(knob, default)
+    best = min(times, key=times.get)
+    if save:
+        cache = _load()
+        cache[_key(knob, code_bits, kind, n)] = {"value": best, "times_ms": times}
+        _save(cache)
+    return {"knob": knob, "value": best, "times_ms": times}
+
+
+def apply(n: int, code_bits: int, kind: int, batched: bool = False) -> dict:
+    """Set the cached best value of the knob for this shape, if any; returns
+    {knob: value} for what was set."""
+    knob = "batch_sort_variant" if batched else f"sort_variant{32 if code_bits == 30 else 64}"
+    hit = _load().get(_key(knob, code_bits, kind, n))
+    if hit is None:
+        return {}
+    lbvh_tune(knob, int(hit["value"]))
+    return {knob: int(hit["value"])}

@@ -35,7 +35,7 @@ __device__ __forceinline__ int64_t scene_size(const int64_t *seg_off, int s)
 // while its level-(L-1) blocks are more than one).  Also clears the control
 // words (tile counters, error flag).
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t *__restrict__ seg_off,
-                                                             int S, int levels,
+                                                             int S, int levels, int tile,
                                                              int32_t *__restrict__ tile_off,
                                                              int32_t *__restrict__ blk_off,
                                                              uint32_t *__restrict__ ctrl)
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t *__re
             __syncthreads();
         };
         const int64_t ns = s < S ? scene_size(seg_off, s) : 0;
-        scan_into((uint32_t)((ns + kBatchTile - 1) / kBatchTile), tile_off, carry_t);
+        scan_into((uint32_t)((ns + tile - 1) / tile), tile_off, carry_t);
         uint32_t blk = (uint32_t)((ns + kChunk - 1) / kChunk);
         for (int L = 0; L <= levels; ++L) {
             if (L > 0) blk = blk > 1 ? (blk + kFanout - 1) / kFanout : 0u;
@@ -192,6 +192,39 @@ __global__ __launch_bounds__(kBlock) void k_batch_walk(const float4 *__restrict_
     if (!FILL) counts[j] = cnt;
 }
 
+// Radix tile shapes of the batched build (threads x keys per thread); the
+// knob "batch_sort_variant" picks one.
+struct BatchSortShape { int threads, items; };
+constexpr BatchSortShape kBatchShapes[] = {{256, 16}, {256, 8}, {512, 8}, {512, 16}};
+
+int batch_sort_variant()
+{
+    const int64_t v = tune_get(TUNE_BATCH_SORT);
+    return (v >= 0 && v < 4) ? (int)v : 0;
+}
+
+template <typename K, int T, int I>
+void launch_seg(int64_t grid, const K *kin, K *kout, const int32_t *vin, int32_t *vout, int64_t N,
+                const SortSegs &segs, int shift, const uint32_t *hist, uint32_t *st, uint32_t *st_next,
+                uint32_t *ctr, uint32_t *err, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_onesweep<K, T, I>), dim3((unsigned)grid), dim3(T), 0, s, kin, kout, vin, vout,
+                       N, segs, shift, hist, st, st_next, ctr, err);
+}
+
+template <typename K>
+void launch_seg_variant(int v, int64_t grid, const K *kin, K *kout, const int32_t *vin, int32_t *vout,
+                        int64_t N, const SortSegs &segs, int shift, const uint32_t *hist,
+                        uint32_t *st, uint32_t *st_next, uint32_t *ctr, uint32_t *err, hipStream_t s)
+{
+    switch (v) {
+    case 1: launch_seg<K, 256, 8>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
+    case 2: launch_seg<K, 512, 8>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
+    case 3: launch_seg<K, 512, 16>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
+    default: launch_seg<K, 256, 16>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
+    }
+}
+
 template <int KIND, typename K>
 hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t N, int levels,
                      int code_bits, lbvh_node *nodes_, K *codes, int32_t *leaf_perm, char *ws,
@@ -212,9 +245,12 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
     float4 *nodes = reinterpret_cast<float4 *>(nodes_);
     const int passes = L.passes;
 
+    const int variant = batch_sort_variant();
+    const int tile = kBatchShapes[variant].threads * kBatchShapes[variant].items;
+    const int64_t tiles_grid = (N + tile - 1) / tile + S;   // <= L.tiles_max
     prof_begin(K_BATCH_PREP, s);
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile_off,
-                       blk_off, ctrl);
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile,
+                       tile_off, blk_off, ctrl);
     hipLaunchKernelGGL((k_batch_morton<KIND, K>), dim3(S), dim3(kSceneThreads), 0, s, prims, seg_off,
                        tile_off, code_bits / 3, scene_box, codes, hist, passes, status[0]);
     prof_end(K_BATCH_PREP, s);
@@ -227,10 +263,9 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
         int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
         uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
         prof_begin(K_SORT, s);
-        hipLaunchKernelGGL((k_onesweep<K, kBatchSortThreads, kBatchSortItems>),
-                           dim3((unsigned)L.tiles_max), dim3(kBatchSortThreads), 0, s, kin, kout, vin,
-                           vout, N, segs, p * kRadixBits, hist + p * kRadix, status[p & 1], st_next,
-                           ctrl + kCtrlTileCounter + p, ctrl + kCtrlError);
+        launch_seg_variant<K>(variant, tiles_grid, kin, kout, vin, vout, N, segs, p * kRadixBits,
+                              hist + p * kRadix, status[p & 1], st_next, ctrl + kCtrlTileCounter + p,
+                              ctrl + kCtrlError, s);
         prof_end(K_SORT, s);
     }
 

@@ -85,7 +85,7 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
     const size_t kb = (size_t)key_bytes(code_bits);
     L.passes = radix_passes(code_bits);
     L.levels = batch_levels(max_scene);
-    L.tiles_max = (N + kBatchTile - 1) / kBatchTile + S;
+    L.tiles_max = (N + kMinBatchTile - 1) / kMinBatchTile + S;
     int64_t span = kChunk;
     for (int lv = 0; lv <= L.levels; ++lv, span *= kFanout) L.blocks_max[lv] = (N + span - 1) / span + S;
     size_t off = 0;
@@ -111,9 +111,9 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 
 namespace {
 // defaults measured on MI355X: 512 x 16 for 30-bit keys, 512 x 8 for 63-bit
-std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}};
-const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64"};
-const int64_t kTuneLimit[TUNE_NUM] = {6, 6};   // values are 0 .. limit-1
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}};
+const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant"};
+const int64_t kTuneLimit[TUNE_NUM] = {6, 6, 4};   // values are 0 .. limit-1
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }

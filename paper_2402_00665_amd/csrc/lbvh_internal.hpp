@@ -24,9 +24,7 @@ constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
 constexpr int kBUThreads = 256;
 constexpr int kMaxBatchLevels = 3;    // kChunk * kFanout^3 >= LBVH_MAX_PRIMS
-constexpr int kBatchSortThreads = 256;  // radix tile of the batched build
-constexpr int kBatchSortItems = 16;
-constexpr int kBatchTile = kBatchSortThreads * kBatchSortItems;
+constexpr int kMinBatchTile = 2048;     // smallest radix tile of the batched build
 constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // query walks cut by aligned blocks of 2^12 leaves
 constexpr int kSplit2 = 7;            // ... then by blocks of 2^7 leaves
@@ -107,7 +105,7 @@ int batch_levels(int64_t max_scene);
 // ------------------------------------------------------------ tuning
 // Launch-shape knobs read by the launchers; set through lbvh_tune.
 
-enum TuneKnob { TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_NUM };
+enum TuneKnob { TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_NUM };
 int64_t tune_get(int knob);
 
 // ------------------------------------------------------------ timing

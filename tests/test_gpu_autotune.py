@@ -1,0 +1,43 @@
+"""GPU test of the self-written autotuner: it times every tile shape on a
+workload, checks each one gives the default's tree bit for bit, caches the
+winner and re-applies it."""
+
+import json
+
+import numpy as np
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_single_and_batched(tmp_path, monkeypatch):
+    import torch
+    import paper_2402_00665_amd as lb
+    from paper_2402_00665_amd import autotune
+    monkeypatch.setenv("LBVH_TUNING_CACHE", str(tmp_path / "tuning.json"))
+    rng = np.random.default_rng(30)
+    p = torch.from_numpy(rng.random((1 << 18, 3), dtype=np.float32)).cuda()
+    defaults = {k: lb.lbvh_tune(k) for k in autotune.KNOB_CANDIDATES}
+    r = autotune.tune(p, 63, reps=3, verbose=True)
+    say(f"single: {r}")
+    assert r["knob"] == "sort_variant64" and set(r["times_ms"]) == set(range(6))
+    assert {k: lb.lbvh_tune(k) for k in defaults} == defaults   # tuning restores the defaults
+    sizes = np.array([3000, 70000, 1, 0, 40000], np.int64)
+    seg = np.zeros(len(sizes) + 1, np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    pb = torch.from_numpy(rng.random((int(seg[-1]), 3), dtype=np.float32)).cuda()
+    rb = autotune.tune(pb, 30, seg_off=torch.from_numpy(seg).cuda(), max_scene=70000, reps=3)
+    say(f"batched: {rb}")
+    assert rb["knob"] == "batch_sort_variant" and set(rb["times_ms"]) == set(range(4))
+    cache = json.loads((tmp_path / "tuning.json").read_text())
+    assert len(cache) == 2
+    try:
+        assert autotune.apply(1 << 18, 63, 0) == {"sort_variant64": r["value"]}
+        assert lb.lbvh_tune("sort_variant64") == r["value"]
+        assert autotune.apply(int(seg[-1]), 30, 0, batched=True) == {"batch_sort_variant": rb["value"]}
+        assert autotune.apply(1 << 10, 63, 0) == {}   # other size bucket: nothing cached
+    finally:
+        for k, v in defaults.items():
+            lb.lbvh_tune(k, v)

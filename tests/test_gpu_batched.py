@@ -192,3 +192,20 @@ def test_batched_workload_full_size():
     say("full batched workload: generating")
     pts, off, q, qoff = workloads.batched()
     batched_parity(pts, off, 63, 0, q, qoff, 0, check_every=16)
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_batched_tile_variants(variant):
+    """Every segmented radix tile shape gives the same trees (tolerance 0)."""
+    import paper_2402_00665_amd as lb
+    old = lb.lbvh_tune("batch_sort_variant", variant)
+    try:
+        rng = np.random.default_rng([23, variant])
+        sizes = np.array([4097, 1, 2048, 0, 100003, 6000, 2047, 16384], np.int64)
+        seg = np.zeros(len(sizes) + 1, np.int64)
+        np.cumsum(sizes, out=seg[1:])
+        pts = rng.random((int(seg[-1]), 3), dtype=np.float32)
+        for bits in (30, 63):
+            batched_parity(pts, seg, bits, 0)
+    finally:
+        lb.lbvh_tune("batch_sort_variant", old)

@@ -220,3 +220,18 @@ def by_name(name: str, scale: float = 1.0) -> Workload:
         return clustered(max(1, int((1 << 24) * scale)),
                          max(1, int((1 << 20) * scale)))
     raise KeyError(name)
+
+
+def serving_request_device(k: int, n: int, m: int = 10000, device="cuda"):
+    """Request k of the serving stream, drawn on the GPU from a generator
+    seeded with k (torch's Philox stream): n points uniform in [0,1)^3
+    (float32 [n,3]) and m spheres with about 8 expected neighbours (float32
+    [m,4]).  Same k, n, m -> same bits on the same torch build."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(1_000_003 * 5 + k)
+    pts = torch.rand((n, 3), generator=g, device=device, dtype=torch.float32)
+    q = torch.empty((m, 4), device=device, dtype=torch.float32)
+    q[:, :3] = torch.rand((m, 3), generator=g, device=device, dtype=torch.float32)
+    q[:, 3] = neighbour_radius(n, 8.0)
+    return pts, q
