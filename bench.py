@@ -97,6 +97,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison (4096 scenes)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the Poisson arrival trace")
+    ap.add_argument("--serve-slots", type=int, default=3, help="streams of the batching server")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="HBM budget for in-flight batches and resident trees")
     ap.add_argument("--build-only", action="store_true",
                     help="time the build alone (no queries in the step)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
@@ -253,6 +259,7 @@ def main():
         log(f"[bench] cpu baseline done: {runs} run(s) in {tb + tq:.1f}s")
 
     batched = None if args.no_batched else bench_batched(args)
+    serving = None if args.no_serving else bench_serving(args)
 
     out = {
         "metric": "rope-LBVH build Mprims/s + stackless Mqueries/s",
@@ -282,6 +289,7 @@ def main():
                     for k, v in kernels.items()},
         "cpu_baseline": cpu,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
@@ -379,6 +387,85 @@ def bench_batched(args, reps: int = 5):
         "wall_speedup": round(plain_all_s / bw, 2),
         "identical": same,
     }
+
+
+# ---------------------------------------------------------------- serving
+
+def bench_serving(args):
+    """The serving stream (Poisson arrivals at 2000 requests/s; each request
+    builds the tree of n uniform points, n log-uniform in [1e3, 4e6], 63-bit
+    codes, and answers 10^4 spheres with about 8 expected neighbours),
+    served twice on the same trace in real time: FIFO one request at a time
+    through the single-tree entry points, and continuous batching through
+    the batched ones on 3 streams.  Latency = completion - arrival; every
+    request's answer is compared between the two on the device."""
+    import torch
+    import workloads
+    from paper_2402_00665_amd import serve
+    t0 = time.time()
+    plan = workloads.serving_plan(seconds=args.serve_seconds)
+    pts, ctr = workloads.serving_pools()
+    dp, dc = torch.from_numpy(pts).cuda(), torch.from_numpy(ctr).cuda()
+    R = len(plan["n"])
+
+    def reqs(lo, hi, shift=0.0):
+        return [serve.Request(k, float(plan["arrival"][k]) - shift, int(plan["n"][k]),
+                              int(plan["m"][k]), int(plan["p_off"][k]), int(plan["q_off"][k]),
+                              float(plan["radius"][k])) for k in range(lo, hi)]
+
+    log(f"[bench] serving: {R} requests over {args.serve_seconds:.0f}s "
+        f"(generated in {time.time() - t0:.1f}s)")
+    budget = int(args.serve_budget_gib * (1 << 30))
+    res = {}
+    outs = {}
+    for mode in ("fifo", "continuous"):
+        ex = (serve.PlainExecutor(dp, dc) if mode == "fifo"
+              else serve.GpuExecutor(dp, dc, slots=args.serve_slots))
+        warm = reqs(0, min(R, 400))
+        wsrv = serve.Server(ex, budget, max_batch=1 if mode == "fifo" else 64)
+        wsrv.run(warm)
+        wsrv.evict_all()
+        torch.cuda.synchronize()
+        srv = serve.Server(ex, budget, max_batch=1 if mode == "fifo" else 64)
+        w0 = time.perf_counter()
+        out = srv.run(reqs(0, R))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        srv.evict_all()
+        s = serve.summarize(out)
+        if not s["ok"]:
+            raise RuntimeError(f"serving {mode}: no request succeeded: {s}")
+        ok = [o for o in out if o.status == serve.LBVH_OK]
+        npts = sum(int(plan["n"][o.rid]) for o in ok)
+        nq = sum(int(plan["m"][o.rid]) for o in ok)
+        s.update({"wall_s": round(wall, 3),
+                  "mprims_per_s": round(npts / s["makespan_s"] / 1e6, 1),
+                  "mqueries_per_s": round(nq / s["makespan_s"] / 1e6, 2),
+                  "batches": len(srv.batches),
+                  "mean_batch": round(float(np.mean([b[1] for b in srv.batches])), 2),
+                  "peak_gib": round(srv.peak_bytes / (1 << 30), 2)})
+        if mode == "continuous":
+            s["slots"] = args.serve_slots
+        res[mode] = s
+        outs[mode] = out
+        log(f"[bench] serving {mode}: {s}")
+        del srv
+    same = True
+    for a, b in zip(outs["fifo"], outs["continuous"]):
+        if a.status != serve.LBVH_OK or b.status != serve.LBVH_OK:
+            same = False
+            break
+        ao, ai = a.csr()
+        bo, bi = b.csr()
+        if not (torch.equal(ao, bo) and torch.equal(ai, bi)):
+            same = False
+            break
+    f, c = res["fifo"], res["continuous"]
+    return {"workload": "serving_stream", "rate_per_s": 2000, "seconds": args.serve_seconds,
+            "requests": R, "budget_gib": args.serve_budget_gib, "fifo": f, "continuous": c,
+            "p99_speedup": round(f["p99_ms"] / c["p99_ms"], 2),
+            "throughput_ratio": round(c["throughput_rps"] / f["throughput_rps"], 3),
+            "identical": same}
 
 
 # --------------------------------------------------------------- profiles

@@ -227,6 +227,18 @@ int lbvh_build_batched(int32_t kind, const float *prims, lbvh_batch *batch,
 int lbvh_build_batched_check(const void *workspace, const lbvh_batch *batch,
                              void *stream);
 
+/* Asynchronous form of lbvh_build_batched_check, for callers that must not
+ * block (a request loop): enqueues on `stream` a 4-byte copy of the batched
+ * build's error word from `workspace` to `flag_out` (pinned host or device
+ * memory, caller-owned, 4-byte aligned).  Once the stream has passed that
+ * copy, a nonzero *flag_out means the build failed as lbvh_build_batched_check
+ * would report it (LBVH_EDEVICE).  A batch with no primitives builds nothing:
+ * then nothing is enqueued and *flag_out is left as it was, so callers zero
+ * it first.  Returns LBVH_EINVAL for null or invalid arguments, LBVH_EHIP if
+ * the copy cannot be enqueued. */
+int lbvh_build_batched_status_async(const void *workspace, const lbvh_batch *batch,
+                                    uint32_t *flag_out, void *stream);
+
 /* Workspace bytes for a batched count call over m queries. */
 int64_t lbvh_query_batched_workspace_bytes(int64_t m);
 

@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
             "lbvh_build_batched_workspace_bytes": (i64, [i64, i32, i64, i32, i32]),
             "lbvh_build_batched": (C.c_int, [i32, P, Bt, P, i64, P]),
             "lbvh_build_batched_check": (C.c_int, [P, Bt, P]),
+            "lbvh_build_batched_status_async": (C.c_int, [P, Bt, P, P]),
             "lbvh_query_batched_workspace_bytes": (i64, [i64]),
             "lbvh_query_batched_spheres_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
             "lbvh_query_batched_boxes_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
@@ -170,6 +171,10 @@ def lbvh_build_batched(kind, prims_ptr, batch: lbvh_batch, ws_ptr, ws_bytes, str
 
 def lbvh_build_batched_check(ws_ptr, batch: lbvh_batch, stream) -> int:
     return lib().lbvh_build_batched_check(ws_ptr, C.byref(batch), stream)
+
+
+def lbvh_build_batched_status_async(ws_ptr, batch: lbvh_batch, flag_ptr, stream) -> int:
+    return lib().lbvh_build_batched_status_async(ws_ptr, C.byref(batch), flag_ptr, stream)
 
 
 def lbvh_query_batched_workspace_bytes(m) -> int:
@@ -398,11 +403,15 @@ class Batch:
         return self.nodes[2 * a: 2 * a + max(2 * (b - a) - 1, 0)]
 
 
-def alloc_batch(seg_off, code_bits: int, max_scene: int, device="cuda") -> Batch:
-    """seg_off: int64 CUDA tensor [S+1]."""
+def alloc_batch(seg_off, code_bits: int, max_scene: int, device="cuda", total_n: int | None = None) -> Batch:
+    """seg_off: int64 CUDA tensor [S+1]; pass ``total_n`` (= seg_off[S]) when
+    it is known on the host, to avoid reading it back from the device."""
     torch = _torch()
     S = int(seg_off.numel()) - 1
-    N = int(seg_off[-1].item()) if S >= 0 else 0
+    if total_n is not None:
+        N = int(total_n)
+    else:
+        N = int(seg_off[-1].item()) if S >= 0 else 0
     nodes = torch.empty((max(2 * N, 1), 8), dtype=torch.int32, device=device)
     codes = torch.empty(max(N, 1), dtype=torch.int32 if code_bits == 30 else torch.int64, device=device)
     perm = torch.empty(max(N, 1), dtype=torch.int32, device=device)

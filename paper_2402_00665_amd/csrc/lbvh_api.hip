@@ -326,6 +326,21 @@ int lbvh_build_batched_check(const void *workspace, const lbvh_batch *b, void *s
     return flag ? LBVH_EDEVICE : LBVH_OK;
 }
 
+int lbvh_build_batched_status_async(const void *workspace, const lbvh_batch *b,
+                                    uint32_t *flag_out, void *stream)
+{
+    if (!b || !workspace || !flag_out) return LBVH_EINVAL;
+    if (!batch_args_ok(b->total_n, b->num_scenes, b->max_scene, b->code_bits, LBVH_POINTS))
+        return LBVH_EINVAL;
+    if (b->num_scenes == 0 || b->total_n == 0) return LBVH_OK;   // nothing built, flag untouched
+    const BatchLayout L = batch_layout(b->total_n, b->num_scenes, b->max_scene, b->code_bits);
+    const hipError_t e = hipMemcpyAsync(flag_out,
+                                        static_cast<const char *>(workspace) + L.ctrl +
+                                            kCtrlError * sizeof(uint32_t),
+                                        sizeof(uint32_t), hipMemcpyDefault, (hipStream_t)stream);
+    return e == hipSuccess ? LBVH_OK : hip_status(e);
+}
+
 int64_t lbvh_query_batched_workspace_bytes(int64_t m)
 {
     if (m < 0 || m > INT32_MAX) return LBVH_EINVAL;

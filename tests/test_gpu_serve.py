@@ -1,0 +1,102 @@
+"""The serving loop on the GPU: every request's answer must be the same in
+the mix (continuous batching over several streams), alone, and through the
+plain one-request-at-a-time path, and a sample must equal the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+POOL_P, POOL_Q = 1 << 22, 1 << 16
+
+
+@pytest.fixture(scope="module")
+def pools():
+    import torch
+    p, c = workloads.serving_pools(POOL_P, POOL_Q)
+    return p, c, torch.from_numpy(p).cuda(), torch.from_numpy(c).cuda()
+
+
+def requests(seed=2, rate=20000.0, seconds=0.02, m=1000, lo=1e3, hi=2e5):
+    from paper_2402_00665_amd import serve
+    p = workloads.serving_plan(rate, seconds, m, lo, hi, pool_points=POOL_P, pool_centres=POOL_Q,
+                               seed_stream=seed)
+    return [serve.Request(k, float(p["arrival"][k]), int(p["n"][k]), int(p["m"][k]),
+                          int(p["p_off"][k]), int(p["q_off"][k]), float(p["radius"][k]))
+            for k in range(len(p["n"]))]
+
+
+def serve_run(pools, reqs, batched=True, budget=64 << 30, slots=3):
+    import torch
+    from paper_2402_00665_amd import serve
+    ex = (serve.GpuExecutor(pools[2], pools[3], slots=slots) if batched
+          else serve.PlainExecutor(pools[2], pools[3]))
+    srv = serve.Server(ex, budget, max_batch=64 if batched else 1)
+    out = srv.run(reqs)
+    torch.cuda.synchronize()
+    return srv, out
+
+
+def same(a, b):
+    import torch
+    ao, ai = a.csr()
+    bo, bi = b.csr()
+    return bool(torch.equal(ao, bo)) and bool(torch.equal(ai, bi))
+
+
+def test_mix_alone_plain_and_oracle(pools):
+    from paper_2402_00665_amd import serve
+    reqs = requests()
+    say(f"serving: {len(reqs)} requests, mixed")
+    srv, mix = serve_run(pools, reqs)
+    assert all(o.status == serve.LBVH_OK for o in mix), [o.error for o in mix if o.status][:3]
+    sizes = [b[1] for b in srv.batches]
+    say(f"  batches: {len(sizes)}, largest {max(sizes)}, summary {serve.summarize(mix)}")
+    assert max(sizes) > 1
+    say("serving: plain FIFO")
+    _, plain = serve_run(pools, reqs, batched=False)
+    bad = [r.rid for r, a, b in zip(reqs, mix, plain) if not same(a, b)]
+    assert not bad, f"mix differs from plain for requests {bad[:10]}"
+    say("serving: alone")
+    for r in reqs[:: max(1, len(reqs) // 25)]:
+        _, alone = serve_run(pools, [serve.Request(r.rid, 0.0, r.n, r.m, r.p_off, r.q_off, r.radius)])
+        assert same(alone[0], mix[r.rid]), f"request {r.rid}: alone != mix"
+    say("serving: oracle sample")
+    pts, ctr = pools[0], pools[1]
+    for r in sorted(reqs, key=lambda r: r.n)[:: max(1, len(reqs) // 6)]:
+        t = oracle.build(0, pts[r.p_off:r.p_off + r.n], 63)
+        q = np.concatenate([ctr[r.q_off:r.q_off + r.m], np.full((r.m, 1), r.radius, np.float32)], 1)
+        eo, ei, _ = oracle.query_traverse(0, q, t)
+        go, gi = mix[r.rid].csr()
+        assert np.array_equal(go.cpu().numpy(), eo) and np.array_equal(gi.cpu().numpy(), ei), \
+            f"request {r.rid} (n={r.n}) differs from the oracle"
+        assert mix[r.rid].hits == len(ei)
+
+
+def test_tight_budget_and_resident_queries(pools):
+    import torch
+    from paper_2402_00665_amd import serve
+    reqs = requests(seed=3, seconds=0.01)
+    _, ref = serve_run(pools, reqs)
+    ex = serve.GpuExecutor(pools[2], pools[3], slots=2)
+    big = max(ex.footprint([r])[0] for r in reqs)
+    srv = serve.Server(ex, 2 * big)
+    out = srv.run(reqs)
+    torch.cuda.synchronize()
+    say(f"  tight budget {2 * big >> 20} MiB: peak {srv.peak_bytes >> 20} MiB, "
+        f"{len(srv.batches)} batches, resident {len(srv.resident)}")
+    assert all(o.status == serve.LBVH_OK for o in out)
+    assert srv.peak_bytes <= 2 * big
+    assert all(same(a, b) for a, b in zip(ref, out))
+    # the last request's tree is resident: its own queries give its answer again
+    r = reqs[-1]
+    centres = pools[3][r.q_off:r.q_off + r.m]
+    o, i = srv.query_resident(r.rid, centres, r.radius)
+    go, gi = out[r.rid].csr()
+    assert torch.equal(o, go) and torch.equal(i, gi)
+    with pytest.raises(KeyError):
+        srv.query_resident(reqs[0].rid, centres, r.radius)

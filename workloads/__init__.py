@@ -222,16 +222,34 @@ def by_name(name: str, scale: float = 1.0) -> Workload:
     raise KeyError(name)
 
 
-def serving_request_device(k: int, n: int, m: int = 10000, device="cuda"):
-    """Request k of the serving stream, drawn on the GPU from a generator
-    seeded with k (torch's Philox stream): n points uniform in [0,1)^3
-    (float32 [n,3]) and m spheres with about 8 expected neighbours (float32
-    [m,4]).  Same k, n, m -> same bits on the same torch build."""
-    import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(1_000_003 * 5 + k)
-    pts = torch.rand((n, 3), generator=g, device=device, dtype=torch.float32)
-    q = torch.empty((m, 4), device=device, dtype=torch.float32)
-    q[:, :3] = torch.rand((m, 3), generator=g, device=device, dtype=torch.float32)
-    q[:, 3] = neighbour_radius(n, 8.0)
-    return pts, q
+SERVING_POOL_POINTS = 1 << 24      # rows of the serving point pool (>= the largest request)
+SERVING_POOL_CENTRES = 1 << 20
+
+
+def serving_pools(points: int = SERVING_POOL_POINTS, centres: int = SERVING_POOL_CENTRES):
+    """Payload pools of the serving stream: float32 [points,3] and
+    [centres,3], uniform in [0,1)^3.  A request's points are a row range of
+    the first, its sphere centres a row range of the second."""
+    rng = _rng(5, 20)
+    return (rng.random((points, 3), dtype=np.float32),
+            rng.random((centres, 3), dtype=np.float32))
+
+
+def serving_plan(rate: float = 2000.0, seconds: float = 30.0, m: int = 10000,
+                 lo: float = 1e3, hi: float = 4e6, neighbours: float = 8.0,
+                 pool_points: int = SERVING_POOL_POINTS,
+                 pool_centres: int = SERVING_POOL_CENTRES, seed_stream: int = 2) -> dict:
+    """The serving stream as arrays: Poisson arrival times (s), sizes n
+    (log-uniform in [lo, hi]), query counts m, payload row offsets into the
+    pools (point offsets a multiple of 4 rows, so every request's points
+    start 16-byte aligned) and the sphere radius for about ``neighbours``
+    expected neighbours."""
+    times, sizes = serving_trace(rate, seconds, lo, hi, seed_stream)
+    sizes = np.minimum(sizes, pool_points)
+    rng = _rng(5, 30 + seed_stream)
+    p_off = rng.integers(0, (pool_points - sizes) // 4 + 1) * 4
+    q_off = rng.integers(0, pool_centres - m + 1, size=sizes.size)
+    radius = np.array([neighbour_radius(int(n), neighbours) if n > 0 else 0.0 for n in sizes],
+                      np.float32)
+    return {"arrival": times, "n": sizes.astype(np.int64), "m": np.full(sizes.size, m, np.int64),
+            "p_off": p_off.astype(np.int64), "q_off": q_off.astype(np.int64), "radius": radius}
