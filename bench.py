@@ -473,15 +473,14 @@ def bench_serving(args):
 KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name
     "k_bounds<": "bounds", "k_bounds_final": "bounds_final", "k_morton": "morton",
     "k_onesweep": "sort_pass", "k_bottomup_l0": "bottomup", "k_bottomup_up": "bottomup_up",
-    "k_split": "query_split", "k_leafwalk<": None, "copyBuffer": "copy",
+    "k_split": "query_split", "k_leafwalk_count": "query_count", "k_leafwalk_fill": "query_fill",
+    "copyBuffer": "copy",
 }
 
 
 def _group(name: str):
     for frag, g in KERNEL_GROUPS.items():
         if frag in name:
-            if frag == "k_leafwalk<":
-                return "query_fill" if "true>" in name.split("k_leafwalk<")[1][:40] else "query_count"
             return g
     return None
 

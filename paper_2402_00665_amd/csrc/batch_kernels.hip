@@ -8,7 +8,8 @@
 //                    digit histograms of scenes that span several tiles
 //   k_onesweep       segmented radix passes (tiles never cross scenes)
 //   k_bottomup_*     Alg. 4 in levels of blocks, blocks never cross scenes
-//   k_batch_walk     Alg. 1 per query on the tree of the query's scene
+//   k_batch_count / k_batch_fill
+//                    Alg. 1 per query on the tree of the query's scene
 //
 // Every scene's tree is exactly the tree a single build of that scene gives
 // (local leaf, node and primitive ids), stored at record 2*seg_off[s].
@@ -136,18 +137,15 @@ __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
 // Alg. 1 for query j on the tree of its scene (no splitting: batched
 // workloads have many scenes and light queries).  Containment reports whole
 // leaf ranges from leaf_perm, as in the single-tree leaf walk.
-template <class Q, bool FILL>
-__global__ __launch_bounds__(kBlock) void k_batch_walk(const float4 *__restrict__ nodes_all,
-                                                       const int32_t *__restrict__ perm_all,
-                                                       const int64_t *__restrict__ seg_off,
-                                                       const int64_t *__restrict__ qseg_off, int S,
-                                                       const float *__restrict__ queries, int64_t m,
-                                                       int32_t *__restrict__ counts,
-                                                       const int64_t *__restrict__ offsets,
-                                                       int32_t *__restrict__ out)
+// Alg. 1 for query j on the tree of its scene (one thread per query); the
+// fill pass writes through a HitStage (the block's queries have consecutive
+// output ranges).
+template <class Q>
+__device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const int32_t *perm_all,
+                                               const int64_t *seg_off, const int64_t *qseg_off, int S,
+                                               const float *queries, int64_t j, int &cnt,
+                                               const HitStage *st, int64_t pos)
 {
-    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= m) return;
     int lo = 0, hi = S - 1;   // scene of query j: largest s with qseg_off[s] <= j
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -156,40 +154,79 @@ __global__ __launch_bounds__(kBlock) void k_batch_walk(const float4 *__restrict_
     }
     const int64_t b0 = seg_off[lo];
     const int n = (int)(seg_off[lo + 1] - b0);
-    int64_t pos = FILL ? offsets[j] : 0;
-    int cnt = 0;
-    if (n > 0) {
-        Tree tr{nodes_all + 4 * b0, perm_all + b0, n};
-        Q q;
-        q.load(queries, (int)j);
-        const int leaf0 = n - 1;
-        int v = 0, i = 0;
-        int64_t budget = 2 * (int64_t)n;
-        while (v != -1 && --budget >= 0) {
-            float4 a, b;
-            tr.load(v, a, b);
-            const int left = __float_as_int(a.w);
-            const int rope = __float_as_int(b.w);
-            const int jr = tr.right_bound(b);
-            if (q.test(a, b)) {
-                if (v >= leaf0) {
-                    if (FILL) out[pos++] = left;
-                    else ++cnt;
-                } else if (q.contains(a, b)) {
-                    if (FILL)
-                        for (int k = i; k <= jr; ++k) out[pos++] = tr.perm[k];
-                    else
-                        cnt += jr - i + 1;
+    if (n <= 0) return;
+    Tree tr{nodes_all + 4 * b0, perm_all + b0, n};
+    Q q;
+    q.load(queries, (int)j);
+    const int leaf0 = n - 1;
+    int v = 0, i = 0;
+    int64_t budget = 2 * (int64_t)n;
+    while (v != -1 && --budget >= 0) {
+        float4 a, b;
+        tr.load(v, a, b);
+        const int left = __float_as_int(a.w);
+        const int rope = __float_as_int(b.w);
+        const int jr = tr.right_bound(b);
+        if (q.test(a, b)) {
+            if (v >= leaf0) {
+                if (st) st->put(pos++, left);
+                else ++cnt;
+            } else if (q.contains(a, b)) {
+                if (st) {
+                    st->range(pos, (int32_t)b0 + i, jr - i + 1);   // perm_all index
+                    pos += jr - i + 1;
                 } else {
-                    v = left;
-                    continue;
+                    cnt += jr - i + 1;
                 }
+            } else {
+                v = left;
+                continue;
             }
-            v = rope;
-            i = jr + 1;
         }
+        v = rope;
+        i = jr + 1;
     }
-    if (!FILL) counts[j] = cnt;
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_batch_count(const float4 *__restrict__ nodes_all,
+                                                        const int32_t *__restrict__ perm_all,
+                                                        const int64_t *__restrict__ seg_off,
+                                                        const int64_t *__restrict__ qseg_off, int S,
+                                                        const float *__restrict__ queries, int64_t m,
+                                                        int32_t *__restrict__ counts)
+{
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= m) return;
+    int cnt = 0;
+    batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, cnt, nullptr, 0);
+    counts[j] = cnt;
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_batch_fill(const float4 *__restrict__ nodes_all,
+                                                       const int32_t *__restrict__ perm_all,
+                                                       const int64_t *__restrict__ seg_off,
+                                                       const int64_t *__restrict__ qseg_off, int S,
+                                                       const float *__restrict__ queries, int64_t m,
+                                                       const int64_t *__restrict__ offsets,
+                                                       int32_t *__restrict__ out)
+{
+    __shared__ int32_t s_hits[kStageHits];
+    __shared__ HitJob s_job[kStageJobs];
+    __shared__ int s_njobs;
+    const int64_t j0 = (int64_t)blockIdx.x * kBlock;
+    if (j0 >= m) return;   // uniform over the block
+    const int64_t j = j0 + threadIdx.x;
+    const int64_t j_end = j0 + kBlock < m ? j0 + kBlock : m;
+    const HitStage st{s_hits, s_job, &s_njobs, out, perm_all, offsets[j0]};
+    if (threadIdx.x == 0) s_njobs = 0;
+    __syncthreads();
+    int unused = 0;
+    if (j < m)
+        batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, unused, &st,
+                          offsets[j]);
+    st.flush(offsets[j_end] - st.base);
 }
 
 // Radix tile shapes of the batched build (threads x keys per thread); the
@@ -298,16 +335,16 @@ hipError_t run_batch_query(const lbvh_batch *b, const float *q, const int64_t *q
     const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
     if (fill) {
         prof_begin(K_QFILL, s);
-        hipLaunchKernelGGL((k_batch_walk<Q, true>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
-                           b->seg_off, qseg_off, b->num_scenes, q, m, nullptr, offsets, indices);
+        hipLaunchKernelGGL((k_batch_fill<Q>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
+                           b->seg_off, qseg_off, b->num_scenes, q, m, offsets, indices);
         prof_end(K_QFILL, s);
         return hipGetLastError();
     }
     int32_t *counts = reinterpret_cast<int32_t *>(ws + L.cnt1);
     int64_t *partials = reinterpret_cast<int64_t *>(ws + L.partials);
     prof_begin(K_QCOUNT, s);
-    hipLaunchKernelGGL((k_batch_walk<Q, false>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
-                       b->seg_off, qseg_off, b->num_scenes, q, m, counts, nullptr, nullptr);
+    hipLaunchKernelGGL((k_batch_count<Q>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
+                       b->seg_off, qseg_off, b->num_scenes, q, m, counts);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(counts, m, nullptr, partials, offsets, s);

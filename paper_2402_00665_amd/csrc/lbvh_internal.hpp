@@ -22,7 +22,7 @@ constexpr int kMortonBlocksMax = 2048;
 constexpr int kChunk = 1024;          // leaves per level-0 block of the bottom-up pass
 constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
-constexpr int kBUThreads = 256;
+constexpr int kBUThreads = 2 * kFanout;  // one thread per handed-over climb
 constexpr int kMaxBatchLevels = 3;    // kChunk * kFanout^3 >= LBVH_MAX_PRIMS
 constexpr int kMinBatchTile = 2048;     // smallest radix tile of the batched build
 constexpr int kScanItems = 8;         // values per thread in the query scan

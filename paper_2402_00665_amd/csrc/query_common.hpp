@@ -91,6 +91,12 @@ struct Tree {
 constexpr int kAllHits = -2;
 __device__ __forceinline__ int4 piece(int q, int v, int i, int hi) { return make_int4(q, v, i, hi); }
 
+// One split level (count or fill pass).  The fill pass stages the pieces of
+// its block's kBlock input items in LDS (their output ranges are
+// consecutive) and writes them out in one coalesced run; pieces past the
+// stage capacity go straight to the output.
+constexpr int kStagePieces = 1024;
+
 template <class Q, bool FILL, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restrict__ queries, int m,
                                                   const int4 *__restrict__ in, const int64_t *in_count,
@@ -99,88 +105,103 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
                                                   const int32_t *__restrict__ overflow,
                                                   int4 *__restrict__ out)
 {
+    __shared__ int4 s_out[FILL ? kStagePieces : 1];
     const int64_t T = FIRST ? (int64_t)m : *in_count;
     const bool pass_through = FILL && *overflow;
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
-         t += (int64_t)gridDim.x * kBlock) {
-        const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
-        if (pass_through) { out[t] = it; continue; }
-        int64_t pos = FILL ? out_off[t] : 0;
-        int cnt = 0;
-        // all-hit range [a, b): one all-hit piece per block it touches
-        auto emit_range = [&](int a, int b) {
-            while (a < b) {
-                const int blk_end = ((a >> shift) + 1) << shift;
-                const int e = blk_end < b ? blk_end : b;
-                if (FILL) out[pos++] = piece(it.x, kAllHits, a, e);
-                else ++cnt;
-                a = e;
-            }
-        };
-        if (it.y == kAllHits) {
-            emit_range(it.z, it.w);
-        } else {
-            Q q;
-            q.load(queries, it.x);
-            int v = it.y, i = it.z;
-            const int hi = it.w;
-            int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
-            while (v != -1 && i < hi && --budget >= 0) {
-                float4 a, b;
-                tr.load(v, a, b);
-                const int j = tr.right_bound(b);
-                if (!q.test(a, b)) {
-                    v = __float_as_int(b.w);
-                    i = j + 1;
-                    continue;
-                }
-                if ((i >> shift) == (j >> shift)) {
-                    const int r = ((i >> shift) + 1) << shift;   // next block start
-                    const int end = r < hi ? r : hi;
-                    if (FILL) out[pos++] = piece(it.x, v, i, end);
-                    else ++cnt;
-                    if (r >= hi || r > tr.n - 1) break;
-                    v = tr.first_at(r);
-                    i = r;
-                    continue;
-                }
-                if (q.contains(a, b)) {   // multi-block node with only hits below
-                    emit_range(i, j + 1 < hi ? j + 1 : hi);
-                    v = __float_as_int(b.w);
-                    i = j + 1;
-                    continue;
-                }
-                v = __float_as_int(a.w);   // multi-block node: descend
-            }
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < T; t0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t t = t0 + threadIdx.x;
+        if (pass_through) {
+            if (t < T) out[t] = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
+            continue;
         }
-        if (!FILL) counts[t] = cnt;
+        int64_t base = 0, total = 0;
+        if (FILL) {
+            const int64_t t_end = t0 + kBlock < T ? t0 + kBlock : T;
+            base = out_off[t0];
+            total = out_off[t_end] - base;
+        }
+        auto put = [&](int64_t pos, int4 v) {
+            const int64_t r = pos - base;
+            if (r < kStagePieces) s_out[r] = v;
+            else out[pos] = v;
+        };
+        if (t < T) {
+            const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
+            int64_t pos = FILL ? out_off[t] : 0;
+            int cnt = 0;
+            // all-hit range [a, b): one all-hit piece per block it touches
+            auto emit_range = [&](int a, int b) {
+                while (a < b) {
+                    const int blk_end = ((a >> shift) + 1) << shift;
+                    const int e = blk_end < b ? blk_end : b;
+                    if (FILL) put(pos++, piece(it.x, kAllHits, a, e));
+                    else ++cnt;
+                    a = e;
+                }
+            };
+            if (it.y == kAllHits) {
+                emit_range(it.z, it.w);
+            } else {
+                Q q;
+                q.load(queries, it.x);
+                int v = it.y, i = it.z;
+                const int hi = it.w;
+                int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
+                while (v != -1 && i < hi && --budget >= 0) {
+                    float4 a, b;
+                    tr.load(v, a, b);
+                    const int j = tr.right_bound(b);
+                    if (!q.test(a, b)) {
+                        v = __float_as_int(b.w);
+                        i = j + 1;
+                        continue;
+                    }
+                    if ((i >> shift) == (j >> shift)) {
+                        const int r = ((i >> shift) + 1) << shift;   // next block start
+                        const int end = r < hi ? r : hi;
+                        if (FILL) put(pos++, piece(it.x, v, i, end));
+                        else ++cnt;
+                        if (r >= hi || r > tr.n - 1) break;
+                        v = tr.first_at(r);
+                        i = r;
+                        continue;
+                    }
+                    if (q.contains(a, b)) {   // multi-block node with only hits below
+                        emit_range(i, j + 1 < hi ? j + 1 : hi);
+                        v = __float_as_int(b.w);
+                        i = j + 1;
+                        continue;
+                    }
+                    v = __float_as_int(a.w);   // multi-block node: descend
+                }
+            }
+            if (!FILL) counts[t] = cnt;
+        }
+        if (FILL) {
+            __syncthreads();
+            const int staged = total < kStagePieces ? (int)total : kStagePieces;
+            for (int k = threadIdx.x; k < staged; k += kBlock) out[base + k] = s_out[k];
+            __syncthreads();   // the stage is reused by the next round
+        }
     }
 }
 
-template <class Q, bool FILL>
-__global__ __launch_bounds__(kBlock) void k_leafwalk(Tree tr, const float *__restrict__ queries,
-                                                     const int4 *__restrict__ in,
-                                                     const int64_t *in_count,
-                                                     int32_t *__restrict__ counts,
-                                                     const int64_t *__restrict__ hit_off,
-                                                     int32_t *__restrict__ out)
+// Count pass of the leaf walks: plain Alg. 1 restricted to each piece's
+// leaf range, counting hits (a contained node counts its whole range).
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leafwalk_count(Tree tr, const float *__restrict__ queries,
+                                                           const int4 *__restrict__ in,
+                                                           const int64_t *in_count,
+                                                           int32_t *__restrict__ counts)
 {
     const int64_t T = *in_count;
     const int leaf0 = tr.leaf0();
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
          t += (int64_t)gridDim.x * kBlock) {
         const int4 it = in[t];
-        int64_t pos = FILL ? hit_off[t] : 0;
         int cnt = 0;
-        // leaves [a, b) are all hits
-        auto take_range = [&](int a, int b) {
-            if (FILL)
-                for (int k = a; k < b; ++k) out[pos++] = tr.perm[k];
-            else
-                cnt += b - a;
-        };
         if (it.y == kAllHits) {
-            take_range(it.z, it.w);
+            cnt = it.w - it.z;
         } else {
             Q q;
             q.load(queries, it.x);
@@ -194,11 +215,10 @@ __global__ __launch_bounds__(kBlock) void k_leafwalk(Tree tr, const float *__res
                 const int rope = __float_as_int(b.w);
                 const int j = tr.right_bound(b);
                 if (q.test(a, b)) {
-                    if (v >= leaf0) {              // leaf: `left` holds its primitive
-                        if (FILL) out[pos++] = left;
-                        else ++cnt;
+                    if (v >= leaf0) {
+                        ++cnt;
                     } else if (q.contains(a, b)) {
-                        take_range(i, j + 1 < hi ? j + 1 : hi);
+                        cnt += (j + 1 < hi ? j + 1 : hi) - i;
                     } else {
                         v = left;
                         continue;
@@ -208,7 +228,123 @@ __global__ __launch_bounds__(kBlock) void k_leafwalk(Tree tr, const float *__res
                 i = j + 1;
             }
         }
-        if (!FILL) counts[t] = cnt;
+        counts[t] = cnt;
+    }
+}
+
+// Staged output of a fill pass.  The kBlock items (pieces or queries) a
+// block takes at a time have consecutive output ranges (item order is
+// output order), so the block gathers their hits in LDS and writes them out
+// in one coalesced run:
+//   1. each thread walks its item; a leaf hit goes to the stage at its
+//      offset from the block's first output slot (put), an all-hit leaf
+//      range becomes a job: output slot, first leaf_perm entry, length;
+//   2. each wave copies whole jobs from leaf_perm, 64 entries per step;
+//   3. the block writes the stage to the output.
+// Hits past the stage capacity, and jobs past the job list, are written
+// straight to the output: every hit lands in the same slot either way.
+constexpr int kStageHits = 4096;
+constexpr int kStageJobs = 256;
+
+struct HitJob {
+    int64_t pos;
+    int32_t a, len;
+};
+
+struct HitStage {
+    int32_t *hits;            // LDS [kStageHits]
+    HitJob *jobs;             // LDS [kStageJobs]
+    int *njobs;               // LDS
+    int32_t *out;
+    const int32_t *perm;      // leaf_perm that job ranges index
+    int64_t base;             // output slot of the block's first item
+
+    __device__ void put(int64_t pos, int32_t v) const
+    {
+        const int64_t r = pos - base;
+        if (r < kStageHits) hits[r] = v;
+        else out[pos] = v;
+    }
+    // perm[a .. a+len) go to output slots pos .. pos+len
+    __device__ void range(int64_t pos, int32_t a, int32_t len) const
+    {
+        if (len <= 0) return;
+        const int j = atomicAdd(njobs, 1);
+        if (j < kStageJobs) jobs[j] = HitJob{pos, a, len};
+        else
+            for (int k = 0; k < len; ++k) put(pos + k, perm[a + k]);
+    }
+    // steps 2 and 3; every thread of the block calls it
+    __device__ void flush(int64_t total) const
+    {
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int nj = *njobs < kStageJobs ? *njobs : kStageJobs;
+        for (int j = wave; j < nj; j += kBlock / 64) {
+            const HitJob jb = jobs[j];
+            for (int k = lane; k < jb.len; k += 64) put(jb.pos + k, perm[jb.a + k]);
+        }
+        __syncthreads();
+        const int staged = total < kStageHits ? (int)total : kStageHits;
+        for (int k = threadIdx.x; k < staged; k += kBlock) out[base + k] = hits[k];
+        __syncthreads();   // the stage is reused by the next round
+    }
+};
+
+// Fill pass of the leaf walks, through a HitStage.
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leafwalk_fill(Tree tr, const float *__restrict__ queries,
+                                                          const int4 *__restrict__ in,
+                                                          const int64_t *in_count,
+                                                          const int64_t *__restrict__ hit_off,
+                                                          int32_t *__restrict__ out)
+{
+    __shared__ int32_t s_hits[kStageHits];
+    __shared__ HitJob s_job[kStageJobs];
+    __shared__ int s_njobs;
+    const int64_t T = *in_count;
+    const int leaf0 = tr.leaf0();
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < T; t0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t t = t0 + threadIdx.x;
+        const int64_t t_end = t0 + kBlock < T ? t0 + kBlock : T;
+        const HitStage st{s_hits, s_job, &s_njobs, out, tr.perm, hit_off[t0]};
+        if (threadIdx.x == 0) s_njobs = 0;
+        __syncthreads();
+        if (t < T) {
+            const int4 it = in[t];
+            int64_t pos = hit_off[t];
+            if (it.y == kAllHits) {
+                st.range(pos, it.z, it.w - it.z);
+            } else {
+                Q q;
+                q.load(queries, it.x);
+                int v = it.y, i = it.z;
+                const int hi = it.w;
+                int64_t budget = 2 * (int64_t)tr.n;
+                while (v != -1 && i < hi && --budget >= 0) {
+                    float4 a, b;
+                    tr.load(v, a, b);
+                    const int left = __float_as_int(a.w);
+                    const int rope = __float_as_int(b.w);
+                    const int j = tr.right_bound(b);
+                    if (q.test(a, b)) {
+                        if (v >= leaf0) {
+                            st.put(pos++, left);
+                        } else if (q.contains(a, b)) {
+                            const int e = j + 1 < hi ? j + 1 : hi;
+                            st.range(pos, i, e - i);
+                            pos += e - i;
+                        } else {
+                            v = left;
+                            continue;
+                        }
+                    }
+                    v = rope;
+                    i = j + 1;
+                }
+            }
+        }
+        st.flush(hit_off[t_end] - st.base);
     }
 }
 

@@ -104,8 +104,8 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     // leaf walks: count hits per piece, scan, per-query offsets
     const unsigned g2 = grid_for(L.cap2);
     prof_begin(K_QCOUNT, s);
-    hipLaunchKernelGGL((k_leafwalk<Q, false>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                       S.count + 1, S.hcnt, nullptr, nullptr);
+    hipLaunchKernelGGL((k_leafwalk_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                       S.count + 1, S.hcnt);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
@@ -121,8 +121,8 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
 {
     Scratch S = carve(ws, L);
     prof_begin(K_QFILL, s);
-    hipLaunchKernelGGL((k_leafwalk<Q, true>), dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr, q,
-                       S.items2, S.count + 1, nullptr, S.hoff, indices);
+    hipLaunchKernelGGL((k_leafwalk_fill<Q>), dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr, q,
+                       S.items2, S.count + 1, S.hoff, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();
 }
