@@ -186,8 +186,13 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
  * The caller allocates every array and fills the descriptor except kind.
  *   seg_off   : device int64 [num_scenes+1], seg_off[0] = 0, non-decreasing,
  *               seg_off[num_scenes] = total_n.
- *   max_scene : an upper bound of every scene's size (host value; sizes the
- *               launch; a larger scene is reported by the check call).
+ *   max_scene : an upper bound of every scene's size (host value).  It sets
+ *               how many bottom-up levels run: the least L >= 0 with
+ *               256 * 256^L >= max_scene, which covers scenes of up to
+ *               256 * 256^L primitives.  A scene beyond that cover is
+ *               reported by the check call (LBVH_EDEVICE) and its tree is
+ *               not valid; a scene above max_scene but within the cover is
+ *               built exactly.
  *   nodes     : device, 2*total_n records.
  *   codes     : device, total_n codes, ascending within each scene.
  *   leaf_perm : device int32 [total_n]: leaf k of scene s (entry

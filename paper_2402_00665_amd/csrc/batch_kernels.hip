@@ -212,16 +212,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_fill(const float4 *__restrict_
                                                        const int64_t *__restrict__ offsets,
                                                        int32_t *__restrict__ out)
 {
-    __shared__ int32_t s_hits[kStageHits];
-    __shared__ HitJob s_job[kStageJobs];
-    __shared__ int s_njobs;
-    const int64_t j0 = (int64_t)blockIdx.x * kBlock;
-    if (j0 >= m) return;   // uniform over the block
-    const int64_t j = j0 + threadIdx.x;
-    const int64_t j_end = j0 + kBlock < m ? j0 + kBlock : m;
-    const HitStage st{s_hits, s_job, &s_njobs, out, perm_all, offsets[j0]};
-    if (threadIdx.x == 0) s_njobs = 0;
-    __syncthreads();
+    __shared__ WaveStageLds lds;
+    const int64_t j0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63);   // the wave's first query
+    if (j0 >= m) return;   // uniform over the wave
+    const int lane = threadIdx.x & 63;
+    const int64_t j = j0 + lane;
+    const int64_t j_end = j0 + 64 < m ? j0 + 64 : m;
+    if (lane == 0) lds.njobs[threadIdx.x >> 6] = 0;
+    wave_sync();
+    const HitStage st = wave_stage(lds, out, perm_all, offsets[j0]);
     int unused = 0;
     if (j < m)
         batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, unused, &st,

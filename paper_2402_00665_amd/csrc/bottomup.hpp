@@ -13,8 +13,8 @@ namespace {
 // workgroup-scope ordering (an agent-scope acquire-release CAS per tree
 // level would write back and invalidate the XCD's L2 every time):
 //   level 0   block b takes the kChunk leaves [A, B) = [b*kChunk, ...):
-//             leaf records, then the climb with `store` and every box of
-//             the chunk in LDS;
+//             leaf records, then the climb with `store`, delta* and every
+//             box of the chunk in LDS;
 //   level L   block b takes the kFanout level-(L-1) blocks under its span
 //             [A, B) and resumes their handed-over threads, with `store` and
 //             the node records in global memory.
@@ -62,6 +62,7 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
                                                              uint32_t *err)
 {
     __shared__ K s_codes[kChunk + 3];        // codes[A-1 .. B+1]
+    __shared__ uint8_t s_delta[kChunk + 2];  // delta*(g) for g in [A-1, B]
     __shared__ int32_t s_store[kChunk];      // store[A .. B-1]
     __shared__ float s_box[6][2 * kChunk];   // internal A.. then leaves A..
     __shared__ int4 s_pend[2];
@@ -85,101 +86,100 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     const int B = min(A + kChunk, n);
     const int cn = B - A;
     const int leaf0 = n - 1;
+    const int tid = threadIdx.x;
 
-    for (int t = threadIdx.x; t < cn + 3; t += kBU0Threads) {
+    for (int t = tid; t < cn + 3; t += kBU0Threads) {
         const int g = A - 1 + t;
         s_codes[t] = (g >= 0 && g < n) ? codes[g] : (K)0;
     }
-    for (int t = threadIdx.x; t < kChunk; t += kBU0Threads) s_store[t] = -1;
-    if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
+    s_store[tid] = -1;
+    if (tid < 2) s_pend[tid] = make_int4(-1, 0, 0, 0);
+    // this thread's leaf i: primitive id and box (a gather), loaded while
+    // the codes arrive
+    const int i = A + tid;
+    int prim = 0;
+    float lo[3], hi[3];
+    if (i < B) {
+        prim = perm[i];
+        Prims<KIND>::one(prims, prim, lo, hi);
+    }
     __syncthreads();
 
-    // delta*(g) for g in [A-1, B]
-    auto delta = [&](int g) -> int {
+    // delta*(g) for g in [A-1, B], from the codes in LDS
+    auto delta_codes = [&](int g) -> int {
         if (g < 0 || g >= n - 1) return 255;
         const K x = s_codes[g - A + 1] ^ s_codes[g - A + 2];
         if (x) return 64 + highest_bit(x);
         return highest_bit((uint32_t)(g ^ (g + 1)));
     };
-
-    // leaves: box, primitive id, rope (Alg. 2 on the range [i, i])
-    for (int i = A + threadIdx.x; i < B; i += kBU0Threads) {
-        const int prim = perm[i];
-        float lo[3], hi[3];
-        Prims<KIND>::one(prims, prim, lo, hi);
-        const int dr = delta(i);
-        const int rope = (i == n - 1) ? -1 : (dr < delta(i + 1) ? leaf0 + i + 1 : i + 1);
+    for (int t = tid; t < cn + 2; t += kBU0Threads) s_delta[t] = (uint8_t)delta_codes(A - 1 + t);
+    // leaf record: box, primitive id, rope (Alg. 2 on the range [i, i])
+    if (i < B) {
+        const int dr = delta_codes(i);
+        const int rope = (i == n - 1) ? -1 : (dr < delta_codes(i + 1) ? leaf0 + i + 1 : i + 1);
         store_node(nodes, leaf0 + i, lo, prim, hi, rope);
-        const int sl = kChunk + (i - A);
+        const int sl = kChunk + tid;
 #pragma unroll
         for (int a = 0; a < 3; ++a) { s_box[a][sl] = lo[a]; s_box[3 + a][sl] = hi[a]; }
     }
     __syncthreads();
 
-    if (n > 1) {
-        for (int i = A + threadIdx.x; i < B; i += kBU0Threads) {
-            int rl = i, rr = i, cur = leaf0 + i;
-            int dl = delta(i - 1), dr = delta(i);
-            float lo[3], hi[3];
-            const int sl = kChunk + (i - A);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) { lo[a] = s_box[a][sl]; hi[a] = s_box[3 + a][sl]; }
-            for (int level = 0;; ++level) {
-                if (level == kMaxDepth) {
-                    __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                int p, sib;
-                if (dr < dl) {                 // left child of its parent
-                    p = rr;
-                    if (p == B - 1) { s_pend[1] = make_int4(cur, rl, rr, 0); break; }
-                    int other = -1;
-                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, rl,
-                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
-                        break;                 // first to arrive
-                    rr = other;
-                    dr = delta(rr);
-                    sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
-                } else {                       // right child of its parent
-                    p = rl - 1;
-                    if (p == A - 1) { s_pend[0] = make_int4(cur, rl, rr, 0); break; }
-                    int other = -1;
-                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, rr,
-                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
-                        break;
-                    rl = other;
-                    dl = delta(rl - 1);
-                    sib = (rl == p) ? leaf0 + p : p;
-                }
-                const int ss = sib >= leaf0 ? kChunk + (sib - leaf0 - A) : sib - A;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = fminf(lo[a], s_box[a][ss]);
-                    hi[a] = fmaxf(hi[a], s_box[3 + a][ss]);
-                }
-                const int q = dr < dl ? rr : rl;   // Karras index of the parent
-                const int left = (rl == p) ? leaf0 + p : p;
-                int qrope;
-                if (rr == n - 1) qrope = -1;
-                else qrope = dr < delta(rr + 1) ? leaf0 + rr + 1 : rr + 1;
-                store_node(nodes, q, lo, left, hi, qrope);
-                const int qs = q - A;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
-                cur = q;
-                if (q == 0) break;
+    // Alg. 4's climb.  Both cases (the node is its parent's left or right
+    // child) run the same instructions with selects, so a wave whose lanes
+    // disagree does not run both.
+    auto delta = [&](int g) -> int { return s_delta[g - A + 1]; };
+    if (n > 1 && i < B) {
+        int rl = i, rr = i, cur = leaf0 + i;
+        int dl = delta(i - 1), dr = delta(i);
+        for (int level = 0;; ++level) {
+            if (level == kMaxDepth) {
+                __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
             }
+            const bool is_left = dr < dl;              // left child of its parent
+            const int p = is_left ? rr : rl - 1;       // the parent's split
+            if (p == (is_left ? B - 1 : A - 1)) {      // the parent is split at a chunk edge
+                s_pend[is_left ? 1 : 0] = make_int4(cur, rl, rr, 0);
+                break;
+            }
+            int other = -1;
+            if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, is_left ? rl : rr,
+                                                     __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+                break;                                 // first to arrive
+            // second to arrive: `other` is the sibling's far end
+            rr = is_left ? other : rr;
+            rl = is_left ? rl : other;
+            const int dn = delta(is_left ? rr : rl - 1);
+            dr = is_left ? dn : dr;
+            dl = is_left ? dl : dn;
+            const int sib = is_left ? ((p + 1 == rr) ? leaf0 + p + 1 : p + 1)
+                                    : ((rl == p) ? leaf0 + p : p);
+            const int ss = sib >= leaf0 ? kChunk + (sib - leaf0 - A) : sib - A;
+            const int d_next = rr == n - 1 ? 255 : delta(rr + 1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fminf(lo[a], s_box[a][ss]);
+                hi[a] = fmaxf(hi[a], s_box[3 + a][ss]);
+            }
+            const int q = dr < dl ? rr : rl;   // Karras index of the parent
+            const int left = (rl == p) ? leaf0 + p : p;
+            const int qrope = rr == n - 1 ? -1 : (dr < d_next ? leaf0 + rr + 1 : rr + 1);
+            store_node(nodes, q, lo, left, hi, qrope);
+            const int qs = q - A;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
+            cur = q;
+            if (q == 0) break;
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < cn; t += kBU0Threads) store[A + t] = s_store[t];
-    if (threadIdx.x < 2) {
-        const int4 st = s_pend[threadIdx.x];
+    if (tid < cn) store[A + tid] = s_store[tid];
+    if (tid < 2) {
+        const int4 st = s_pend[tid];
         if (bl.last && st.x >= 0)   // a climb stopped below the root of its tree
             __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pend[2 * blockIdx.x + threadIdx.x] = st;
+        pend[2 * blockIdx.x + tid] = st;
     }
 }
 

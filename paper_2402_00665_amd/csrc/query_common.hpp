@@ -91,11 +91,23 @@ struct Tree {
 constexpr int kAllHits = -2;
 __device__ __forceinline__ int4 piece(int q, int v, int i, int hi) { return make_int4(q, v, i, hi); }
 
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// all lanes of the wave have issued their LDS accesses before any lane's
+// later ones (LDS executes a wave's accesses in order; this keeps the
+// compiler from moving them across)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One split level (count or fill pass).  The fill pass stages the pieces of
-// its block's kBlock input items in LDS (their output ranges are
-// consecutive) and writes them out in one coalesced run; pieces past the
-// stage capacity go straight to the output.
-constexpr int kStagePieces = 1024;
+// each wave's 64 input items in the wave's LDS region (their output ranges
+// are consecutive) and writes them out in one coalesced run; pieces past
+// the stage capacity go straight to the output.
+constexpr int kWavePieces = 256;
 
 template <class Q, bool FILL, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restrict__ queries, int m,
@@ -105,24 +117,27 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
                                                   const int32_t *__restrict__ overflow,
                                                   int4 *__restrict__ out)
 {
-    __shared__ int4 s_out[FILL ? kStagePieces : 1];
+    __shared__ int4 s_out[FILL ? kWavesPerBlock : 1][FILL ? kWavePieces : 1];
     const int64_t T = FIRST ? (int64_t)m : *in_count;
     const bool pass_through = FILL && *overflow;
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < T; t0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t t = t0 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int4 *stage = s_out[FILL ? threadIdx.x >> 6 : 0];
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T;
+         t0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t t = t0 + lane;
         if (pass_through) {
             if (t < T) out[t] = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
             continue;
         }
         int64_t base = 0, total = 0;
         if (FILL) {
-            const int64_t t_end = t0 + kBlock < T ? t0 + kBlock : T;
+            const int64_t t_end = t0 + 64 < T ? t0 + 64 : T;
             base = out_off[t0];
             total = out_off[t_end] - base;
         }
         auto put = [&](int64_t pos, int4 v) {
             const int64_t r = pos - base;
-            if (r < kStagePieces) s_out[r] = v;
+            if (r < kWavePieces) stage[r] = v;
             else out[pos] = v;
         };
         if (t < T) {
@@ -178,10 +193,10 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
             if (!FILL) counts[t] = cnt;
         }
         if (FILL) {
-            __syncthreads();
-            const int staged = total < kStagePieces ? (int)total : kStagePieces;
-            for (int k = threadIdx.x; k < staged; k += kBlock) out[base + k] = s_out[k];
-            __syncthreads();   // the stage is reused by the next round
+            wave_sync();
+            const int staged = total < kWavePieces ? (int)total : kWavePieces;
+            for (int k = lane; k < staged; k += 64) out[base + k] = stage[k];
+            wave_sync();   // the stage is reused by the wave's next items
         }
     }
 }
@@ -232,66 +247,118 @@ __global__ __launch_bounds__(kBlock) void k_leafwalk_count(Tree tr, const float 
     }
 }
 
-// Staged output of a fill pass.  The kBlock items (pieces or queries) a
-// block takes at a time have consecutive output ranges (item order is
-// output order), so the block gathers their hits in LDS and writes them out
-// in one coalesced run:
-//   1. each thread walks its item; a leaf hit goes to the stage at its
-//      offset from the block's first output slot (put), an all-hit leaf
-//      range becomes a job: output slot, first leaf_perm entry, length;
-//   2. each wave copies whole jobs from leaf_perm, 64 entries per step;
-//   3. the block writes the stage to the output.
+// Staged output of a fill pass, per wave.  The 64 items (pieces or
+// queries) a wave takes at a time have consecutive output ranges (item
+// order is output order), so the wave gathers their hits in its own LDS
+// region and writes them out in one coalesced run:
+//   1. each lane walks its item; a leaf hit goes to the stage at its offset
+//      from the wave's first output slot (put), an all-hit leaf range
+//      becomes a job: output slot, first leaf_perm entry, length;
+//   2. the wave copies the jobs from leaf_perm, 64 entries per lane step,
+//      with up to kCopyDepth independent loads per lane in flight (a dense
+//      query's pieces are mostly such ranges: copying them one dependent
+//      load at a time is what made filling slower than counting);
+//   3. the wave writes the stage to the output.
 // Hits past the stage capacity, and jobs past the job list, are written
 // straight to the output: every hit lands in the same slot either way.
-constexpr int kStageHits = 4096;
-constexpr int kStageJobs = 256;
+// Only the wave synchronises with itself, so a long walk holds up its own
+// wave and no other.
+constexpr int kWaveHits = 1024;
+constexpr int kWaveJobs = 128;
+constexpr int kCopyDepth = 8;
 
 struct HitJob {
-    int64_t pos;
+    int32_t rel;              // output slot - the wave's first slot
     int32_t a, len;
 };
 
+struct WaveStageLds {
+    int32_t hits[kWavesPerBlock][kWaveHits];
+    HitJob jobs[kWavesPerBlock][kWaveJobs];
+    int njobs[kWavesPerBlock];
+};
+
 struct HitStage {
-    int32_t *hits;            // LDS [kStageHits]
-    HitJob *jobs;             // LDS [kStageJobs]
-    int *njobs;               // LDS
+    int32_t *hits;            // the wave's LDS [kWaveHits]
+    HitJob *jobs;             // the wave's LDS [kWaveJobs]
+    int *njobs;               // the wave's LDS counter
     int32_t *out;
     const int32_t *perm;      // leaf_perm that job ranges index
-    int64_t base;             // output slot of the block's first item
+    int64_t base;             // output slot of the wave's first item
 
     __device__ void put(int64_t pos, int32_t v) const
     {
         const int64_t r = pos - base;
-        if (r < kStageHits) hits[r] = v;
+        if (r < kWaveHits) hits[r] = v;
         else out[pos] = v;
     }
     // perm[a .. a+len) go to output slots pos .. pos+len
     __device__ void range(int64_t pos, int32_t a, int32_t len) const
     {
         if (len <= 0) return;
-        const int j = atomicAdd(njobs, 1);
-        if (j < kStageJobs) jobs[j] = HitJob{pos, a, len};
-        else
-            for (int k = 0; k < len; ++k) put(pos + k, perm[a + k]);
+        const int64_t rel = pos - base;
+        const int j = rel <= INT32_MAX ? atomicAdd(njobs, 1) : kWaveJobs;
+        if (j < kWaveJobs) {
+            jobs[j] = HitJob{(int32_t)rel, a, len};
+            return;
+        }
+        // no room: this lane copies the range, kCopyDepth loads at a time
+        for (int k0 = 0; k0 < len; k0 += kCopyDepth) {
+            int32_t v[kCopyDepth];
+#pragma unroll
+            for (int u = 0; u < kCopyDepth; ++u)
+                if (k0 + u < len) v[u] = perm[a + k0 + u];
+#pragma unroll
+            for (int u = 0; u < kCopyDepth; ++u)
+                if (k0 + u < len) put(pos + k0 + u, v[u]);
+        }
     }
-    // steps 2 and 3; every thread of the block calls it
+    // steps 2 and 3; every lane of the wave calls it
     __device__ void flush(int64_t total) const
     {
-        __syncthreads();
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        const int nj = *njobs < kStageJobs ? *njobs : kStageJobs;
-        for (int j = wave; j < nj; j += kBlock / 64) {
-            const HitJob jb = jobs[j];
-            for (int k = lane; k < jb.len; k += 64) put(jb.pos + k, perm[jb.a + k]);
+        const int lane = threadIdx.x & 63;
+        wave_sync();
+        const int nj = *njobs < kWaveJobs ? *njobs : kWaveJobs;
+        // walk the jobs in 64-entry slices; each round loads up to
+        // kCopyDepth slices (of one or more jobs) before storing any
+        int j = 0, off = 0;   // next slice: job j from entry off (uniform)
+        while (j < nj) {
+            int32_t v[kCopyDepth];
+            int64_t dst[kCopyDepth];
+#pragma unroll
+            for (int u = 0; u < kCopyDepth; ++u) {
+                dst[u] = -1;
+                if (j < nj) {
+                    const HitJob jb = jobs[j];
+                    const int k = off + lane;
+                    if (k < jb.len) {
+                        v[u] = perm[jb.a + k];
+                        dst[u] = base + jb.rel + k;
+                    }
+                    off += 64;
+                    if (off >= jb.len) { ++j; off = 0; }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kCopyDepth; ++u)
+                if (dst[u] >= 0) put(dst[u], v[u]);
         }
-        __syncthreads();
-        const int staged = total < kStageHits ? (int)total : kStageHits;
-        for (int k = threadIdx.x; k < staged; k += kBlock) out[base + k] = hits[k];
-        __syncthreads();   // the stage is reused by the next round
+        wave_sync();
+        const int staged = total < kWaveHits ? (int)total : kWaveHits;
+        for (int k = lane; k < staged; k += 64) out[base + k] = hits[k];
+        if (lane == 0) *njobs = 0;
+        wave_sync();   // the stage is reused by the wave's next items
     }
 };
 
-// Fill pass of the leaf walks, through a HitStage.
+__device__ __forceinline__ HitStage wave_stage(WaveStageLds &lds, int32_t *out, const int32_t *perm,
+                                               int64_t base)
+{
+    const int w = threadIdx.x >> 6;
+    return HitStage{lds.hits[w], lds.jobs[w], &lds.njobs[w], out, perm, base};
+}
+
+// Fill pass of the leaf walks, through a per-wave HitStage.
 template <class Q>
 __global__ __launch_bounds__(kBlock) void k_leafwalk_fill(Tree tr, const float *__restrict__ queries,
                                                           const int4 *__restrict__ in,
@@ -299,17 +366,18 @@ __global__ __launch_bounds__(kBlock) void k_leafwalk_fill(Tree tr, const float *
                                                           const int64_t *__restrict__ hit_off,
                                                           int32_t *__restrict__ out)
 {
-    __shared__ int32_t s_hits[kStageHits];
-    __shared__ HitJob s_job[kStageJobs];
-    __shared__ int s_njobs;
+    __shared__ WaveStageLds lds;
     const int64_t T = *in_count;
     const int leaf0 = tr.leaf0();
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < T; t0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t t = t0 + threadIdx.x;
-        const int64_t t_end = t0 + kBlock < T ? t0 + kBlock : T;
-        const HitStage st{s_hits, s_job, &s_njobs, out, tr.perm, hit_off[t0]};
-        if (threadIdx.x == 0) s_njobs = 0;
-        __syncthreads();
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) lds.njobs[threadIdx.x >> 6] = 0;
+    wave_sync();
+    // the wave's items: 64 consecutive ones per step of the grid-stride loop
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T;
+         t0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t t = t0 + lane;
+        const int64_t t_end = t0 + 64 < T ? t0 + 64 : T;
+        const HitStage st = wave_stage(lds, out, tr.perm, hit_off[t0]);
         if (t < T) {
             const int4 it = in[t];
             int64_t pos = hit_off[t];

@@ -123,14 +123,31 @@ def test_batched_box_queries_and_duplicates():
 
 
 def test_max_scene_too_small_is_reported():
+    """max_scene = 100 launches no level above the 256-leaf blocks, so a
+    scene of 3000 points cannot be finished: the check call reports it."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng(22)
     seg = np.array([0, 3000, 5000], np.int64)
     pts = rng.random((5000, 3), dtype=np.float32)
-    b, _, _ = run_batched(pts, seg, 30, 0, max_scene=1000)
+    b, _, _ = run_batched(pts, seg, 30, 0, max_scene=100)
     with pytest.raises(lb.LbvhError) as e:
         lb.check_batched(b)
     assert e.value.status == lb.LBVH_EDEVICE
+
+
+def test_max_scene_below_size_within_cover_is_exact():
+    """max_scene = 1000 launches one level above the 256-leaf blocks
+    (covering 65536 leaves), so a 3000-point scene is still built exactly."""
+    import paper_2402_00665_amd as lb
+    rng = np.random.default_rng(24)
+    seg = np.array([0, 3000, 5000], np.int64)
+    pts = rng.random((5000, 3), dtype=np.float32)
+    b, _, _ = run_batched(pts, seg, 30, 0, max_scene=1000)
+    lb.check_batched(b)
+    nodes_h, codes_h, perm_h = host_arrays(b)
+    for s in range(2):
+        ref = oracle.build(0, pts[seg[s]:seg[s + 1]], 30)
+        check_scene(b, s, seg, ref, nodes_h, codes_h, perm_h)
 
 
 def test_graph_capture_replays_identically():
