@@ -234,39 +234,34 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict_
                 __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
-            int p, sib;
-            if (dr < dl) {
-                p = rr;
-                if (p == B - 1) { s_pend[1] = make_int4(cur, rl, rr, 0); break; }
-                int other = -1;
-                if (__hip_atomic_compare_exchange_strong(&store[p], &other, rl, __ATOMIC_ACQ_REL,
-                                                         __ATOMIC_ACQUIRE,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
-                    break;
-                rr = other;
-                dr = delta_rank(codes, rr, n);
-                sib = (p + 1 == rr) ? leaf0 + p + 1 : p + 1;
-            } else {
-                p = rl - 1;
-                if (p == A - 1) { s_pend[0] = make_int4(cur, rl, rr, 0); break; }
-                int other = -1;
-                if (__hip_atomic_compare_exchange_strong(&store[p], &other, rr, __ATOMIC_ACQ_REL,
-                                                         __ATOMIC_ACQUIRE,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP))
-                    break;
-                rl = other;
-                dl = delta_rank(codes, rl - 1, n);
-                sib = (rl == p) ? leaf0 + p : p;
+            const bool is_left = dr < dl;              // left child of its parent
+            const int p = is_left ? rr : rl - 1;       // the parent's split
+            if (p == (is_left ? B - 1 : A - 1)) {      // split at this block's edge
+                s_pend[is_left ? 1 : 0] = make_int4(cur, rl, rr, 0);
+                break;
             }
+            int other = -1;
+            if (__hip_atomic_compare_exchange_strong(&store[p], &other, is_left ? rl : rr,
+                                                     __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+                break;                                 // first to arrive
+            rr = is_left ? other : rr;
+            rl = is_left ? rl : other;
+            const int sib = is_left ? ((p + 1 == rr) ? leaf0 + p + 1 : p + 1)
+                                    : ((rl == p) ? leaf0 + p : p);
+            // the sibling's box and the two delta* values the step needs are
+            // independent loads: issue them together
             const float4 *sp = nodes + 2 * (int64_t)sib;
             const float4 s0 = sp[0], s1 = sp[1];
+            const int dn = delta_rank(codes, is_left ? rr : rl - 1, n);
+            const int d_next = delta_rank(codes, rr + 1, n);   // 255 past the end
+            dr = is_left ? dn : dr;
+            dl = is_left ? dl : dn;
             lo[0] = fminf(lo[0], s0.x); lo[1] = fminf(lo[1], s0.y); lo[2] = fminf(lo[2], s0.z);
             hi[0] = fmaxf(hi[0], s1.x); hi[1] = fmaxf(hi[1], s1.y); hi[2] = fmaxf(hi[2], s1.z);
             const int q = dr < dl ? rr : rl;
             const int left = (rl == p) ? leaf0 + p : p;
-            int qrope;
-            if (rr == n - 1) qrope = -1;
-            else qrope = dr < delta_rank(codes, rr + 1, n) ? leaf0 + rr + 1 : rr + 1;
+            const int qrope = rr == n - 1 ? -1 : (dr < d_next ? leaf0 + rr + 1 : rr + 1);
             store_node(nodes, q, lo, left, hi, qrope);
             cur = q;
             if (q == 0) break;
