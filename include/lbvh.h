@@ -290,6 +290,11 @@ const char *lbvh_last_hip_error(void);
  *   "batch_sort_variant": tile shape of the batched build's segmented
  *       radix passes: 0 = 256 x 16 (default), 1 = 256 x 8, 2 = 512 x 8,
  *       3 = 512 x 16.
+ *   "query_split1", "query_split2": the single-tree count call cuts each
+ *       query's Alg. 1 walk into pieces at aligned blocks of 2^split1
+ *       leaves, then cuts those at blocks of 2^split2 leaves, and walks the
+ *       pieces in parallel; values 2 .. 24 (defaults 12 and 7).  The fill
+ *       call reuses the count call's pieces.
  * Results never depend on the knobs; only speed does.  Calls already
  * enqueued keep the shapes they were enqueued with. */
 int64_t lbvh_tune(const char *name, int64_t value);

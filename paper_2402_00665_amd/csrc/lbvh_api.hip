@@ -111,9 +111,11 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 
 namespace {
 // defaults measured on MI355X: 512 x 16 for 30-bit keys, 512 x 8 for 63-bit
-std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}};
-const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant"};
-const int64_t kTuneLimit[TUNE_NUM] = {6, 6, 4};   // values are 0 .. limit-1
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}};
+const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
+                                    "query_split1", "query_split2"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2};     // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {5, 5, 3, 24, 24};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
@@ -472,7 +474,7 @@ int64_t lbvh_tune(const char *name, int64_t value)
     for (int k = 0; k < TUNE_NUM; ++k) {
         if (strcmp(name, kTuneNames[k]) == 0) {
             if (value < 0) return g_tune[k].load();
-            if (value >= kTuneLimit[k]) return LBVH_EINVAL;
+            if (value < kTuneMin[k] || value > kTuneMax[k]) return LBVH_EINVAL;
             return g_tune[k].exchange(value);
         }
     }

@@ -26,8 +26,8 @@ constexpr int kBUThreads = 2 * kFanout;  // one thread per handed-over climb
 constexpr int kMaxBatchLevels = 3;    // kChunk * kFanout^3 >= LBVH_MAX_PRIMS
 constexpr int kMinBatchTile = 2048;     // smallest radix tile of the batched build
 constexpr int kScanItems = 8;         // values per thread in the query scan
-constexpr int kSplit1 = 12;           // query walks cut by aligned blocks of 2^12 leaves
-constexpr int kSplit2 = 7;            // ... then by blocks of 2^7 leaves
+constexpr int kSplit1 = 12;           // default: query walks cut by aligned blocks of 2^12 leaves
+constexpr int kSplit2 = 7;            // default: ... then by blocks of 2^7 leaves
 constexpr int kQueryGridMax = 8192;   // blocks of the grid-stride query kernels
 constexpr int kScanTile = kBlock * kScanItems;
 
@@ -105,7 +105,9 @@ int batch_levels(int64_t max_scene);
 // ------------------------------------------------------------ tuning
 // Launch-shape knobs read by the launchers; set through lbvh_tune.
 
-enum TuneKnob { TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_NUM };
+enum TuneKnob {
+    TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_NUM
+};
 int64_t tune_get(int knob);
 
 // ------------------------------------------------------------ timing

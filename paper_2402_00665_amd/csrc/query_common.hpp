@@ -201,49 +201,132 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
     }
 }
 
-// Count pass of the leaf walks: plain Alg. 1 restricted to each piece's
-// leaf range, counting hits (a contained node counts its whole range).
-template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leafwalk_count(Tree tr, const float *__restrict__ queries,
-                                                           const int4 *__restrict__ in,
-                                                           const int64_t *in_count,
-                                                           int32_t *__restrict__ counts)
+// The leaf level: one wave per level-2 piece.  A piece covers the leaves
+// [i, hi) of one aligned block of at most 2^split2 leaves, and its hits
+// are the leaves of that range whose boxes pass the test, in index order:
+// the tests are monotone under box inclusion, so every ancestor of a
+// passing leaf passes too, and Alg. 1 restricted to [i, hi) reports exactly
+// those leaves, in that order.  The wave tests 64 consecutive leaf records
+// per step (coalesced loads, no dependent chain) and counts with a ballot;
+// the fill pass writes each hit at its rank among the step's hits.  An
+// all-hit piece needs no test.
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
-    const int64_t T = *in_count;
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// A piece wider than this (a split level that ran out of piece capacity
+// passes its pieces through unsplit) keeps the walk's pruning: one lane
+// runs plain Alg. 1 from the piece's start node over [i, hi), with the
+// containment shortcut.  Returns the hit count; FILL writes the hits.
+constexpr int kLeafScanMax = 1024;
+
+template <class Q, bool FILL>
+__device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, int32_t *out,
+                              int64_t pos)
+{
     const int leaf0 = tr.leaf0();
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T;
-         t += (int64_t)gridDim.x * kBlock) {
-        const int4 it = in[t];
-        int cnt = 0;
-        if (it.y == kAllHits) {
-            cnt = it.w - it.z;
-        } else {
-            Q q;
-            q.load(queries, it.x);
-            int v = it.y, i = it.z;
-            const int hi = it.w;
-            int64_t budget = 2 * (int64_t)tr.n;
-            while (v != -1 && i < hi && --budget >= 0) {
-                float4 a, b;
-                tr.load(v, a, b);
-                const int left = __float_as_int(a.w);
-                const int rope = __float_as_int(b.w);
-                const int j = tr.right_bound(b);
-                if (q.test(a, b)) {
-                    if (v >= leaf0) {
-                        ++cnt;
-                    } else if (q.contains(a, b)) {
-                        cnt += (j + 1 < hi ? j + 1 : hi) - i;
-                    } else {
-                        v = left;
-                        continue;
-                    }
-                }
-                v = rope;
-                i = j + 1;
+    int64_t cnt = 0;
+    int64_t budget = 2 * (int64_t)tr.n;
+    while (v != -1 && i < hi && --budget >= 0) {
+        float4 a, b;
+        tr.load(v, a, b);
+        const int left = __float_as_int(a.w);
+        const int j = tr.right_bound(b);
+        if (q.test(a, b)) {
+            if (v >= leaf0) {
+                if (FILL) out[pos + cnt] = left;
+                ++cnt;
+            } else if (q.contains(a, b)) {
+                const int e = j + 1 < hi ? j + 1 : hi;
+                if (FILL)
+                    for (int k = i; k < e; ++k) out[pos + cnt + (k - i)] = tr.perm[k];
+                cnt += e - i;
+            } else {
+                v = left;
+                continue;
             }
         }
-        counts[t] = cnt;
+        v = __float_as_int(b.w);
+        i = j + 1;
+    }
+    return cnt;
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_count(Tree tr, const float *__restrict__ queries,
+                                                       const int4 *__restrict__ in,
+                                                       const int64_t *in_count,
+                                                       int32_t *__restrict__ counts)
+{
+    const int64_t T = *in_count;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; t < T; t += nw) {
+        const int4 it = in[t];
+        int cnt = it.w - it.z;
+        if (it.y != kAllHits && it.w - it.z > kLeafScanMax) {
+            Q q;
+            q.load(queries, it.x);
+            if (lane == 0) counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0);
+            continue;
+        }
+        if (it.y != kAllHits) {
+            Q q;
+            q.load(queries, it.x);
+            cnt = 0;
+            for (int k0 = it.z; k0 < it.w; k0 += 128) {   // two steps of 64 in flight
+                const int k = k0 + lane, k2 = k + 64;
+                float4 a, b, c, d;
+                if (k < it.w) tr.load(tr.leaf0() + k, a, b);
+                if (k2 < it.w) tr.load(tr.leaf0() + k2, c, d);
+                const bool h = k < it.w && q.test(a, b);
+                const bool h2 = k2 < it.w && q.test(c, d);
+                cnt += __popcll(__ballot(h)) + __popcll(__ballot(h2));
+            }
+        }
+        if (lane == 0) counts[t] = cnt;
+    }
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__restrict__ queries,
+                                                      const int4 *__restrict__ in,
+                                                      const int64_t *in_count,
+                                                      const int64_t *__restrict__ hit_off,
+                                                      int32_t *__restrict__ out)
+{
+    const int64_t T = *in_count;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; t < T; t += nw) {
+        const int4 it = in[t];
+        int64_t pos = hit_off[t];
+        if (it.y == kAllHits) {
+            for (int k = lane; k < it.w - it.z; k += 64) out[pos + k] = tr.perm[it.z + k];
+            continue;
+        }
+        Q q;
+        q.load(queries, it.x);
+        if (it.w - it.z > kLeafScanMax) {
+            if (lane == 0) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos);
+            continue;
+        }
+        for (int k0 = it.z; k0 < it.w; k0 += 128) {
+            const int k = k0 + lane, k2 = k + 64;
+            float4 a, b, c, d;
+            if (k < it.w) tr.load(tr.leaf0() + k, a, b);
+            if (k2 < it.w) tr.load(tr.leaf0() + k2, c, d);
+            const bool h = k < it.w && q.test(a, b);
+            const bool h2 = k2 < it.w && q.test(c, d);
+            const uint64_t m = __ballot(h), m2 = __ballot(h2);
+            if (h) out[pos + lanes_below(m)] = __float_as_int(a.w);      // leaf: its primitive
+            pos += __popcll(m);
+            if (h2) out[pos + lanes_below(m2)] = __float_as_int(c.w);
+            pos += __popcll(m2);
+        }
     }
 }
 
@@ -356,64 +439,6 @@ __device__ __forceinline__ HitStage wave_stage(WaveStageLds &lds, int32_t *out, 
 {
     const int w = threadIdx.x >> 6;
     return HitStage{lds.hits[w], lds.jobs[w], &lds.njobs[w], out, perm, base};
-}
-
-// Fill pass of the leaf walks, through a per-wave HitStage.
-template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leafwalk_fill(Tree tr, const float *__restrict__ queries,
-                                                          const int4 *__restrict__ in,
-                                                          const int64_t *in_count,
-                                                          const int64_t *__restrict__ hit_off,
-                                                          int32_t *__restrict__ out)
-{
-    __shared__ WaveStageLds lds;
-    const int64_t T = *in_count;
-    const int leaf0 = tr.leaf0();
-    const int lane = threadIdx.x & 63;
-    if (lane == 0) lds.njobs[threadIdx.x >> 6] = 0;
-    wave_sync();
-    // the wave's items: 64 consecutive ones per step of the grid-stride loop
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T;
-         t0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t t = t0 + lane;
-        const int64_t t_end = t0 + 64 < T ? t0 + 64 : T;
-        const HitStage st = wave_stage(lds, out, tr.perm, hit_off[t0]);
-        if (t < T) {
-            const int4 it = in[t];
-            int64_t pos = hit_off[t];
-            if (it.y == kAllHits) {
-                st.range(pos, it.z, it.w - it.z);
-            } else {
-                Q q;
-                q.load(queries, it.x);
-                int v = it.y, i = it.z;
-                const int hi = it.w;
-                int64_t budget = 2 * (int64_t)tr.n;
-                while (v != -1 && i < hi && --budget >= 0) {
-                    float4 a, b;
-                    tr.load(v, a, b);
-                    const int left = __float_as_int(a.w);
-                    const int rope = __float_as_int(b.w);
-                    const int j = tr.right_bound(b);
-                    if (q.test(a, b)) {
-                        if (v >= leaf0) {
-                            st.put(pos++, left);
-                        } else if (q.contains(a, b)) {
-                            const int e = j + 1 < hi ? j + 1 : hi;
-                            st.range(pos, i, e - i);
-                            pos += e - i;
-                        } else {
-                            v = left;
-                            continue;
-                        }
-                    }
-                    v = rope;
-                    i = j + 1;
-                }
-            }
-        }
-        st.flush(hit_off[t_end] - st.base);
-    }
 }
 
 __global__ void k_zero_i64(int64_t *p, int64_t count)

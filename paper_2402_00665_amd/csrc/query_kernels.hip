@@ -17,9 +17,14 @@
 //   (node, i, block end) and jumps to the largest node starting at the next
 //   block: internal node r if it is a right child (its split >= r), else
 //   leaf r.  Everything it skips lies inside the emitted block.
-// * Level 1 splits each query's whole walk by 2^kSplit1 leaves, level 2
-//   splits each level-1 piece by 2^kSplit2 leaves, and the leaf walk runs
-//   each level-2 piece as plain Alg. 1 restricted to its leaf range.
+// * Level 1 splits each query's whole walk by 2^split1 leaves, level 2
+//   splits each level-1 piece by 2^split2 leaves (tuning knobs).
+// * The leaf level gives each level-2 piece [i, hi) to one wave, which tests
+//   its leaves 64 at a time: both tests are monotone under box inclusion
+//   (every ancestor of a passing leaf passes), so Alg. 1 restricted to
+//   [i, hi) reports exactly the passing leaves of [i, hi), in index order.
+//   A piece wider than kLeafScanMax leaves (left unsplit after a capacity
+//   overflow) is walked with plain Alg. 1 by one lane instead.
 // * A passing node whose box the query contains has only hits below it: its
 //   leaf range [i, j] is reported from leaf_perm without visiting it (as
 //   all-hit pieces in the split levels).  Alg. 1 would visit the same
@@ -72,10 +77,11 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
 {
     Scratch S = carve(ws, L);
     const unsigned gm = grid_for(m);
-    // level 1: queries -> pieces of 2^kSplit1 leaves
+    const int split1 = (int)tune_get(TUNE_QSPLIT1), split2 = (int)tune_get(TUNE_QSPLIT2);
+    // level 1: queries -> pieces of 2^split1 leaves
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, false, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
-                       nullptr, kSplit1, S.cnt1, nullptr, nullptr, nullptr);
+                       nullptr, split1, S.cnt1, nullptr, nullptr, nullptr);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt1, m, nullptr, S.partials, S.off1, s);
@@ -84,13 +90,13 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, true, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
-                       nullptr, kSplit1, nullptr, S.off1, S.ovf + 0, S.items1);
+                       nullptr, split1, nullptr, S.off1, S.ovf + 0, S.items1);
     prof_end(K_QSPLIT, s);
-    // level 2: pieces -> pieces of 2^kSplit2 leaves
+    // level 2: pieces -> pieces of 2^split2 leaves
     const unsigned g1 = grid_for(L.cap1);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, false, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m,
-                       S.items1, S.count + 0, kSplit2, S.cnt2, nullptr, nullptr, nullptr);
+                       S.items1, S.count + 0, split2, S.cnt2, nullptr, nullptr, nullptr);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt2, L.cap1, S.count + 0, S.partials, S.off2, s);
@@ -99,12 +105,12 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, true, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m, S.items1,
-                       S.count + 0, kSplit2, nullptr, S.off2, S.ovf + 1, S.items2);
+                       S.count + 0, split2, nullptr, S.off2, S.ovf + 1, S.items2);
     prof_end(K_QSPLIT, s);
-    // leaf walks: count hits per piece, scan, per-query offsets
+    // leaf level: count hits per piece, scan, per-query offsets
     const unsigned g2 = grid_for(L.cap2);
     prof_begin(K_QCOUNT, s);
-    hipLaunchKernelGGL((k_leafwalk_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+    hipLaunchKernelGGL((k_leaf_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
                        S.count + 1, S.hcnt);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
@@ -121,7 +127,7 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
 {
     Scratch S = carve(ws, L);
     prof_begin(K_QFILL, s);
-    hipLaunchKernelGGL((k_leafwalk_fill<Q>), dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr, q,
+    hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr, q,
                        S.items2, S.count + 1, S.hoff, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();

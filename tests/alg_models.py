@@ -278,7 +278,7 @@ def alg3(delta, n, policy="random", seed=0):
     return children, ranges, root[0]
 
 
-def split_walk(n, left, rope, perm, test, S1, S2, contains=None):
+def split_walk(n, left, rope, perm, test, S1, S2, contains=None, leaf_scan=None):
     """A query's Alg. 1 walk cut into independent pieces by aligned leaf
     blocks, the way the GPU query kernels run it.
 
@@ -294,8 +294,11 @@ def split_walk(n, left, rope, perm, test, S1, S2, contains=None):
     ``contains`` (node -> the query contains its box), a passing multi-block
     node that is contained becomes all-hit ranges split at block bounds, and
     a contained internal node in the last level reports its whole leaf range
-    without being walked.  Returns the hits in order (must equal the plain
-    walk)."""
+    without being walked.  With ``leaf_scan``, a last-level piece [i, hi) no
+    wider than leaf_scan is not walked: its hits are the leaves of [i, hi)
+    that pass, in index order (the predicates are monotone under box
+    inclusion, so every ancestor of a passing leaf passes).  Returns the
+    hits in order (must equal the plain walk)."""
     ni = n - 1
 
     def idx(v):
@@ -347,6 +350,8 @@ def split_walk(n, left, rope, perm, test, S1, S2, contains=None):
     def walk(v, i, hi):
         if v == ALL:
             return [int(perm[k]) for k in range(i, hi)]
+        if leaf_scan is not None and hi - i <= leaf_scan:
+            return [int(perm[k]) for k in range(i, hi) if test(ni + k)]
         out = []
         while v != -1 and i < hi:
             j = jend(v)

@@ -248,6 +248,12 @@ def test_split_walk_equals_plain_walk(name, scale, S1, S2):
         got = split_walk(t.n, left, rope, t.perm, lambda v: pred(t.aabb[v], q), S1, S2,
                          lambda v: contains(w.qkind, t.aabb[v], q))
         assert got == ref
+        # the GPU leaf level: pieces no wider than the scan limit test their
+        # leaves directly (and a limit below the piece width keeps the walk)
+        for scan in (1 << S2, (1 << S2) // 2):
+            got = split_walk(t.n, left, rope, t.perm, lambda v: pred(t.aabb[v], q), S1, S2,
+                             lambda v: contains(w.qkind, t.aabb[v], q), leaf_scan=scan)
+            assert got == ref
 
 
 def contains(qkind, box, q):
