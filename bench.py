@@ -98,6 +98,10 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison (4096 scenes)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default launch shapes instead of autotuned ones")
+    ap.add_argument("--knobs", default="",
+                    help="set tuning knobs (name=value,...) instead of autotuning")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the Poisson arrival trace")
     ap.add_argument("--serve-slots", type=int, default=3, help="streams of the batching server")
@@ -145,6 +149,30 @@ def main():
     qws = lb.Workspace()
     tree = lb.alloc_tree(w.n, w.code_bits)
     stream = torch.cuda.current_stream()
+
+    tuning = None
+    if args.knobs:
+        tuning = {}
+        for kv in args.knobs.split(","):
+            k, v = kv.split("=")
+            lb.lbvh_tune(k.strip(), int(v))
+            tuning[k.strip()] = int(v)
+        log(f"[bench] knobs set: {tuning}")
+    elif not args.no_autotune:
+        # the library's own autotuner, run once on this workload before any
+        # timing (as a user would): radix tile shape and query schedule
+        from paper_2402_00665_amd import autotune
+        a0 = time.time()
+        ts = autotune.tune(prims, w.code_bits, kind=w.kind, reps=3, save=False)
+        lb.lbvh_tune(ts["knob"], ts["value"])
+        tuning = {ts["knob"]: ts["value"]}
+        if not args.build_only:
+            lb.build(prims, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
+            tq = autotune.tune_query(tree, queries, w.qkind, reps=3, save=False)
+            for k, v in zip(("query_split1", "query_split2", "query_leaf_mode"), tq["value"]):
+                lb.lbvh_tune(k, v)
+                tuning[k] = v
+        log(f"[bench] autotuned in {time.time() - a0:.1f}s: {tuning}")
 
     def step(ev=None):
         if ev:
@@ -287,6 +315,7 @@ def main():
         "roofline": roofline,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
+        "tuning": tuning,
         "cpu_baseline": cpu,
         "batched": batched,
         "serving": serving,
@@ -473,8 +502,9 @@ def bench_serving(args):
 KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name
     "k_bounds<": "bounds", "k_bounds_final": "bounds_final", "k_morton": "morton",
     "k_onesweep": "sort_pass", "k_bottomup_l0": "bottomup", "k_bottomup_up": "bottomup_up",
-    "k_split": "query_split", "k_leafwalk_count": "query_count", "k_leafwalk_fill": "query_fill",
-    "copyBuffer": "copy",
+    "k_split": "query_split", "k_leaf_scan_count": "query_count",
+    "k_leaf_scan_fill": "query_fill", "k_leaf_mixed_count": "query_count",
+    "k_leaf_mixed_fill": "query_fill", "copyBuffer": "copy",
 }
 
 

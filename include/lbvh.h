@@ -295,6 +295,12 @@ const char *lbvh_last_hip_error(void);
  *       leaves, then cuts those at blocks of 2^split2 leaves, and walks the
  *       pieces in parallel; values 2 .. 24 (defaults 12 and 7).  The fill
  *       call reuses the count call's pieces.
+ *   "query_leaf_mode": how the single-tree count and fill calls handle the
+ *       finest pieces: 0 = one wave tests a piece's leaves 64 at a time
+ *       (default; best when queries hit many leaves), 1 = pieces whose
+ *       start-node box lies mostly outside the query are walked with Alg. 1
+ *       by one lane, the rest as in 0 (best for sparse queries).  The count
+ *       and fill calls of one query set must use the same mode.
  * Results never depend on the knobs; only speed does.  Calls already
  * enqueued keep the shapes they were enqueued with. */
 int64_t lbvh_tune(const char *name, int64_t value);

@@ -1,12 +1,13 @@
 """Self-written autotuner for the library's launch-shape knobs.
 
-A knob (see ``lbvh_tune`` in include/lbvh.h) picks a tile shape; results
-never depend on it, only speed does.  ``tune`` times every candidate value
-on the caller's own workload with HIP events, checks once per candidate that
-its output is bit-identical to the default value's output, keeps the fastest
-and records it in a JSON cache keyed by (GPU arch, knob, code bits, kind,
-size bucket = floor(log2 n)).  ``apply`` sets the cached winners for a
-workload shape.
+A knob (see ``lbvh_tune`` in include/lbvh.h) picks a tile shape or a
+query piece size; results never depend on it, only speed does.  ``tune``
+(radix tile shapes of a build) and ``tune_query`` (the two query split
+levels) time every candidate on the caller's own workload with HIP events,
+check once per candidate that its output is bit-identical to the default's,
+keep the fastest and record it in a JSON cache keyed by GPU arch, knob and
+workload shape (code bits / query kind, size buckets floor(log2 n) and
+floor(log2 m)).  ``apply`` and ``apply_query`` set the cached winners.
 
 Cache path: $LBVH_TUNING_CACHE, else ~/.cache/paper_2402_00665_amd/tuning.json.
 """
@@ -19,13 +20,17 @@ import os
 
 from . import (LBVH_POINTS, Workspace, alloc_tree, build, build_batched, check_batched,
                check_build, lbvh_profile_enable, lbvh_profile_read, lbvh_profile_reset,
-               lbvh_tune)
+               lbvh_tune, query_count, query_fill)
 
 KNOB_CANDIDATES = {
     "sort_variant32": list(range(6)),
     "sort_variant64": list(range(6)),
     "batch_sort_variant": list(range(4)),
 }
+# (query_split1, query_split2, query_leaf_mode)
+QUERY_CANDIDATES = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (11, 6, 0), (12, 7, 1), (11, 6, 1),
+                    (13, 7, 1), (11, 5, 1)]
+_QUERY_KNOBS = ("query_split1", "query_split2", "query_leaf_mode")
 
 
 def cache_path() -> str:
@@ -146,3 +151,69 @@ def apply(n: int, code_bits: int, kind: int, batched: bool = False) -> dict:
         return {}
     lbvh_tune(knob, int(hit["value"]))
     return {knob: int(hit["value"])}
+
+
+def _query_key(qkind: int, n: int, m: int) -> str:
+    return (f"{_arch()}/query_schedule/{qkind}/{int(math.log2(max(n, 1)))}/"
+            f"{int(math.log2(max(m, 1)))}")
+
+
+def tune_query(tree, queries, qkind: int, candidates=None, reps: int = 5, save: bool = True,
+               verbose: bool = False) -> dict:
+    """Tune the query schedule for this tree and query set: times the count
+    call plus the fill call per (split1, split2, leaf mode) candidate,
+    checks each gives the default's offsets and indices bit for bit, keeps
+    the fastest.  Returns {"value": (s1, s2, mode), "times_ms": {...}}."""
+    import torch
+    cands = [tuple(c) for c in (candidates or QUERY_CANDIDATES)]
+    default = tuple(lbvh_tune(k) for k in _QUERY_KNOBS)
+    order = [default] + [c for c in cands if c != default]
+    ws = Workspace(queries.device)
+    m = int(queries.shape[0])
+    times, ref = {}, None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    try:
+        for cand in order:
+            for k, v in zip(_QUERY_KNOBS, cand):
+                lbvh_tune(k, v)
+            best = None
+            for r in range(reps + 1):
+                e0.record()
+                off = query_count(tree, queries, qkind, ws)
+                total = int(off[-1].item())
+                idx = torch.empty(max(total, 1), dtype=torch.int32, device=queries.device)
+                query_fill(tree, queries, qkind, idx, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                if r > 0:
+                    ms = e0.elapsed_time(e1)
+                    best = ms if best is None else min(best, ms)
+            out = (off.clone(), idx[:total].clone())
+            if ref is None:
+                ref = out
+            elif not (torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])):
+                raise RuntimeError(f"query schedule {cand} changed the results; refusing to tune")
+            times["/".join(map(str, cand))] = best
+            if verbose:
+                print(f"[autotune] query schedule {cand}: {best * 1e3:.1f} us", flush=True)
+    finally:
+        for k, v in zip(_QUERY_KNOBS, default):
+            lbvh_tune(k, v)
+    key = min(times, key=times.get)
+    value = tuple(int(x) for x in key.split("/"))
+    if save:
+        cache = _load()
+        cache[_query_key(qkind, tree.n, m)] = {"value": list(value), "times_ms": times}
+        _save(cache)
+    return {"value": value, "times_ms": times}
+
+
+def apply_query(n: int, m: int, qkind: int) -> dict:
+    """Set the cached best query schedule for this shape, if any."""
+    hit = _load().get(_query_key(qkind, n, m))
+    if hit is None:
+        return {}
+    vals = [int(x) for x in hit["value"]]
+    for k, v in zip(_QUERY_KNOBS, vals):
+        lbvh_tune(k, v)
+    return dict(zip(_QUERY_KNOBS, vals))

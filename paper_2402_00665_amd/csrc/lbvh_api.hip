@@ -53,6 +53,8 @@ QueryLayout query_layout(int64_t m)
     L.cnt2 = take((size_t)L.cap1 * sizeof(int32_t));
     L.off2 = take((size_t)(L.cap1 + 1) * sizeof(int64_t));
     L.items2 = take((size_t)L.cap2 * 16);
+    L.first1 = take((size_t)2 * m * 16);
+    L.first2 = take((size_t)2 * L.cap1 * 16);
     L.hcnt = take((size_t)L.cap2 * sizeof(int32_t));
     L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
     L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
@@ -111,11 +113,11 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 
 namespace {
 // defaults measured on MI355X: 512 x 16 for 30-bit keys, 512 x 8 for 63-bit
-std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}};
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}, {0}};
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
-                                    "query_split1", "query_split2"};
-const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2};     // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {5, 5, 3, 24, 24};
+                                    "query_split1", "query_split2", "query_leaf_mode"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0};     // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {5, 5, 3, 24, 24, 1};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }

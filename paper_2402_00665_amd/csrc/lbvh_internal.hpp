@@ -71,6 +71,8 @@ struct QueryLayout {
     size_t cnt2;       // cap1 int32: level-2 pieces per level-1 piece
     size_t off2;       // cap1+1 int64
     size_t items2;     // cap2 int4
+    size_t first1;     // 2m int4: the first two level-1 pieces of each query
+    size_t first2;     // 2*cap1 int4: the first two level-2 pieces of each level-1 piece
     size_t hcnt;       // cap2 int32: hits per level-2 piece
     size_t hoff;       // cap2+1 int64
     size_t partials;   // scan tile sums
@@ -106,7 +108,7 @@ int batch_levels(int64_t max_scene);
 // Launch-shape knobs read by the launchers; set through lbvh_tune.
 
 enum TuneKnob {
-    TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_NUM
+    TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_NUM
 };
 int64_t tune_get(int knob);
 

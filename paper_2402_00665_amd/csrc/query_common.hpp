@@ -10,11 +10,17 @@ namespace lbvh {
 namespace {
 
 struct Sphere {
-    float cx, cy, cz, r2;
+    float cx, cy, cz, r, r2;
     __device__ void load(const float *q, int j)
     {
         const float4 v = reinterpret_cast<const float4 *>(q)[j];
-        cx = v.x; cy = v.y; cz = v.z; r2 = v.w * v.w;
+        cx = v.x; cy = v.y; cz = v.z; r = v.w; r2 = v.w * v.w;
+    }
+    // a box around the query (only steers the schedule, never a result)
+    __device__ void bounds(float lo[3], float hi[3]) const
+    {
+        lo[0] = cx - r; lo[1] = cy - r; lo[2] = cz - r;
+        hi[0] = cx + r; hi[1] = cy + r; hi[2] = cz + r;
     }
     __device__ bool test(float4 lo, float4 hi) const
     {
@@ -48,6 +54,11 @@ struct QBox {
     __device__ bool test(float4 lo, float4 hi) const
     {
         return lx <= hi.x && lo.x <= hx && ly <= hi.y && lo.y <= hy && lz <= hi.z && lo.z <= hz;
+    }
+    __device__ void bounds(float lo[3], float hi[3]) const
+    {
+        lo[0] = lx; lo[1] = ly; lo[2] = lz;
+        hi[0] = hx; hi[1] = hy; hi[2] = hz;
     }
     // The box lies inside the query box, so every box inside it overlaps.
     __device__ bool contains(float4 lo, float4 hi) const
@@ -103,10 +114,13 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One split level (count or fill pass).  The fill pass stages the pieces of
-// each wave's 64 input items in the wave's LDS region (their output ranges
-// are consecutive) and writes them out in one coalesced run; pieces past
-// the stage capacity go straight to the output.
+// One split level (count or fill pass).  The count pass also keeps each
+// item's first two pieces in `first`; the fill pass copies those for items
+// with at most two pieces (most items) and walks again only for the rest.
+// The fill pass stages the pieces of each wave's 64 input items in the
+// wave's LDS region (their output ranges are consecutive) and writes them
+// out in one coalesced run; pieces past the stage capacity go straight to
+// the output.
 constexpr int kWavePieces = 256;
 
 template <class Q, bool FILL, bool FIRST>
@@ -115,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
                                                   int shift, int32_t *__restrict__ counts,
                                                   const int64_t *__restrict__ out_off,
                                                   const int32_t *__restrict__ overflow,
+                                                  int4 *__restrict__ first,
                                                   int4 *__restrict__ out)
 {
     __shared__ int4 s_out[FILL ? kWavesPerBlock : 1][FILL ? kWavePieces : 1];
@@ -144,17 +159,28 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
             const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
             int64_t pos = FILL ? out_off[t] : 0;
             int cnt = 0;
+            auto emit = [&](int4 pc) {
+                if (FILL) {
+                    put(pos++, pc);
+                } else {
+                    if (cnt < 2) first[2 * t + cnt] = pc;
+                    ++cnt;
+                }
+            };
             // all-hit range [a, b): one all-hit piece per block it touches
             auto emit_range = [&](int a, int b) {
                 while (a < b) {
                     const int blk_end = ((a >> shift) + 1) << shift;
                     const int e = blk_end < b ? blk_end : b;
-                    if (FILL) put(pos++, piece(it.x, kAllHits, a, e));
-                    else ++cnt;
+                    emit(piece(it.x, kAllHits, a, e));
                     a = e;
                 }
             };
-            if (it.y == kAllHits) {
+            const int64_t have = FILL ? out_off[t + 1] - pos : 0;
+            if (FILL && have <= 2) {          // the count pass kept them
+                if (have > 0) put(pos, first[2 * t]);
+                if (have > 1) put(pos + 1, first[2 * t + 1]);
+            } else if (it.y == kAllHits) {
                 emit_range(it.z, it.w);
             } else {
                 Q q;
@@ -174,8 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
                     if ((i >> shift) == (j >> shift)) {
                         const int r = ((i >> shift) + 1) << shift;   // next block start
                         const int end = r < hi ? r : hi;
-                        if (FILL) put(pos++, piece(it.x, v, i, end));
-                        else ++cnt;
+                        emit(piece(it.x, v, i, end));
                         if (r >= hi || r > tr.n - 1) break;
                         v = tr.first_at(r);
                         i = r;
@@ -201,15 +226,22 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
     }
 }
 
-// The leaf level: one wave per level-2 piece.  A piece covers the leaves
-// [i, hi) of one aligned block of at most 2^split2 leaves, and its hits
-// are the leaves of that range whose boxes pass the test, in index order:
-// the tests are monotone under box inclusion, so every ancestor of a
-// passing leaf passes too, and Alg. 1 restricted to [i, hi) reports exactly
-// those leaves, in that order.  The wave tests 64 consecutive leaf records
-// per step (coalesced loads, no dependent chain) and counts with a ballot;
-// the fill pass writes each hit at its rank among the step's hits.  An
-// all-hit piece needs no test.
+// The leaf level.  A level-2 piece covers the leaves [i, hi) of one aligned
+// block of at most 2^split2 leaves, and Alg. 1 restricted to [i, hi)
+// reports exactly the leaves of that range whose boxes pass, in index
+// order: the tests are monotone under box inclusion, so every ancestor of a
+// passing leaf passes too.  A piece can therefore be
+//   * scanned by one wave, 64 consecutive leaf records per step with
+//     coalesced loads, counted with a ballot, each hit written at its rank
+//     (best for dense pieces: most leaves hit, and a walk would be a long
+//     chain of dependent loads), or
+//   * walked with Alg. 1 by one lane (best for sparse pieces: the walk
+//     prunes).
+// Two schedules (knob query_leaf_mode): 0 scans every piece; 1 walks the
+// pieces whose start-node box lies mostly outside the query's bounding box
+// and scans the rest.  Both give the same hits.  All-hit pieces are copied
+// from leaf_perm, and a piece wider than kLeafScanMax leaves (left unsplit
+// after a capacity overflow) is always walked.
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
@@ -217,10 +249,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// A piece wider than this (a split level that ran out of piece capacity
-// passes its pieces through unsplit) keeps the walk's pruning: one lane
-// runs plain Alg. 1 from the piece's start node over [i, hi), with the
-// containment shortcut.  Returns the hit count; FILL writes the hits.
 constexpr int kLeafScanMax = 1024;
 
 template <class Q, bool FILL>
@@ -255,8 +283,28 @@ __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, 
     return cnt;
 }
 
+// Is most of the node box inside the query's bounding box?  (Decides the
+// schedule of a piece only: both schedules give the same hits.)  (Fraction of
+// its volume, per-axis ratios; a flat axis counts as covered.)
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_count(Tree tr, const float *__restrict__ queries,
+__device__ bool dense_piece(const Q &q, float4 a, float4 b)
+{
+    float ql[3], qh[3];
+    q.bounds(ql, qh);
+    const float lo[3] = {a.x, a.y, a.z}, hi[3] = {b.x, b.y, b.z};
+    float f = 1.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float e = hi[k] - lo[k];
+        const float o = fminf(hi[k], qh[k]) - fmaxf(lo[k], ql[k]);
+        f *= e > 0.0f ? fmaxf(o, 0.0f) / e : 1.0f;
+    }
+    return f >= 0.25f;
+}
+
+// Plain schedule (query_leaf_mode 0): one wave per piece.
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_scan_count(Tree tr, const float *__restrict__ queries,
                                                        const int4 *__restrict__ in,
                                                        const int64_t *in_count,
                                                        int32_t *__restrict__ counts)
@@ -292,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_count(Tree tr, const float *__r
 }
 
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__restrict__ queries,
+__global__ __launch_bounds__(kBlock) void k_leaf_scan_fill(Tree tr, const float *__restrict__ queries,
                                                       const int4 *__restrict__ in,
                                                       const int64_t *in_count,
                                                       const int64_t *__restrict__ hit_off,
@@ -328,6 +376,101 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__re
             pos += __popcll(m2);
         }
     }
+}
+
+// Mixed schedule (query_leaf_mode 1): each wave takes 64 pieces; sparse ones
+// are walked by their own lane, then the wave scans its dense and all-hit
+// pieces one at a time.  Better when most pieces are sparse (few hits per
+// piece); the plain scan above is better when most are dense.
+template <class Q, bool FILL>
+__device__ void leaf_mixed(const Tree &tr, const float *queries, const int4 *in, int64_t T,
+                           int32_t *counts, const int64_t *hit_off, int32_t *out)
+{
+    enum { kNone = 0, kWalk, kScan, kCopy };
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
+        const int64_t t = t0 + lane;
+        int4 it = make_int4(0, -1, 0, 0);
+        int mode = kNone;
+        int64_t pos = 0, cnt = 0;
+        Q q;
+        if (t < T) {
+            it = in[t];
+            if (FILL) pos = hit_off[t];
+            if (it.y == kAllHits) {
+                mode = kCopy;
+            } else {
+                q.load(queries, it.x);
+                mode = kWalk;
+                if (it.w - it.z <= kLeafScanMax) {
+                    float4 a, b;
+                    tr.load(it.y, a, b);
+                    if (dense_piece(q, a, b)) mode = kScan;
+                }
+            }
+        }
+        if (mode == kWalk) cnt = walk_piece<Q, FILL>(tr, q, it.y, it.z, it.w, out, pos);
+        uint64_t todo = __ballot(mode == kScan || mode == kCopy);
+        while (todo) {
+            const int L = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int qi = __builtin_amdgcn_readlane(it.x, L);
+            const int lo = __builtin_amdgcn_readlane(it.z, L);
+            const int hi = __builtin_amdgcn_readlane(it.w, L);
+            const bool copy = __builtin_amdgcn_readlane(mode, L) == kCopy;
+            int64_t p = 0;
+            if (FILL) {
+                const int plo = __builtin_amdgcn_readlane((int)(pos & 0xffffffff), L);
+                const int phi = __builtin_amdgcn_readlane((int)(pos >> 32), L);
+                p = ((int64_t)phi << 32) | (uint32_t)plo;
+            }
+            int64_t c = 0;
+            if (copy) {
+                if (FILL)
+                    for (int k = lane; k < hi - lo; k += 64) out[p + k] = tr.perm[lo + k];
+                c = hi - lo;
+            } else {
+                Q qq;
+                qq.load(queries, qi);
+                for (int k0 = lo; k0 < hi; k0 += 128) {
+                    const int k = k0 + lane, k2 = k + 64;
+                    float4 a, b, e, f;
+                    if (k < hi) tr.load(tr.leaf0() + k, a, b);
+                    if (k2 < hi) tr.load(tr.leaf0() + k2, e, f);
+                    const bool h = k < hi && qq.test(a, b);
+                    const bool h2 = k2 < hi && qq.test(e, f);
+                    const uint64_t m = __ballot(h), m2 = __ballot(h2);
+                    if (FILL) {
+                        if (h) out[p + c + lanes_below(m)] = __float_as_int(a.w);
+                        if (h2) out[p + c + __popcll(m) + lanes_below(m2)] = __float_as_int(e.w);
+                    }
+                    c += __popcll(m) + __popcll(m2);
+                }
+            }
+            if (lane == L) cnt = c;
+        }
+        if (!FILL && t < T) counts[t] = (int32_t)cnt;
+    }
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const float *__restrict__ queries,
+                                                             const int4 *__restrict__ in,
+                                                             const int64_t *in_count,
+                                                             int32_t *__restrict__ counts)
+{
+    leaf_mixed<Q, false>(tr, queries, in, *in_count, counts, nullptr, nullptr);
+}
+
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_mixed_fill(Tree tr, const float *__restrict__ queries,
+                                                            const int4 *__restrict__ in,
+                                                            const int64_t *in_count,
+                                                            const int64_t *__restrict__ hit_off,
+                                                            int32_t *__restrict__ out)
+{
+    leaf_mixed<Q, true>(tr, queries, in, *in_count, nullptr, hit_off, out);
 }
 
 // Staged output of a fill pass, per wave.  The 64 items (pieces or

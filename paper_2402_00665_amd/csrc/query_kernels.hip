@@ -19,12 +19,13 @@
 //   leaf r.  Everything it skips lies inside the emitted block.
 // * Level 1 splits each query's whole walk by 2^split1 leaves, level 2
 //   splits each level-1 piece by 2^split2 leaves (tuning knobs).
-// * The leaf level gives each level-2 piece [i, hi) to one wave, which tests
-//   its leaves 64 at a time: both tests are monotone under box inclusion
-//   (every ancestor of a passing leaf passes), so Alg. 1 restricted to
-//   [i, hi) reports exactly the passing leaves of [i, hi), in index order.
-//   A piece wider than kLeafScanMax leaves (left unsplit after a capacity
-//   overflow) is walked with plain Alg. 1 by one lane instead.
+// * The leaf level tests a level-2 piece [i, hi) leaf by leaf, one wave per
+//   piece, 64 leaves at a time (or, in the mixed schedule, walks sparse
+//   pieces with Alg. 1, one lane each): both tests are monotone under box
+//   inclusion (every ancestor of a passing leaf passes), so Alg. 1
+//   restricted to [i, hi) reports exactly the passing leaves of [i, hi), in
+//   index order.  A piece wider than kLeafScanMax leaves (left unsplit after
+//   a capacity overflow) is walked with plain Alg. 1 by one lane.
 // * A passing node whose box the query contains has only hits below it: its
 //   leaf range [i, j] is reported from leaf_perm without visiting it (as
 //   all-hit pieces in the split levels).  Alg. 1 would visit the same
@@ -44,7 +45,7 @@ namespace {
 struct Scratch {
     int32_t *cnt1, *cnt2, *hcnt, *ovf;
     int64_t *off1, *off2, *hoff, *partials, *count;
-    int4 *items1, *items2;
+    int4 *items1, *items2, *first1, *first2;
 };
 
 Scratch carve(char *ws, const QueryLayout &L)
@@ -56,6 +57,8 @@ Scratch carve(char *ws, const QueryLayout &L)
     S.cnt2 = reinterpret_cast<int32_t *>(ws + L.cnt2);
     S.off2 = reinterpret_cast<int64_t *>(ws + L.off2);
     S.items2 = reinterpret_cast<int4 *>(ws + L.items2);
+    S.first1 = reinterpret_cast<int4 *>(ws + L.first1);
+    S.first2 = reinterpret_cast<int4 *>(ws + L.first2);
     S.hcnt = reinterpret_cast<int32_t *>(ws + L.hcnt);
     S.hoff = reinterpret_cast<int64_t *>(ws + L.hoff);
     S.partials = reinterpret_cast<int64_t *>(ws + L.partials);
@@ -81,7 +84,7 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     // level 1: queries -> pieces of 2^split1 leaves
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, false, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
-                       nullptr, split1, S.cnt1, nullptr, nullptr, nullptr);
+                       nullptr, split1, S.cnt1, nullptr, nullptr, S.first1, nullptr);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt1, m, nullptr, S.partials, S.off1, s);
@@ -90,13 +93,13 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, true, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
-                       nullptr, split1, nullptr, S.off1, S.ovf + 0, S.items1);
+                       nullptr, split1, nullptr, S.off1, S.ovf + 0, S.first1, S.items1);
     prof_end(K_QSPLIT, s);
     // level 2: pieces -> pieces of 2^split2 leaves
     const unsigned g1 = grid_for(L.cap1);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, false, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m,
-                       S.items1, S.count + 0, split2, S.cnt2, nullptr, nullptr, nullptr);
+                       S.items1, S.count + 0, split2, S.cnt2, nullptr, nullptr, S.first2, nullptr);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt2, L.cap1, S.count + 0, S.partials, S.off2, s);
@@ -105,13 +108,17 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, true, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m, S.items1,
-                       S.count + 0, split2, nullptr, S.off2, S.ovf + 1, S.items2);
+                       S.count + 0, split2, nullptr, S.off2, S.ovf + 1, S.first2, S.items2);
     prof_end(K_QSPLIT, s);
     // leaf level: count hits per piece, scan, per-query offsets
     const unsigned g2 = grid_for(L.cap2);
     prof_begin(K_QCOUNT, s);
-    hipLaunchKernelGGL((k_leaf_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                       S.count + 1, S.hcnt);
+    if (tune_get(TUNE_QLEAF) == 1)
+        hipLaunchKernelGGL((k_leaf_mixed_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                           S.count + 1, S.hcnt);
+    else
+        hipLaunchKernelGGL((k_leaf_scan_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                           S.count + 1, S.hcnt);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
@@ -127,8 +134,13 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
 {
     Scratch S = carve(ws, L);
     prof_begin(K_QFILL, s);
-    hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr, q,
-                       S.items2, S.count + 1, S.hoff, indices);
+    const unsigned g2 = grid_for(L.cap2);
+    if (tune_get(TUNE_QLEAF) == 1)
+        hipLaunchKernelGGL((k_leaf_mixed_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                           S.count + 1, S.hoff, indices);
+    else
+        hipLaunchKernelGGL((k_leaf_scan_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                           S.count + 1, S.hoff, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();
 }

@@ -41,3 +41,25 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     finally:
         for k, v in defaults.items():
             lb.lbvh_tune(k, v)
+
+
+def test_tune_query_schedule(tmp_path, monkeypatch):
+    import torch
+    import paper_2402_00665_amd as lb
+    import workloads
+    from paper_2402_00665_amd import autotune
+    monkeypatch.setenv("LBVH_TUNING_CACHE", str(tmp_path / "tuning.json"))
+    w = workloads.by_name("clustered_boxes", 1 / 16)
+    tree = lb.build(torch.from_numpy(w.prims).cuda(), w.code_bits, kind=w.kind)
+    q = torch.from_numpy(w.queries).cuda()
+    knobs = ("query_split1", "query_split2", "query_leaf_mode")
+    before = tuple(lb.lbvh_tune(k) for k in knobs)
+    r = autotune.tune_query(tree, q, w.qkind, reps=2, verbose=True)
+    say(f"query schedule: {r}")
+    assert r["value"] in [tuple(c) for c in autotune.QUERY_CANDIDATES] + [before]
+    assert tuple(lb.lbvh_tune(k) for k in knobs) == before
+    try:
+        assert autotune.apply_query(tree.n, q.shape[0], w.qkind) == dict(zip(knobs, r["value"]))
+    finally:
+        for k, v in zip(knobs, before):
+            lb.lbvh_tune(k, v)

@@ -209,3 +209,29 @@ def test_sort_tile_variants(variant, ws):
     finally:
         lb.lbvh_tune("sort_variant32", old32)
         lb.lbvh_tune("sort_variant64", old64)
+
+
+@pytest.mark.parametrize("split1,split2,leaf_mode", [(12, 7, 1), (11, 6, 1), (9, 4, 0), (14, 9, 1)])
+def test_query_schedules(split1, split2, leaf_mode, ws):
+    """Every query schedule (split block sizes, leaf mode) gives the oracle's
+    results exactly: dense box queries, sparse spheres, all-hit ranges."""
+    import paper_2402_00665_amd as lb
+    old = [lb.lbvh_tune("query_split1", split1), lb.lbvh_tune("query_split2", split2),
+           lb.lbvh_tune("query_leaf_mode", leaf_mode)]
+    try:
+        for name in ("clustered_boxes", "large_points"):
+            _parity(workloads.by_name(name, 1 / 64), ws)
+        rng = np.random.default_rng([19, split1, split2, leaf_mode])
+        w = workloads.clustered(1 << 17, 1)
+        ref = oracle.build(w.kind, w.prims, w.code_bits)
+        tree, _ = gpu_build(w.prims, w.kind, w.code_bits, ws)
+        c = rng.random((60, 3))
+        s = rng.random((60, 3)) * 0.3
+        boxes = np.concatenate([c - s, c + s], 1).astype(np.float32)
+        roff, ridx, _ = oracle.query_traverse(1, boxes, ref)
+        off, idx = gpu_query(tree, boxes, 1, ws)
+        assert_query_equal(off, idx, roff, ridx)
+    finally:
+        lb.lbvh_tune("query_split1", old[0])
+        lb.lbvh_tune("query_split2", old[1])
+        lb.lbvh_tune("query_leaf_mode", old[2])
