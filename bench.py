@@ -60,6 +60,9 @@ def build_model_bytes_per_prim(P: int, K: int, d: int) -> float:
 
 
 KERNEL_SOURCES = ["paper_2402_00665_amd/csrc/build_kernels.hip",
+                  "paper_2402_00665_amd/csrc/bottomup.hpp",
+                  "paper_2402_00665_amd/csrc/radix_sort.hpp",
+                  "paper_2402_00665_amd/csrc/device_common.hpp",
                   "paper_2402_00665_amd/csrc/lbvh_internal.hpp"]
 
 
