@@ -105,7 +105,11 @@ int64_t lbvh_build_workspace_bytes(int64_t n, int32_t code_bits, int32_t kind);
  *   compare-and-swap per internal node, names each parent by its Karras
  *   index, and writes its left child, rope and box.
  *   prims      : device, float [n][3] (points) or [n][6] (boxes), finite,
- *                lo <= hi per axis for boxes.
+ *                lo <= hi per axis for boxes.  Non-finite coordinates are
+ *                not rejected: the tree is still well formed (leaf_perm a
+ *                permutation, every child and rope a valid node id, no
+ *                access outside the arrays), but its boxes, and the
+ *                answers of queries against it, are unspecified.
  *   n          : 0 <= n <= LBVH_MAX_PRIMS.  n = 0 gives an empty tree.
  *   code_bits  : 30 (uint32 codes) or 63 (uint64 codes).
  *   tree       : host descriptor with nodes, codes and leaf_perm set

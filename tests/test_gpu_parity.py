@@ -235,3 +235,39 @@ def test_query_schedules(split1, split2, leaf_mode, ws):
         lb.lbvh_tune("query_split1", old[0])
         lb.lbvh_tune("query_split2", old[1])
         lb.lbvh_tune("query_leaf_mode", old[2])
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_non_finite_inputs_give_a_well_formed_tree(kind, bits, ws):
+    """NaN and infinite coordinates: the tree's structure stays valid (a
+    permutation of the leaves, every link a node id, a preorder walk over
+    ropes and left children visits every leaf once), and queries run."""
+    import paper_2402_00665_amd as lb
+    rng = np.random.default_rng([26, kind, bits])
+    n = 20000
+    p = rng.random((n, 3 if kind == 0 else 6), dtype=np.float32)
+    if kind == 1:
+        p[:, 3:] = p[:, :3] + 0.01
+    bad = rng.choice(n, 300, replace=False)
+    p[bad[:100], 0] = np.nan
+    p[bad[100:200], 1] = np.inf
+    p[bad[200:], 2] = -np.inf
+    tree, _ = gpu_build(p, kind, bits, ws)
+    lb.check_build(tree)
+    _, perm, left, rope, _ = host_tree(tree)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    assert np.all((left >= 0) & (left < 2 * n - 1))
+    assert np.all((rope >= -1) & (rope < 2 * n - 1))
+    # Alg. 1 with every test passing visits each leaf once, in order
+    seen, v = [], 0
+    while v != -1 and len(seen) <= n:
+        if v >= n - 1:
+            seen.append(v - (n - 1))
+            v = rope[v]
+        else:
+            v = left[v]
+    assert seen == list(range(n))
+    q = workloads.spheres(rng.random((500, 3), dtype=np.float32), np.float32(0.05))
+    off, idx = gpu_query(tree, q, 0, ws)
+    assert off[0] == 0 and np.all(np.diff(off) >= 0) and np.all((idx >= 0) & (idx < n))
