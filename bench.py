@@ -345,6 +345,14 @@ def bench_batched(args, reps: int = 5):
     dp, ds = torch.from_numpy(pts).cuda(), torch.from_numpy(off).cuda()
     dq, dqs = torch.from_numpy(q).cuda(), torch.from_numpy(qoff).cuda()
     ws, qws = lb.Workspace(), lb.Workspace()
+    tuned = None
+    if not args.no_autotune and not args.knobs:
+        from paper_2402_00665_amd import autotune
+        t = autotune.tune(dp, 63, kind=lb.LBVH_POINTS, seg_off=ds, max_scene=max_scene, reps=2,
+                          save=False)
+        lb.lbvh_tune(t["knob"], t["value"])
+        tuned = {t["knob"]: t["value"]}
+        log(f"[bench] batched: autotuned {tuned}")
     b = lb.build_batched(dp, ds, 63, max_scene, workspace=ws)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
@@ -415,6 +423,7 @@ def bench_batched(args, reps: int = 5):
         "plain_build_ms": round(plain_build_s * 1e3, 3),
         "plain_wall_ms": round(plain_all_s * 1e3, 3),
         "plain_mprims_per_s": round(N / plain_build_s / 1e6, 1),
+        "tuning": tuned,
         "build_speedup": round(plain_build_s * 1e3 / bb, 2),
         "wall_speedup": round(plain_all_s / bw, 2),
         "identical": same,
@@ -458,6 +467,7 @@ def bench_serving(args):
         wsrv.run(warm)
         wsrv.evict_all()
         torch.cuda.synchronize()
+        torch.cuda.empty_cache()   # both modes start from the same allocator state
         srv = serve.Server(ex, budget, max_batch=1 if mode == "fifo" else 64)
         w0 = time.perf_counter()
         out = srv.run(reqs(0, R))

@@ -31,6 +31,7 @@ ERR_EXECUTOR while the loop goes on.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -136,12 +137,21 @@ class Server:
     device memory; ``max_batch`` and ``max_batch_points`` cap a batch."""
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 64,
-                 max_batch_points: int = 1 << 25, clock=None, keep_resident: bool = True):
+                 max_batch_points: int = 1 << 25, clock=None, keep_resident: bool = True,
+                 pause_gc: bool | None = None):
         self.ex = executor
+        # Python's cyclic collector, when it walks a heap holding tens of
+        # thousands of responses and tensors, stalls the loop for tens of
+        # milliseconds (it set the latency tail); run() collects once and
+        # pauses it, reference counting still frees everything (default: on
+        # with the wall clock, off with a virtual one)
+        self.pause_gc = pause_gc
         self.budget = int(budget_bytes)
         self.max_batch = max(1, int(max_batch))
         self.max_points = int(max_batch_points)
         self.clock = clock or WallClock()
+        if self.pause_gc is None:
+            self.pause_gc = isinstance(self.clock, WallClock)
         self.keep_resident = keep_resident
         self.resident = collections.OrderedDict()   # bid -> (_InFlight, {rid: k})
         self.where = {}                              # rid -> bid of its resident tree
@@ -172,6 +182,19 @@ class Server:
     # --------------------------------------------------------------- loop
 
     def run(self, requests) -> list[Response]:
+        gc_was_on = gc.isenabled()
+        if self.pause_gc:
+            gc.collect()
+            gc.disable()
+        if isinstance(self.clock, WallClock):
+            self.clock.t0 = time.perf_counter()   # arrivals count from the loop's start
+        try:
+            return self._run(requests)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _run(self, requests) -> list[Response]:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         out = {r.rid: Response(r.rid, LBVH_OK, r.arrival) for r in reqs}
         waiting = collections.deque()

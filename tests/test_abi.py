@@ -121,3 +121,15 @@ def test_one_hip_runtime_per_process():
     maps = open("/proc/self/maps").read()
     runtimes = {ln.split()[-1] for ln in maps.splitlines() if "libamdhip64" in ln}
     assert len(runtimes) == 1, runtimes
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with status 2 and
+    says so (before touching any GPU)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

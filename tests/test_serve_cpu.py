@@ -186,3 +186,29 @@ def test_summary_percentiles():
     s = serve.summarize(out)
     assert s["ok"] == 100 and s["p50_ms"] == pytest.approx(50.5) and s["p99_ms"] == pytest.approx(99.01)
     assert s["throughput_rps"] == pytest.approx(1000.0)
+
+
+def test_run_pauses_and_restores_gc(pools):
+    import gc
+    reqs = plan_requests(seed=10)[:10]
+    seen = []
+
+    class Probe(FakeExecutor):
+        def submit(self, reqs, slot):
+            seen.append(gc.isenabled())
+            return super().submit(reqs, slot)
+
+    def go():
+        clock = serve.VirtualClock()
+        srv = serve.Server(Probe(clock, *pools), 1 << 40, clock=clock, pause_gc=True)
+        return srv.run(reqs)
+
+    assert gc.isenabled()
+    out = go()
+    assert gc.isenabled() and not any(seen) and all(o.status == serve.LBVH_OK for o in out)
+    gc.disable()
+    try:
+        go()
+        assert not gc.isenabled()   # left as it was
+    finally:
+        gc.enable()
