@@ -56,6 +56,7 @@ QueryLayout query_layout(int64_t m)
     L.first1 = take((size_t)2 * m * 16);
     L.first2 = take((size_t)2 * L.cap1 * 16);
     L.hcnt = take((size_t)L.cap2 * sizeof(int32_t));
+    L.hcache = take((size_t)L.cap2 * 8 * sizeof(int32_t));
     L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
     L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
     L.ctrl = take(128);

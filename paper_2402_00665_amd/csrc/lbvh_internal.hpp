@@ -74,6 +74,7 @@ struct QueryLayout {
     size_t first1;     // 2m int4: the first two level-1 pieces of each query
     size_t first2;     // 2*cap1 int4: the first two level-2 pieces of each level-1 piece
     size_t hcnt;       // cap2 int32: hits per level-2 piece
+    size_t hcache;     // cap2 x 8 int32: each level-2 piece's first hits
     size_t hoff;       // cap2+1 int64
     size_t partials;   // scan tile sums
     size_t ctrl;       // overflow flags and piece counts

@@ -251,9 +251,14 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 
 constexpr int kLeafScanMax = 1024;
 
+// The count pass keeps each piece's first kHitCache hits in the workspace;
+// the fill pass copies them for pieces with at most that many hits (sparse
+// queries: most pieces) instead of testing or walking the piece again.
+constexpr int kHitCache = 8;
+
 template <class Q, bool FILL>
 __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, int32_t *out,
-                              int64_t pos)
+                              int64_t pos, int32_t *cache = nullptr)
 {
     const int leaf0 = tr.leaf0();
     int64_t cnt = 0;
@@ -266,11 +271,15 @@ __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, 
         if (q.test(a, b)) {
             if (v >= leaf0) {
                 if (FILL) out[pos + cnt] = left;
+                else if (cache && cnt < kHitCache) cache[cnt] = left;
                 ++cnt;
             } else if (q.contains(a, b)) {
                 const int e = j + 1 < hi ? j + 1 : hi;
                 if (FILL)
                     for (int k = i; k < e; ++k) out[pos + cnt + (k - i)] = tr.perm[k];
+                else if (cache)
+                    for (int k = i; k < e && cnt + (k - i) < kHitCache; ++k)
+                        cache[cnt + (k - i)] = tr.perm[k];
                 cnt += e - i;
             } else {
                 v = left;
@@ -307,7 +316,8 @@ template <class Q>
 __global__ __launch_bounds__(kBlock) void k_leaf_scan_count(Tree tr, const float *__restrict__ queries,
                                                        const int4 *__restrict__ in,
                                                        const int64_t *in_count,
-                                                       int32_t *__restrict__ counts)
+                                                       int32_t *__restrict__ counts,
+                                                       int32_t *__restrict__ cache)
 {
     const int64_t T = *in_count;
     const int lane = threadIdx.x & 63;
@@ -318,13 +328,16 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan_count(Tree tr, const float
         if (it.y != kAllHits && it.w - it.z > kLeafScanMax) {
             Q q;
             q.load(queries, it.x);
-            if (lane == 0) counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0);
+            if (lane == 0)
+                counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0,
+                                                          cache + t * kHitCache);
             continue;
         }
         if (it.y != kAllHits) {
             Q q;
             q.load(queries, it.x);
             cnt = 0;
+            int32_t *kept = cache + t * kHitCache;
             for (int k0 = it.z; k0 < it.w; k0 += 128) {   // two steps of 64 in flight
                 const int k = k0 + lane, k2 = k + 64;
                 float4 a, b, c, d;
@@ -332,7 +345,11 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan_count(Tree tr, const float
                 if (k2 < it.w) tr.load(tr.leaf0() + k2, c, d);
                 const bool h = k < it.w && q.test(a, b);
                 const bool h2 = k2 < it.w && q.test(c, d);
-                cnt += __popcll(__ballot(h)) + __popcll(__ballot(h2));
+                const uint64_t m = __ballot(h), m2 = __ballot(h2);
+                const int r = cnt + (int)lanes_below(m), r2 = cnt + __popcll(m) + (int)lanes_below(m2);
+                if (h && r < kHitCache) kept[r] = __float_as_int(a.w);
+                if (h2 && r2 < kHitCache) kept[r2] = __float_as_int(c.w);
+                cnt += __popcll(m) + __popcll(m2);
             }
         }
         if (lane == 0) counts[t] = cnt;
@@ -344,6 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan_fill(Tree tr, const float 
                                                       const int4 *__restrict__ in,
                                                       const int64_t *in_count,
                                                       const int64_t *__restrict__ hit_off,
+                                                      const int32_t *__restrict__ cache,
                                                       int32_t *__restrict__ out)
 {
     const int64_t T = *in_count;
@@ -354,6 +372,11 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan_fill(Tree tr, const float 
         int64_t pos = hit_off[t];
         if (it.y == kAllHits) {
             for (int k = lane; k < it.w - it.z; k += 64) out[pos + k] = tr.perm[it.z + k];
+            continue;
+        }
+        const int64_t have = hit_off[t + 1] - pos;
+        if (have <= kHitCache) {   // the count pass kept them
+            if (lane < have) out[pos + lane] = cache[t * kHitCache + lane];
             continue;
         }
         Q q;
@@ -384,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan_fill(Tree tr, const float 
 // piece); the plain scan above is better when most are dense.
 template <class Q, bool FILL>
 __device__ void leaf_mixed(const Tree &tr, const float *queries, const int4 *in, int64_t T,
-                           int32_t *counts, const int64_t *hit_off, int32_t *out)
+                           int32_t *counts, const int64_t *hit_off, int32_t *cache, int32_t *out)
 {
     enum { kNone = 0, kWalk, kScan, kCopy };
     const int lane = threadIdx.x & 63;
@@ -410,7 +433,16 @@ __device__ void leaf_mixed(const Tree &tr, const float *queries, const int4 *in,
                 }
             }
         }
-        if (mode == kWalk) cnt = walk_piece<Q, FILL>(tr, q, it.y, it.z, it.w, out, pos);
+        if (FILL && mode != kNone && mode != kCopy) {
+            const int64_t have = hit_off[t + 1] - pos;
+            if (have <= kHitCache) {   // the count pass kept them
+                for (int k = 0; k < have; ++k) out[pos + k] = cache[t * kHitCache + k];
+                mode = kNone;
+            }
+        }
+        if (mode == kWalk)
+            cnt = walk_piece<Q, FILL>(tr, q, it.y, it.z, it.w, out, pos,
+                                      FILL ? nullptr : cache + t * kHitCache);
         uint64_t todo = __ballot(mode == kScan || mode == kCopy);
         while (todo) {
             const int L = __ffsll((unsigned long long)todo) - 1;
@@ -433,6 +465,7 @@ __device__ void leaf_mixed(const Tree &tr, const float *queries, const int4 *in,
             } else {
                 Q qq;
                 qq.load(queries, qi);
+                const int64_t tl = t0 + L;   // the piece's index
                 for (int k0 = lo; k0 < hi; k0 += 128) {
                     const int k = k0 + lane, k2 = k + 64;
                     float4 a, b, e, f;
@@ -441,9 +474,13 @@ __device__ void leaf_mixed(const Tree &tr, const float *queries, const int4 *in,
                     const bool h = k < hi && qq.test(a, b);
                     const bool h2 = k2 < hi && qq.test(e, f);
                     const uint64_t m = __ballot(h), m2 = __ballot(h2);
+                    const int64_t r = c + lanes_below(m), r2 = c + __popcll(m) + lanes_below(m2);
                     if (FILL) {
-                        if (h) out[p + c + lanes_below(m)] = __float_as_int(a.w);
-                        if (h2) out[p + c + __popcll(m) + lanes_below(m2)] = __float_as_int(e.w);
+                        if (h) out[p + r] = __float_as_int(a.w);
+                        if (h2) out[p + r2] = __float_as_int(e.w);
+                    } else {
+                        if (h && r < kHitCache) cache[tl * kHitCache + r] = __float_as_int(a.w);
+                        if (h2 && r2 < kHitCache) cache[tl * kHitCache + r2] = __float_as_int(e.w);
                     }
                     c += __popcll(m) + __popcll(m2);
                 }
@@ -458,9 +495,10 @@ template <class Q>
 __global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const float *__restrict__ queries,
                                                              const int4 *__restrict__ in,
                                                              const int64_t *in_count,
-                                                             int32_t *__restrict__ counts)
+                                                             int32_t *__restrict__ counts,
+                                                             int32_t *__restrict__ cache)
 {
-    leaf_mixed<Q, false>(tr, queries, in, *in_count, counts, nullptr, nullptr);
+    leaf_mixed<Q, false>(tr, queries, in, *in_count, counts, nullptr, cache, nullptr);
 }
 
 template <class Q>
@@ -468,9 +506,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_mixed_fill(Tree tr, const float
                                                             const int4 *__restrict__ in,
                                                             const int64_t *in_count,
                                                             const int64_t *__restrict__ hit_off,
+                                                            int32_t *__restrict__ cache,
                                                             int32_t *__restrict__ out)
 {
-    leaf_mixed<Q, true>(tr, queries, in, *in_count, nullptr, hit_off, out);
+    leaf_mixed<Q, true>(tr, queries, in, *in_count, nullptr, hit_off, cache, out);
 }
 
 // Staged output of a fill pass, per wave.  The 64 items (pieces or

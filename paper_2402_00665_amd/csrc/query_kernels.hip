@@ -46,6 +46,7 @@ struct Scratch {
     int32_t *cnt1, *cnt2, *hcnt, *ovf;
     int64_t *off1, *off2, *hoff, *partials, *count;
     int4 *items1, *items2, *first1, *first2;
+    int32_t *hcache;
 };
 
 Scratch carve(char *ws, const QueryLayout &L)
@@ -59,6 +60,7 @@ Scratch carve(char *ws, const QueryLayout &L)
     S.items2 = reinterpret_cast<int4 *>(ws + L.items2);
     S.first1 = reinterpret_cast<int4 *>(ws + L.first1);
     S.first2 = reinterpret_cast<int4 *>(ws + L.first2);
+    S.hcache = reinterpret_cast<int32_t *>(ws + L.hcache);
     S.hcnt = reinterpret_cast<int32_t *>(ws + L.hcnt);
     S.hoff = reinterpret_cast<int64_t *>(ws + L.hoff);
     S.partials = reinterpret_cast<int64_t *>(ws + L.partials);
@@ -115,10 +117,10 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     prof_begin(K_QCOUNT, s);
     if (tune_get(TUNE_QLEAF) == 1)
         hipLaunchKernelGGL((k_leaf_mixed_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hcnt);
+                           S.count + 1, S.hcnt, S.hcache);
     else
         hipLaunchKernelGGL((k_leaf_scan_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hcnt);
+                           S.count + 1, S.hcnt, S.hcache);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
@@ -137,10 +139,10 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
     const unsigned g2 = grid_for(L.cap2);
     if (tune_get(TUNE_QLEAF) == 1)
         hipLaunchKernelGGL((k_leaf_mixed_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hoff, indices);
+                           S.count + 1, S.hoff, S.hcache, indices);
     else
         hipLaunchKernelGGL((k_leaf_scan_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hoff, indices);
+                           S.count + 1, S.hoff, S.hcache, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();
 }
