@@ -255,8 +255,10 @@ int64_t lbvh_query_batched_workspace_bytes(int64_t m);
  * qseg_off[s] <= j < qseg_off[s+1] (device int64 [num_scenes+1]) and walks
  * that scene's tree (Alg. 1; same predicates and order as the single-tree
  * calls).  Indices are primitive ids local to the scene.  The count call
- * writes CSR offsets [m+1]; the fill call repeats the walk and writes the
- * ids at those offsets. */
+ * writes CSR offsets [m+1] and keeps each query's first hits in the
+ * workspace; the fill call, given the same workspace (unchanged since the
+ * count call of the same queries), copies those for queries with few hits
+ * and repeats the walk for the others, writing the ids at the offsets. */
 int lbvh_query_batched_spheres_count(const lbvh_batch *batch, const float *xyzr,
                                      const int64_t *qseg_off, int64_t m,
                                      int64_t *offsets, void *workspace,
@@ -268,10 +270,12 @@ int lbvh_query_batched_boxes_count(const lbvh_batch *batch, const float *lohi,
 int lbvh_query_batched_spheres_fill(const lbvh_batch *batch, const float *xyzr,
                                     const int64_t *qseg_off, int64_t m,
                                     const int64_t *offsets, int32_t *indices,
+                                    const void *workspace, int64_t workspace_bytes,
                                     void *stream);
 int lbvh_query_batched_boxes_fill(const lbvh_batch *batch, const float *lohi,
                                   const int64_t *qseg_off, int64_t m,
                                   const int64_t *offsets, int32_t *indices,
+                                  const void *workspace, int64_t workspace_bytes,
                                   void *stream);
 
 /* ------------------------------------------------------------ utilities */

@@ -81,8 +81,8 @@ def lib() -> C.CDLL:
             "lbvh_query_batched_workspace_bytes": (i64, [i64]),
             "lbvh_query_batched_spheres_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
             "lbvh_query_batched_boxes_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
-            "lbvh_query_batched_spheres_fill": (C.c_int, [Bt, P, P, i64, P, P, P]),
-            "lbvh_query_batched_boxes_fill": (C.c_int, [Bt, P, P, i64, P, P, P]),
+            "lbvh_query_batched_spheres_fill": (C.c_int, [Bt, P, P, i64, P, P, P, i64, P]),
+            "lbvh_query_batched_boxes_fill": (C.c_int, [Bt, P, P, i64, P, P, P, i64, P]),
             "lbvh_build_workspace_bytes": (i64, [i64, i32, i32]),
             "lbvh_build": (C.c_int, [i32, P, i64, i32, T, P, i64, P]),
             "lbvh_build_points": (C.c_int, [P, i64, i32, T, P, i64, P]),
@@ -191,14 +191,16 @@ def lbvh_query_batched_boxes_count(batch, q_ptr, qseg_ptr, m, off_ptr, ws_ptr, w
                                                ws_bytes, stream)
 
 
-def lbvh_query_batched_spheres_fill(batch, q_ptr, qseg_ptr, m, off_ptr, idx_ptr, stream) -> int:
+def lbvh_query_batched_spheres_fill(batch, q_ptr, qseg_ptr, m, off_ptr, idx_ptr, ws_ptr, ws_bytes,
+                                    stream) -> int:
     return lib().lbvh_query_batched_spheres_fill(C.byref(batch), q_ptr, qseg_ptr, m, off_ptr, idx_ptr,
-                                                stream)
+                                                ws_ptr, ws_bytes, stream)
 
 
-def lbvh_query_batched_boxes_fill(batch, q_ptr, qseg_ptr, m, off_ptr, idx_ptr, stream) -> int:
+def lbvh_query_batched_boxes_fill(batch, q_ptr, qseg_ptr, m, off_ptr, idx_ptr, ws_ptr, ws_bytes,
+                                  stream) -> int:
     return lib().lbvh_query_batched_boxes_fill(C.byref(batch), q_ptr, qseg_ptr, m, off_ptr, idx_ptr,
-                                              stream)
+                                              ws_ptr, ws_bytes, stream)
 
 
 def lbvh_profile_enable(on: bool) -> int:
@@ -467,14 +469,16 @@ def query_batched_count(batch: Batch, queries, qseg_off, qkind: int, workspace: 
     return offsets
 
 
-def query_batched_fill(batch: Batch, queries, qseg_off, qkind: int, offsets, indices, stream=None):
-    """Second batched call, asynchronous: indices int32 [offsets[m]] (the
-    tensor must hold at least one element)."""
+def query_batched_fill(batch: Batch, queries, qseg_off, qkind: int, offsets, indices,
+                       workspace: Workspace, stream=None):
+    """Second batched call, asynchronous, with the count call's workspace:
+    indices int32 [offsets[m]] (the tensor must hold at least one element)."""
     q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
     m = int(q.shape[0])
+    ws = workspace.buf
     fill = lbvh_query_batched_spheres_fill if qkind == SPHERES else lbvh_query_batched_boxes_fill
     _check(fill(batch.desc, q.data_ptr() if m else None, qseg_off.data_ptr(), m, offsets.data_ptr(),
-                indices.data_ptr(), _stream(stream)), "batched query fill")
+                indices.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)), "batched query fill")
     return indices
 
 
@@ -496,5 +500,5 @@ def query_batched(batch: Batch, queries, qseg_off, qkind: int, workspace: Worksp
     buf = torch.empty(max(total, 1), dtype=torch.int32, device=q.device)
     fill = lbvh_query_batched_spheres_fill if qkind == SPHERES else lbvh_query_batched_boxes_fill
     _check(fill(batch.desc, q.data_ptr() if m else None, qseg_off.data_ptr(), m, offsets.data_ptr(),
-                buf.data_ptr(), _stream(stream)), "batched query fill")
+                buf.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)), "batched query fill")
     return offsets, buf[:total]

@@ -140,11 +140,17 @@ __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
 // Alg. 1 for query j on the tree of its scene (one thread per query); the
 // fill pass writes through a HitStage (the block's queries have consecutive
 // output ranges).
+// The batched count keeps each query's first kBatchHitCache hits (scenes
+// are small, so most queries have fewer); the fill copies them instead of
+// walking again.
+constexpr int kBatchHitCache = 64;
+
 template <class Q>
 __device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const int32_t *perm_all,
                                                const int64_t *seg_off, const int64_t *qseg_off, int S,
                                                const float *queries, int64_t j, int &cnt,
-                                               const HitStage *st, int64_t pos)
+                                               const HitStage *st, int64_t pos,
+                                               int32_t *kept = nullptr)
 {
     int lo = 0, hi = S - 1;   // scene of query j: largest s with qseg_off[s] <= j
     while (lo < hi) {
@@ -169,13 +175,20 @@ __device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const in
         const int jr = tr.right_bound(b);
         if (q.test(a, b)) {
             if (v >= leaf0) {
-                if (st) st->put(pos++, left);
-                else ++cnt;
+                if (st) {
+                    st->put(pos++, left);
+                } else {
+                    if (kept && cnt < kBatchHitCache) kept[cnt] = left;
+                    ++cnt;
+                }
             } else if (q.contains(a, b)) {
                 if (st) {
                     st->range(pos, (int32_t)b0 + i, jr - i + 1);   // perm_all index
                     pos += jr - i + 1;
                 } else {
+                    if (kept)
+                        for (int k = i; k <= jr && cnt + (k - i) < kBatchHitCache; ++k)
+                            kept[cnt + (k - i)] = tr.perm[k];
                     cnt += jr - i + 1;
                 }
             } else {
@@ -194,12 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_count(const float4 *__restrict
                                                         const int64_t *__restrict__ seg_off,
                                                         const int64_t *__restrict__ qseg_off, int S,
                                                         const float *__restrict__ queries, int64_t m,
-                                                        int32_t *__restrict__ counts)
+                                                        int32_t *__restrict__ counts,
+                                                        int32_t *__restrict__ cache)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= m) return;
     int cnt = 0;
-    batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, cnt, nullptr, 0);
+    batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, cnt, nullptr, 0,
+                      cache + j * kBatchHitCache);
     counts[j] = cnt;
 }
 
@@ -210,6 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_fill(const float4 *__restrict_
                                                        const int64_t *__restrict__ qseg_off, int S,
                                                        const float *__restrict__ queries, int64_t m,
                                                        const int64_t *__restrict__ offsets,
+                                                       const int32_t *__restrict__ cache,
                                                        int32_t *__restrict__ out)
 {
     __shared__ WaveStageLds lds;
@@ -222,9 +238,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_fill(const float4 *__restrict_
     wave_sync();
     const HitStage st = wave_stage(lds, out, perm_all, offsets[j0]);
     int unused = 0;
-    if (j < m)
-        batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, unused, &st,
-                          offsets[j]);
+    if (j < m) {
+        const int64_t pos = offsets[j], have = offsets[j + 1] - pos;
+        if (have <= kBatchHitCache)   // the count call kept them
+            for (int k = 0; k < have; ++k) st.put(pos + k, cache[j * kBatchHitCache + k]);
+        else
+            batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, unused, &st, pos);
+    }
     st.flush(offsets[j_end] - st.base);
 }
 
@@ -332,10 +352,11 @@ hipError_t run_batch_query(const lbvh_batch *b, const float *q, const int64_t *q
 {
     const float4 *nodes = reinterpret_cast<const float4 *>(b->nodes);
     const unsigned g = (unsigned)((m + kBlock - 1) / kBlock);
+    int32_t *cache = reinterpret_cast<int32_t *>(ws + L.hcache);
     if (fill) {
         prof_begin(K_QFILL, s);
         hipLaunchKernelGGL((k_batch_fill<Q>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
-                           b->seg_off, qseg_off, b->num_scenes, q, m, offsets, indices);
+                           b->seg_off, qseg_off, b->num_scenes, q, m, offsets, cache, indices);
         prof_end(K_QFILL, s);
         return hipGetLastError();
     }
@@ -343,7 +364,7 @@ hipError_t run_batch_query(const lbvh_batch *b, const float *q, const int64_t *q
     int64_t *partials = reinterpret_cast<int64_t *>(ws + L.partials);
     prof_begin(K_QCOUNT, s);
     hipLaunchKernelGGL((k_batch_count<Q>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
-                       b->seg_off, qseg_off, b->num_scenes, q, m, counts);
+                       b->seg_off, qseg_off, b->num_scenes, q, m, counts, cache);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(counts, m, nullptr, partials, offsets, s);

@@ -70,6 +70,7 @@ QueryLayout batch_query_layout(int64_t m)
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     L.cnt1 = take((size_t)(m + 1) * sizeof(int32_t));
+    L.hcache = take((size_t)m * 64 * sizeof(int32_t));   // first 64 hits of each query
     L.partials = take((size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
     L.total = off;
     return L;
@@ -362,10 +363,8 @@ static int batched_query(int qkind, const lbvh_batch *b, const float *q, const i
         return LBVH_EINVAL;
     if (fill && m > 0 && !indices) return LBVH_EINVAL;
     const QueryLayout L = batch_query_layout(m);
-    if (!fill) {
-        if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
-        if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
-    }
+    if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
+    if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
     hipError_t e = launch_query_batched(qkind, b, q, qseg_off, m, offsets, indices, fill,
                                         static_cast<char *>(workspace), L, (hipStream_t)stream);
     return hip_status(e);
@@ -389,17 +388,18 @@ int lbvh_query_batched_boxes_count(const lbvh_batch *b, const float *lohi, const
 
 int lbvh_query_batched_spheres_fill(const lbvh_batch *b, const float *xyzr, const int64_t *qseg_off,
                                     int64_t m, const int64_t *offsets, int32_t *indices,
-                                    void *stream)
+                                    const void *workspace, int64_t workspace_bytes, void *stream)
 {
     return batched_query(0, b, xyzr, qseg_off, m, const_cast<int64_t *>(offsets), indices, true,
-                         nullptr, 0, stream);
+                         const_cast<void *>(workspace), workspace_bytes, stream);
 }
 
 int lbvh_query_batched_boxes_fill(const lbvh_batch *b, const float *lohi, const int64_t *qseg_off,
-                                  int64_t m, const int64_t *offsets, int32_t *indices, void *stream)
+                                  int64_t m, const int64_t *offsets, int32_t *indices,
+                                  const void *workspace, int64_t workspace_bytes, void *stream)
 {
     return batched_query(1, b, lohi, qseg_off, m, const_cast<int64_t *>(offsets), indices, true,
-                         nullptr, 0, stream);
+                         const_cast<void *>(workspace), workspace_bytes, stream);
 }
 
 int64_t lbvh_query_workspace_bytes(int64_t m)

@@ -82,7 +82,7 @@ struct QueryLayout {
 };
 
 QueryLayout query_layout(int64_t m);
-QueryLayout batch_query_layout(int64_t m);   // counts and scan sums only
+QueryLayout batch_query_layout(int64_t m);   // counts, first hits, scan sums
 
 struct BatchLayout {
     size_t ctrl;       // kCtrlWords uint32

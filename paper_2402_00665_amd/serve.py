@@ -543,7 +543,7 @@ class GpuExecutor(_GpuBase):
                 h.indices = torch.empty(max(total, 1), dtype=torch.int32, device=self.dev)
                 if h.M:
                     lb.query_batched_fill(h.batch, h.queries[:h.M], h.qseg_d, lb.SPHERES, h.offsets,
-                                          h.indices, stream=h.stream)
+                                          h.indices, self.qws[h.slot], stream=h.stream)
                 h.ev = torch.cuda.Event()
                 h.ev.record(h.stream)
             h.phase = 1
