@@ -145,11 +145,40 @@ def test_workspace_reuse_across_sizes(ws):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["large_points", "clustered_boxes"])
 def test_full_size(name, ws):
-    """Full-size workloads in the configuration the benchmark times: every
-    build output and every query result."""
+    """Full-size workloads with the default launch shapes: every build
+    output and every query result."""
     say(f"full-size {name}: generating")
     w = workloads.by_name(name)
     _parity(w, ws)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["large_points", "clustered_boxes"])
+def test_full_size_autotuned(name, ws):
+    """Full-size workloads in the launch configuration the benchmark times:
+    the autotuner's picks for this workload (radix tile shape, query split
+    levels and leaf schedule), then every build output and query result."""
+    import torch
+    import paper_2402_00665_amd as lb
+    from paper_2402_00665_amd import autotune
+    w = workloads.by_name(name)
+    knobs = ("sort_variant32", "sort_variant64", "query_split1", "query_split2", "query_leaf_mode")
+    old = {k: lb.lbvh_tune(k) for k in knobs}
+    try:
+        p = torch.from_numpy(w.prims).cuda()
+        t = autotune.tune(p, w.code_bits, kind=w.kind, reps=2, save=False)
+        lb.lbvh_tune(t["knob"], t["value"])
+        tree = lb.build(p, w.code_bits, kind=w.kind)
+        tq = autotune.tune_query(tree, torch.from_numpy(w.queries).cuda(), w.qkind, reps=1,
+                                 save=False)
+        for k, v in zip(knobs[2:], tq["value"]):
+            lb.lbvh_tune(k, v)
+        say(f"full-size {name}, tuned: {t['knob']}={t['value']} query={tq['value']}")
+        del tree, p
+        _parity(w, ws)
+    finally:
+        for k, v in old.items():
+            lb.lbvh_tune(k, v)
 
 
 def test_large_queries_all_hit_ranges(ws):
