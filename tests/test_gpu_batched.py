@@ -12,14 +12,20 @@ from gpu_util import first_mismatch, say
 pytestmark = pytest.mark.gpu
 
 
-def run_batched(prims, seg_off, bits, kind, max_scene=None, ws=None):
+def run_batched(prims, seg_off, bits, kind, max_scene=None, ws=None, shift=0):
+    """shift: floats of padding before the primitives in their device
+    buffer, so that shift=2 gives an array that is 8- but not 16-byte
+    aligned."""
     import torch
     import paper_2402_00665_amd as lb
     sizes = np.diff(seg_off)
     max_scene = int(sizes.max()) if max_scene is None else max_scene
     say(f"  batched build: S={len(sizes)} N={int(seg_off[-1])} bits={bits} kind={kind} "
-        f"max_scene={max_scene}")
-    dp = torch.from_numpy(np.ascontiguousarray(prims)).cuda()
+        f"max_scene={max_scene} shift={shift}")
+    host = torch.from_numpy(np.ascontiguousarray(prims))
+    flat = torch.zeros(host.numel() + shift, dtype=torch.float32, device="cuda")
+    dp = flat[shift:].view(host.shape)
+    dp.copy_(host)
     ds = torch.from_numpy(np.ascontiguousarray(seg_off, dtype=np.int64)).cuda()
     b = lb.build_batched(dp, ds, bits, max_scene, kind=kind, workspace=ws)
     return b, dp, ds
@@ -52,10 +58,10 @@ def host_arrays(b):
 
 
 def batched_parity(prims, seg_off, bits, kind, queries=None, qseg=None, qkind=0, ws=None,
-                   check_every=1):
+                   check_every=1, shift=0):
     import torch
     import paper_2402_00665_amd as lb
-    b, dp, ds = run_batched(prims, seg_off, bits, kind, ws=ws)
+    b, dp, ds = run_batched(prims, seg_off, bits, kind, ws=ws, shift=shift)
     lb.check_batched(b)
     nodes_h, codes_h, perm_h = host_arrays(b)
     S = len(seg_off) - 1
@@ -103,6 +109,28 @@ def test_mixed_scene_sizes(kind, bits):
     q = workloads.spheres(rng.random((len(sizes) * m_per, 3), dtype=np.float32), np.float32(0.05))
     qseg = np.arange(len(sizes) + 1, dtype=np.int64) * m_per
     batched_parity(prims, seg, bits, kind, q, qseg, 0)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_prims_8_byte_aligned(kind):
+    """Primitives 8 bytes past a 16-byte boundary, scenes starting at every
+    residue modulo 4: the scene loader's head, 48-byte groups and tail must
+    cover each scene exactly once."""
+    import torch
+    rng = np.random.default_rng([22, kind])
+    sizes = np.array([1, 2, 3, 4, 5, 6, 7, 9, 1030, 2, 4099, 3, 20000, 1, 13], np.int64)
+    seg = np.zeros(len(sizes) + 1, np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    N = int(seg[-1])
+    if kind == 0:
+        prims = rng.random((N, 3), dtype=np.float32)
+    else:
+        c = rng.random((N, 3))
+        h = rng.random((N, 3)) * 0.01
+        prims = np.concatenate([c - h, c + h], 1).astype(np.float32)
+    b = batched_parity(prims, seg, 63, kind, shift=2)
+    assert b is not None
+    torch.cuda.synchronize()
 
 
 def test_batched_workload_reduced():
