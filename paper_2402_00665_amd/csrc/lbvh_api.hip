@@ -53,10 +53,11 @@ QueryLayout query_layout(int64_t m)
     L.cnt2 = take((size_t)L.cap1 * sizeof(int32_t));
     L.off2 = take((size_t)(L.cap1 + 1) * sizeof(int64_t));
     L.items2 = take((size_t)L.cap2 * 16);
-    L.first1 = take((size_t)2 * m * 16);
-    L.first2 = take((size_t)2 * L.cap1 * 16);
+    L.app_piece = take((size_t)L.cap2 * 16);   // shared by both levels (cap2 >= cap1)
+    L.app_item = take((size_t)L.cap2 * sizeof(int64_t));
+    L.app_rank = take((size_t)L.cap2 * sizeof(int32_t));
     L.hcnt = take((size_t)L.cap2 * sizeof(int32_t));
-    L.hcache = take((size_t)L.cap2 * 8 * sizeof(int32_t));
+    L.hmask = take((size_t)L.cap2 * kMaskWords * sizeof(uint64_t));
     L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
     L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
     L.ctrl = take(128);

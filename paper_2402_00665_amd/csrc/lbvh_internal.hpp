@@ -29,6 +29,8 @@ constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // default: query walks cut by aligned blocks of 2^12 leaves
 constexpr int kSplit2 = 7;            // default: ... then by blocks of 2^7 leaves
 constexpr int kQueryGridMax = 8192;   // blocks of the grid-stride query kernels
+constexpr int kMaskLeaves = 256;     // widest level-2 piece that gets a leaf-hit mask
+constexpr int kMaskWords = kMaskLeaves / 64;
 constexpr int kScanTile = kBlock * kScanItems;
 
 // ctrl words at the start of the build workspace
@@ -71,10 +73,12 @@ struct QueryLayout {
     size_t cnt2;       // cap1 int32: level-2 pieces per level-1 piece
     size_t off2;       // cap1+1 int64
     size_t items2;     // cap2 int4
-    size_t first1;     // 2m int4: the first two level-1 pieces of each query
-    size_t first2;     // 2*cap1 int4: the first two level-2 pieces of each level-1 piece
+    size_t app_piece;  // cap2 int4: pieces appended by a split level's count pass
+    size_t app_item;   // cap2 int64: ... the item each came from
+    size_t app_rank;   // cap2 int32: ... and its rank among that item's pieces
     size_t hcnt;       // cap2 int32: hits per level-2 piece
-    size_t hcache;     // cap2 x 8 int32: each level-2 piece's first hits
+    size_t hmask;      // cap2 x kMaskWords uint64: leaf-hit mask of each level-2 piece
+    size_t hcache;     // batched: m x 64 int32, each query's first hits
     size_t hoff;       // cap2+1 int64
     size_t partials;   // scan tile sums
     size_t ctrl;       // overflow flags and piece counts

@@ -114,116 +114,192 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One split level (count or fill pass).  The count pass also keeps each
-// item's first two pieces in `first`; the fill pass copies those for items
-// with at most two pieces (most items) and walks again only for the rest.
-// The fill pass stages the pieces of each wave's 64 input items in the
-// wave's LDS region (their output ranges are consecutive) and writes them
-// out in one coalesced run; pieces past the stage capacity go straight to
-// the output.
-constexpr int kWavePieces = 256;
+// set lanes of mask below this lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
 
-template <class Q, bool FILL, bool FIRST>
+// One split level's count pass: Alg. 1 from each item (a query, or a piece
+// of the level above), cut at aligned blocks of 2^shift leaves.  Every
+// piece it finds is appended to a list together with its item and its rank
+// among that item's pieces.  After the scan of the counts, k_split_scatter
+// puts each piece at its item's offset plus its rank: the order a second
+// walk would emit them in, so no item is walked twice.  Past `cap` pieces
+// the list stops growing; the level then overflows and passes its items
+// through.
+//
+// Appends go to the wave's LDS stage.  After each append step the wave's
+// active lanes check the stage and, once it holds kAppendStage - 64 or more
+// entries (one step adds at most 64), move it to the list with one atomic;
+// the wave flushes the rest when its items are done.  The lanes of a wave
+// execute together, so the active ones can do this from inside their
+// diverged walks.
+constexpr int kAppendStage = 256;
+
+struct AppendLds {
+    int4 piece[kWavesPerBlock][kAppendStage];
+    int64_t item[kWavesPerBlock][kAppendStage];
+    int32_t rank[kWavesPerBlock][kAppendStage];
+    uint32_t n[kWavesPerBlock];
+};
+
+struct WaveAppend {
+    int4 *piece;
+    int64_t *item;
+    int32_t *rank;
+    uint32_t *n;
+    unsigned long long *count;
+    int64_t cap;
+    int4 *g_piece;
+    int64_t *g_item;
+    int32_t *g_rank;
+
+    __device__ void to_list(unsigned long long slot, int4 pc, int64_t t, int32_t r) const
+    {
+        if (slot < (unsigned long long)cap) {
+            g_piece[slot] = pc;
+            g_item[slot] = t;
+            g_rank[slot] = r;
+        }
+    }
+    // by the wave's active lanes, all with the same view of the stage
+    __device__ void flush() const
+    {
+        wave_sync();
+        const uint32_t total = *n;
+        const uint32_t staged = total < (uint32_t)kAppendStage ? total : (uint32_t)kAppendStage;
+        const uint64_t act = __ballot(1);
+        const int r = (int)lanes_below(act), na = __popcll(act), first = __ffsll((unsigned long long)act) - 1;
+        unsigned long long base = 0;
+        if (r == 0 && staged > 0u) base = atomicAdd(count, (unsigned long long)staged);
+        base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(base >> 32), first) << 32) |
+               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, first);
+        for (uint32_t k = r; k < staged; k += na) to_list(base + k, piece[k], item[k], rank[k]);
+        wave_sync();
+        if (r == 0) *n = 0u;
+        wave_sync();
+    }
+    // The stage holds fewer than kAppendStage - 64 entries before a step
+    // (it is flushed after any step that reaches that), and a step adds at
+    // most 64, so k < kAppendStage.
+    __device__ void put(int4 pc, int64_t t, int32_t r) const
+    {
+        // one LDS atomic for the step's active lanes, entries in lane order
+        const uint64_t act = __ballot(1);
+        const uint32_t below = lanes_below(act), cnt = (uint32_t)__popcll(act);
+        const int first = __ffsll((unsigned long long)act) - 1;
+        uint32_t base = 0u;
+        if (below == 0u) base = atomicAdd(n, cnt);
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, first);
+        const uint32_t k = base + below;
+        piece[k] = pc;
+        item[k] = t;
+        rank[k] = r;
+        if (base + cnt >= (uint32_t)(kAppendStage - 64)) flush();
+    }
+};
+
+template <class Q, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restrict__ queries, int m,
                                                   const int4 *__restrict__ in, const int64_t *in_count,
                                                   int shift, int32_t *__restrict__ counts,
-                                                  const int64_t *__restrict__ out_off,
-                                                  const int32_t *__restrict__ overflow,
-                                                  int4 *__restrict__ first,
-                                                  int4 *__restrict__ out)
+                                                  unsigned long long *app_count, int64_t cap,
+                                                  int4 *__restrict__ app_piece,
+                                                  int64_t *__restrict__ app_item,
+                                                  int32_t *__restrict__ app_rank)
 {
-    __shared__ int4 s_out[FILL ? kWavesPerBlock : 1][FILL ? kWavePieces : 1];
+    __shared__ AppendLds lds;
+    const int wv = threadIdx.x >> 6;
+    const WaveAppend ap{lds.piece[wv], lds.item[wv], lds.rank[wv], &lds.n[wv], app_count, cap,
+                        app_piece, app_item, app_rank};
+    if ((threadIdx.x & 63) == 0) lds.n[wv] = 0u;
+    wave_sync();
     const int64_t T = FIRST ? (int64_t)m : *in_count;
-    const bool pass_through = FILL && *overflow;
-    const int lane = threadIdx.x & 63;
-    int4 *stage = s_out[FILL ? threadIdx.x >> 6 : 0];
-    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T;
-         t0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t t = t0 + lane;
-        if (pass_through) {
-            if (t < T) out[t] = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
-            continue;
-        }
-        int64_t base = 0, total = 0;
-        if (FILL) {
-            const int64_t t_end = t0 + 64 < T ? t0 + 64 : T;
-            base = out_off[t0];
-            total = out_off[t_end] - base;
-        }
-        auto put = [&](int64_t pos, int4 v) {
-            const int64_t r = pos - base;
-            if (r < kWavePieces) stage[r] = v;
-            else out[pos] = v;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T; t += (int64_t)gridDim.x * kBlock) {
+        const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
+        int cnt = 0;
+        auto emit = [&](int4 pc) {
+            ap.put(pc, t, cnt);
+            ++cnt;
         };
-        if (t < T) {
-            const int4 it = FIRST ? piece((int)t, 0, 0, tr.n) : in[t];
-            int64_t pos = FILL ? out_off[t] : 0;
-            int cnt = 0;
-            auto emit = [&](int4 pc) {
-                if (FILL) {
-                    put(pos++, pc);
-                } else {
-                    if (cnt < 2) first[2 * t + cnt] = pc;
-                    ++cnt;
-                }
-            };
-            // all-hit range [a, b): one all-hit piece per block it touches
-            auto emit_range = [&](int a, int b) {
-                while (a < b) {
-                    const int blk_end = ((a >> shift) + 1) << shift;
-                    const int e = blk_end < b ? blk_end : b;
-                    emit(piece(it.x, kAllHits, a, e));
-                    a = e;
-                }
-            };
-            const int64_t have = FILL ? out_off[t + 1] - pos : 0;
-            if (FILL && have <= 2) {          // the count pass kept them
-                if (have > 0) put(pos, first[2 * t]);
-                if (have > 1) put(pos + 1, first[2 * t + 1]);
-            } else if (it.y == kAllHits) {
-                emit_range(it.z, it.w);
-            } else {
-                Q q;
-                q.load(queries, it.x);
-                int v = it.y, i = it.z;
-                const int hi = it.w;
-                int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
-                while (v != -1 && i < hi && --budget >= 0) {
-                    float4 a, b;
-                    tr.load(v, a, b);
-                    const int j = tr.right_bound(b);
-                    if (!q.test(a, b)) {
-                        v = __float_as_int(b.w);
-                        i = j + 1;
-                        continue;
-                    }
-                    if ((i >> shift) == (j >> shift)) {
-                        const int r = ((i >> shift) + 1) << shift;   // next block start
-                        const int end = r < hi ? r : hi;
-                        emit(piece(it.x, v, i, end));
-                        if (r >= hi || r > tr.n - 1) break;
-                        v = tr.first_at(r);
-                        i = r;
-                        continue;
-                    }
-                    if (q.contains(a, b)) {   // multi-block node with only hits below
-                        emit_range(i, j + 1 < hi ? j + 1 : hi);
-                        v = __float_as_int(b.w);
-                        i = j + 1;
-                        continue;
-                    }
-                    v = __float_as_int(a.w);   // multi-block node: descend
-                }
+        // all-hit range [a, b): one all-hit piece per block it touches
+        auto emit_range = [&](int a, int b) {
+            while (a < b) {
+                const int blk_end = ((a >> shift) + 1) << shift;
+                const int e = blk_end < b ? blk_end : b;
+                emit(piece(it.x, kAllHits, a, e));
+                a = e;
             }
-            if (!FILL) counts[t] = cnt;
+        };
+        if (it.y == kAllHits) {
+            emit_range(it.z, it.w);
+        } else {
+            Q q;
+            q.load(queries, it.x);
+            int v = it.y, i = it.z;
+            const int hi = it.w;
+            int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
+            while (v != -1 && i < hi && --budget >= 0) {
+                float4 a, b;
+                tr.load(v, a, b);
+                const int j = tr.right_bound(b);
+                if (!q.test(a, b)) {
+                    v = __float_as_int(b.w);
+                    i = j + 1;
+                    continue;
+                }
+                if ((i >> shift) == (j >> shift)) {
+                    const int r = ((i >> shift) + 1) << shift;   // next block start
+                    const int end = r < hi ? r : hi;
+                    emit(piece(it.x, v, i, end));
+                    if (r >= hi || r > tr.n - 1) break;
+                    v = tr.first_at(r);
+                    i = r;
+                    continue;
+                }
+                if (q.contains(a, b)) {   // multi-block node with only hits below
+                    emit_range(i, j + 1 < hi ? j + 1 : hi);
+                    v = __float_as_int(b.w);
+                    i = j + 1;
+                    continue;
+                }
+                v = __float_as_int(a.w);   // multi-block node: descend
+            }
         }
-        if (FILL) {
-            wave_sync();
-            const int staged = total < kWavePieces ? (int)total : kWavePieces;
-            for (int k = lane; k < staged; k += 64) out[base + k] = stage[k];
-            wave_sync();   // the stage is reused by the wave's next items
-        }
+        counts[t] = cnt;
     }
+    ap.flush();   // every lane of the wave
+}
+
+// A split level's output: each appended piece to slot out_off[item] + rank,
+// or, when the level overflowed, its items passed through unchanged.
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_split_scatter(int n, int m, const int4 *__restrict__ in,
+                                                          const int64_t *in_count,
+                                                          const int64_t *__restrict__ out_off,
+                                                          const int32_t *__restrict__ overflow,
+                                                          const unsigned long long *app_count,
+                                                          const int4 *__restrict__ app_piece,
+                                                          const int64_t *__restrict__ app_item,
+                                                          const int32_t *__restrict__ app_rank,
+                                                          int4 *__restrict__ out)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (*overflow) {
+        const int64_t T = FIRST ? (int64_t)m : *in_count;
+        for (int64_t t = t0; t < T; t += stride) out[t] = FIRST ? piece((int)t, 0, 0, n) : in[t];
+        return;
+    }
+    const int64_t A = (int64_t)*app_count;   // no overflow: every piece was kept
+    for (int64_t k = t0; k < A; k += stride) out[out_off[app_item[k]] + app_rank[k]] = app_piece[k];
+}
+
+__global__ void k_split_reset(unsigned long long *app_count)
+{
+    if (threadIdx.x < 2) app_count[threadIdx.x] = 0ull;
 }
 
 // The leaf level.  A level-2 piece covers the leaves [i, hi) of one aligned
@@ -243,24 +319,47 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
 // from leaf_perm, and a piece wider than kLeafScanMax leaves (left unsplit
 // after a capacity overflow) is always walked.
 
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
 constexpr int kLeafScanMax = 1024;
 
-// The count pass keeps each piece's first kHitCache hits in the workspace;
-// the fill pass copies them for pieces with at most that many hits (sparse
-// queries: most pieces) instead of testing or walking the piece again.
-constexpr int kHitCache = 8;
+// Leaf-hit masks.  The count pass gives every level-2 piece at most
+// kMaskLeaves (256) wide one bit per leaf of its range [i, hi) (bit k of word w:
+// leaf i + 64 w + k), set for each hit.  The fill pass writes leaf_perm of
+// the set bits in ascending leaf order, which is the order Alg. 1 reports
+// them in, without loading or testing a box again.  Wider pieces (a split
+// of more than 8 levels, or a level left unsplit after a capacity overflow)
+// are tested again by the fill.
+struct LeafMask {
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    // bits [a, e) of the mask, 0 <= a <= e <= kMaskLeaves
+    __device__ void set(int a, int e)
+    {
+        auto part = [&](int w) -> uint64_t {
+            const int lo = a > 64 * w ? a - 64 * w : 0;
+            const int hi = e < 64 * w + 64 ? e - 64 * w : 64;
+            if (lo >= hi) return 0;
+            const uint64_t ones = hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull);
+            return ones << lo;
+        };
+        w0 |= part(0); w1 |= part(1); w2 |= part(2); w3 |= part(3);
+    }
+    __device__ void store(uint64_t *dst, int width) const
+    {
+        dst[0] = w0;
+        if (width > 64) dst[1] = w1;
+        if (width > 128) dst[2] = w2;
+        if (width > 192) dst[3] = w3;
+    }
+};
 
+// Alg. 1 restricted to the leaves [i, hi) from node v, by one lane: counts
+// the hits, and writes them from slot pos of out (FILL) or sets them in
+// *mask (count pass, pieces at most kMaskLeaves wide).
 template <class Q, bool FILL>
 __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, int32_t *out,
-                              int64_t pos, int32_t *cache = nullptr)
+                              int64_t pos, LeafMask *mask = nullptr)
 {
     const int leaf0 = tr.leaf0();
+    const int i0 = i;
     int64_t cnt = 0;
     int64_t budget = 2 * (int64_t)tr.n;
     while (v != -1 && i < hi && --budget >= 0) {
@@ -271,15 +370,14 @@ __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, 
         if (q.test(a, b)) {
             if (v >= leaf0) {
                 if (FILL) out[pos + cnt] = left;
-                else if (cache && cnt < kHitCache) cache[cnt] = left;
+                else if (mask) mask->set(i - i0, i - i0 + 1);
                 ++cnt;
             } else if (q.contains(a, b)) {
                 const int e = j + 1 < hi ? j + 1 : hi;
                 if (FILL)
                     for (int k = i; k < e; ++k) out[pos + cnt + (k - i)] = tr.perm[k];
-                else if (cache)
-                    for (int k = i; k < e && cnt + (k - i) < kHitCache; ++k)
-                        cache[cnt + (k - i)] = tr.perm[k];
+                else if (mask)
+                    mask->set(i - i0, e - i0);
                 cnt += e - i;
             } else {
                 v = left;
@@ -311,205 +409,200 @@ __device__ bool dense_piece(const Q &q, float4 a, float4 b)
     return f >= 0.25f;
 }
 
+// One wave tests the leaves [lo, hi) of a piece, 64 consecutive leaf
+// records per step (two steps in flight), and returns the hit count; with
+// FILL it writes the hits from slot pos of out, else, for a piece at most
+// kMaskLeaves wide, it stores the ballots as the piece's mask.
+template <class Q, bool FILL>
+__device__ int64_t scan_piece(const Tree &tr, const Q &q, int lo, int hi, int32_t *out, int64_t pos,
+                              uint64_t *mask)
+{
+    const int lane = threadIdx.x & 63;
+    const bool keep = !FILL && hi - lo <= kMaskLeaves;
+    int64_t c = 0;
+    for (int k0 = lo; k0 < hi; k0 += 128) {
+        const int k = k0 + lane, k2 = k + 64;
+        float4 a, b, e, f;
+        if (k < hi) tr.load(tr.leaf0() + k, a, b);
+        if (k2 < hi) tr.load(tr.leaf0() + k2, e, f);
+        const bool h = k < hi && q.test(a, b);
+        const bool h2 = k2 < hi && q.test(e, f);
+        const uint64_t m = __ballot(h), m2 = __ballot(h2);
+        if (FILL) {
+            if (h) out[pos + c + lanes_below(m)] = __float_as_int(a.w);   // leaf: its primitive
+            if (h2) out[pos + c + __popcll(m) + lanes_below(m2)] = __float_as_int(e.w);
+        } else if (keep && lane == 0) {
+            const int w = (k0 - lo) >> 6;
+            mask[w] = m;
+            if (k0 + 64 < hi) mask[w + 1] = m2;
+        }
+        c += __popcll(m) + __popcll(m2);
+    }
+    return c;
+}
+
 // Plain schedule (query_leaf_mode 0): one wave per piece.
 template <class Q>
 __global__ __launch_bounds__(kBlock) void k_leaf_scan_count(Tree tr, const float *__restrict__ queries,
                                                        const int4 *__restrict__ in,
                                                        const int64_t *in_count,
                                                        int32_t *__restrict__ counts,
-                                                       int32_t *__restrict__ cache)
+                                                       uint64_t *__restrict__ masks)
 {
     const int64_t T = *in_count;
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; t < T; t += nw) {
         const int4 it = in[t];
-        int cnt = it.w - it.z;
-        if (it.y != kAllHits && it.w - it.z > kLeafScanMax) {
-            Q q;
-            q.load(queries, it.x);
-            if (lane == 0)
-                counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0,
-                                                          cache + t * kHitCache);
-            continue;
-        }
+        int64_t cnt = it.w - it.z;
         if (it.y != kAllHits) {
             Q q;
             q.load(queries, it.x);
-            cnt = 0;
-            int32_t *kept = cache + t * kHitCache;
-            for (int k0 = it.z; k0 < it.w; k0 += 128) {   // two steps of 64 in flight
-                const int k = k0 + lane, k2 = k + 64;
-                float4 a, b, c, d;
-                if (k < it.w) tr.load(tr.leaf0() + k, a, b);
-                if (k2 < it.w) tr.load(tr.leaf0() + k2, c, d);
-                const bool h = k < it.w && q.test(a, b);
-                const bool h2 = k2 < it.w && q.test(c, d);
-                const uint64_t m = __ballot(h), m2 = __ballot(h2);
-                const int r = cnt + (int)lanes_below(m), r2 = cnt + __popcll(m) + (int)lanes_below(m2);
-                if (h && r < kHitCache) kept[r] = __float_as_int(a.w);
-                if (h2 && r2 < kHitCache) kept[r2] = __float_as_int(c.w);
-                cnt += __popcll(m) + __popcll(m2);
+            if (it.w - it.z > kLeafScanMax) {
+                if (lane == 0) counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0);
+                continue;
             }
+            cnt = scan_piece<Q, false>(tr, q, it.z, it.w, nullptr, 0, masks + t * kMaskWords);
         }
-        if (lane == 0) counts[t] = cnt;
-    }
-}
-
-template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_scan_fill(Tree tr, const float *__restrict__ queries,
-                                                      const int4 *__restrict__ in,
-                                                      const int64_t *in_count,
-                                                      const int64_t *__restrict__ hit_off,
-                                                      const int32_t *__restrict__ cache,
-                                                      int32_t *__restrict__ out)
-{
-    const int64_t T = *in_count;
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; t < T; t += nw) {
-        const int4 it = in[t];
-        int64_t pos = hit_off[t];
-        if (it.y == kAllHits) {
-            for (int k = lane; k < it.w - it.z; k += 64) out[pos + k] = tr.perm[it.z + k];
-            continue;
-        }
-        const int64_t have = hit_off[t + 1] - pos;
-        if (have <= kHitCache) {   // the count pass kept them
-            if (lane < have) out[pos + lane] = cache[t * kHitCache + lane];
-            continue;
-        }
-        Q q;
-        q.load(queries, it.x);
-        if (it.w - it.z > kLeafScanMax) {
-            if (lane == 0) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos);
-            continue;
-        }
-        for (int k0 = it.z; k0 < it.w; k0 += 128) {
-            const int k = k0 + lane, k2 = k + 64;
-            float4 a, b, c, d;
-            if (k < it.w) tr.load(tr.leaf0() + k, a, b);
-            if (k2 < it.w) tr.load(tr.leaf0() + k2, c, d);
-            const bool h = k < it.w && q.test(a, b);
-            const bool h2 = k2 < it.w && q.test(c, d);
-            const uint64_t m = __ballot(h), m2 = __ballot(h2);
-            if (h) out[pos + lanes_below(m)] = __float_as_int(a.w);      // leaf: its primitive
-            pos += __popcll(m);
-            if (h2) out[pos + lanes_below(m2)] = __float_as_int(c.w);
-            pos += __popcll(m2);
-        }
+        if (lane == 0) counts[t] = (int32_t)cnt;
     }
 }
 
 // Mixed schedule (query_leaf_mode 1): each wave takes 64 pieces; sparse ones
-// are walked by their own lane, then the wave scans its dense and all-hit
-// pieces one at a time.  Better when most pieces are sparse (few hits per
-// piece); the plain scan above is better when most are dense.
-template <class Q, bool FILL>
-__device__ void leaf_mixed(const Tree &tr, const float *queries, const int4 *in, int64_t T,
-                           int32_t *counts, const int64_t *hit_off, int32_t *cache, int32_t *out)
+// are walked by their own lane, then the wave scans its dense pieces one at
+// a time.  Better when most pieces are sparse (few hits per piece); the
+// plain scan above is better when most are dense.  Both record the same
+// masks.
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const float *__restrict__ queries,
+                                                             const int4 *__restrict__ in,
+                                                             const int64_t *in_count,
+                                                             int32_t *__restrict__ counts,
+                                                             uint64_t *__restrict__ masks)
 {
-    enum { kNone = 0, kWalk, kScan, kCopy };
+    const int64_t T = *in_count;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
         const int64_t t = t0 + lane;
         int4 it = make_int4(0, -1, 0, 0);
-        int mode = kNone;
-        int64_t pos = 0, cnt = 0;
-        Q q;
+        bool scan = false;
+        int64_t cnt = 0;
         if (t < T) {
             it = in[t];
-            if (FILL) pos = hit_off[t];
             if (it.y == kAllHits) {
-                mode = kCopy;
+                cnt = it.w - it.z;
             } else {
+                Q q;
                 q.load(queries, it.x);
-                mode = kWalk;
+                bool walk = true;
                 if (it.w - it.z <= kLeafScanMax) {
                     float4 a, b;
                     tr.load(it.y, a, b);
-                    if (dense_piece(q, a, b)) mode = kScan;
+                    walk = !dense_piece(q, a, b);
+                }
+                if (walk) {
+                    const bool keep = it.w - it.z <= kMaskLeaves;
+                    LeafMask mk;
+                    cnt = walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0, keep ? &mk : nullptr);
+                    if (keep) mk.store(masks + t * kMaskWords, it.w - it.z);
+                } else {
+                    scan = true;
                 }
             }
         }
-        if (FILL && mode != kNone && mode != kCopy) {
-            const int64_t have = hit_off[t + 1] - pos;
-            if (have <= kHitCache) {   // the count pass kept them
-                for (int k = 0; k < have; ++k) out[pos + k] = cache[t * kHitCache + k];
-                mode = kNone;
-            }
-        }
-        if (mode == kWalk)
-            cnt = walk_piece<Q, FILL>(tr, q, it.y, it.z, it.w, out, pos,
-                                      FILL ? nullptr : cache + t * kHitCache);
-        uint64_t todo = __ballot(mode == kScan || mode == kCopy);
+        uint64_t todo = __ballot(scan);
         while (todo) {
             const int L = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
             const int qi = __builtin_amdgcn_readlane(it.x, L);
             const int lo = __builtin_amdgcn_readlane(it.z, L);
             const int hi = __builtin_amdgcn_readlane(it.w, L);
-            const bool copy = __builtin_amdgcn_readlane(mode, L) == kCopy;
-            int64_t p = 0;
-            if (FILL) {
-                const int plo = __builtin_amdgcn_readlane((int)(pos & 0xffffffff), L);
-                const int phi = __builtin_amdgcn_readlane((int)(pos >> 32), L);
-                p = ((int64_t)phi << 32) | (uint32_t)plo;
-            }
-            int64_t c = 0;
-            if (copy) {
-                if (FILL)
-                    for (int k = lane; k < hi - lo; k += 64) out[p + k] = tr.perm[lo + k];
-                c = hi - lo;
-            } else {
-                Q qq;
-                qq.load(queries, qi);
-                const int64_t tl = t0 + L;   // the piece's index
-                for (int k0 = lo; k0 < hi; k0 += 128) {
-                    const int k = k0 + lane, k2 = k + 64;
-                    float4 a, b, e, f;
-                    if (k < hi) tr.load(tr.leaf0() + k, a, b);
-                    if (k2 < hi) tr.load(tr.leaf0() + k2, e, f);
-                    const bool h = k < hi && qq.test(a, b);
-                    const bool h2 = k2 < hi && qq.test(e, f);
-                    const uint64_t m = __ballot(h), m2 = __ballot(h2);
-                    const int64_t r = c + lanes_below(m), r2 = c + __popcll(m) + lanes_below(m2);
-                    if (FILL) {
-                        if (h) out[p + r] = __float_as_int(a.w);
-                        if (h2) out[p + r2] = __float_as_int(e.w);
-                    } else {
-                        if (h && r < kHitCache) cache[tl * kHitCache + r] = __float_as_int(a.w);
-                        if (h2 && r2 < kHitCache) cache[tl * kHitCache + r2] = __float_as_int(e.w);
-                    }
-                    c += __popcll(m) + __popcll(m2);
-                }
-            }
+            Q q;
+            q.load(queries, qi);
+            const int64_t c = scan_piece<Q, false>(tr, q, lo, hi, nullptr, 0, masks + (t0 + L) * kMaskWords);
             if (lane == L) cnt = c;
         }
-        if (!FILL && t < T) counts[t] = (int32_t)cnt;
+        if (t < T) counts[t] = (int32_t)cnt;
     }
 }
 
-template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const float *__restrict__ queries,
-                                                             const int4 *__restrict__ in,
-                                                             const int64_t *in_count,
-                                                             int32_t *__restrict__ counts,
-                                                             int32_t *__restrict__ cache)
-{
-    leaf_mixed<Q, false>(tr, queries, in, *in_count, counts, nullptr, cache, nullptr);
-}
+// Fill for both schedules: one wave per piece, kFillGroup pieces at a time.
+// The group's descriptors, output slots and masks are loaded together, then
+// the leaf_perm entries of all its masked hits, then the stores, so a group
+// costs two dependent round trips to memory.  All-hit pieces are copied from
+// leaf_perm, and pieces wider than kMaskLeaves are tested again: scanned,
+// or walked by one lane beyond kLeafScanMax.
+constexpr int kFillGroup = 4;
 
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_mixed_fill(Tree tr, const float *__restrict__ queries,
-                                                            const int4 *__restrict__ in,
-                                                            const int64_t *in_count,
-                                                            const int64_t *__restrict__ hit_off,
-                                                            int32_t *__restrict__ cache,
-                                                            int32_t *__restrict__ out)
+__global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__restrict__ queries,
+                                                 const int4 *__restrict__ in, const int64_t *in_count,
+                                                 const int64_t *__restrict__ hit_off,
+                                                 const uint64_t *__restrict__ masks,
+                                                 int32_t *__restrict__ out)
 {
-    leaf_mixed<Q, true>(tr, queries, in, *in_count, nullptr, hit_off, cache, out);
+    constexpr int G = kFillGroup;
+    const int64_t T = *in_count;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t t0 = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * G; t0 < T; t0 += nw * G) {
+        int4 it[G];
+        int64_t pos[G];
+        uint64_t words[G][kMaskWords];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t t = t0 + g;
+            it[g] = make_int4(0, kAllHits, 0, 0);   // past the end: an empty copy
+            pos[g] = 0;
+            if (t < T) {
+                it[g] = in[t];
+                pos[g] = hit_off[t];
+                // all words, whatever the width: unused ones are ignored
+#pragma unroll
+                for (int w = 0; w < kMaskWords; ++w) words[g][w] = masks[t * kMaskWords + w];
+            }
+        }
+        int32_t v[G][kMaskWords];
+        bool masked[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int width = it[g].w - it[g].z;
+            masked[g] = it[g].y != kAllHits && width <= kMaskLeaves;
+#pragma unroll
+            for (int w = 0; w < kMaskWords; ++w) {
+                if (!masked[g] || 64 * w >= width) words[g][w] = 0ull;
+                if ((words[g][w] >> lane) & 1ull) v[g][w] = tr.perm[it[g].z + 64 * w + lane];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            int64_t p = pos[g];
+#pragma unroll
+            for (int w = 0; w < kMaskWords; ++w) {
+                const uint64_t m = words[g][w];
+                if ((m >> lane) & 1ull) out[p + lanes_below(m)] = v[g][w];
+                p += __popcll(m);
+            }
+        }
+        for (int g = 0; g < G; ++g) {
+            if (masked[g]) continue;
+            const int64_t t = t0 + g;
+            const int width = it[g].w - it[g].z;
+            if (it[g].y == kAllHits) {
+                for (int k = lane; k < width; k += 64) out[pos[g] + k] = tr.perm[it[g].z + k];
+                continue;
+            }
+            if (hit_off[t + 1] == pos[g]) continue;
+            Q q;
+            q.load(queries, it[g].x);
+            if (width > kLeafScanMax) {
+                if (lane == 0) walk_piece<Q, true>(tr, q, it[g].y, it[g].z, it[g].w, out, pos[g]);
+                continue;
+            }
+            scan_piece<Q, true>(tr, q, it[g].z, it[g].w, out, pos[g], nullptr);
+        }
+    }
 }
 
 // Staged output of a fill pass, per wave.  The 64 items (pieces or

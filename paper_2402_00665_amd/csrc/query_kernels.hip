@@ -45,8 +45,11 @@ namespace {
 struct Scratch {
     int32_t *cnt1, *cnt2, *hcnt, *ovf;
     int64_t *off1, *off2, *hoff, *partials, *count;
-    int4 *items1, *items2, *first1, *first2;
-    int32_t *hcache;
+    int4 *items1, *items2, *app_piece;
+    int64_t *app_item;
+    int32_t *app_rank;
+    unsigned long long *app_count;
+    uint64_t *hmask;
 };
 
 Scratch carve(char *ws, const QueryLayout &L)
@@ -58,14 +61,16 @@ Scratch carve(char *ws, const QueryLayout &L)
     S.cnt2 = reinterpret_cast<int32_t *>(ws + L.cnt2);
     S.off2 = reinterpret_cast<int64_t *>(ws + L.off2);
     S.items2 = reinterpret_cast<int4 *>(ws + L.items2);
-    S.first1 = reinterpret_cast<int4 *>(ws + L.first1);
-    S.first2 = reinterpret_cast<int4 *>(ws + L.first2);
-    S.hcache = reinterpret_cast<int32_t *>(ws + L.hcache);
+    S.app_piece = reinterpret_cast<int4 *>(ws + L.app_piece);
+    S.app_item = reinterpret_cast<int64_t *>(ws + L.app_item);
+    S.app_rank = reinterpret_cast<int32_t *>(ws + L.app_rank);
+    S.hmask = reinterpret_cast<uint64_t *>(ws + L.hmask);
     S.hcnt = reinterpret_cast<int32_t *>(ws + L.hcnt);
     S.hoff = reinterpret_cast<int64_t *>(ws + L.hoff);
     S.partials = reinterpret_cast<int64_t *>(ws + L.partials);
     S.ovf = reinterpret_cast<int32_t *>(ws + L.ctrl);              // [0] level 1, [1] level 2
     S.count = reinterpret_cast<int64_t *>(ws + L.ctrl + 64);       // [0] pieces 1, [1] pieces 2
+    S.app_count = reinterpret_cast<unsigned long long *>(ws + L.ctrl + 96);   // [0] level 1, [1] level 2
     return S;
 }
 
@@ -85,8 +90,9 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     const int split1 = (int)tune_get(TUNE_QSPLIT1), split2 = (int)tune_get(TUNE_QSPLIT2);
     // level 1: queries -> pieces of 2^split1 leaves
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL((k_split<Q, false, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
-                       nullptr, split1, S.cnt1, nullptr, nullptr, S.first1, nullptr);
+    hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(64), 0, s, S.app_count);
+    hipLaunchKernelGGL((k_split<Q, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr, nullptr,
+                       split1, S.cnt1, S.app_count + 0, L.cap1, S.app_piece, S.app_item, S.app_rank);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt1, m, nullptr, S.partials, S.off1, s);
@@ -94,14 +100,16 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
                        S.ovf + 0, S.count + 0);
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL((k_split<Q, true, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr,
-                       nullptr, split1, nullptr, S.off1, S.ovf + 0, S.first1, S.items1);
+    hipLaunchKernelGGL(k_split_scatter<true>, dim3(grid_for(L.cap1)), dim3(kBlock), 0, s, tr.n, m,
+                       nullptr, nullptr, S.off1, S.ovf + 0, S.app_count + 0, S.app_piece, S.app_item,
+                       S.app_rank, S.items1);
     prof_end(K_QSPLIT, s);
     // level 2: pieces -> pieces of 2^split2 leaves
     const unsigned g1 = grid_for(L.cap1);
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL((k_split<Q, false, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m,
-                       S.items1, S.count + 0, split2, S.cnt2, nullptr, nullptr, S.first2, nullptr);
+    hipLaunchKernelGGL((k_split<Q, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m, S.items1,
+                       S.count + 0, split2, S.cnt2, S.app_count + 1, L.cap2, S.app_piece, S.app_item,
+                       S.app_rank);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt2, L.cap1, S.count + 0, S.partials, S.off2, s);
@@ -109,18 +117,19 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
                        S.ovf + 1, S.count + 1);
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL((k_split<Q, true, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m, S.items1,
-                       S.count + 0, split2, nullptr, S.off2, S.ovf + 1, S.first2, S.items2);
+    hipLaunchKernelGGL(k_split_scatter<false>, dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr.n, m,
+                       S.items1, S.count + 0, S.off2, S.ovf + 1, S.app_count + 1, S.app_piece,
+                       S.app_item, S.app_rank, S.items2);
     prof_end(K_QSPLIT, s);
     // leaf level: count hits per piece, scan, per-query offsets
     const unsigned g2 = grid_for(L.cap2);
     prof_begin(K_QCOUNT, s);
     if (tune_get(TUNE_QLEAF) == 1)
         hipLaunchKernelGGL((k_leaf_mixed_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hcnt, S.hcache);
+                           S.count + 1, S.hcnt, S.hmask);
     else
         hipLaunchKernelGGL((k_leaf_scan_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hcnt, S.hcache);
+                           S.count + 1, S.hcnt, S.hmask);
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
@@ -137,12 +146,8 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
     Scratch S = carve(ws, L);
     prof_begin(K_QFILL, s);
     const unsigned g2 = grid_for(L.cap2);
-    if (tune_get(TUNE_QLEAF) == 1)
-        hipLaunchKernelGGL((k_leaf_mixed_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hoff, S.hcache, indices);
-    else
-        hipLaunchKernelGGL((k_leaf_scan_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                           S.count + 1, S.hoff, S.hcache, indices);
+    hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2, S.count + 1,
+                       S.hoff, S.hmask, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();
 }
