@@ -307,8 +307,9 @@ const char *lbvh_last_hip_error(void);
  *       finest pieces: 0 = one wave tests a piece's leaves 64 at a time
  *       (default; best when queries hit many leaves), 1 = pieces whose
  *       start-node box lies mostly outside the query are walked with Alg. 1
- *       by one lane, the rest as in 0 (best for sparse queries).  The count
- *       and fill calls of one query set must use the same mode.
+ *       by one lane, the rest as in 0 (best for sparse queries).  Both
+ *       record the same per-piece hit masks, and the fill call reads those
+ *       whatever the knobs are when it is enqueued.
  * Results never depend on the knobs; only speed does.  Calls already
  * enqueued keep the shapes they were enqueued with. */
 int64_t lbvh_tune(const char *name, int64_t value);
