@@ -31,9 +31,13 @@
 //   all-hit pieces in the split levels).  Alg. 1 would visit the same
 //   leaves in the same order and report the same primitives.
 // Pieces are emitted in walk order, so concatenating their hits gives the
-// plain walk's hits in the plain walk's order.  Each level is a count pass,
-// a scan and a fill pass; a level whose pieces would exceed the workspace
-// capacity passes its pieces through unsplit (same results, less parallel).
+// plain walk's hits in the plain walk's order.  A split level is one walk
+// per item that appends each piece with its rank among the item's pieces,
+// a scan of the per-item counts and a scatter of the pieces to offset +
+// rank; a level whose pieces would exceed the workspace capacity passes its
+// items through unsplit (same results, less parallel).  The leaf level's
+// count records a hit mask per piece, and the fill call writes leaf_perm of
+// the set bits.
 // No contraction: the sphere test is evaluated exactly as written.
 #pragma clang fp contract(off)
 
