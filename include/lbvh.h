@@ -293,7 +293,7 @@ const char *lbvh_last_hip_error(void);
  * a value out of range.  Knobs:
  *   "sort_variant32", "sort_variant64": tile shape of the radix passes for
  *       30-bit / 63-bit codes: 0 = 256 threads x 16 keys, 1 = 256 x 8,
- *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8
+ *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8, 6 = 768 x 16
  *       (defaults 4 and 3).
  *   "batch_sort_variant": tile shape of the batched build's segmented
  *       radix passes: 0 = 256 x 16 (default), 1 = 256 x 8, 2 = 512 x 8,

@@ -23,8 +23,8 @@ from . import (LBVH_POINTS, Workspace, alloc_tree, build, build_batched, check_b
                lbvh_tune, query_count, query_fill)
 
 KNOB_CANDIDATES = {
-    "sort_variant32": list(range(6)),
-    "sort_variant64": list(range(6)),
+    "sort_variant32": list(range(7)),
+    "sort_variant64": list(range(7)),
     "batch_sort_variant": list(range(4)),
 }
 # (query_split1, query_split2, query_leaf_mode)

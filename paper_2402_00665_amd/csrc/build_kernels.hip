@@ -142,7 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
 // Tile shapes of the radix pass (threads x keys per thread); the tuning
 // knob "sort_variant" picks one (see lbvh_tune).
 struct SortShape { int threads, items; };
-constexpr SortShape kSortShapes[] = {{256, 16}, {256, 8}, {256, 24}, {512, 8}, {512, 16}, {1024, 8}};
+constexpr SortShape kSortShapes[] = {{256, 16}, {256, 8}, {256, 24}, {512, 8}, {512, 16}, {1024, 8},
+                                     {768, 16}};
 constexpr int kSortShapeCount = sizeof(kSortShapes) / sizeof(kSortShapes[0]);
 
 template <typename K>
@@ -174,6 +175,7 @@ void launch_onesweep(int variant, const K *kin, K *kout, const int32_t *vin, int
     case 3: launch_one<K, 512, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
     case 4: launch_one<K, 512, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
     case 5: launch_one<K, 1024, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    case 6: launch_one<K, 768, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
     default: launch_one<K, 256, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
     }
 }

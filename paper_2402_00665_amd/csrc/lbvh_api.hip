@@ -120,7 +120,7 @@ std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}, {0
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
                                     "query_split1", "query_split2", "query_leaf_mode"};
 const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0};     // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {5, 5, 3, 24, 24, 1};
+const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }

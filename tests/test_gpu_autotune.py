@@ -22,7 +22,7 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     defaults = {k: lb.lbvh_tune(k) for k in autotune.KNOB_CANDIDATES}
     r = autotune.tune(p, 63, reps=3, verbose=True)
     say(f"single: {r}")
-    assert r["knob"] == "sort_variant64" and set(r["times_ms"]) == set(range(6))
+    assert r["knob"] == "sort_variant64" and set(r["times_ms"]) == set(range(7))
     assert {k: lb.lbvh_tune(k) for k in defaults} == defaults   # tuning restores the defaults
     sizes = np.array([3000, 70000, 1, 0, 40000], np.int64)
     seg = np.zeros(len(sizes) + 1, np.int64)

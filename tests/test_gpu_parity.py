@@ -222,7 +222,7 @@ def test_piece_capacity_overflow_passes_through(ws):
     assert_query_equal(off, idx, roff, ridx)
 
 
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(7))
 def test_sort_tile_variants(variant, ws):
     """Every radix-pass tile shape gives the same tree (tolerance 0)."""
     import paper_2402_00665_amd as lb
