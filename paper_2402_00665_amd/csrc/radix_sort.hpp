@@ -97,13 +97,16 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         const int64_t idx = wbase + k * 64 + lane;
         const bool ok = idx < ns;
         const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-        uint64_t peers = __ballot(ok);
+        // lanes whose digit differs from this lane's in some bit: for each
+        // bit, the ballot of lanes that have it, flipped where this lane has
+        // it (a sign-extended bit as the xor mask)
+        uint64_t diff = 0;
 #pragma unroll
         for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
+            diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
         }
+        const uint64_t peers = __ballot(ok) & ~diff;
         const uint32_t below = count_below(peers);
         const uint32_t cnt = s_wcnt[wave][d];
         rank[k] = cnt + below;
