@@ -78,15 +78,20 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 
     // wave w owns keys [base + w*64*ITEMS, ...); item k of lane l is key
     // base + w*64*ITEMS + k*64 + l, so (item, lane) order is input order
+    // keys of this tile: rem = how many (at most TILE), tile-local offsets
+    // from here on fit 32 bits
+    const int64_t rem64 = ns - base;
+    const int rem = rem64 < TILE ? (int)rem64 : TILE;
+    const int lofs = wave * 64 * ITEMS + lane;   // tile-local offset of item 0
+    const K *kp = keys_in + b0 + base + lofs;
+    const int32_t *vp = vals_in ? vals_in + b0 + base + lofs : nullptr;
     K key[ITEMS];
     int32_t val[ITEMS];
-    const int64_t wbase = base + (int64_t)wave * 64 * ITEMS;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const int64_t idx = wbase + k * 64 + lane;
-        const bool ok = idx < ns;
-        key[k] = ok ? keys_in[b0 + idx] : (K)0;
-        val[k] = vals_in ? (ok ? vals_in[b0 + idx] : 0) : (int32_t)idx;
+        const bool ok = lofs + k * 64 < rem;
+        key[k] = ok ? kp[k * 64] : (K)0;
+        val[k] = vp ? (ok ? vp[k * 64] : 0) : (int32_t)(base + lofs + k * 64);
     }
 
     // stable rank within the wave: lanes holding the same digit find each
@@ -94,8 +99,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const int64_t idx = wbase + k * 64 + lane;
-        const bool ok = idx < ns;
+        const bool ok = lofs + k * 64 < rem;
         const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
         // lanes whose digit differs from this lane's in some bit: for each
         // bit, the ballot of lanes that have it, flipped where this lane has
@@ -167,26 +171,27 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         const uint32_t dk = (uint32_t)(key[k] >> shift) & (kRadix - 1);
         pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
     }
-    const int64_t rem = ns - base;
-    const int valid = rem < TILE ? (int)rem : TILE;
-
-    // keys: into LDS in tile-sorted order, then out in runs
+    // keys: into LDS in tile-sorted order, then out in runs (segment-local
+    // positions fit 32 bits: a segment holds at most 2^30 keys)
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
-        if (wbase + k * 64 + lane < ns) s_buf[pos[k]] = key[k];
+        if (lofs + k * 64 < rem) s_buf[pos[k]] = key[k];
     __syncthreads();
-    int64_t dst[ITEMS];
+    K *ko = keys_out + b0;
+    int32_t *vo = vals_out + b0;
+    const uint32_t nsu = (uint32_t)ns;
+    uint32_t dst[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const int p = k * THREADS + tid;
-        dst[k] = -1;
-        if (p < valid) {
+        dst[k] = ~0u;
+        if (p < rem) {
             const K kk = s_buf[p];
             const uint32_t dk = (uint32_t)(kk >> shift) & (kRadix - 1);
-            const int64_t out = (int64_t)s_gbase[dk] + (p - (int)s_start[dk]);
-            if (out >= 0 && out < ns) {
-                keys_out[b0 + out] = kk;
-                dst[k] = b0 + out;
+            const uint32_t out = s_gbase[dk] + (uint32_t)p - s_start[dk];
+            if (out < nsu) {
+                ko[out] = kk;
+                dst[k] = out;
             } else {   // inconsistent histogram: flag it rather than write outside
                 __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -197,11 +202,11 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
-        if (wbase + k * 64 + lane < ns) s_vals[pos[k]] = val[k];
+        if (lofs + k * 64 < rem) s_vals[pos[k]] = val[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
-        if (dst[k] >= 0) vals_out[dst[k]] = s_vals[k * THREADS + tid];
+        if (dst[k] != ~0u) vo[dst[k]] = s_vals[k * THREADS + tid];
 }
 
 }  // namespace
