@@ -516,8 +516,7 @@ KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name
     "k_bounds<": "bounds", "k_bounds_final": "bounds_final", "k_morton": "morton",
     "k_onesweep": "sort_pass", "k_bottomup_l0": "bottomup", "k_bottomup_up": "bottomup_up",
     "k_split": "query_split", "k_leaf_scan_count": "query_count",
-    "k_leaf_scan_fill": "query_fill", "k_leaf_mixed_count": "query_count",
-    "k_leaf_mixed_fill": "query_fill", "copyBuffer": "copy",
+    "k_leaf_mixed_count": "query_count", "k_leaf_fill": "query_fill", "copyBuffer": "copy",
 }
 
 
