@@ -240,10 +240,13 @@ def test_sort_tile_variants(variant, ws):
         lb.lbvh_tune("sort_variant64", old64)
 
 
-@pytest.mark.parametrize("split1,split2,leaf_mode", [(12, 7, 1), (11, 6, 1), (9, 4, 0), (14, 9, 1)])
+@pytest.mark.parametrize("split1,split2,leaf_mode", [(12, 7, 1), (11, 6, 1), (9, 4, 0), (14, 9, 1),
+                                                      (8, 12, 0), (10, 10, 1), (6, 3, 0)])
 def test_query_schedules(split1, split2, leaf_mode, ws):
     """Every query schedule (split block sizes, leaf mode) gives the oracle's
-    results exactly: dense box queries, sparse spheres, all-hit ranges."""
+    results exactly: dense box queries, sparse spheres, all-hit ranges.  Also
+    a second level no finer than the first (one piece per item), and blocks
+    small enough that the levels overflow and pass their items through."""
     import paper_2402_00665_amd as lb
     old = [lb.lbvh_tune("query_split1", split1), lb.lbvh_tune("query_split2", split2),
            lb.lbvh_tune("query_leaf_mode", leaf_mode)]
