@@ -245,6 +245,11 @@ def main():
         "traffic": None if traffic is None else int(traffic),
         "alg_bytes_per_launch": int(dk["alg_bytes_per_launch"]),
         "ms_per_launch": round(dk["ms_per_launch"], 4),
+        # the measured HBM bytes over the same launch time: how close the
+        # kernel runs to the memory system, whatever its algorithmic bytes
+        "traffic_gbps": None if traffic is None else round(traffic / (dk["ms_per_launch"] * 1e-3) / 1e9, 1),
+        "traffic_frac": None if traffic is None else
+        round(traffic / (dk["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
     }
     model_bytes = build_model_bytes_per_prim(P, K, d) * w.n
 
