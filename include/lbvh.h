@@ -150,8 +150,9 @@ int64_t lbvh_query_workspace_bytes(int64_t m);
  * multiply-add).  Box j is lohi[j] = (lo.xyz, hi.xyz): B matches if
  * lo <= B.hi and B.lo <= hi on every axis (closed boxes).
  * Each query's walk is run as independent pieces over aligned blocks of
- * leaves (same nodes, same order); the pieces and their hit offsets are
- * kept in the workspace for the fill call.
+ * leaves (same nodes, same order); the pieces, a hit mask per piece and
+ * the hit offsets are kept in the workspace for the fill call, which tests
+ * no box again for pieces of at most 256 leaves.
  *   xyzr / lohi : device, float [m][4] / [m][6], 16-byte aligned.
  *   offsets     : device int64 [m+1]; receives the CSR offsets,
  *                 offsets[0] = 0 and offsets[m] = total number of hits.
