@@ -303,3 +303,49 @@ def test_non_finite_inputs_give_a_well_formed_tree(kind, bits, ws):
     q = workloads.spheres(rng.random((500, 3), dtype=np.float32), np.float32(0.05))
     off, idx = gpu_query(tree, q, 0, ws)
     assert off[0] == 0 and np.all(np.diff(off) >= 0) and np.all((idx >= 0) & (idx < n))
+
+
+def test_graph_capture_single_tree(ws):
+    """Build, count and fill of one tree enqueue kernels only (no memset, no
+    host synchronisation), so they can be captured in a HIP graph; every
+    replay, with eager work between replays, reproduces the eager bits."""
+    import torch
+    import paper_2402_00665_amd as lb
+    w = workloads.by_name("clustered_boxes", 1 / 64)
+    dp = torch.from_numpy(w.prims).cuda()
+    dq = torch.from_numpy(w.queries).cuda()
+    bws, qws = lb.Workspace(), lb.Workspace()
+    tree = lb.build(dp, w.code_bits, kind=w.kind, workspace=bws)
+    off, idx = lb.query(tree, dq, w.qkind, workspace=qws)
+    torch.cuda.synchronize()
+    total = int(off[-1].item())
+    assert total > 0
+    eager_nodes, eager_off, eager_idx = tree.nodes.clone(), off.clone(), idx.clone()
+    offsets = torch.empty_like(off)
+    indices = torch.empty(total, dtype=torch.int32, device="cuda")
+
+    def enqueue():
+        lb.build(dp, w.code_bits, kind=w.kind, workspace=bws, tree=tree)
+        lb.query_count(tree, dq, w.qkind, qws, offsets=offsets)
+        lb.query_fill(tree, dq, w.qkind, indices, qws)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            enqueue()
+    torch.cuda.synchronize()
+    for r in range(4):
+        tree.nodes.zero_()
+        offsets.zero_()
+        indices.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(tree.nodes, eager_nodes), f"replay {r}: nodes differ"
+        assert torch.equal(offsets, eager_off), f"replay {r}: offsets differ"
+        assert torch.equal(indices, eager_idx), f"replay {r}: indices differ"
+        x = torch.rand(1000, device="cuda").sum()   # eager work between replays
+        x.item()
+    lb.check_build(tree)
