@@ -116,6 +116,9 @@ def parse():
                     help="fraction of the workload the oracle baseline runs on")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="repeat the oracle baseline until this much CPU time is spent (max 8 runs)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched build + queries (no plain per-scene leg, no "
+                         "single-tree or serving legs); for profiling the batched kernels")
     ap.add_argument("--summarize", nargs=3, metavar=("STATS_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="turn rocprofv3 outputs (kernel-trace --stats run, --pmc FETCH_SIZE "
                          "run, --pmc WRITE_SIZE run) into profiles/ summaries and exit")
@@ -125,6 +128,25 @@ def parse():
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def copy_bandwidth() -> float:
+    """GB/s of a 256 MiB device-to-device copy (read + write), for context;
+    it is also the copy of known size the traffic counters are scaled by."""
+    import torch
+    buf = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(buf)
+    for _ in range(3):
+        dst.copy_(buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(buf)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * buf.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del buf, dst
+    return gbps
 
 
 def main():
@@ -142,6 +164,13 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    if args.batched_only:
+        for kv in filter(None, args.knobs.split(",")):
+            k, v = kv.split("=")
+            lb.lbvh_tune(k.strip(), int(v))
+        batched = bench_batched(args, plain=False)
+        print(json.dumps({"batched": batched, "copy_gbps": round(copy_bandwidth(), 1)}), flush=True)
+        return
     t0 = time.time()
     w = workloads.by_name(args.workload)
     log(f"[bench] workload {w.name}: n={w.n} m={w.m} bits={w.code_bits} "
@@ -253,19 +282,7 @@ def main():
     }
     model_bytes = build_model_bytes_per_prim(P, K, d) * w.n
 
-    # stream-copy bandwidth in the same run, for context
-    buf = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(buf)
-    for _ in range(3):
-        dst.copy_(buf)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        dst.copy_(buf)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 2 * buf.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del buf, dst
+    copy_gbps = copy_bandwidth()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -333,7 +350,7 @@ def main():
 
 # ---------------------------------------------------------------- batched
 
-def bench_batched(args, reps: int = 5):
+def bench_batched(args, reps: int = 5, plain: bool = True):
     """4096 uniform point sets (sizes log-uniform in [32, 65536], 63-bit
     codes, 64 spheres of radius 0.05 each): one batched launch sequence for
     all scenes against one plain build + query per scene, same GPU, same
@@ -382,6 +399,17 @@ def bench_batched(args, reps: int = 5):
         bt.append(ev[0].elapsed_time(ev[1]))
         qt.append(ev[1].elapsed_time(ev[2]))
 
+    bb, bq, bw = float(np.median(bt)), float(np.median(qt)), float(np.median(wt))
+    res = {
+        "workload": "batched_scenes", "scenes": S, "n": N, "m": m, "code_bits": 63,
+        "batched_build_ms": round(bb, 4), "batched_query_ms": round(bq, 4),
+        "batched_wall_ms": round(bw * 1e3, 3),
+        "batched_mprims_per_s": round(N / (bb * 1e-3) / 1e6, 1),
+        "tuning": tuned,
+    }
+    if not plain:
+        return res
+
     # plain: one single-scene build and one query call per scene
     off_h, qoff_h = off.tolist(), qoff.tolist()
     trees = [lb.alloc_tree(off_h[s + 1] - off_h[s], 63) for s in range(S)]
@@ -419,20 +447,15 @@ def bench_batched(args, reps: int = 5):
         po, pi = pres[s]
         same &= bool(torch.equal(boff[qa:qe + 1] - boff[qa], po))
         same &= bool(torch.equal(bidx[int(boff[qa]):int(boff[qe])], pi))
-    bb, bq, bw = float(np.median(bt)), float(np.median(qt)), float(np.median(wt))
-    return {
-        "workload": "batched_scenes", "scenes": S, "n": N, "m": m, "code_bits": 63,
-        "batched_build_ms": round(bb, 4), "batched_query_ms": round(bq, 4),
-        "batched_wall_ms": round(bw * 1e3, 3),
-        "batched_mprims_per_s": round(N / (bb * 1e-3) / 1e6, 1),
+    res.update({
         "plain_build_ms": round(plain_build_s * 1e3, 3),
         "plain_wall_ms": round(plain_all_s * 1e3, 3),
         "plain_mprims_per_s": round(N / plain_build_s / 1e6, 1),
-        "tuning": tuned,
         "build_speedup": round(plain_build_s * 1e3 / bb, 2),
         "wall_speedup": round(plain_all_s / bw, 2),
         "identical": same,
-    }
+    })
+    return res
 
 
 # ---------------------------------------------------------------- serving
@@ -520,8 +543,10 @@ def bench_serving(args):
 KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name
     "k_bounds<": "bounds", "k_bounds_final": "bounds_final", "k_morton": "morton",
     "k_onesweep": "sort_pass", "k_bottomup_l0": "bottomup", "k_bottomup_up": "bottomup_up",
-    "k_split": "query_split", "k_leaf_scan_count": "query_count",
+    "k_split": "query_split", "k_leaf_scan_count": "query_count", "k_leaf_count_wide": "query_count",
     "k_leaf_mixed_count": "query_count", "k_leaf_fill": "query_fill", "copyBuffer": "copy",
+    "k_batch_plan": "batch_plan", "k_batch_morton": "morton", "k_batch_count": "query_count",
+    "k_batch_fill": "query_fill",
 }
 
 
@@ -541,6 +566,7 @@ def summarize(args):
     import collections
     import glob
     stats_dir, fetch_dir, write_dir = args.summarize
+    name = "batched_scenes" if args.batched_only else args.workload
 
     def one(pattern):
         got = glob.glob(os.path.join(pattern, "**", "*"), recursive=True)
@@ -548,7 +574,7 @@ def summarize(args):
 
     stats = [f for f in one(stats_dir) if f.endswith("kernel_stats.csv")][0]
     rows = list(csv.DictReader(open(stats)))
-    lines = [f"# Kernel time: {args.workload}", "",
+    lines = [f"# Kernel time: {name}", "",
              f"Command: `{args.command}`", "",
              "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
     for r in rows:
@@ -558,7 +584,7 @@ def summarize(args):
                      f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", f"kernels_{args.workload}.md"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"kernels_{name}.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
     def per_dispatch(d, counter):
@@ -593,11 +619,11 @@ def summarize(args):
         wb = sum(dv["write"]) / max(len(dv["write"]), 1)
         kernels[grp] = {"fetch_bytes_per_launch": int(fb), "write_bytes_per_launch": int(wb),
                         "hbm_bytes_per_launch": int(fb + wb), "launches": len(dv["fetch"])}
-    doc = {"workload": args.workload, "command": args.command,
+    doc = {"workload": name, "command": args.command,
            "calibration": {"fetch_scale": cf, "write_scale": cw,
                            "copy_kernel": "__amd_rocclr_copyBuffer, 256 MiB device copy"},
            "source_sha256": source_hash(), "kernels": kernels}
-    with open(os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json"), "w") as f:
         json.dump(doc, f, indent=1)
     print(json.dumps(doc, indent=1))
 

@@ -28,8 +28,8 @@ KNOB_CANDIDATES = {
     "batch_sort_variant": list(range(4)),
 }
 # (query_split1, query_split2, query_leaf_mode)
-QUERY_CANDIDATES = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (11, 6, 0), (12, 7, 1), (11, 6, 1),
-                    (13, 7, 1), (11, 5, 1)]
+QUERY_CANDIDATES = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (12, 6, 0), (13, 7, 0), (11, 6, 0),
+                    (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1)]
 _QUERY_KNOBS = ("query_split1", "query_split2", "query_leaf_mode")
 
 

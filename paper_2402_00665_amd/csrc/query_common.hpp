@@ -456,15 +456,31 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan_count(Tree tr, const float
         const int4 it = in[t];
         int64_t cnt = it.w - it.z;
         if (it.y != kAllHits) {
+            if (it.w - it.z > kLeafScanMax) continue;   // k_leaf_count_wide
             Q q;
             q.load(queries, it.x);
-            if (it.w - it.z > kLeafScanMax) {
-                if (lane == 0) counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0);
-                continue;
-            }
             cnt = scan_piece<Q, false>(tr, q, it.z, it.w, nullptr, 0, masks + t * kMaskWords);
         }
         if (lane == 0) counts[t] = (int32_t)cnt;
+    }
+}
+
+// Count of the pieces wider than kLeafScanMax (left unsplit after a split
+// level overflowed) for the plain schedule: Alg. 1 by one lane per piece,
+// all lanes in parallel.
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_count_wide(Tree tr, const float *__restrict__ queries,
+                                                       const int4 *__restrict__ in,
+                                                       const int64_t *in_count,
+                                                       int32_t *__restrict__ counts)
+{
+    const int64_t T = *in_count;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < T; t += (int64_t)gridDim.x * kBlock) {
+        const int4 it = in[t];
+        if (it.y == kAllHits || it.w - it.z <= kLeafScanMax) continue;
+        Q q;
+        q.load(queries, it.x);
+        counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0);
     }
 }
 
@@ -531,8 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const floa
 // The group's descriptors, output slots and masks are loaded together, then
 // the leaf_perm entries of all its masked hits, then the stores, so a group
 // costs two dependent round trips to memory.  All-hit pieces are copied from
-// leaf_perm, and pieces wider than kMaskLeaves are tested again: scanned,
-// or walked by one lane beyond kLeafScanMax.
+// leaf_perm; pieces wider than kMaskLeaves are left to k_leaf_fill_wide.
 constexpr int kFillGroup = 4;
 
 template <class Q>
@@ -585,22 +600,61 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__re
                 p += __popcll(m);
             }
         }
-        for (int g = 0; g < G; ++g) {
-            if (masked[g]) continue;
-            const int64_t t = t0 + g;
+        for (int g = 0; g < G; ++g) {   // all-hit pieces (wider ones: k_leaf_fill_wide)
+            if (it[g].y != kAllHits) continue;
             const int width = it[g].w - it[g].z;
-            if (it[g].y == kAllHits) {
-                for (int k = lane; k < width; k += 64) out[pos[g] + k] = tr.perm[it[g].z + k];
-                continue;
+            for (int k = lane; k < width; k += 64) out[pos[g] + k] = tr.perm[it[g].z + k];
+        }
+    }
+}
+
+// Fill of the pieces wider than kMaskLeaves (only after a split level
+// overflowed, or with split2 above 8), 64 pieces per wave at a time: a
+// sparse piece, or one wider than kLeafScanMax, is walked with Alg. 1 by its
+// own lane; the wave then scans its dense ones one after another.
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float *__restrict__ queries,
+                                                      const int4 *__restrict__ in,
+                                                      const int64_t *in_count,
+                                                      const int64_t *__restrict__ hit_off,
+                                                      int32_t *__restrict__ out)
+{
+    const int64_t T = *in_count;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
+        const int64_t t = t0 + lane;
+        int4 it = make_int4(0, kAllHits, 0, 0);
+        int64_t pos = 0;
+        bool scan = false;
+        if (t < T) {
+            it = in[t];
+            pos = hit_off[t];
+            if (it.y != kAllHits && it.w - it.z > kMaskLeaves && hit_off[t + 1] > pos) {
+                Q q;
+                q.load(queries, it.x);
+                bool walk = true;
+                if (it.w - it.z <= kLeafScanMax) {
+                    float4 a, b;
+                    tr.load(it.y, a, b);
+                    walk = !dense_piece(q, a, b);
+                }
+                if (walk) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos);
+                else scan = true;
             }
-            if (hit_off[t + 1] == pos[g]) continue;
+        }
+        uint64_t todo = __ballot(scan);
+        while (todo) {
+            const int L = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int qi = __builtin_amdgcn_readlane(it.x, L);
+            const int lo = __builtin_amdgcn_readlane(it.z, L);
+            const int hi = __builtin_amdgcn_readlane(it.w, L);
+            const int plo = __builtin_amdgcn_readlane((int)(pos & 0xffffffff), L);
+            const int phi = __builtin_amdgcn_readlane((int)(pos >> 32), L);
             Q q;
-            q.load(queries, it[g].x);
-            if (width > kLeafScanMax) {
-                if (lane == 0) walk_piece<Q, true>(tr, q, it[g].y, it[g].z, it[g].w, out, pos[g]);
-                continue;
-            }
-            scan_piece<Q, true>(tr, q, it[g].z, it[g].w, out, pos[g], nullptr);
+            q.load(queries, qi);
+            scan_piece<Q, true>(tr, q, lo, hi, out, ((int64_t)phi << 32) | (uint32_t)plo, nullptr);
         }
     }
 }

@@ -131,9 +131,12 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     if (tune_get(TUNE_QLEAF) == 1)
         hipLaunchKernelGGL((k_leaf_mixed_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
                            S.count + 1, S.hcnt, S.hmask);
-    else
+    else {
         hipLaunchKernelGGL((k_leaf_scan_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
                            S.count + 1, S.hcnt, S.hmask);
+        hipLaunchKernelGGL((k_leaf_count_wide<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                           S.count + 1, S.hcnt);
+    }
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
@@ -152,6 +155,8 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
     const unsigned g2 = grid_for(L.cap2);
     hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2, S.count + 1,
                        S.hoff, S.hmask, indices);
+    hipLaunchKernelGGL((k_leaf_fill_wide<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
+                       S.count + 1, S.hoff, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();
 }
