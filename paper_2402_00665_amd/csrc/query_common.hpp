@@ -543,12 +543,52 @@ __global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const floa
     }
 }
 
-// Fill for both schedules: one wave per piece, kFillGroup pieces at a time.
-// The group's descriptors, output slots and masks are loaded together, then
-// the leaf_perm entries of all its masked hits, then the stores, so a group
-// costs two dependent round trips to memory.  All-hit pieces are copied from
-// leaf_perm; pieces wider than kMaskLeaves are left to k_leaf_fill_wide.
-constexpr int kFillGroup = 4;
+// Fill for both schedules, 64 pieces per wave at a time, with the hits of
+// all 64 spread evenly over the lanes:
+//   1. lane l loads piece t0 + l: its descriptor, output slot and mask (an
+//      all-hit piece at most kMaskLeaves wide counts as a full mask);
+//   2. a wave scan of the masks' popcounts gives each piece's first hit
+//      among the wave's H hits;
+//   3. lane l takes hits l, l + 64, ...: it finds the piece (binary search
+//      over the scan, read from other lanes with __shfl), the set bit of
+//      that rank in the piece's mask, and writes leaf_perm of that leaf to
+//      the piece's slot plus the rank.  kFillUnroll hits per lane are
+//      loaded before any is stored, so a wave's pieces cost a round trip
+//      for the descriptors and about one per 64 * kFillUnroll hits.
+// When the wave's pieces average kDenseFill hits or more, it instead writes
+// each piece's mask words with the whole wave (a lane per leaf, coalesced),
+// four pieces per step.  Bits are ranked in ascending leaf order, Alg. 1's
+// order.  All-hit pieces
+// wider than kMaskLeaves are copied by the whole wave; other wider pieces
+// are left to k_leaf_fill_wide.
+constexpr int kFillUnroll = 4;
+constexpr int kDenseFill = 16;   // hits per piece (wave average) from which whole-wave writes win
+
+// position of the set bit of rank r (r < popcount(x)) in x
+__device__ __forceinline__ int select_bit(uint64_t x, int r)
+{
+    int pos = 0;
+#pragma unroll
+    for (int half = 32; half >= 1; half >>= 1) {
+        const uint64_t low = x & ((1ull << half) - 1ull);
+        const int c = __popcll(low);
+        if (r >= c) {
+            r -= c;
+            x >>= half;
+            pos += half;
+        } else {
+            x = low;
+        }
+    }
+    return pos;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
 
 template <class Q>
 __global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__restrict__ queries,
@@ -557,53 +597,122 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__re
                                                  const uint64_t *__restrict__ masks,
                                                  int32_t *__restrict__ out)
 {
-    constexpr int G = kFillGroup;
     const int64_t T = *in_count;
     const int lane = threadIdx.x & 63;
-    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t t0 = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * G; t0 < T; t0 += nw * G) {
-        int4 it[G];
-        int64_t pos[G];
-        uint64_t words[G][kMaskWords];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
+        const int64_t t = t0 + lane;
+        int4 it = make_int4(0, kAllHits, 0, 0);   // past the end: empty
+        int64_t pos = 0;
+        uint64_t w[kMaskWords] = {0ull, 0ull, 0ull, 0ull};
+        if (t < T) {
+            it = in[t];
+            pos = hit_off[t];
+            const int width = it.w - it.z;
+            if (width <= kMaskLeaves) {
+                if (it.y == kAllHits) {
+                    LeafMask full;
+                    full.set(0, width);
+                    w[0] = full.w0; w[1] = full.w1; w[2] = full.w2; w[3] = full.w3;
+                } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int64_t t = t0 + g;
-            it[g] = make_int4(0, kAllHits, 0, 0);   // past the end: an empty copy
-            pos[g] = 0;
-            if (t < T) {
-                it[g] = in[t];
-                pos[g] = hit_off[t];
-                // all words, whatever the width: unused ones are ignored
-#pragma unroll
-                for (int w = 0; w < kMaskWords; ++w) words[g][w] = masks[t * kMaskWords + w];
+                    for (int k = 0; k < kMaskWords; ++k)
+                        if (64 * k < width) w[k] = masks[t * kMaskWords + k];
+                }
             }
         }
-        int32_t v[G][kMaskWords];
-        bool masked[G];
+        const int c = __popcll(w[0]) + __popcll(w[1]) + __popcll(w[2]) + __popcll(w[3]);
+        // wave scan: first hit of each piece among the wave's hits
+        int incl = c;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int width = it[g].w - it[g].z;
-            masked[g] = it[g].y != kAllHits && width <= kMaskLeaves;
-#pragma unroll
-            for (int w = 0; w < kMaskWords; ++w) {
-                if (!masked[g] || 64 * w >= width) words[g][w] = 0ull;
-                if ((words[g][w] >> lane) & 1ull) v[g][w] = tr.perm[it[g].z + 64 * w + lane];
-            }
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
         }
+        const int base = incl - c;
+        const int H = __shfl(incl, 63);
+        if (H >= 64 * kDenseFill) {
+            // dense pieces: the whole wave writes one mask word of one piece
+            // per step (coalesced), four pieces' loads in flight
+            for (int g0 = 0; g0 < 64; g0 += 4) {
+                int32_t v[4][kMaskWords];
+                int64_t d[4][kMaskWords];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            int64_t p = pos[g];
+                for (int g = 0; g < 4; ++g) {
+                    const int L = g0 + g;
+                    const int z = __builtin_amdgcn_readlane(it.z, L);
+                    const int64_t p = ((int64_t)__builtin_amdgcn_readlane((int)(pos >> 32), L) << 32) |
+                                      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)pos, L);
+                    int prefix = 0;
 #pragma unroll
-            for (int w = 0; w < kMaskWords; ++w) {
-                const uint64_t m = words[g][w];
-                if ((m >> lane) & 1ull) out[p + lanes_below(m)] = v[g][w];
-                p += __popcll(m);
+                    for (int k = 0; k < kMaskWords; ++k) {
+                        const uint64_t wk =
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(w[k] >> 32), L) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)w[k], L);
+                        d[g][k] = -1;
+                        if ((wk >> lane) & 1ull) {
+                            v[g][k] = tr.perm[z + 64 * k + lane];
+                            d[g][k] = p + prefix + lanes_below(wk);
+                        }
+                        prefix += __popcll(wk);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int k = 0; k < kMaskWords; ++k)
+                        if (d[g][k] >= 0) out[d[g][k]] = v[g][k];
             }
+        } else
+        for (int h0 = 0; h0 < H; h0 += 64 * kFillUnroll) {
+            int32_t v[kFillUnroll];
+            int64_t dst[kFillUnroll];
+#pragma unroll
+            for (int u = 0; u < kFillUnroll; ++u) {
+                const int h = h0 + u * 64 + lane;
+                dst[u] = -1;
+                // every lane takes part in the shuffles; only h < H is used
+                int lo = 0, hi = 63;   // the last piece whose first hit is <= h
+#pragma unroll
+                for (int step = 0; step < 6; ++step) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (__shfl(base, mid) <= h) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int r0 = h - __shfl(base, lo);   // rank of hit h in its piece
+                int r = r0;
+                const int z = __shfl(it.z, lo);
+                const int64_t p = (int64_t)shfl64((uint64_t)pos, lo);
+                uint64_t x = 0ull;
+                int word = 0;
+#pragma unroll
+                for (int k = 0; k < kMaskWords; ++k) {
+                    const uint64_t wk = shfl64(w[k], lo);
+                    const int ck = __popcll(wk);
+                    if (x == 0ull) {
+                        if (r < ck) { x = wk; word = k; }
+                        else r -= ck;
+                    }
+                }
+                if (h < H && x != 0ull) {   // no lane-crossing reads in here
+                    const int leaf = z + 64 * word + select_bit(x, r);
+                    v[u] = tr.perm[leaf];
+                    dst[u] = p + r0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kFillUnroll; ++u)
+                if (dst[u] >= 0) out[dst[u]] = v[u];
         }
-        for (int g = 0; g < G; ++g) {   // all-hit pieces (wider ones: k_leaf_fill_wide)
-            if (it[g].y != kAllHits) continue;
-            const int width = it[g].w - it[g].z;
-            for (int k = lane; k < width; k += 64) out[pos[g] + k] = tr.perm[it[g].z + k];
+        // all-hit pieces wider than a mask: the whole wave copies each
+        uint64_t wide = __ballot(t < T && it.y == kAllHits && it.w - it.z > kMaskLeaves);
+        while (wide) {
+            const int L = __ffsll((unsigned long long)wide) - 1;
+            wide &= wide - 1;
+            const int z = __builtin_amdgcn_readlane(it.z, L);
+            const int e = __builtin_amdgcn_readlane(it.w, L);
+            const int64_t p = (int64_t)shfl64((uint64_t)pos, L);
+            for (int k = lane; k < e - z; k += 64) out[p + k] = tr.perm[z + k];
         }
     }
 }
