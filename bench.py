@@ -4,6 +4,13 @@ One step = one full pass of the path over resident inputs: build (scene box,
 Morton codes, radix sort, Alg. 4 bottom-up pass) followed by the stackless
 range queries (count pass, offset scan, read of the total, fill pass).
 
+The timed steps launch the library's kernels directly (--graph replays the
+build from a HIP graph captured once: same kernels, same buffers, measured
+the same); the queries include the read of the hit total between count and
+fill.  Per-kernel times come from a second, untimed pass of the same steps
+with the library's per-launch events on, which cost about 65 us of host
+time per build when left in the timed loop.
+
 Prints one JSON line:
   value        build throughput, Mprims/s (n / mean build time of a step)
   ms_per_step  mean wall time of a whole step (build + queries)
@@ -110,6 +117,9 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=3, help="streams of the batching server")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0,
                     help="HBM budget for in-flight batches and resident trees")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the timed builds from a HIP graph captured once instead of "
+                         "launching them one kernel at a time (measured the same)")
     ap.add_argument("--build-only", action="store_true",
                     help="time the build alone (no queries in the step)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
@@ -206,10 +216,28 @@ def main():
                 tuning[k] = v
         log(f"[bench] autotuned in {time.time() - a0:.1f}s: {tuning}")
 
-    def step(ev=None):
+    def build_eager():
+        lb.build(prims, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
+
+    run_build = build_eager
+    if args.graph:
+        # the build's launches captured once in a HIP graph and replayed:
+        # the same kernels on the same buffers, one launch call per build
+        build_eager()
+        torch.cuda.synchronize()
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(graph, stream=gs):
+                build_eager()
+        torch.cuda.synchronize()
+        run_build = graph.replay
+
+    def step(ev=None, build=None):
         if ev:
             ev[0].record(stream)
-        lb.build(prims, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
+        (build or run_build)()
         if ev:
             ev[1].record(stream)
         off, idx = (None, None) if args.build_only else lb.query(tree, queries, w.qkind, workspace=qws)
@@ -223,8 +251,6 @@ def main():
     lb.check_build(tree)
     log(f"[bench] warmup {args.warmup} done")
 
-    lb.lbvh_profile_reset()
-    lb.lbvh_profile_enable(True)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -234,8 +260,17 @@ def main():
         hits = int(idx.numel()) if idx is not None else 0
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    lb.lbvh_profile_enable(False)
+    lb.check_build(tree)
     log(f"[bench] timed {args.steps} steps in {wall:.3f}s")
+
+    # per-kernel times: the same steps again, eager, with the library's
+    # per-launch events on (kept out of the timed loop above)
+    lb.lbvh_profile_reset()
+    lb.lbvh_profile_enable(True)
+    for _ in range(args.steps):
+        step(build=build_eager)
+    torch.cuda.synchronize()
+    lb.lbvh_profile_enable(False)
 
     build_ms = [e[0].elapsed_time(e[1]) for e in evs]
     query_ms = [e[1].elapsed_time(e[2]) for e in evs]
@@ -329,7 +364,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "kind": "points" if w.kind == 0 else "boxes",
                    "code_bits": w.code_bits, "m": w.m,
-                   "queries": "spheres" if w.qkind == 0 else "boxes"},
+                   "queries": "spheres" if w.qkind == 0 else "boxes",
+                   "build_launch": "hip_graph" if args.graph else "eager"},
         "build_ms": round(mean_build, 4),
         "queries": None if args.build_only else {
             "mqueries_per_s": round(w.m / (mean_query * 1e-3) / 1e6, 2),
