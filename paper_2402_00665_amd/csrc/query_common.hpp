@@ -308,9 +308,9 @@ __global__ void k_split_reset(unsigned long long *app_count)
 // order: the tests are monotone under box inclusion, so every ancestor of a
 // passing leaf passes too.  A piece can therefore be
 //   * scanned by one wave, 64 consecutive leaf records per step with
-//     coalesced loads, counted with a ballot, each hit written at its rank
-//     (best for dense pieces: most leaves hit, and a walk would be a long
-//     chain of dependent loads), or
+//     coalesced loads, each step's ballot counting the hits and kept as a
+//     word of the piece's hit mask (best for dense pieces: most leaves hit,
+//     and a walk would be a long chain of dependent loads), or
 //   * walked with Alg. 1 by one lane (best for sparse pieces: the walk
 //     prunes).
 // Two schedules (knob query_leaf_mode): 0 scans every piece; 1 walks the
