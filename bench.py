@@ -211,7 +211,8 @@ def main():
         if not args.build_only:
             lb.build(prims, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
             tq = autotune.tune_query(tree, queries, w.qkind, reps=3, save=False)
-            for k, v in zip(("query_split1", "query_split2", "query_leaf_mode"), tq["value"]):
+            for k, v in zip(("query_split1", "query_split2", "query_leaf_mode", "query_order"),
+                            tq["value"]):
                 lb.lbvh_tune(k, v)
                 tuning[k] = v
         log(f"[bench] autotuned in {time.time() - a0:.1f}s: {tuning}")

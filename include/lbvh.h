@@ -152,7 +152,10 @@ int64_t lbvh_query_workspace_bytes(int64_t m);
  * Each query's walk is run as independent pieces over aligned blocks of
  * leaves (same nodes, same order); the pieces, a hit mask per piece and
  * the hit offsets are kept in the workspace for the fill call, which tests
- * no box again for pieces of at most 256 leaves.
+ * no box again for pieces of at most 256 leaves.  With the "query_order"
+ * knob the walks run in a Morton order of the queries; the workspace then
+ * also keeps the reordered queries and each one's shift to its output
+ * slot.
  *   xyzr / lohi : device, float [m][4] / [m][6], 16-byte aligned.
  *   offsets     : device int64 [m+1]; receives the CSR offsets,
  *                 offsets[0] = 0 and offsets[m] = total number of hits.
@@ -311,6 +314,13 @@ const char *lbvh_last_hip_error(void);
  *       by one lane, the rest as in 0 (best for sparse queries).  Both
  *       record the same per-piece hit masks, and the fill call reads those
  *       whatever the knobs are when it is enqueued.
+ *   "query_order": 1 = the single-tree count call first sorts the queries
+ *       by a 16-bit Morton key of their centres (in the root's box) and
+ *       walks them in that order, so that neighbouring threads walk
+ *       neighbouring parts of the tree; offsets and indices still come out
+ *       in the caller's query order.  0 = the caller's order (default).
+ *       The count call records which it did in the workspace, and the fill
+ *       call follows that whatever the knob is when it is enqueued.
  * Results never depend on the knobs; only speed does.  Calls already
  * enqueued keep the shapes they were enqueued with. */
 int64_t lbvh_tune(const char *name, int64_t value);
@@ -322,7 +332,8 @@ int64_t lbvh_tune(const char *name, int64_t value);
  * launches since the last reset.  Names: "bounds", "bounds_final",
  * "morton", "sort_pass", "bottomup" (level 0 of the bottom-up pass),
  * "bottomup_up" (its upper levels), "batch_prep" (batched plan and
- * per-scene codes), "query_split",
+ * per-scene codes), "query_order" (the query sort and the mapping back to
+ * the caller's order), "query_split",
  * "query_count", "query_fill", "scan" (scans and offset bookkeeping).
  * Returns LBVH_EINVAL for an unknown name. */
 int lbvh_profile_enable(int32_t on);

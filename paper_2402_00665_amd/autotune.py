@@ -27,10 +27,12 @@ KNOB_CANDIDATES = {
     "sort_variant64": list(range(7)),
     "batch_sort_variant": list(range(4)),
 }
-# (query_split1, query_split2, query_leaf_mode)
-QUERY_CANDIDATES = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (12, 6, 0), (13, 7, 0), (11, 6, 0),
-                    (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1)]
-_QUERY_KNOBS = ("query_split1", "query_split2", "query_leaf_mode")
+# (query_split1, query_split2, query_leaf_mode, query_order): each split
+# schedule with the queries as given and in Morton order
+_SPLITS = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (12, 6, 0), (13, 7, 0), (11, 6, 0),
+           (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1)]
+QUERY_CANDIDATES = [s + (o,) for o in (0, 1) for s in _SPLITS]
+_QUERY_KNOBS = ("query_split1", "query_split2", "query_leaf_mode", "query_order")
 
 
 def cache_path() -> str:
@@ -161,9 +163,10 @@ def _query_key(qkind: int, n: int, m: int) -> str:
 def tune_query(tree, queries, qkind: int, candidates=None, reps: int = 5, save: bool = True,
                verbose: bool = False) -> dict:
     """Tune the query schedule for this tree and query set: times the count
-    call plus the fill call per (split1, split2, leaf mode) candidate,
-    checks each gives the default's offsets and indices bit for bit, keeps
-    the fastest.  Returns {"value": (s1, s2, mode), "times_ms": {...}}."""
+    call plus the fill call per (split1, split2, leaf mode, query order)
+    candidate, checks each gives the default's offsets and indices bit for
+    bit, keeps the fastest.  Returns {"value": (s1, s2, mode, order),
+    "times_ms": {...}}."""
     import torch
     cands = [tuple(c) for c in (candidates or QUERY_CANDIDATES)]
     default = tuple(lbvh_tune(k) for k in _QUERY_KNOBS)

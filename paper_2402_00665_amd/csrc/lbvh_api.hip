@@ -61,7 +61,22 @@ QueryLayout query_layout(int64_t m)
     L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
     L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
     L.ctrl = take(128);
+    L.qsorted = take((size_t)m * 6 * sizeof(float));
+    L.qperm = take((size_t)m * sizeof(int32_t));
+    L.qoff = take((size_t)(m + 1) * sizeof(int64_t));
     L.total = off;
+    // the query-order sort's buffers live in `hmask`, which is first
+    // written by the leaf level, after the sort is done with them
+    const size_t qtiles = (size_t)((m + kQOrderTile - 1) / kQOrderTile);
+    size_t q = L.hmask;
+    auto inner = [&](size_t bytes) { size_t at = q; q = align256(q + bytes); return at; };
+    L.qkeys[0] = inner((size_t)m * sizeof(uint32_t));
+    L.qkeys[1] = inner((size_t)m * sizeof(uint32_t));
+    L.qvals = inner((size_t)m * sizeof(int32_t));
+    L.qstatus[0] = inner(qtiles * kRadix * sizeof(uint32_t));
+    L.qstatus[1] = inner(qtiles * kRadix * sizeof(uint32_t));
+    L.qhist = inner((size_t)kQOrderPasses * kRadix * sizeof(uint32_t));
+    // hmask holds 32 * cap2 >= 192 m + 131072 bytes: more than the above
     return L;
 }
 
@@ -116,11 +131,12 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 
 namespace {
 // defaults measured on MI355X: 512 x 16 for 30-bit keys, 512 x 8 for 63-bit
-std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}, {0}};
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}, {0}, {0}};
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
-                                    "query_split1", "query_split2", "query_leaf_mode"};
-const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0};     // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1};
+                                    "query_split1", "query_split2", "query_leaf_mode",
+                                    "query_order"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0};     // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1, 1};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
@@ -166,7 +182,7 @@ Profiler &prof()
 }
 const char *kNames[K_NUM] = {"bounds", "bounds_final", "morton", "sort_pass", "bottomup",
                              "query_count", "query_fill", "scan", "query_split", "bottomup_up",
-                             "batch_prep"};
+                             "batch_prep", "query_order"};
 }  // namespace
 
 void prof_begin(int id, hipStream_t s)

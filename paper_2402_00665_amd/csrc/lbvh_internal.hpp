@@ -29,6 +29,9 @@ constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // default: query walks cut by aligned blocks of 2^12 leaves
 constexpr int kSplit2 = 7;            // default: ... then by blocks of 2^7 leaves
 constexpr int kQueryGridMax = 8192;   // blocks of the grid-stride query kernels
+constexpr int kQOrderTile = 2048;     // keys per tile of the query-order sort (256 x 8)
+constexpr int kQOrderPasses = 2;      // 16-bit query-order keys: two 8-bit digits
+constexpr int kQOrderKeyBlocks = 256;  // blocks of the query-order key kernel
 constexpr int kMaskLeaves = 256;     // widest level-2 piece that gets a leaf-hit mask
 constexpr int kMaskWords = kMaskLeaves / 64;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -81,7 +84,17 @@ struct QueryLayout {
     size_t hcache;     // batched: m x 64 int32, each query's first hits
     size_t hoff;       // cap2+1 int64
     size_t partials;   // scan tile sums
-    size_t ctrl;       // overflow flags and piece counts
+    size_t ctrl;       // overflow flags, piece counts, query-order flag and sort counters
+    // query order (single tree): the reordered copy of the queries, each
+    // reordered position's caller index, and the offsets in reordered order
+    size_t qsorted;    // m x 6 float
+    size_t qperm;      // m int32
+    size_t qoff;       // m+1 int64
+    // the order's radix sort, inside `hmask` (unused until the leaf level)
+    size_t qkeys[2];   // m uint32 each
+    size_t qvals;      // m int32 (first pass's values)
+    size_t qstatus[2]; // qtiles x kRadix uint32 each
+    size_t qhist;      // 2 x kRadix uint32
     size_t total;
 };
 
@@ -113,7 +126,8 @@ int batch_levels(int64_t max_scene);
 // Launch-shape knobs read by the launchers; set through lbvh_tune.
 
 enum TuneKnob {
-    TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_NUM
+    TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_QORDER,
+    TUNE_NUM
 };
 int64_t tune_get(int knob);
 
@@ -121,7 +135,7 @@ int64_t tune_get(int knob);
 
 enum KernelId {
     K_BOUNDS = 0, K_BOUNDS_FINAL, K_MORTON, K_SORT, K_BOTTOMUP,
-    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_BOTTOMUP_UP, K_BATCH_PREP, K_NUM
+    K_QCOUNT, K_QFILL, K_SCAN, K_QSPLIT, K_BOTTOMUP_UP, K_BATCH_PREP, K_QORDER, K_NUM
 };
 
 void prof_begin(int id, hipStream_t s);

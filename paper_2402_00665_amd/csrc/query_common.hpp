@@ -10,6 +10,7 @@ namespace lbvh {
 namespace {
 
 struct Sphere {
+    static constexpr int kFloats = 4;   // x, y, z, r
     float cx, cy, cz, r, r2;
     __device__ void load(const float *q, int j)
     {
@@ -44,6 +45,7 @@ struct Sphere {
 };
 
 struct QBox {
+    static constexpr int kFloats = 6;   // lo.xyz, hi.xyz
     float lx, ly, lz, hx, hy, hz;
     __device__ void load(const float *q, int j)
     {
@@ -295,11 +297,6 @@ __global__ __launch_bounds__(kBlock) void k_split_scatter(int n, int m, const in
     }
     const int64_t A = (int64_t)*app_count;   // no overflow: every piece was kept
     for (int64_t k = t0; k < A; k += stride) out[out_off[app_item[k]] + app_rank[k]] = app_piece[k];
-}
-
-__global__ void k_split_reset(unsigned long long *app_count)
-{
-    if (threadIdx.x < 2) app_count[threadIdx.x] = 0ull;
 }
 
 // The leaf level.  A level-2 piece covers the leaves [i, hi) of one aligned
@@ -590,14 +587,27 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The count call can process the queries in another order than the
+// caller's (the "query_order" knob).  Then the pieces name positions in a
+// reordered copy of the queries, and the hits of a piece go to its offset
+// in that order plus its query's shift (caller-order offset minus
+// reordered offset).  `flag`, written by the count call, says which case
+// holds, so the fill does not depend on the knob.
+struct QueryMap {
+    const int32_t *flag;     // nonzero: the queries were reordered
+    const float *sorted;     // the reordered copy
+    const int64_t *shift;    // per reordered position
+};
+
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__restrict__ queries,
-                                                 const int4 *__restrict__ in, const int64_t *in_count,
+__global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const int4 *__restrict__ in,
+                                                 const int64_t *in_count,
                                                  const int64_t *__restrict__ hit_off,
                                                  const uint64_t *__restrict__ masks,
-                                                 int32_t *__restrict__ out)
+                                                 QueryMap qm, int32_t *__restrict__ out)
 {
     const int64_t T = *in_count;
+    const bool reordered = *qm.flag != 0;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
@@ -607,7 +617,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__re
         uint64_t w[kMaskWords] = {0ull, 0ull, 0ull, 0ull};
         if (t < T) {
             it = in[t];
-            pos = hit_off[t];
+            pos = hit_off[t] + (reordered ? qm.shift[it.x] : 0);
             const int width = it.w - it.z;
             if (width <= kMaskLeaves) {
                 if (it.y == kAllHits) {
@@ -722,13 +732,15 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill(Tree tr, const float *__re
 // sparse piece, or one wider than kLeafScanMax, is walked with Alg. 1 by its
 // own lane; the wave then scans its dense ones one after another.
 template <class Q>
-__global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float *__restrict__ queries,
+__global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float *__restrict__ queries_in,
                                                       const int4 *__restrict__ in,
                                                       const int64_t *in_count,
                                                       const int64_t *__restrict__ hit_off,
-                                                      int32_t *__restrict__ out)
+                                                      QueryMap qm, int32_t *__restrict__ out)
 {
     const int64_t T = *in_count;
+    const bool reordered = *qm.flag != 0;
+    const float *queries = reordered ? qm.sorted : queries_in;
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
@@ -738,8 +750,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float 
         bool scan = false;
         if (t < T) {
             it = in[t];
-            pos = hit_off[t];
-            if (it.y != kAllHits && it.w - it.z > kMaskLeaves && hit_off[t + 1] > pos) {
+            const int64_t h0 = hit_off[t];
+            pos = h0 + (reordered ? qm.shift[it.x] : 0);
+            if (it.y != kAllHits && it.w - it.z > kMaskLeaves && hit_off[t + 1] > h0) {
                 Q q;
                 q.load(queries, it.x);
                 bool walk = true;
@@ -994,19 +1007,31 @@ __global__ void k_level_check(const int64_t *__restrict__ off, const int64_t *pa
     *count = over ? parents : total;
 }
 
-// offsets[q] = hit offset of query q's first leaf-walk piece.
+// offsets[q] = hit offset of query q's first leaf-walk piece.  With `perm`
+// (queries processed in another order: position q holds caller query
+// perm[q]) it also writes query q's hit count to counts[perm[q]].
 __global__ __launch_bounds__(kBlock) void k_compose(const int64_t *__restrict__ off1,
                                                     const int32_t *__restrict__ ovf1,
                                                     const int64_t *__restrict__ off2,
                                                     const int32_t *__restrict__ ovf2,
                                                     const int64_t *__restrict__ hit_off, int m,
-                                                    int64_t *__restrict__ offsets)
+                                                    int64_t *__restrict__ offsets,
+                                                    const int32_t *__restrict__ perm,
+                                                    int32_t *__restrict__ counts)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q > m) return;
-    const int64_t p1 = *ovf1 ? q : off1[q];
-    const int64_t p2 = *ovf2 ? p1 : off2[p1];
-    offsets[q] = hit_off[p2];
+    auto first_hit = [&](int64_t x) {
+        const int64_t p1 = *ovf1 ? x : off1[x];
+        const int64_t p2 = *ovf2 ? p1 : off2[p1];
+        return hit_off[p2];
+    };
+    const int64_t h = first_hit(q);
+    offsets[q] = h;
+    if (perm && q < m) {
+        const uint32_t j = (uint32_t)perm[q];
+        if (j < (uint32_t)m) counts[j] = (int32_t)(first_hit(q + 1) - h);
+    }
 }
 
 // Exclusive scan of int32 counts into int64 offsets (three launches).

@@ -42,9 +42,107 @@
 #pragma clang fp contract(off)
 
 #include "query_common.hpp"
+#include "radix_sort.hpp"
 
 namespace lbvh {
 namespace {
+
+// ------------------------------------------------------------ query order
+//
+// With the "query_order" knob set, the count call first sorts the queries
+// by a 16-bit Morton key of their centres (quantised in the root's box,
+// clamped to it) and runs every split and leaf level on the sorted copy,
+// so that neighbouring lanes and waves walk neighbouring parts of the tree
+// and share its records in the caches.  Only the schedule changes: each
+// query's pieces, hits and hit order are what they are in the caller's
+// order.  At the end, the per-query counts go back to the caller's order,
+// their scan gives the caller's offsets, and each sorted position gets the
+// shift that moves its hits to its caller-order slot (applied by the fill).
+
+// keys of the queries, their digit histograms (LDS, then one global add
+// per digit and block), and the first sort pass's cleared look-back status
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_qorder_keys(Tree tr, const float *__restrict__ queries,
+                                                   int m, uint32_t *__restrict__ keys,
+                                                   uint32_t *hist, uint32_t *__restrict__ status0,
+                                                   int64_t status_words)
+{
+    __shared__ uint32_t lh[kQOrderPasses * kRadix];
+    for (int j = threadIdx.x; j < kQOrderPasses * kRadix; j += kBlock) lh[j] = 0u;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = gid; j < status_words; j += stride) status0[j] = 0u;
+    __syncthreads();
+    float4 a, b;
+    tr.load(0, a, b);   // the root's box (leaf 0's when n = 1)
+    const float rlo[3] = {a.x, a.y, a.z}, rhi[3] = {b.x, b.y, b.z};
+    float scale[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float ext = rhi[k] - rlo[k];
+        scale[k] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+    }
+    for (int64_t i = gid; i < m; i += stride) {
+        Q q;
+        q.load(queries, (int)i);
+        float lo[3], hi[3];
+        q.bounds(lo, hi);
+        uint32_t c[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float t = ((lo[k] + hi[k]) * 0.5f - rlo[k]) * scale[k];
+            c[k] = (uint32_t)fminf(fmaxf(t, 0.0f), 1023.0f);   // NaN -> 0
+        }
+        const uint32_t key = Code<uint32_t>::make(c[0], c[1], c[2]) >> 14;
+        keys[i] = key;
+        atomicAdd(&lh[key & (kRadix - 1)], 1u);
+        atomicAdd(&lh[kRadix + (key >> kRadixBits)], 1u);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kQOrderPasses * kRadix; j += kBlock)
+        if (lh[j]) atomicAdd(&hist[j], lh[j]);
+}
+
+// the sorted copy of the queries
+template <class Q>
+__global__ __launch_bounds__(kBlock) void k_qorder_gather(const float *__restrict__ queries,
+                                                     const int32_t *__restrict__ perm, int m,
+                                                     float *__restrict__ sorted)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const uint32_t j = (uint32_t)perm[i];
+        if (j >= (uint32_t)m) continue;   // only after a failed sort (flagged there)
+#pragma unroll
+        for (int k = 0; k < Q::kFloats; ++k)
+            sorted[Q::kFloats * i + k] = queries[Q::kFloats * (int64_t)j + k];
+    }
+}
+
+// shift of each sorted position: caller-order offset - sorted-order offset
+__global__ __launch_bounds__(kBlock) void k_qorder_shift(const int64_t *__restrict__ off_sorted,
+                                                    const int32_t *__restrict__ perm,
+                                                    const int64_t *__restrict__ offsets, int m,
+                                                    int64_t *__restrict__ shift)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride)
+        shift[i] = (uint32_t)perm[i] < (uint32_t)m ? offsets[perm[i]] - off_sorted[i] : 0;
+}
+
+// start of a count call: the split levels' append counters, the order
+// flag the fill reads, and (when reordering) the sort's tile counters and
+// histograms
+__global__ void k_query_reset(unsigned long long *app_count, int32_t *order_flag, int order,
+                              uint32_t *tile_counters, uint32_t *hist)
+{
+    if (threadIdx.x < 2) app_count[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *order_flag = order;
+    if (order) {
+        if (threadIdx.x < kQOrderPasses) tile_counters[threadIdx.x] = 0u;
+        for (int j = threadIdx.x; j < kQOrderPasses * kRadix; j += blockDim.x) hist[j] = 0u;
+    }
+}
 
 struct Scratch {
     int32_t *cnt1, *cnt2, *hcnt, *ovf;
@@ -54,6 +152,13 @@ struct Scratch {
     int32_t *app_rank;
     unsigned long long *app_count;
     uint64_t *hmask;
+    int32_t *order_flag;     // nonzero: this count call reordered the queries
+    uint32_t *sort_ctr;      // the order sort's tile counters, then its error word
+    float *qsorted;
+    int32_t *qperm;
+    int64_t *qoff;
+    uint32_t *qkeys[2], *qstatus[2], *qhist;
+    int32_t *qvals;
 };
 
 Scratch carve(char *ws, const QueryLayout &L)
@@ -75,6 +180,17 @@ Scratch carve(char *ws, const QueryLayout &L)
     S.ovf = reinterpret_cast<int32_t *>(ws + L.ctrl);              // [0] level 1, [1] level 2
     S.count = reinterpret_cast<int64_t *>(ws + L.ctrl + 64);       // [0] pieces 1, [1] pieces 2
     S.app_count = reinterpret_cast<unsigned long long *>(ws + L.ctrl + 96);   // [0] level 1, [1] level 2
+    S.order_flag = reinterpret_cast<int32_t *>(ws + L.ctrl + 8);
+    S.sort_ctr = reinterpret_cast<uint32_t *>(ws + L.ctrl + 16);   // [0], [1] tiles, [2] error
+    S.qsorted = reinterpret_cast<float *>(ws + L.qsorted);
+    S.qperm = reinterpret_cast<int32_t *>(ws + L.qperm);
+    S.qoff = reinterpret_cast<int64_t *>(ws + L.qoff);
+    for (int k = 0; k < 2; ++k) {
+        S.qkeys[k] = reinterpret_cast<uint32_t *>(ws + L.qkeys[k]);
+        S.qstatus[k] = reinterpret_cast<uint32_t *>(ws + L.qstatus[k]);
+    }
+    S.qvals = reinterpret_cast<int32_t *>(ws + L.qvals);
+    S.qhist = reinterpret_cast<uint32_t *>(ws + L.qhist);
     return S;
 }
 
@@ -92,9 +208,35 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     Scratch S = carve(ws, L);
     const unsigned gm = grid_for(m);
     const int split1 = (int)tune_get(TUNE_QSPLIT1), split2 = (int)tune_get(TUNE_QSPLIT2);
+    const bool order = tune_get(TUNE_QORDER) != 0 && m > 1;
+    prof_begin(K_QSPLIT, s);
+    hipLaunchKernelGGL(k_query_reset, dim3(1), dim3(kBlock), 0, s, S.app_count, S.order_flag,
+                       order ? 1 : 0, S.sort_ctr, S.qhist);
+    prof_end(K_QSPLIT, s);
+    int64_t *const caller_offsets = offsets;
+    if (order) {
+        // sort the queries by key (two stable 8-bit passes), then copy them
+        prof_begin(K_QORDER, s);
+        const int64_t qtiles = ((int64_t)m + kQOrderTile - 1) / kQOrderTile;
+        // few blocks, so that few global histogram adds meet on each word
+        const unsigned gk = (unsigned)std::min<int64_t>(kQOrderKeyBlocks, (m + 16 * kBlock - 1) / (16 * kBlock));
+        hipLaunchKernelGGL((k_qorder_keys<Q>), dim3(gk), dim3(kBlock), 0, s, tr, q, m, S.qkeys[0],
+                           S.qhist, S.qstatus[0], qtiles * kRadix);
+        const SortSegs one{nullptr, nullptr, 1, 0};
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 256, 8>), dim3((unsigned)qtiles), dim3(256), 0, s,
+                           S.qkeys[0], S.qkeys[1], nullptr, S.qvals, (int64_t)m, one, 0, S.qhist,
+                           S.qstatus[0], S.qstatus[1], S.sort_ctr + 0, S.sort_ctr + 2);
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 256, 8>), dim3((unsigned)qtiles), dim3(256), 0, s,
+                           S.qkeys[1], S.qkeys[0], S.qvals, S.qperm, (int64_t)m, one, kRadixBits,
+                           S.qhist + kRadix, S.qstatus[1], nullptr, S.sort_ctr + 1, S.sort_ctr + 2);
+        hipLaunchKernelGGL((k_qorder_gather<Q>), dim3(gm), dim3(kBlock), 0, s, q, S.qperm, m,
+                           S.qsorted);
+        prof_end(K_QORDER, s);
+        q = S.qsorted;
+        offsets = S.qoff;
+    }
     // level 1: queries -> pieces of 2^split1 leaves
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(64), 0, s, S.app_count);
     hipLaunchKernelGGL((k_split<Q, true>), dim3(gm), dim3(kBlock), 0, s, tr, q, m, nullptr, nullptr,
                        split1, S.cnt1, S.app_count + 0, L.cap1, S.app_piece, S.app_item, S.app_rank);
     prof_end(K_QSPLIT, s);
@@ -140,9 +282,21 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
+    // with the order: also the per-query counts in the caller's order (in
+    // cnt1, free since level 1)
     hipLaunchKernelGGL(k_compose, dim3((unsigned)((m + kBlock) / kBlock)), dim3(kBlock), 0, s, S.off1,
-                       S.ovf + 0, S.off2, S.ovf + 1, S.hoff, m, offsets);
+                       S.ovf + 0, S.off2, S.ovf + 1, S.hoff, m, offsets,
+                       order ? S.qperm : nullptr, S.cnt1);
     prof_end(K_SCAN, s);
+    if (order) {
+        // back to the caller's order: the counts' scan, and each sorted
+        // position's shift (in off1, free since the compose)
+        prof_begin(K_QORDER, s);
+        scan(S.cnt1, m, nullptr, S.partials, caller_offsets, s);
+        hipLaunchKernelGGL(k_qorder_shift, dim3(gm), dim3(kBlock), 0, s, S.qoff, S.qperm,
+                           caller_offsets, m, S.off1);
+        prof_end(K_QORDER, s);
+    }
     return hipGetLastError();
 }
 
@@ -153,10 +307,11 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
     Scratch S = carve(ws, L);
     prof_begin(K_QFILL, s);
     const unsigned g2 = grid_for(L.cap2);
-    hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2, S.count + 1,
-                       S.hoff, S.hmask, indices);
+    const QueryMap qm{S.order_flag, S.qsorted, S.off1};
+    hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, S.items2, S.count + 1,
+                       S.hoff, S.hmask, qm, indices);
     hipLaunchKernelGGL((k_leaf_fill_wide<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
-                       S.count + 1, S.hoff, indices);
+                       S.count + 1, S.hoff, qm, indices);
     prof_end(K_QFILL, s);
     return hipGetLastError();
 }

@@ -97,10 +97,25 @@ def test_invalid_arguments_are_rejected_without_side_effects():
 
 def test_profile_names():
     for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "bottomup_up",
-                 "query_split", "query_count", "query_fill", "scan"]:
+                 "query_split", "query_count", "query_fill", "scan", "query_order", "batch_prep"]:
         assert lb.lbvh_profile_read(name)[1] >= 0
     with pytest.raises(lb.LbvhError):
         lb.lbvh_profile_read("nope")
+
+
+def test_tune_knobs():
+    """Every knob reads back, takes a value in range and refuses one out of
+    range (no GPU needed: knobs are host state)."""
+    ranges = {"sort_variant32": 6, "sort_variant64": 6, "batch_sort_variant": 3,
+              "query_split1": 24, "query_split2": 24, "query_leaf_mode": 1, "query_order": 1}
+    for name, hi in ranges.items():
+        old = lb.lbvh_tune(name)
+        assert old >= 0
+        assert lb.lbvh_tune(name, hi) == old
+        assert lb.lbvh_tune(name) == hi
+        assert lb.lbvh_tune(name, old) == hi
+        assert lb.lbvh_tune(name, hi + 1) == lb.LBVH_EINVAL
+    assert lb.lbvh_tune("no_such_knob", 0) == lb.LBVH_EINVAL
 
 
 def test_product_path_does_not_import_the_oracle():

@@ -52,7 +52,7 @@ def test_tune_query_schedule(tmp_path, monkeypatch):
     w = workloads.by_name("clustered_boxes", 1 / 16)
     tree = lb.build(torch.from_numpy(w.prims).cuda(), w.code_bits, kind=w.kind)
     q = torch.from_numpy(w.queries).cuda()
-    knobs = ("query_split1", "query_split2", "query_leaf_mode")
+    knobs = ("query_split1", "query_split2", "query_leaf_mode", "query_order")
     before = tuple(lb.lbvh_tune(k) for k in knobs)
     r = autotune.tune_query(tree, q, w.qkind, reps=2, verbose=True)
     say(f"query schedule: {r}")

@@ -162,7 +162,8 @@ def test_full_size_autotuned(name, ws):
     import paper_2402_00665_amd as lb
     from paper_2402_00665_amd import autotune
     w = workloads.by_name(name)
-    knobs = ("sort_variant32", "sort_variant64", "query_split1", "query_split2", "query_leaf_mode")
+    knobs = ("sort_variant32", "sort_variant64", "query_split1", "query_split2", "query_leaf_mode",
+             "query_order")
     old = {k: lb.lbvh_tune(k) for k in knobs}
     try:
         p = torch.from_numpy(w.prims).cuda()
@@ -240,20 +241,22 @@ def test_sort_tile_variants(variant, ws):
         lb.lbvh_tune("sort_variant64", old64)
 
 
-@pytest.mark.parametrize("split1,split2,leaf_mode", [(12, 7, 1), (11, 6, 1), (9, 4, 0), (14, 9, 1),
-                                                      (8, 12, 0), (10, 10, 1), (6, 3, 0)])
-def test_query_schedules(split1, split2, leaf_mode, ws):
-    """Every query schedule (split block sizes, leaf mode) gives the oracle's
-    results exactly: dense box queries, sparse spheres, all-hit ranges.  Also
-    a second level no finer than the first (one piece per item), and blocks
-    small enough that the levels overflow and pass their items through."""
+@pytest.mark.parametrize("split1,split2,leaf_mode,order", [
+    (12, 7, 1, 0), (11, 6, 1, 0), (9, 4, 0, 0), (14, 9, 1, 0), (8, 12, 0, 0), (10, 10, 1, 0),
+    (6, 3, 0, 0), (12, 7, 0, 1), (12, 6, 1, 1), (8, 12, 0, 1), (6, 3, 0, 1)])
+def test_query_schedules(split1, split2, leaf_mode, order, ws):
+    """Every query schedule (split block sizes, leaf mode, query order) gives
+    the oracle's results exactly: dense box queries, sparse spheres, all-hit
+    ranges.  Also a second level no finer than the first (one piece per
+    item), and blocks small enough that the levels overflow and pass their
+    items through."""
     import paper_2402_00665_amd as lb
     old = [lb.lbvh_tune("query_split1", split1), lb.lbvh_tune("query_split2", split2),
-           lb.lbvh_tune("query_leaf_mode", leaf_mode)]
+           lb.lbvh_tune("query_leaf_mode", leaf_mode), lb.lbvh_tune("query_order", order)]
     try:
         for name in ("clustered_boxes", "large_points"):
             _parity(workloads.by_name(name, 1 / 64), ws)
-        rng = np.random.default_rng([19, split1, split2, leaf_mode])
+        rng = np.random.default_rng([19, split1, split2, leaf_mode, order])
         w = workloads.clustered(1 << 17, 1)
         ref = oracle.build(w.kind, w.prims, w.code_bits)
         tree, _ = gpu_build(w.prims, w.kind, w.code_bits, ws)
@@ -267,6 +270,67 @@ def test_query_schedules(split1, split2, leaf_mode, ws):
         lb.lbvh_tune("query_split1", old[0])
         lb.lbvh_tune("query_split2", old[1])
         lb.lbvh_tune("query_leaf_mode", old[2])
+        lb.lbvh_tune("query_order", old[3])
+
+
+def test_query_order_edge_cases(ws):
+    """Queries processed in Morton order ("query_order" = 1) give the
+    caller-order CSR of the oracle exactly: query counts around the sort's
+    2048-key tile (one tile, a ragged second tile, several tiles), queries
+    outside the scene box, a NaN query, a one-leaf tree, split levels that
+    overflow, and a fill enqueued after the knob was switched back (the
+    fill follows what the count call did)."""
+    import torch
+    import paper_2402_00665_amd as lb
+    old = lb.lbvh_tune("query_order", 1)
+    try:
+        rng = np.random.default_rng(41)
+        for bits in (30, 63):
+            p = rng.random((50000, 3), dtype=np.float32)
+            ref = oracle.build(0, p, bits)
+            tree, _ = gpu_build(p, 0, bits, ws)
+            for m in (1, 2, 3, 2047, 2048, 2049, 10007):
+                c = (rng.random((m, 3)) * 1.4 - 0.2).astype(np.float32)   # some outside
+                q = workloads.spheres(c, np.float32(0.03))
+                if m > 2:
+                    q[m // 2, 0] = np.nan
+                roff, ridx, _ = oracle.query_traverse(0, q, ref)
+                off, idx = gpu_query(tree, q, 0, ws)
+                assert_query_equal(off, idx, roff, ridx)
+            s = rng.random((777, 3)) * 0.1
+            boxes = np.concatenate([c[:777] - s, c[:777] + s], 1).astype(np.float32)
+            roff, ridx, _ = oracle.query_traverse(1, boxes, ref)
+            off, idx = gpu_query(tree, boxes, 1, ws)
+            assert_query_equal(off, idx, roff, ridx)
+        # one leaf
+        p1 = rng.random((1, 3), dtype=np.float32)
+        ref1 = oracle.build(0, p1, 30)
+        tree1, _ = gpu_build(p1, 0, 30, ws)
+        q1 = workloads.spheres(rng.random((300, 3), dtype=np.float32), np.float32(0.5))
+        roff, ridx, _ = oracle.query_traverse(0, q1, ref1)
+        off, idx = gpu_query(tree1, q1, 0, ws)
+        assert_query_equal(off, idx, roff, ridx)
+        # split levels overflow: a few queries cover all 2^20 leaves
+        p2 = rng.random((1 << 20, 3), dtype=np.float32)
+        ref2 = oracle.build(0, p2, 30)
+        tree2, _ = gpu_build(p2, 0, 30, ws)
+        q2 = workloads.spheres(rng.random((600, 3), dtype=np.float32), np.float32(0.01))
+        q2[::97, 3] = 2.0
+        roff, ridx, _ = oracle.query_traverse(0, q2, ref2)
+        off, idx = gpu_query(tree2, q2, 0, ws)
+        assert_query_equal(off, idx, roff, ridx)
+        # count reordered, knob switched off, then fill
+        dq = torch.from_numpy(q2).cuda()
+        qws = lb.Workspace()
+        offt = lb.query_count(tree2, dq, 0, qws)
+        lb.lbvh_tune("query_order", 0)
+        total = int(offt[-1].item())
+        idxt = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+        lb.query_fill(tree2, dq, 0, idxt, qws)
+        torch.cuda.synchronize()
+        assert_query_equal(offt.cpu().numpy(), idxt[:total].cpu().numpy(), roff, ridx)
+    finally:
+        lb.lbvh_tune("query_order", old)
 
 
 @pytest.mark.parametrize("bits", [30, 63])
