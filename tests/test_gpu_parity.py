@@ -243,13 +243,15 @@ def test_sort_tile_variants(variant, ws):
 
 @pytest.mark.parametrize("split1,split2,leaf_mode,order", [
     (12, 7, 1, 0), (11, 6, 1, 0), (9, 4, 0, 0), (14, 9, 1, 0), (8, 12, 0, 0), (10, 10, 1, 0),
-    (6, 3, 0, 0), (12, 7, 0, 1), (12, 6, 1, 1), (8, 12, 0, 1), (6, 3, 0, 1)])
+    (6, 3, 0, 0), (12, 7, 0, 1), (12, 6, 1, 1), (8, 12, 0, 1), (6, 3, 0, 1), (24, 24, 0, 1),
+    (24, 6, 1, 0)])
 def test_query_schedules(split1, split2, leaf_mode, order, ws):
     """Every query schedule (split block sizes, leaf mode, query order) gives
     the oracle's results exactly: dense box queries, sparse spheres, all-hit
     ranges.  Also a second level no finer than the first (one piece per
-    item), and blocks small enough that the levels overflow and pass their
-    items through."""
+    item), blocks larger than the tree (one unsplit walk per query), and
+    blocks small enough that the levels overflow and pass their items
+    through."""
     import paper_2402_00665_amd as lb
     old = [lb.lbvh_tune("query_split1", split1), lb.lbvh_tune("query_split2", split2),
            lb.lbvh_tune("query_leaf_mode", leaf_mode), lb.lbvh_tune("query_order", order)]
