@@ -281,7 +281,7 @@ def main():
 
     kernels = {}
     for name in ["bounds", "bounds_final", "morton", "sort_pass", "bottomup", "bottomup_up",
-                 "query_split", "query_count", "scan", "query_fill"]:
+                 "query_order", "query_split", "query_count", "scan", "query_fill"]:
         tot, cnt = lb.lbvh_profile_read(name)
         if cnt:
             kernels[name] = {"ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
@@ -588,7 +588,8 @@ def bench_serving(args):
 
 # --------------------------------------------------------------- profiles
 
-KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name
+KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name (first match wins)
+    "k_onesweep<unsigned int, 512, 4>": "query_order", "k_qorder": "query_order",
     "k_bounds<": "bounds", "k_bounds_final": "bounds_final", "k_morton": "morton",
     "k_onesweep": "sort_pass", "k_bottomup_l0": "bottomup", "k_bottomup_up": "bottomup_up",
     "k_split": "query_split", "k_leaf_scan_count": "query_count", "k_leaf_count_wide": "query_count",

@@ -29,7 +29,7 @@ constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // default: query walks cut by aligned blocks of 2^12 leaves
 constexpr int kSplit2 = 7;            // default: ... then by blocks of 2^7 leaves
 constexpr int kQueryGridMax = 8192;   // blocks of the grid-stride query kernels
-constexpr int kQOrderTile = 2048;     // keys per tile of the query-order sort (256 x 8)
+constexpr int kQOrderTile = 2048;     // keys per tile of the query-order sort (512 x 4)
 constexpr int kQOrderPasses = 2;      // 16-bit query-order keys: two 8-bit digits
 constexpr int kQOrderKeyBlocks = 256;  // blocks of the query-order key kernel
 constexpr int kMaskLeaves = 256;     // widest level-2 piece that gets a leaf-hit mask

@@ -223,10 +223,10 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
         hipLaunchKernelGGL((k_qorder_keys<Q>), dim3(gk), dim3(kBlock), 0, s, tr, q, m, S.qkeys[0],
                            S.qhist, S.qstatus[0], qtiles * kRadix);
         const SortSegs one{nullptr, nullptr, 1, 0};
-        hipLaunchKernelGGL((k_onesweep<uint32_t, 256, 8>), dim3((unsigned)qtiles), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4>), dim3((unsigned)qtiles), dim3(512), 0, s,
                            S.qkeys[0], S.qkeys[1], nullptr, S.qvals, (int64_t)m, one, 0, S.qhist,
                            S.qstatus[0], S.qstatus[1], S.sort_ctr + 0, S.sort_ctr + 2);
-        hipLaunchKernelGGL((k_onesweep<uint32_t, 256, 8>), dim3((unsigned)qtiles), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4>), dim3((unsigned)qtiles), dim3(512), 0, s,
                            S.qkeys[1], S.qkeys[0], S.qvals, S.qperm, (int64_t)m, one, kRadixBits,
                            S.qhist + kRadix, S.qstatus[1], nullptr, S.sort_ctr + 1, S.sort_ctr + 2);
         hipLaunchKernelGGL((k_qorder_gather<Q>), dim3(gm), dim3(kBlock), 0, s, q, S.qperm, m,
