@@ -371,10 +371,21 @@ def test_non_finite_inputs_give_a_well_formed_tree(kind, bits, ws):
     assert off[0] == 0 and np.all(np.diff(off) >= 0) and np.all((idx >= 0) & (idx < n))
 
 
-def test_graph_capture_single_tree(ws):
+@pytest.mark.parametrize("order", [0, 1])
+def test_graph_capture_single_tree(order, ws):
     """Build, count and fill of one tree enqueue kernels only (no memset, no
     host synchronisation), so they can be captured in a HIP graph; every
-    replay, with eager work between replays, reproduces the eager bits."""
+    replay, with eager work between replays, reproduces the eager bits.
+    Also with the queries walked in Morton order."""
+    import paper_2402_00665_amd as lb
+    old_order = lb.lbvh_tune("query_order", order)
+    try:
+        _graph_capture_single_tree()
+    finally:
+        lb.lbvh_tune("query_order", old_order)
+
+
+def _graph_capture_single_tree():
     import torch
     import paper_2402_00665_amd as lb
     w = workloads.by_name("clustered_boxes", 1 / 64)
