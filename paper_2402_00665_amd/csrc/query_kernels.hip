@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_qorder_gather(const float *__restric
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
         const uint32_t j = (uint32_t)perm[i];
-        if (j >= (uint32_t)m) continue;   // only after a failed sort (flagged there)
+        if (j >= (uint32_t)m) continue;   // never for a sort that completed; no stray reads otherwise
 #pragma unroll
         for (int k = 0; k < Q::kFloats; ++k)
             sorted[Q::kFloats * i + k] = queries[Q::kFloats * (int64_t)j + k];
