@@ -327,8 +327,10 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
 
     prof_begin(K_BOTTOMUP, s);
     BatchLevel bl{seg_off, blk_off, nullptr, S, levels == 0};
+    // delta* bytes for the upper levels: in the sort's other key buffer, free now
+    uint8_t *dstar = reinterpret_cast<uint8_t *>(keys_alt);
     hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3((unsigned)L.blocks_max[0]), dim3(kBU0Threads),
-                       0, s, codes, leaf_perm, prims, (int)N, store, nodes, pend[0], bl,
+                       0, s, codes, leaf_perm, prims, (int)N, store, nodes, pend[0], bl, dstar,
                        ctrl + kCtrlError);
     prof_end(K_BOTTOMUP, s);
     int64_t span = kChunk;
@@ -336,8 +338,8 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
         const int64_t next = span * kFanout;
         BatchLevel up{seg_off, blk_off + lv * (S + 1), blk_off + (lv - 1) * (S + 1), S, lv == levels};
         prof_begin(K_BOTTOMUP_UP, s);
-        hipLaunchKernelGGL((k_bottomup_up<K>), dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads), 0, s,
-                           codes, (int)N, span, next, store, nodes, pend[(lv - 1) & 1], pend[lv & 1],
+        hipLaunchKernelGGL(k_bottomup_up, dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads), 0, s,
+                           dstar, (int)N, span, next, store, nodes, pend[(lv - 1) & 1], pend[lv & 1],
                            up, ctrl + kCtrlError);
         prof_end(K_BOTTOMUP_UP, s);
         span = next;

@@ -28,6 +28,10 @@ namespace {
 // the second thread to arrive, exactly as in Alg. 4.
 
 //
+// Level 0 computes delta* of its boundaries from the codes in LDS and also
+// stores them as one byte each (`dstar`, in a buffer the sort no longer
+// needs); the upper levels read those bytes instead of pairs of codes.
+//
 // Batched trees: every scene is its own problem (local leaf and node ids);
 // its leaves sit at seg_off[s] in the sorted arrays and its 2n_s-1 node
 // records at record 2*seg_off[s].  Level-L blocks of all scenes share one
@@ -59,6 +63,7 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
                                                              int n_all, int32_t *__restrict__ store_all,
                                                              float4 *__restrict__ nodes_all,
                                                              int4 *__restrict__ pend, BatchLevel bl,
+                                                             uint8_t *__restrict__ dstar_all,
                                                              uint32_t *err)
 {
     __shared__ K s_codes[kChunk + 3];        // codes[A-1 .. B+1]
@@ -105,7 +110,10 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     }
     __syncthreads();
 
-    // delta*(g) for g in [A-1, B], from the codes in LDS
+    // delta*(g) for g in [A-1, B], from the codes in LDS: the rank of the
+    // highest differing bit of the augmented keys (code, sorted position) of
+    // leaves g and g+1, codes ranking above any index bit; +inf (255) for
+    // g = -1 and g = n-1
     auto delta_codes = [&](int g) -> int {
         if (g < 0 || g >= n - 1) return 255;
         const K x = s_codes[g - A + 1] ^ s_codes[g - A + 2];
@@ -128,6 +136,8 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     // child) run the same instructions with selects, so a wave whose lanes
     // disagree does not run both.
     auto delta = [&](int g) -> int { return s_delta[g - A + 1]; };
+    // this chunk's boundaries g in [A, B), g < n-1, for the upper levels
+    if (i < B && i < n - 1) dstar_all[b0 + i] = s_delta[tid + 1];
     if (n > 1 && i < B) {
         int rl = i, rr = i, cur = leaf0 + i;
         int dl = delta(i - 1), dr = delta(i);
@@ -183,9 +193,8 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     }
 }
 
-template <typename K>
-__global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict__ codes_all, int n_all,
-                                                            int64_t child_span, int64_t span,
+__global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__restrict__ dstar_all,
+                                                            int n_all, int64_t child_span, int64_t span,
                                                             int32_t *store_all, float4 *nodes_all,
                                                             const int4 *__restrict__ pend_in,
                                                             int4 *__restrict__ pend_out, BatchLevel bl,
@@ -214,10 +223,12 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict_
         slot_lo = 2 * (A / child_span);
         slot_hi = 2 * ((B + child_span - 1) / child_span);
     }
-    const K *codes = codes_all + b0;
+    const uint8_t *dstar = dstar_all + b0;
     int32_t *store = store_all + b0;
     float4 *nodes = nodes_all + 4 * b0;
     const int leaf0 = n - 1;
+    // delta*(g), +inf (255) outside [0, n-2], as level 0 stored it
+    auto delta = [&](int g) -> int { return (g < 0 || g >= n - 1) ? 255 : (int)dstar[g]; };
     if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
     __syncthreads();
 
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict_
         const float4 *own = nodes + 2 * (int64_t)cur;
         const float4 o0 = own[0], o1 = own[1];
         float lo[3] = {o0.x, o0.y, o0.z}, hi[3] = {o1.x, o1.y, o1.z};
-        int dl = delta_rank(codes, rl - 1, n), dr = delta_rank(codes, rr, n);
+        int dl = delta(rl - 1), dr = delta(rr);
         for (int level = 0;; ++level) {
             if (level == kMaxDepth) {
                 __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -249,12 +260,12 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const K *__restrict_
             rl = is_left ? rl : other;
             const int sib = is_left ? ((p + 1 == rr) ? leaf0 + p + 1 : p + 1)
                                     : ((rl == p) ? leaf0 + p : p);
-            // the sibling's box and the two delta* values the step needs are
+            // the sibling's box and the two delta* bytes the step needs are
             // independent loads: issue them together
             const float4 *sp = nodes + 2 * (int64_t)sib;
             const float4 s0 = sp[0], s1 = sp[1];
-            const int dn = delta_rank(codes, is_left ? rr : rl - 1, n);
-            const int d_next = delta_rank(codes, rr + 1, n);   // 255 past the end
+            const int dn = delta(is_left ? rr : rl - 1);
+            const int d_next = delta(rr + 1);   // 255 past the end
             dr = is_left ? dn : dr;
             dl = is_left ? dl : dn;
             lo[0] = fminf(lo[0], s0.x); lo[1] = fminf(lo[1], s0.y); lo[2] = fminf(lo[2], s0.z);

@@ -236,8 +236,10 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
     int nbu = (n + kChunk - 1) / kChunk;
     BatchLevel one{nullptr, nullptr, nullptr, 1, nbu == 1};
+    // delta* bytes for the upper levels: in the sort's other key buffer, free now
+    uint8_t *dstar = reinterpret_cast<uint8_t *>(keys_alt);
     hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
-                       leaf_perm, prims, n, store, nodes, pend[0], one, ctrl + kCtrlError);
+                       leaf_perm, prims, n, store, nodes, pend[0], one, dstar, ctrl + kCtrlError);
     prof_end(K_BOTTOMUP, s);
     int64_t span = kChunk;
     int in = 0;
@@ -246,7 +248,7 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
         const int nbn = (int)((n + next - 1) / next);
         one.last = nbn == 1;
         prof_begin(K_BOTTOMUP_UP, s);
-        hipLaunchKernelGGL((k_bottomup_up<K>), dim3(nbn), dim3(kBUThreads), 0, s, codes, n, span,
+        hipLaunchKernelGGL(k_bottomup_up, dim3(nbn), dim3(kBUThreads), 0, s, dstar, n, span,
                            next, store, nodes, pend[in], pend[in ^ 1], one, ctrl + kCtrlError);
         prof_end(K_BOTTOMUP_UP, s);
         in ^= 1;

@@ -175,18 +175,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh /* 
 
 // ---------------------------------------------------------- Alg. 4 bits
 
-// delta*(i): rank of the highest differing bit of the augmented keys
-// (code, sorted position) of leaves i and i+1; codes that differ rank
-// above any index bit.  Out of range (i = -1 or n-1) is +inf (255).
-template <typename K>
-__device__ __forceinline__ int delta_rank(const K *__restrict__ codes, int i, int n)
-{
-    if (i < 0 || i >= n - 1) return 255;
-    const K x = codes[i] ^ codes[i + 1];
-    if (x) return 64 + highest_bit(x);
-    return highest_bit((uint32_t)(i ^ (i + 1)));
-}
-
 __device__ __forceinline__ void store_node(float4 *nodes, int id, const float lo[3], int left,
                                            const float hi[3], int rope)
 {
