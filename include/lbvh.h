@@ -138,6 +138,7 @@ int lbvh_build_boxes(const float *lohi, int64_t n, int32_t code_bits,
 int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits,
                      int32_t kind, void *stream);
 
+
 /* ------------------------------------------------------------- queries */
 
 /* Workspace bytes for the count and fill calls over m queries. */
@@ -172,7 +173,9 @@ int lbvh_query_boxes_count(const lbvh_tree *tree, const float *lohi, int64_t m,
 
 /* Second call: write, for query j, the input indices of the matching
  * primitives into indices[offsets[j] .. offsets[j+1]) in traversal order
- * (ascending Morton-order position).
+ * (ascending Morton-order position): the hits Alg. 1 reports, stored as
+ * its "store the result" step leaves open (Sec. 2).  A fill never writes
+ * more than the count call counted for a query, whatever the knobs.
  *   indices   : device int32 [offsets[m]] (non-NULL even when empty).
  *   workspace : the workspace of the preceding count call on the same tree
  *               and queries, untouched since (enqueue both on one stream or
@@ -183,6 +186,15 @@ int lbvh_query_spheres_fill(const lbvh_tree *tree, const float *xyzr, int64_t m,
 int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
                           int32_t *indices, const void *workspace,
                           int64_t workspace_bytes, void *stream);
+
+/* Synchronise the stream and report an error that the last count call over
+ * m queries flagged in `workspace` (LBVH_EDEVICE), else LBVH_OK.  Flagged:
+ * a walk that spent its node-visit budget before the sentinel (never for a
+ * tree this library built, unless the "query_walk_budget" knob caps it), or
+ * a failed query-order sort.  The offsets and indices of such a call are
+ * then not Alg. 1's.  Each count call clears the word first.  For tests and
+ * debugging; the count call itself never synchronises. */
+int lbvh_query_check(const void *workspace, int64_t m, void *stream);
 
 /* ------------------------------------------------------------- batched */
 
@@ -255,6 +267,9 @@ int lbvh_build_batched_status_async(const void *workspace, const lbvh_batch *bat
 /* Workspace bytes for a batched count call over m queries. */
 int64_t lbvh_query_batched_workspace_bytes(int64_t m);
 
+/* lbvh_query_check for the batched count call's workspace (m queries). */
+int lbvh_query_batched_check(const void *workspace, int64_t m, void *stream);
+
 /* Range queries on a batch: query j belongs to the scene s with
  * qseg_off[s] <= j < qseg_off[s+1] (device int64 [num_scenes+1]) and walks
  * that scene's tree (Alg. 1; same predicates and order as the single-tree
@@ -295,13 +310,19 @@ const char *lbvh_last_hip_error(void);
  * Sets knob `name` to `value` and returns the previous value; a negative
  * `value` only reads the knob.  Returns LBVH_EINVAL for an unknown name or
  * a value out of range.  Knobs:
+ *   "radix_bits32", "radix_bits64": digit width of the radix sort (single
+ *       and batched builds) for 30-bit / 63-bit codes: 8 or 10 bits
+ *       (4 or 3 passes; default 8) and 8, 9 or 11 bits (8, 7 or 6 passes;
+ *       default 9).  Other values are refused.
  *   "sort_variant32", "sort_variant64": tile shape of the radix passes for
  *       30-bit / 63-bit codes: 0 = 256 threads x 16 keys, 1 = 256 x 8,
  *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8, 6 = 768 x 16
- *       (defaults 4 and 3).
+ *       (defaults 4 and 6).  A shape whose tile holds fewer keys than the
+ *       digit width needs (4096 for 11-bit digits) or whose tables do not
+ *       fit the LDS runs as 512 x 16 (30-bit) or 512 x 8 (63-bit).
  *   "batch_sort_variant": tile shape of the batched build's segmented
  *       radix passes: 0 = 256 x 16 (default), 1 = 256 x 8, 2 = 512 x 8,
- *       3 = 512 x 16.
+ *       3 = 512 x 16 (1 runs as 0 with 11-bit digits).
  *   "query_split1", "query_split2": the single-tree count call cuts each
  *       query's Alg. 1 walk into pieces at aligned blocks of 2^split1
  *       leaves, then cuts those at blocks of 2^split2 leaves, and walks the
@@ -321,8 +342,12 @@ const char *lbvh_last_hip_error(void);
  *       in the caller's query order.  0 = the caller's order (default).
  *       The count call records which it did in the workspace, and the fill
  *       call follows that whatever the knob is when it is enqueued.
- * Results never depend on the knobs; only speed does.  Calls already
- * enqueued keep the shapes they were enqueued with. */
+ *   "query_walk_budget": for tests of the error path: caps the node visits
+ *       of each walk of a count call (0 = no cap beyond 2n, the default).
+ *       A walk that hits the cap stops; lbvh_query_check then reports it.
+ * Results never depend on the knobs other than query_walk_budget; only
+ * speed does.  Calls already enqueued keep the shapes they were enqueued
+ * with. */
 int64_t lbvh_tune(const char *name, int64_t value);
 
 /* Per-kernel timing.  While enabled, every launch the library makes is

@@ -49,8 +49,12 @@ def _load():
         lib.orc_pred_box.argtypes = [P, P]
         lib.orc_query_brute.argtypes = [i32, P, i64, i32, P, P, i64, P, i64]
         lib.orc_query_brute.restype = i64
-        lib.orc_query_traverse.argtypes = [i32, P, i64, i64, P, P, P, P, P, P, i64, P]
+        lib.orc_query_traverse.argtypes = [i32, P, i64, i64, P, P, P, P, P, P]
         lib.orc_query_traverse.restype = i64
+        lib.orc_query_fill.argtypes = [i32, P, i64, i64, P, P, P, P, P, P]
+        lib.orc_threads.argtypes = [i32]
+        lib.orc_threads.restype = None
+        lib.orc_threads(1)
         _lib = lib
     return _lib
 
@@ -223,8 +227,14 @@ def query_traverse(qkind: int, queries: np.ndarray, tree: Tree):
     offsets = np.zeros(m + 1, np.int64)
     vis = np.zeros(1, np.int64)
     total = lib.orc_query_traverse(qkind, _p(queries), m, tree.n, _p(tree.left), _p(tree.rope),
-                                   _p(tree.aabb), _p(tree.perm), _p(offsets), None, 0, _p(vis))
+                                   _p(tree.aabb), _p(tree.perm), _p(offsets), _p(vis))
     idx = np.zeros(max(total, 1), np.int32)
-    lib.orc_query_traverse(qkind, _p(queries), m, tree.n, _p(tree.left), _p(tree.rope),
-                           _p(tree.aabb), _p(tree.perm), _p(offsets), _p(idx), total, _p(vis))
+    lib.orc_query_fill(qkind, _p(queries), m, tree.n, _p(tree.left), _p(tree.rope),
+                       _p(tree.aabb), _p(tree.perm), _p(offsets), _p(idx))
     return offsets, idx[:total].copy(), int(vis[0])
+
+
+def threads(t: int):
+    """Host threads of the oracle's independent loops (1 = sequential); the
+    results are the same for every count."""
+    _load().orc_threads(int(t))

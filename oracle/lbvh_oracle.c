@@ -26,6 +26,14 @@
  * Floating point: IEEE binary32, round to nearest even, no contraction
  * (compile with -ffp-contract=off), no flush of denormals.
  *
+ * Threads: the loops whose iterations are independent (scene box, Morton
+ * codes, delta*, boxes, one Alg. 1 walk per query) carry OpenMP pragmas so
+ * that the benchmark can also time the oracle on several host cores
+ * (orc_threads).  Each iteration computes exactly what it computes alone,
+ * and min/max are exact, so every result is bit-identical for any thread
+ * count; the sort, the top-down split recursion and the rope walk stay
+ * sequential.
+ *
  * Conventions where the paper is silent or garbled (each is a reading):
  *   - delta* is a dissimilarity: the rank of the highest differing bit of the
  *     two adjacent augmented keys (code, sorted position), with
@@ -45,6 +53,10 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_POINTS 0
 #define ORC_BOXES 1
@@ -68,17 +80,39 @@ static void prim_box(int kind, const float *prims, int64_t i, float box[6])
 static float fmin_(float a, float b) { return b < a ? b : a; }
 static float fmax_(float a, float b) { return b > a ? b : a; }
 
-/* Scene box: componentwise min of lo and max of hi over all primitives. */
+/* Number of host threads the parallel loops use (1 = plain sequential). */
+void orc_threads(int t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}
+
+/* Scene box: componentwise min of lo and max of hi over all primitives
+ * (each thread folds its share, then the shares are folded together: for
+ * finite coordinates min and max are exact, so the order does not matter). */
 int orc_scene_box(int kind, const float *prims, int64_t n, float out[6])
 {
     if (n <= 0) return -1;
-    float box[6];
     prim_box(kind, prims, 0, out);
-    for (int64_t i = 1; i < n; ++i) {
-        prim_box(kind, prims, i, box);
+#pragma omp parallel
+    {
+        float part[6], box[6];
+        memcpy(part, out, sizeof(part));
+#pragma omp for schedule(static)
+        for (int64_t i = 1; i < n; ++i) {
+            prim_box(kind, prims, i, box);
+            for (int a = 0; a < 3; ++a) {
+                part[a] = fmin_(part[a], box[a]);
+                part[3 + a] = fmax_(part[3 + a], box[3 + a]);
+            }
+        }
+#pragma omp critical
         for (int a = 0; a < 3; ++a) {
-            out[a] = fmin_(out[a], box[a]);
-            out[3 + a] = fmax_(out[3 + a], box[3 + a]);
+            out[a] = fmin_(out[a], part[a]);
+            out[3 + a] = fmax_(out[3 + a], part[3 + a]);
         }
     }
     return 0;
@@ -125,8 +159,9 @@ int orc_morton(int kind, const float *prims, int64_t n, int bits,
     float maxq = (float)((1u << b) - 1u);
     float scale[3];
     orc_scales(scene, bits, scale);
-    float box[6];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
+        float box[6];
         prim_box(kind, prims, i, box);
         uint32_t q[3];
         for (int a = 0; a < 3; ++a) {
@@ -177,7 +212,8 @@ static int highest_bit(uint64_t x)
  * keys augmented with their index when codes are equal). */
 int orc_delta(const uint64_t *sorted, int64_t n, uint8_t *delta)
 {
-    for (int64_t i = 0; i + 1 < n; ++i) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n - 1; ++i) {
         uint64_t x = sorted[i] ^ sorted[i + 1];
         if (x) delta[i] = (uint8_t)(64 + highest_bit(x));
         else delta[i] = (uint8_t)highest_bit((uint64_t)i ^ (uint64_t)(i + 1));
@@ -267,7 +303,9 @@ int orc_aabbs(int kind, const float *prims, const int32_t *perm,
 {
     if (n <= 0) return 0;
     int64_t ni = n - 1;
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) prim_box(kind, prims, perm[k], aabb + 6 * (ni + k));
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t id = 0; id < ni; ++id) {
         float *dst = aabb + 6 * id;
         const float *first = aabb + 6 * (ni + rlo[id]);
@@ -352,40 +390,72 @@ int64_t orc_query_brute(int qkind, const float *queries, int64_t j, int kind,
     return h;
 }
 
-/* Alg. 1 on the oracle tree for queries [0, m).  offsets[m+1] receives the
- * CSR offsets; if indices is non-NULL the hits (primitive ids, in traversal
- * order) are written there (capacity cap).  visits, if non-NULL, receives
- * the total number of node visits.  Returns the total number of hits. */
+/* Alg. 1 for one query from the root: a passing internal node sends the
+ * walk to its left child, a passing leaf is reported and the walk follows
+ * its rope, a failing node sends it along its rope, the sentinel ends it.
+ * Writes the hits (primitive ids, in traversal order) to out if non-NULL;
+ * returns the number of hits and adds the node visits to *visits. */
+static int64_t walk_one(int qkind, const float *q, int64_t n, const int32_t *left,
+                        const int32_t *rope, const float *aabb, const int32_t *perm,
+                        int32_t *out, int64_t *visits)
+{
+    int64_t ni = n - 1, hits = 0, nvis = 0;
+    if (n > 0) {
+        int32_t node = 0; /* root */
+        do {
+            ++nvis;
+            if (pred(qkind, aabb + 6 * (int64_t)node, q)) {
+                if (node >= ni) {
+                    if (out) out[hits] = perm[node - ni];
+                    ++hits;
+                    node = rope[node];
+                } else {
+                    node = left[node];
+                }
+            } else {
+                node = rope[node];
+            }
+        } while (node != -1);
+    }
+    *visits += nvis;
+    return hits;
+}
+
+/* Alg. 1 on the oracle tree for queries [0, m): offsets[m+1] receives the
+ * CSR offsets (each query's hit count, then their running sum); visits, if
+ * non-NULL, the total number of node visits.  Returns the total number of
+ * hits.  The walks are independent (one per query). */
 int64_t orc_query_traverse(int qkind, const float *queries, int64_t m, int64_t n,
                            const int32_t *left, const int32_t *rope,
                            const float *aabb, const int32_t *perm,
-                           int64_t *offsets, int32_t *indices, int64_t cap,
-                           int64_t *visits)
+                           int64_t *offsets, int64_t *visits)
 {
     int qw = qkind == ORC_SPHERES ? 4 : 6;
-    int64_t ni = n - 1, total = 0, nvis = 0;
+    int64_t nvis = 0;
     offsets[0] = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nvis)
     for (int64_t j = 0; j < m; ++j) {
-        const float *q = queries + qw * j;
-        if (n > 0) {
-            int32_t node = 0; /* root */
-            do {
-                ++nvis;
-                if (pred(qkind, aabb + 6 * (int64_t)node, q)) {
-                    if (node >= ni) {
-                        if (indices && total < cap) indices[total] = perm[node - ni];
-                        ++total;
-                        node = rope[node];
-                    } else {
-                        node = left[node];
-                    }
-                } else {
-                    node = rope[node];
-                }
-            } while (node != -1);
-        }
-        offsets[j + 1] = total;
+        int64_t v = 0;
+        offsets[j + 1] = walk_one(qkind, queries + qw * j, n, left, rope, aabb, perm, NULL, &v);
+        nvis += v;
     }
+    for (int64_t j = 0; j < m; ++j) offsets[j + 1] += offsets[j];
     if (visits) *visits = nvis;
-    return total;
+    return offsets[m];
+}
+
+/* The hits of Alg. 1 for queries [0, m): query j's primitive ids, in
+ * traversal order, into indices[offsets[j] .. offsets[j+1]) (offsets as
+ * orc_query_traverse wrote them). */
+int orc_query_fill(int qkind, const float *queries, int64_t m, int64_t n,
+                   const int32_t *left, const int32_t *rope, const float *aabb,
+                   const int32_t *perm, const int64_t *offsets, int32_t *indices)
+{
+    int qw = qkind == ORC_SPHERES ? 4 : 6;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t v = 0;
+        walk_one(qkind, queries + qw * j, n, left, rope, aabb, perm, indices + offsets[j], &v);
+    }
+    return 0;
 }

@@ -1,7 +1,9 @@
 """Compile the plain C oracle into ``oracle/liblbvh_oracle.so`` with gcc.
 
 IEEE binary32 semantics are kept: no contraction into fused multiply-adds,
-no fast-math, SSE arithmetic (no x87 excess precision).
+no fast-math, SSE arithmetic (no x87 excess precision).  OpenMP is on for
+the oracle's independent loops (``orc_threads`` picks the thread count; the
+default is one).
 """
 
 import os
@@ -13,7 +15,7 @@ SRC = os.path.join(HERE, "lbvh_oracle.c")
 LIB = os.path.join(HERE, "liblbvh_oracle.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-          "-fno-fast-math", "-mfpmath=sse", "-msse2", "-Wall", "-Wextra"]
+          "-fno-fast-math", "-mfpmath=sse", "-msse2", "-fopenmp", "-Wall", "-Wextra"]
 
 
 def build(verbose: bool = False) -> str:

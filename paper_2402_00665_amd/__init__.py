@@ -79,6 +79,8 @@ def lib() -> C.CDLL:
             "lbvh_build_batched_check": (C.c_int, [P, Bt, P]),
             "lbvh_build_batched_status_async": (C.c_int, [P, Bt, P, P]),
             "lbvh_query_batched_workspace_bytes": (i64, [i64]),
+            "lbvh_query_check": (C.c_int, [P, i64, P]),
+            "lbvh_query_batched_check": (C.c_int, [P, i64, P]),
             "lbvh_query_batched_spheres_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
             "lbvh_query_batched_boxes_count": (C.c_int, [Bt, P, P, i64, P, P, i64, P]),
             "lbvh_query_batched_spheres_fill": (C.c_int, [Bt, P, P, i64, P, P, P, i64, P]),
@@ -155,6 +157,14 @@ def lbvh_query_spheres_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -
 
 def lbvh_query_boxes_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> int:
     return lib().lbvh_query_boxes_fill(C.byref(tree), q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_query_check(ws_ptr, m, stream) -> int:
+    return lib().lbvh_query_check(ws_ptr, m, stream)
+
+
+def lbvh_query_batched_check(ws_ptr, m, stream) -> int:
+    return lib().lbvh_query_batched_check(ws_ptr, m, stream)
 
 
 def lbvh_tune(name: str, value: int = -1) -> int:
@@ -354,6 +364,13 @@ def query_count(tree: Tree, queries, qkind: int, workspace: Workspace, offsets=N
     _check(f(tree.desc, q.data_ptr() if m else None, m, offsets.data_ptr(), ws.data_ptr(),
              ws.numel(), _stream(stream)), "query count")
     return offsets
+
+
+def check_query(workspace: Workspace, m: int, batched: bool = False, stream=None):
+    """Synchronise and raise if the last count call on this workspace (m
+    queries) flagged an error."""
+    f = lbvh_query_batched_check if batched else lbvh_query_check
+    _check(f(workspace.buf.data_ptr(), m, _stream(stream)), "lbvh_query_check")
 
 
 def query_fill(tree: Tree, queries, qkind: int, indices, workspace: Workspace, stream=None):

@@ -18,16 +18,15 @@ BuildLayout build_layout(int64_t n, int code_bits)
 {
     BuildLayout L{};
     const size_t kb = (size_t)key_bytes(code_bits);
-    L.passes = radix_passes(code_bits);
-    L.ntiles = (n + kMinSortTile - 1) / kMinSortTile;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     L.scene = take(3 * sizeof(float4));
     L.partials = take((size_t)kBoundsBlocksMax * 8 * sizeof(float));
     L.ctrl = take(kCtrlWords * sizeof(uint32_t));
-    L.hist = take((size_t)L.passes * kRadix * sizeof(uint32_t));
-    L.status[0] = take((size_t)L.ntiles * kRadix * sizeof(uint32_t));
-    L.status[1] = take((size_t)L.ntiles * kRadix * sizeof(uint32_t));
+    L.hist = take((size_t)radix_hist_words(code_bits) * sizeof(uint32_t));
+    const size_t status_words = (size_t)radix_status_words(n, code_bits, 0);
+    L.status[0] = take(status_words * sizeof(uint32_t));
+    L.status[1] = take(status_words * sizeof(uint32_t));
     L.keys_alt = take((size_t)n * kb);
     L.vals[0] = take((size_t)n * sizeof(int32_t));
     L.vals[1] = take((size_t)n * sizeof(int32_t));
@@ -88,6 +87,7 @@ QueryLayout batch_query_layout(int64_t m)
     L.cnt1 = take((size_t)(m + 1) * sizeof(int32_t));
     L.hcache = take((size_t)m * 64 * sizeof(int32_t));   // first 64 hits of each query
     L.partials = take((size_t)((m + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+    L.ctrl = take(128);
     L.total = off;
     return L;
 }
@@ -103,9 +103,7 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 {
     BatchLayout L{};
     const size_t kb = (size_t)key_bytes(code_bits);
-    L.passes = radix_passes(code_bits);
     L.levels = batch_levels(max_scene);
-    L.tiles_max = (N + kMinBatchTile - 1) / kMinBatchTile + S;
     int64_t span = kChunk;
     for (int lv = 0; lv <= L.levels; ++lv, span *= kFanout) L.blocks_max[lv] = (N + span - 1) / span + S;
     size_t off = 0;
@@ -114,9 +112,10 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
     L.scene_box = take((size_t)S * 3 * sizeof(float4));
     L.tile_off = take((size_t)(S + 1) * sizeof(int32_t));
     L.blk_off = take((size_t)(L.levels + 1) * (S + 1) * sizeof(int32_t));
-    L.hist = take((size_t)S * L.passes * kRadix * sizeof(uint32_t));
-    L.status[0] = take((size_t)L.tiles_max * kRadix * sizeof(uint32_t));
-    L.status[1] = take((size_t)L.tiles_max * kRadix * sizeof(uint32_t));
+    L.hist = take((size_t)S * radix_hist_words(code_bits) * sizeof(uint32_t));
+    const size_t status_words = (size_t)radix_status_words(N, code_bits, S);
+    L.status[0] = take(status_words * sizeof(uint32_t));
+    L.status[1] = take(status_words * sizeof(uint32_t));
     L.keys_alt = take((size_t)N * kb);
     L.vals[0] = take((size_t)N * sizeof(int32_t));
     L.vals[1] = take((size_t)N * sizeof(int32_t));
@@ -130,16 +129,24 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 // ---------------------------------------------------------------- tuning
 
 namespace {
-// defaults measured on MI355X: 512 x 16 for 30-bit keys, 512 x 8 for 63-bit
-std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {3}, {0}, {kSplit1}, {kSplit2}, {0}, {0}};
+// defaults measured on MI355X: 8-bit digits and 512 x 16 tiles for 30-bit
+// keys, 9-bit digits and 768 x 16 tiles for 63-bit keys
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {6}, {0}, {kSplit1}, {kSplit2}, {0}, {0}, {8}, {9}, {0}};
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
                                     "query_split1", "query_split2", "query_leaf_mode",
-                                    "query_order"};
-const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0};     // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1, 1};
+                                    "query_order", "radix_bits32", "radix_bits64",
+                                    "query_walk_budget"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0};   // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1, 1, 10, 11, INT32_MAX};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
+
+int radix_bits(int code_bits)
+{
+    const int b = (int)tune_get(code_bits <= 32 ? TUNE_RADIX_BITS32 : TUNE_RADIX_BITS64);
+    return radix_bits_ok(code_bits, b) ? b : 8;
+}
 
 // ---------------------------------------------------------------- timing
 
@@ -486,6 +493,29 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m, i
     return query_fill(1, tree, lohi, m, indices, workspace, workspace_bytes, stream);
 }
 
+static int query_check(const void *workspace, size_t ctrl, void *stream)
+{
+    if (hipError_t e = hipStreamSynchronize((hipStream_t)stream); e != hipSuccess) return hip_status(e);
+    uint32_t flag = 0;
+    if (hipError_t e = hipMemcpy(&flag, static_cast<const char *>(workspace) + ctrl + kQueryErrorByte,
+                                 sizeof(flag), hipMemcpyDeviceToHost);
+        e != hipSuccess)
+        return hip_status(e);
+    return flag ? LBVH_EDEVICE : LBVH_OK;
+}
+
+int lbvh_query_check(const void *workspace, int64_t m, void *stream)
+{
+    if (!workspace || m < 0 || m > INT32_MAX) return LBVH_EINVAL;
+    return query_check(workspace, query_layout(m).ctrl, stream);
+}
+
+int lbvh_query_batched_check(const void *workspace, int64_t m, void *stream)
+{
+    if (!workspace || m < 0 || m > INT32_MAX) return LBVH_EINVAL;
+    return query_check(workspace, batch_query_layout(m).ctrl, stream);
+}
+
 const char *lbvh_last_hip_error(void) { return hipGetErrorString(t_last_hip); }
 
 int64_t lbvh_tune(const char *name, int64_t value)
@@ -495,6 +525,8 @@ int64_t lbvh_tune(const char *name, int64_t value)
         if (strcmp(name, kTuneNames[k]) == 0) {
             if (value < 0) return g_tune[k].load();
             if (value < kTuneMin[k] || value > kTuneMax[k]) return LBVH_EINVAL;
+            if (k == TUNE_RADIX_BITS32 && !radix_bits_ok(30, (int)value)) return LBVH_EINVAL;
+            if (k == TUNE_RADIX_BITS64 && !radix_bits_ok(63, (int)value)) return LBVH_EINVAL;
             return g_tune[k].exchange(value);
         }
     }
