@@ -12,13 +12,19 @@ with the library's per-launch events on, which cost about 65 us of host
 time per build when left in the timed loop.
 
 Prints one JSON line:
-  value        build throughput, Mprims/s (n / mean build time of a step)
+  value        build throughput, Mprims/s (n / median build time of the
+               timed steps: 3 warmups, then the median of 10 by default)
   ms_per_step  mean wall time of a whole step (build + queries)
-  queries      query throughput of the same steps
-  roofline     the dominant kernel's algorithmic bytes per launch over its
-               mean launch time (HIP events the library records on the
-               launch stream), against the 8 TB/s HBM peak
-  cpu_baseline the plain single-threaded C oracle on a bounded sample
+  queries      query throughput of the same steps (median), and their
+               roofline: bytes per query from the oracle's exact Alg. 1 visit
+               counts on the identical tree
+  roofline     the dominant build kernel (level 0 of the bottom-up pass):
+               its stage bytes in the fixed byte model, K + P + 100 per
+               primitive for all n leaves one launch processes, over its mean
+               launch time (HIP events the library records on the launch
+               stream), against the 8 TB/s HBM peak
+  cpu_baseline the plain C oracle on the host's cores (all of them, with
+               OpenMP over its independent loops), and on one core
 
 Default workload: 2^24 clustered boxes with 30-bit codes and 2^20 box
 queries of side 0.01 (the 2^24-primitive configuration).
@@ -60,10 +66,39 @@ def build_bytes_per_prim(P: int, K: int, d: int) -> dict:
     }
 
 
-# The fixed whole-build byte model used for the roofline target
-# (bounds P, Morton P + K, sort 2K + (2d-1)(K+4), bottom-up K + P + 100).
-def build_model_bytes_per_prim(P: int, K: int, d: int) -> float:
-    return P + (P + K) + (2 * K + (2 * d - 1) * (K + 4)) + (K + P + 100)
+# The fixed whole-build byte model used for the roofline target, with
+# 8-bit digits (d8 = ceil(bits / 8) passes):
+#   bounds P, Morton P + K, sort 2K + (2 d8 - 1)(K + 4), bottom-up K + P + 100
+# (the bottom-up stage: codes K, leaf_perm 4, primitive gather P, store init
+# 4, store CAS 8, sibling box 24, leaf record 28, internal record 32).
+def model_stage_bytes_per_prim(P: int, K: int, d8: int) -> dict:
+    return {"bounds": P, "morton": P + K, "sort": 2 * K + (2 * d8 - 1) * (K + 4),
+            "bottomup": K + P + 100}
+
+
+def build_model_bytes_per_prim(P: int, K: int, d8: int) -> float:
+    return float(sum(model_stage_bytes_per_prim(P, K, d8).values()))
+
+
+def host_info() -> dict:
+    """Host cores this process may use (its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set) and the CPU model."""
+    affinity = len(os.sched_getaffinity(0))
+    cores = affinity
+    try:
+        cores = max(1, min(affinity, int(os.environ.get("OMP_NUM_THREADS", affinity))))
+    except ValueError:
+        pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cores": cores, "affinity_cores": affinity, "cpu_model": model}
 
 
 KERNEL_SOURCES = ["paper_2402_00665_amd/csrc/build_kernels.hip",
@@ -100,7 +135,8 @@ def measured_traffic(workload: str, kernel: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed steps (the reported build and query times are their medians)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="clustered_boxes",
                     choices=["clustered_boxes", "large_points", "small_points"])
@@ -124,8 +160,8 @@ def parse():
                     help="time the build alone (no queries in the step)")
     ap.add_argument("--cpu-sample", type=float, default=1.0,
                     help="fraction of the workload the oracle baseline runs on")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="repeat the oracle baseline until this much CPU time is spent (max 8 runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="repeat each oracle baseline leg until this much time is spent (max 8 runs)")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched build + queries (no plain per-scene leg, no "
                          "single-tree or serving legs); for profiling the batched kernels")
@@ -206,8 +242,9 @@ def main():
         from paper_2402_00665_amd import autotune
         a0 = time.time()
         ts = autotune.tune(prims, w.code_bits, kind=w.kind, reps=3, save=False)
-        lb.lbvh_tune(ts["knob"], ts["value"])
-        tuning = {ts["knob"]: ts["value"]}
+        for k, v in ts["knobs"].items():
+            lb.lbvh_tune(k, v)
+        tuning = dict(ts["knobs"])
         if not args.build_only:
             lb.build(prims, w.code_bits, kind=w.kind, workspace=ws, tree=tree)
             tq = autotune.tune_query(tree, queries, w.qkind, reps=3, save=False)
@@ -275,8 +312,8 @@ def main():
 
     build_ms = [e[0].elapsed_time(e[1]) for e in evs]
     query_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    mean_build = float(np.mean(build_ms))
-    mean_query = float(np.mean(query_ms))
+    med_build = float(np.median(build_ms))
+    med_query = float(np.median(query_ms))
     ms_per_step = wall * 1e3 / args.steps
 
     kernels = {}
@@ -289,7 +326,9 @@ def main():
 
     P = 12 if w.kind == 0 else 24
     K = 4 if w.code_bits == 30 else 8
-    d = (w.code_bits + 7) // 8
+    d8 = (w.code_bits + 7) // 8
+    radix_bits = lb.lbvh_tune(f"radix_bits{32 if w.code_bits == 30 else 64}")
+    d = (w.code_bits + radix_bits - 1) // radix_bits
     bpp = build_bytes_per_prim(P, K, d)
     for name, b in bpp.items():
         if name in kernels:
@@ -300,59 +339,100 @@ def main():
     dom = max(build_kernels, key=lambda k: build_kernels[k]["ms_per_step"])
     dk = kernels[dom]
     traffic = measured_traffic(w.name, dom)
+    # the dominant kernel's stage bytes in the fixed model: the bottom-up
+    # stage for level 0 (it takes all n leaves), else the kernel's own bytes
+    stage = model_stage_bytes_per_prim(P, K, d8)
+    unit_bytes = stage["bottomup"] if dom == "bottomup" else bpp[dom]
+    roof_bytes = unit_bytes * w.n
+    achieved = roof_bytes / (dk["ms_per_launch"] * 1e-3) / 1e9
     roofline = {
         "kernel": dom,
         "bound": "hbm",
-        "achieved": round(dk["achieved_gbps"], 1),
+        "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBPS,
         "unit": "GB/s",
-        "frac": round(dk["achieved_gbps"] / HBM_PEAK_GBPS, 4),
+        "frac": round(achieved / HBM_PEAK_GBPS, 4),
         "traffic": None if traffic is None else int(traffic),
-        "alg_bytes_per_launch": int(dk["alg_bytes_per_launch"]),
+        "bytes_per_unit": unit_bytes,
+        "units_per_launch": w.n,
+        "alg_bytes_per_launch": int(roof_bytes),
         "ms_per_launch": round(dk["ms_per_launch"], 4),
+        # the bytes the kernel itself must move (LDS-resident sibling boxes
+        # and arrival flags not counted), over the same time
+        "kernel_bytes_per_launch": int(dk["alg_bytes_per_launch"]),
+        "kernel_frac": round(dk["achieved_gbps"] / HBM_PEAK_GBPS, 4),
         # the measured HBM bytes over the same launch time: how close the
         # kernel runs to the memory system, whatever its algorithmic bytes
         "traffic_gbps": None if traffic is None else round(traffic / (dk["ms_per_launch"] * 1e-3) / 1e9, 1),
         "traffic_frac": None if traffic is None else
         round(traffic / (dk["ms_per_launch"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
     }
-    model_bytes = build_model_bytes_per_prim(P, K, d) * w.n
+    model_bytes = build_model_bytes_per_prim(P, K, d8) * w.n
 
     copy_gbps = copy_bandwidth()
 
     cpu = None
+    visits = None
     if not args.no_cpu_baseline:
         import oracle
+        host = host_info()
         ns = max(1, int(w.n * args.cpu_sample))
         ms_ = max(1, int(w.m * args.cpu_sample))
         sub_p = np.ascontiguousarray(w.prims[:ns])
         sub_q = np.ascontiguousarray(w.queries[:ms_])
-        log(f"[bench] cpu baseline: oracle on {ns} primitives, {ms_} queries")
-        tb = tq = 0.0
-        runs = 0
-        while runs == 0 or (tb + tq < args.cpu_seconds and runs < 8):
-            c0 = time.perf_counter()
-            ref = oracle.build(w.kind, sub_p, w.code_bits)
-            c1 = time.perf_counter()
-            oracle.query_traverse(w.qkind, sub_q, ref)
-            c2 = time.perf_counter()
-            tb, tq, runs = tb + (c1 - c0), tq + (c2 - c1), runs + 1
-            del ref
-        cpu = {"value": round(runs * ns / tb / 1e6, 3), "unit": "Mprims/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{runs} run(s) of: build over the first {ns} of the {w.n} primitives, "
-                         f"then Alg. 1 for the first {ms_} of the {w.m} queries on the oracle "
-                         "tree; single-threaded C",
-               "build_s": round(tb / runs, 3), "query_s": round(tq / runs, 3),
-               "queries_mqps": round(runs * ms_ / tq / 1e6, 3)}
-        log(f"[bench] cpu baseline done: {runs} run(s) in {tb + tq:.1f}s")
+        legs = {}
+        for threads in (host["cores"], 1):
+            log(f"[bench] cpu baseline: oracle on {ns} primitives, {ms_} queries, {threads} thread(s)")
+            oracle.threads(threads)
+            tb = tq = 0.0
+            runs = 0
+            try:
+                while runs == 0 or (tb + tq < args.cpu_seconds and runs < 8):
+                    c0 = time.perf_counter()
+                    ref = oracle.build(w.kind, sub_p, w.code_bits)
+                    c1 = time.perf_counter()
+                    _, _, vis = oracle.query_traverse(w.qkind, sub_q, ref)
+                    c2 = time.perf_counter()
+                    tb, tq, runs = tb + (c1 - c0), tq + (c2 - c1), runs + 1
+                    del ref
+            finally:
+                oracle.threads(1)
+            if ns == w.n and ms_ == w.m:
+                visits = vis
+            legs[threads] = {"value": round(runs * ns / tb / 1e6, 3), "cores": threads,
+                             "runs": runs, "build_s": round(tb / runs, 3),
+                             "query_s": round(tq / runs, 3),
+                             "queries_mqps": round(runs * ms_ / tq / 1e6, 3)}
+            log(f"[bench] cpu baseline, {threads} thread(s): {runs} run(s) in {tb + tq:.1f}s")
+        T = host["cores"]
+        cpu = {"value": legs[T]["value"], "unit": "Mprims/s", "cores": T, "kind": "oracle",
+               "sample": f"build over the first {ns} of the {w.n} primitives (scene box, Morton "
+                         "codes, qsort, top-down tree, DFS ropes, range-union boxes), then Alg. 1 "
+                         f"for the first {ms_} of the {w.m} queries on the oracle tree; C with "
+                         f"OpenMP over its independent loops on {T} thread(s) (sort, top-down "
+                         "split and rope walk sequential)",
+               "host": host, "build_s": legs[T]["build_s"], "query_s": legs[T]["query_s"],
+               "queries_mqps": legs[T]["queries_mqps"], "runs": legs[T]["runs"],
+               "single_thread": legs[1]}
+
+    qroof = None
+    if visits is not None and not args.build_only:
+        # bytes per query call: the query (16 or 24 B) and its offset (8 B),
+        # one 32-byte node record per Alg. 1 visit, 4 B per hit written
+        qbytes = w.m * ((16 if w.qkind == 0 else 24) + 8) + 32 * visits + 4 * hits
+        qgbps = qbytes / (med_query * 1e-3) / 1e9
+        qroof = {"bound": "hbm", "achieved": round(qgbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                 "frac": round(qgbps / HBM_PEAK_GBPS, 4), "bytes": int(qbytes),
+                 "visits": int(visits), "visits_per_query": round(visits / w.m, 2),
+                 "note": "node bytes counted once per visit; upper tree levels stay in cache, "
+                         "so this can exceed what HBM alone would allow"}
 
     batched = None if args.no_batched else bench_batched(args)
     serving = None if args.no_serving else bench_serving(args)
 
     out = {
         "metric": "rope-LBVH build Mprims/s + stackless Mqueries/s",
-        "value": round(w.n / (mean_build * 1e-3) / 1e6, 2),
+        "value": round(w.n / (med_build * 1e-3) / 1e6, 2),
         "unit": "Mprims/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -364,15 +444,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "kind": "points" if w.kind == 0 else "boxes",
-                   "code_bits": w.code_bits, "m": w.m,
+                   "code_bits": w.code_bits, "radix_bits": radix_bits, "m": w.m,
                    "queries": "spheres" if w.qkind == 0 else "boxes",
                    "build_launch": "hip_graph" if args.graph else "eager"},
-        "build_ms": round(mean_build, 4),
+        "build_ms": round(med_build, 4),
+        "build_ms_mean": round(float(np.mean(build_ms)), 4),
         "queries": None if args.build_only else {
-            "mqueries_per_s": round(w.m / (mean_query * 1e-3) / 1e6, 2),
-            "ms": round(mean_query, 4), "hits": hits},
+            "mqueries_per_s": round(w.m / (med_query * 1e-3) / 1e6, 2),
+            "ms": round(med_query, 4), "ms_mean": round(float(np.mean(query_ms)), 4),
+            "hits": hits, "roofline": qroof},
         "build_model_bytes": int(model_bytes),
-        "build_model_gbps": round(model_bytes / (mean_build * 1e-3) / 1e9, 1),
+        "build_model_gbps": round(model_bytes / (med_build * 1e-3) / 1e9, 1),
+        "build_model_frac": round(model_bytes / (med_build * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "copy_gbps": round(copy_gbps, 1),
         "roofline": roofline,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
@@ -409,8 +492,9 @@ def bench_batched(args, reps: int = 5, plain: bool = True):
         from paper_2402_00665_amd import autotune
         t = autotune.tune(dp, 63, kind=lb.LBVH_POINTS, seg_off=ds, max_scene=max_scene, reps=2,
                           save=False)
-        lb.lbvh_tune(t["knob"], t["value"])
-        tuned = {t["knob"]: t["value"]}
+        for k, v in t["knobs"].items():
+            lb.lbvh_tune(k, v)
+        tuned = dict(t["knobs"])
         log(f"[bench] batched: autotuned {tuned}")
     b = lb.build_batched(dp, ds, 63, max_scene, workspace=ws)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]

@@ -1,9 +1,10 @@
 """Self-written autotuner for the library's launch-shape knobs.
 
-A knob (see ``lbvh_tune`` in include/lbvh.h) picks a tile shape or a
-query piece size; results never depend on it, only speed does.  ``tune``
-(radix tile shapes of a build) and ``tune_query`` (the two query split
-levels) time every candidate on the caller's own workload with HIP events,
+A knob (see ``lbvh_tune`` in include/lbvh.h) picks a digit width, a tile
+shape or a query piece size; results never depend on it, only speed does.
+``tune`` (radix digit width and tile shape of a build) and ``tune_query``
+(the query schedule) time every candidate on the caller's own workload with
+HIP events,
 check once per candidate that its output is bit-identical to the default's,
 keep the fastest and record it in a JSON cache keyed by GPU arch, knob and
 workload shape (code bits / query kind, size buckets floor(log2 n) and
@@ -26,6 +27,8 @@ KNOB_CANDIDATES = {
     "sort_variant32": list(range(7)),
     "sort_variant64": list(range(7)),
     "batch_sort_variant": list(range(4)),
+    "radix_bits32": [8, 10],
+    "radix_bits64": [8, 9, 11],
 }
 # (query_split1, query_split2, query_leaf_mode, query_order): each split
 # schedule with the queries as given and in Morton order
@@ -67,6 +70,13 @@ def _save(cache: dict):
     os.replace(tmp, path)
 
 
+def _sort_ms(prep: str):
+    """ms of the codes kernel and all radix passes since the last reset."""
+    t0, _ = lbvh_profile_read(prep)
+    t1, _ = lbvh_profile_read("sort_pass")
+    return t0 + t1
+
+
 def _time_single(prims, code_bits, kind, ws, tree, reps):
     import torch
     for _ in range(2):
@@ -78,9 +88,9 @@ def _time_single(prims, code_bits, kind, ws, tree, reps):
         build(prims, code_bits, kind=kind, workspace=ws, tree=tree)
     torch.cuda.synchronize()
     lbvh_profile_enable(False)
-    ms, cnt = lbvh_profile_read("sort_pass")
+    ms = _sort_ms("morton")
     check_build(tree)
-    return ms / max(cnt, 1)
+    return ms / reps
 
 
 def _time_batched(prims, seg_off, code_bits, kind, max_scene, ws, batch, reps):
@@ -94,24 +104,33 @@ def _time_batched(prims, seg_off, code_bits, kind, max_scene, ws, batch, reps):
         build_batched(prims, seg_off, code_bits, max_scene, kind=kind, workspace=ws, batch=batch)
     torch.cuda.synchronize()
     lbvh_profile_enable(False)
-    ms, cnt = lbvh_profile_read("sort_pass")
+    ms = _sort_ms("batch_prep")
     check_batched(batch)
-    return ms / max(cnt, 1)
+    return ms / reps
+
+
+def sort_knobs(code_bits: int, batched: bool):
+    """(digit-width knob, tile-shape knob) of a build."""
+    width = f"radix_bits{32 if code_bits == 30 else 64}"
+    shape = "batch_sort_variant" if batched else f"sort_variant{32 if code_bits == 30 else 64}"
+    return width, shape
 
 
 def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene: int | None = None,
          reps: int = 5, save: bool = True, verbose: bool = False) -> dict:
-    """Tune the radix-pass tile shape for this workload (a single tree, or
-    a batch when ``seg_off`` is given).  Returns {"knob", "value",
-    "times_ms": {value: ms per pass}}; every candidate is checked to give the
-    same tree, bit for bit, as the first (default) candidate."""
+    """Tune the radix digit width and tile shape for this workload (a single
+    tree, or a batch when ``seg_off`` is given): each (width, shape) pair is
+    timed as the codes kernel plus all radix passes of a build.  Returns
+    {"knobs": {width knob: bits, shape knob: shape}, "times_ms": {"bits/shape":
+    ms per build}}; every candidate is checked to give the same tree, bit for
+    bit, as the first (current) one."""
     import torch
     if kind is None:
         kind = LBVH_POINTS if prims.shape[1] == 3 else 1
     batched = seg_off is not None
-    knob = "batch_sort_variant" if batched else f"sort_variant{32 if code_bits == 30 else 64}"
-    cands = KNOB_CANDIDATES[knob]
-    default = lbvh_tune(knob)
+    wk, sk = sort_knobs(code_bits, batched)
+    default = (lbvh_tune(wk), lbvh_tune(sk))
+    cands = [(b, v) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
     order = [default] + [c for c in cands if c != default]
     ws = Workspace(prims.device)
     n = int(prims.shape[0])
@@ -122,37 +141,41 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
         obj = alloc_tree(n, code_bits, prims.device)
     times, ref = {}, None
     try:
-        for v in order:
-            lbvh_tune(knob, v)
+        for b, v in order:
+            lbvh_tune(wk, b)
+            lbvh_tune(sk, v)
             t = (_time_batched(prims, seg_off, code_bits, kind, max_scene, ws, obj, reps) if batched
                  else _time_single(prims, code_bits, kind, ws, obj, reps))
             out = torch.cat([obj.nodes.flatten(), obj.leaf_perm]).clone()
             if ref is None:
                 ref = out
             elif not torch.equal(out, ref):
-                raise RuntimeError(f"{knob}={v} changed the tree; refusing to tune with it")
-            times[v] = t
+                raise RuntimeError(f"{wk}={b}, {sk}={v} changed the tree; refusing to tune with it")
+            times[f"{b}/{v}"] = t
             if verbose:
-                print(f"[autotune] {knob}={v}: {t * 1e3:.1f} us per pass", flush=True)
+                print(f"[autotune] {wk}={b} {sk}={v}: {t * 1e3:.1f} us per build", flush=True)
     finally:
-        lbvh_tune(knob, default)
+        lbvh_tune(wk, default[0])
+        lbvh_tune(sk, default[1])
     best = min(times, key=times.get)
+    knobs = dict(zip((wk, sk), (int(x) for x in best.split("/"))))
     if save:
         cache = _load()
-        cache[_key(knob, code_bits, kind, n)] = {"value": best, "times_ms": times}
+        cache[_key(sk, code_bits, kind, n)] = {"knobs": knobs, "times_ms": times}
         _save(cache)
-    return {"knob": knob, "value": best, "times_ms": times}
+    return {"knobs": knobs, "times_ms": times}
 
 
 def apply(n: int, code_bits: int, kind: int, batched: bool = False) -> dict:
-    """Set the cached best value of the knob for this shape, if any; returns
-    {knob: value} for what was set."""
-    knob = "batch_sort_variant" if batched else f"sort_variant{32 if code_bits == 30 else 64}"
-    hit = _load().get(_key(knob, code_bits, kind, n))
-    if hit is None:
+    """Set the cached best digit width and tile shape for this shape, if
+    any; returns {knob: value} for what was set."""
+    _, sk = sort_knobs(code_bits, batched)
+    hit = _load().get(_key(sk, code_bits, kind, n))
+    if hit is None or "knobs" not in hit:
         return {}
-    lbvh_tune(knob, int(hit["value"]))
-    return {knob: int(hit["value"])}
+    for k, v in hit["knobs"].items():
+        lbvh_tune(k, int(v))
+    return {k: int(v) for k, v in hit["knobs"].items()}
 
 
 def _query_key(qkind: int, n: int, m: int) -> str:

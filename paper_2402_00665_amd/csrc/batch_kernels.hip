@@ -72,18 +72,20 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t *__re
 }
 
 // One block per scene: scene box (min/max), scale 2^b / extent, Morton codes
-// (written in place of the scene's primitives' order), digit histograms of
-// every radix pass for scenes spanning several tiles, and the first pass's
-// look-back status of those tiles cleared.
-template <int KIND, typename K>
+// (written in place of the scene's primitives' order), digit histograms
+// (BITS-wide digits) of every radix pass for scenes spanning several tiles,
+// and the first pass's look-back status of those tiles cleared.
+template <int KIND, typename K, int BITS>
 __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
     const float *__restrict__ prims, const int64_t *__restrict__ seg_off,
     const int32_t *__restrict__ tile_off, int bits_per_axis, float4 *__restrict__ scene_box,
-    K *__restrict__ codes, uint32_t *__restrict__ hist, int passes, uint32_t *__restrict__ status0)
+    K *__restrict__ codes, uint32_t *__restrict__ hist, uint32_t *__restrict__ status0)
 {
+    constexpr int R = 1 << BITS;
+    constexpr int PASSES = ((sizeof(K) == 4 ? 30 : 63) + BITS - 1) / BITS;
     __shared__ float sh[(kSceneThreads / 64) * 6];
     __shared__ float4 s_box[3];
-    __shared__ uint32_t lh[8 * kRadix];
+    __shared__ uint32_t lh[PASSES * R];
     using P = Prims<KIND>;
     const int s = blockIdx.x;
     const int64_t b0 = seg_off[s];
@@ -91,7 +93,7 @@ __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
     if (ns == 0) return;
     const bool multi = tile_off[s + 1] - tile_off[s] > 1;
     if (multi)
-        for (int j = threadIdx.x; j < passes * kRadix; j += kSceneThreads) lh[j] = 0u;
+        for (int j = threadIdx.x; j < PASSES * R; j += kSceneThreads) lh[j] = 0u;
 
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = threadIdx.x; i < ns; i += kSceneThreads) {
@@ -123,14 +125,15 @@ __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
         const K c = code_of<KIND, K>(lo, hi, slo, sc);
         codes[b0 + i] = c;
         if (multi)
-            for (int p = 0; p < passes; ++p)
-                atomicAdd(&lh[p * kRadix + (uint32_t)((c >> (p * kRadixBits)) & (kRadix - 1))], 1u);
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p)
+                atomicAdd(&lh[p * R + (uint32_t)((c >> (p * BITS)) & (R - 1))], 1u);
     }
     if (!multi) return;
     __syncthreads();
-    uint32_t *hs = hist + (int64_t)s * passes * kRadix;
-    for (int j = threadIdx.x; j < passes * kRadix; j += kSceneThreads) hs[j] = lh[j];
-    const int64_t w0 = (int64_t)tile_off[s] * kRadix, w1 = (int64_t)tile_off[s + 1] * kRadix;
+    uint32_t *hs = hist + (int64_t)s * PASSES * R;
+    for (int j = threadIdx.x; j < PASSES * R; j += kSceneThreads) hs[j] = lh[j];
+    const int64_t w0 = (int64_t)tile_off[s] * R, w1 = (int64_t)tile_off[s + 1] * R;
     for (int64_t w = w0 + threadIdx.x; w < w1; w += kSceneThreads) status0[w] = 0u;
 }
 
@@ -150,7 +153,8 @@ __device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const in
                                                const int64_t *seg_off, const int64_t *qseg_off, int S,
                                                const float *queries, int64_t j, int &cnt,
                                                const HitStage *st, int64_t pos,
-                                               int32_t *kept = nullptr)
+                                               int32_t *kept = nullptr, uint32_t *err = nullptr,
+                                               int64_t budget_cap = 0, int64_t end = 0)
 {
     int lo = 0, hi = S - 1;   // scene of query j: largest s with qseg_off[s] <= j
     while (lo < hi) {
@@ -161,12 +165,12 @@ __device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const in
     const int64_t b0 = seg_off[lo];
     const int n = (int)(seg_off[lo + 1] - b0);
     if (n <= 0) return;
-    Tree tr{nodes_all + 4 * b0, perm_all + b0, n};
+    Tree tr{nodes_all + 4 * b0, perm_all + b0, n, err, budget_cap};
     Q q;
     q.load(queries, (int)j);
     const int leaf0 = n - 1;
     int v = 0, i = 0;
-    int64_t budget = 2 * (int64_t)n;
+    int64_t budget = tr.walk_budget();
     while (v != -1 && --budget >= 0) {
         float4 a, b;
         tr.load(v, a, b);
@@ -176,14 +180,16 @@ __device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const in
         if (q.test(a, b)) {
             if (v >= leaf0) {
                 if (st) {
-                    st->put(pos++, left);
+                    if (pos < end) st->put(pos, left);   // never past the counted hits
+                    ++pos;
                 } else {
                     if (kept && cnt < kBatchHitCache) kept[cnt] = left;
                     ++cnt;
                 }
             } else if (q.contains(a, b)) {
                 if (st) {
-                    st->range(pos, (int32_t)b0 + i, jr - i + 1);   // perm_all index
+                    const int64_t len = jr - i + 1 < end - pos ? jr - i + 1 : end - pos;
+                    st->range(pos, (int32_t)b0 + i, (int32_t)len);   // perm_all index
                     pos += jr - i + 1;
                 } else {
                     if (kept)
@@ -199,6 +205,7 @@ __device__ __forceinline__ void batch_walk_one(const float4 *nodes_all, const in
         v = rope;
         i = jr + 1;
     }
+    if (budget < 0) tr.budget_spent();
 }
 
 template <class Q>
@@ -208,14 +215,21 @@ __global__ __launch_bounds__(kBlock) void k_batch_count(const float4 *__restrict
                                                         const int64_t *__restrict__ qseg_off, int S,
                                                         const float *__restrict__ queries, int64_t m,
                                                         int32_t *__restrict__ counts,
-                                                        int32_t *__restrict__ cache)
+                                                        int32_t *__restrict__ cache, uint32_t *err,
+                                                        int64_t budget_cap)
 {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= m) return;
     int cnt = 0;
     batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, cnt, nullptr, 0,
-                      cache + j * kBatchHitCache);
+                      cache + j * kBatchHitCache, err, budget_cap);
     counts[j] = cnt;
+}
+
+// Start of a batched count call: clear its error word.
+__global__ void k_batch_query_reset(uint32_t *err)
+{
+    if (threadIdx.x == 0) *err = 0u;
 }
 
 template <class Q>
@@ -243,41 +257,80 @@ __global__ __launch_bounds__(kBlock) void k_batch_fill(const float4 *__restrict_
         if (have <= kBatchHitCache)   // the count call kept them
             for (int k = 0; k < have; ++k) st.put(pos + k, cache[j * kBatchHitCache + k]);
         else
-            batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, unused, &st, pos);
+            batch_walk_one<Q>(nodes_all, perm_all, seg_off, qseg_off, S, queries, j, unused, &st, pos,
+                              nullptr, nullptr, 0, pos + have);
     }
     st.flush(offsets[j_end] - st.base);
 }
 
 // Radix tile shapes of the batched build (threads x keys per thread); the
-// knob "batch_sort_variant" picks one.
+// knob "batch_sort_variant" picks one.  A shape below the digit width's
+// minimum tile is replaced by 256 x 16.
 struct BatchSortShape { int threads, items; };
 constexpr BatchSortShape kBatchShapes[] = {{256, 16}, {256, 8}, {512, 8}, {512, 16}};
 
-int batch_sort_variant()
+int batch_sort_variant(int bits)
 {
     const int64_t v = tune_get(TUNE_BATCH_SORT);
-    return (v >= 0 && v < 4) ? (int)v : 0;
+    const int var = (v >= 0 && v < 4) ? (int)v : 0;
+    return kBatchShapes[var].threads * kBatchShapes[var].items >= radix_min_tile(bits) ? var : 0;
 }
 
-template <typename K, int T, int I>
+template <typename K, int T, int I, int B>
 void launch_seg(int64_t grid, const K *kin, K *kout, const int32_t *vin, int32_t *vout, int64_t N,
-                const SortSegs &segs, int shift, const uint32_t *hist, uint32_t *st, uint32_t *st_next,
-                uint32_t *ctr, uint32_t *err, hipStream_t s)
+                const SortSegs &segs, int shift, int nbits, const uint32_t *hist, uint32_t *st,
+                uint32_t *st_next, uint32_t *ctr, uint32_t *err, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_onesweep<K, T, I>), dim3((unsigned)grid), dim3(T), 0, s, kin, kout, vin, vout,
-                       N, segs, shift, hist, st, st_next, ctr, err);
+    hipLaunchKernelGGL((k_onesweep<K, T, I, B>), dim3((unsigned)grid), dim3(T), 0, s, kin, kout, vin,
+                       vout, N, segs, shift, nbits, hist, st, st_next, ctr, err);
 }
 
-template <typename K>
+template <typename K, int B>
 void launch_seg_variant(int v, int64_t grid, const K *kin, K *kout, const int32_t *vin, int32_t *vout,
-                        int64_t N, const SortSegs &segs, int shift, const uint32_t *hist,
+                        int64_t N, const SortSegs &segs, int shift, int nbits, const uint32_t *hist,
                         uint32_t *st, uint32_t *st_next, uint32_t *ctr, uint32_t *err, hipStream_t s)
 {
+#define LBVH_SEG_ARGS grid, kin, kout, vin, vout, N, segs, shift, nbits, hist, st, st_next, ctr, err, s
     switch (v) {
-    case 1: launch_seg<K, 256, 8>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
-    case 2: launch_seg<K, 512, 8>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
-    case 3: launch_seg<K, 512, 16>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
-    default: launch_seg<K, 256, 16>(grid, kin, kout, vin, vout, N, segs, shift, hist, st, st_next, ctr, err, s); break;
+    case 1: launch_seg<K, 256, 8, B>(LBVH_SEG_ARGS); break;
+    case 2: launch_seg<K, 512, 8, B>(LBVH_SEG_ARGS); break;
+    case 3: launch_seg<K, 512, 16, B>(LBVH_SEG_ARGS); break;
+    default: launch_seg<K, 256, 16, B>(LBVH_SEG_ARGS); break;
+    }
+#undef LBVH_SEG_ARGS
+}
+
+// Per-scene codes and the segmented radix passes of one digit width.  The
+// Morton kernel writes the codes to the buffer that makes the last pass end
+// in the batch's codes array; the last pass writes leaf_perm.
+template <int KIND, typename K, int B>
+void run_batch_sort(const float *prims, const int64_t *seg_off, int S, int64_t N, int code_bits,
+                    K *codes, int32_t *leaf_perm, int32_t *tile_off, float4 *scene_box, uint32_t *ctrl,
+                    uint32_t *hist, uint32_t *status[2], K *keys_alt, int32_t *vals[2], int variant,
+                    hipStream_t s)
+{
+    const int passes = radix_passes(code_bits, B);
+    const int tile = kBatchShapes[variant].threads * kBatchShapes[variant].items;
+    const int64_t tiles_grid = (N + tile - 1) / tile + S;   // within the look-back tables
+    K *first = (passes & 1) ? keys_alt : codes;
+    K *second = (passes & 1) ? codes : keys_alt;
+    hipLaunchKernelGGL((k_batch_morton<KIND, K, B>), dim3(S), dim3(kSceneThreads), 0, s, prims,
+                       seg_off, tile_off, code_bits / 3, scene_box, first, hist, status[0]);
+    prof_end(K_BATCH_PREP, s);
+
+    const SortSegs segs{seg_off, tile_off, S, (int64_t)passes << B};
+    for (int p = 0; p < passes; ++p) {
+        const K *kin = (p & 1) ? second : first;
+        K *kout = (p & 1) ? first : second;
+        const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
+        int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
+        uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
+        const int nbits = std::min(B, code_bits - p * B);
+        prof_begin(K_SORT, s);
+        launch_seg_variant<K, B>(variant, tiles_grid, kin, kout, vin, vout, N, segs, p * B, nbits,
+                                 hist + ((int64_t)p << B), status[p & 1], st_next,
+                                 ctrl + kCtrlTileCounter + p, ctrl + kCtrlError, s);
+        prof_end(K_SORT, s);
     }
 }
 
@@ -299,31 +352,24 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
     int32_t *store = reinterpret_cast<int32_t *>(ws + L.store);
     int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
     float4 *nodes = reinterpret_cast<float4 *>(nodes_);
-    const int passes = L.passes;
 
-    const int variant = batch_sort_variant();
+    const int bits = radix_bits(code_bits);
+    const int variant = batch_sort_variant(bits);
     const int tile = kBatchShapes[variant].threads * kBatchShapes[variant].items;
-    const int64_t tiles_grid = (N + tile - 1) / tile + S;   // <= L.tiles_max
     prof_begin(K_BATCH_PREP, s);
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile,
                        tile_off, blk_off, ctrl);
-    hipLaunchKernelGGL((k_batch_morton<KIND, K>), dim3(S), dim3(kSceneThreads), 0, s, prims, seg_off,
-                       tile_off, code_bits / 3, scene_box, codes, hist, passes, status[0]);
-    prof_end(K_BATCH_PREP, s);
-
-    const SortSegs segs{seg_off, tile_off, S, passes * kRadix};
-    for (int p = 0; p < passes; ++p) {
-        const K *kin = (p & 1) ? keys_alt : codes;
-        K *kout = (p & 1) ? codes : keys_alt;
-        const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
-        int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
-        uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
-        prof_begin(K_SORT, s);
-        launch_seg_variant<K>(variant, tiles_grid, kin, kout, vin, vout, N, segs, p * kRadixBits,
-                              hist + p * kRadix, status[p & 1], st_next, ctrl + kCtrlTileCounter + p,
-                              ctrl + kCtrlError, s);
-        prof_end(K_SORT, s);
+#define LBVH_BSORT_ARGS prims, seg_off, S, N, code_bits, codes, leaf_perm, tile_off, scene_box, ctrl, \
+                        hist, status, keys_alt, vals, variant, s
+    if constexpr (sizeof(K) == 4) {
+        if (bits == 10) run_batch_sort<KIND, K, 10>(LBVH_BSORT_ARGS);
+        else run_batch_sort<KIND, K, 8>(LBVH_BSORT_ARGS);
+    } else {
+        if (bits == 11) run_batch_sort<KIND, K, 11>(LBVH_BSORT_ARGS);
+        else if (bits == 9) run_batch_sort<KIND, K, 9>(LBVH_BSORT_ARGS);
+        else run_batch_sort<KIND, K, 8>(LBVH_BSORT_ARGS);
     }
+#undef LBVH_BSORT_ARGS
 
     prof_begin(K_BOTTOMUP, s);
     BatchLevel bl{seg_off, blk_off, nullptr, S, levels == 0};
@@ -364,9 +410,12 @@ hipError_t run_batch_query(const lbvh_batch *b, const float *q, const int64_t *q
     }
     int32_t *counts = reinterpret_cast<int32_t *>(ws + L.cnt1);
     int64_t *partials = reinterpret_cast<int64_t *>(ws + L.partials);
+    uint32_t *err = reinterpret_cast<uint32_t *>(ws + L.ctrl + kQueryErrorByte);
     prof_begin(K_QCOUNT, s);
+    hipLaunchKernelGGL(k_batch_query_reset, dim3(1), dim3(64), 0, s, err);
     hipLaunchKernelGGL((k_batch_count<Q>), dim3(g), dim3(kBlock), 0, s, nodes, b->leaf_perm,
-                       b->seg_off, qseg_off, b->num_scenes, q, m, counts, cache);
+                       b->seg_off, qseg_off, b->num_scenes, q, m, counts, cache, err,
+                       tune_get(TUNE_QBUDGET));
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
     scan(counts, m, nullptr, partials, offsets, s);
@@ -404,7 +453,8 @@ hipError_t launch_query_batched(int qkind, const lbvh_batch *b, const float *q,
 {
     if (m == 0) {
         if (fill) return hipSuccess;
-        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(kBlock), 0, s, offsets, (int64_t)1);
+        hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(kBlock), 0, s, offsets, (int64_t)1,
+                           reinterpret_cast<uint32_t *>(ws + L.ctrl + kQueryErrorByte));
         return hipGetLastError();
     }
     return qkind == 0 ? run_batch_query<Sphere>(b, q, qseg_off, m, offsets, indices, fill, ws, L, s)

@@ -88,19 +88,21 @@ __global__ __launch_bounds__(kBlock) void k_bounds_final(const float *__restrict
 
 // -------------------------------------------------------------- Morton
 
-// Codes in input order, LDS digit histograms of every radix pass folded
-// into the global ones, and one side job that must precede the sort: clear
-// the look-back status of the first sort pass.
-template <int KIND, typename K>
+// Codes in input order, LDS digit histograms of every radix pass (BITS-wide
+// digits) folded into the global ones, and one side job that must precede
+// the sort: clear the look-back status of the first sort pass.
+template <int KIND, typename K, int BITS>
 __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ prims, int n,
                                                    const float4 *__restrict__ scene,
                                                    K *__restrict__ codes, uint32_t *__restrict__ hist,
-                                                   int passes, uint32_t *__restrict__ status0,
+                                                   uint32_t *__restrict__ status0,
                                                    int64_t status_words)
 {
     using P = Prims<KIND>;
-    __shared__ uint32_t lh[8 * kRadix];
-    for (int j = threadIdx.x; j < passes * kRadix; j += kBlock) lh[j] = 0u;
+    constexpr int R = 1 << BITS;
+    constexpr int PASSES = ((sizeof(K) == 4 ? 30 : 63) + BITS - 1) / BITS;
+    __shared__ uint32_t lh[PASSES * R];
+    for (int j = threadIdx.x; j < PASSES * R; j += kBlock) lh[j] = 0u;
 
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -116,8 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
 #pragma unroll
         for (int k = 0; k < P::G; ++k) {
             c[k] = code_of<KIND, K>(lo[k], hi[k], slo, sc);
-            for (int p = 0; p < passes; ++p)
-                atomicAdd(&lh[p * kRadix + (uint32_t)((c[k] >> (p * kRadixBits)) & (kRadix - 1))], 1u);
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p)
+                atomicAdd(&lh[p * R + (uint32_t)((c[k] >> (p * BITS)) & (R - 1))], 1u);
         }
 #pragma unroll
         for (int k = 0; k < P::G; ++k) codes[g * P::G + k] = c[k];
@@ -127,56 +130,117 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
             float lo[3], hi[3];
             P::one(prims, i, lo, hi);
             K c = code_of<KIND, K>(lo, hi, slo, sc);
-            for (int p = 0; p < passes; ++p)
-                atomicAdd(&lh[p * kRadix + (uint32_t)((c >> (p * kRadixBits)) & (kRadix - 1))], 1u);
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p)
+                atomicAdd(&lh[p * R + (uint32_t)((c >> (p * BITS)) & (R - 1))], 1u);
             codes[i] = c;
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < passes * kRadix; j += kBlock)
+    for (int j = threadIdx.x; j < PASSES * R; j += kBlock)
         if (lh[j]) atomicAdd(&hist[j], lh[j]);
 }
 
 // ------------------------------------------------------ launchers
 
 // Tile shapes of the radix pass (threads x keys per thread); the tuning
-// knob "sort_variant" picks one (see lbvh_tune).
+// knob "sort_variant" picks one (see lbvh_tune).  A shape whose tile is
+// below the digit width's minimum, or whose digit tables and key buffer
+// exceed the LDS, is replaced by the width's default shape.
 struct SortShape { int threads, items; };
 constexpr SortShape kSortShapes[] = {{256, 16}, {256, 8}, {256, 24}, {512, 8}, {512, 16}, {1024, 8},
                                      {768, 16}};
 constexpr int kSortShapeCount = sizeof(kSortShapes) / sizeof(kSortShapes[0]);
 
-template <typename K>
-int sort_variant()
+constexpr size_t sort_lds_bytes(int key_bytes, int threads, int items, int bits)
 {
-    const int64_t v = tune_get(sizeof(K) == 4 ? TUNE_SORT_VARIANT32 : TUNE_SORT_VARIANT64);
-    return (v >= 0 && v < kSortShapeCount) ? (int)v : 0;
+    return (size_t)(threads / 64) * ((bits <= 9 ? 4u : 2u) << bits) + (8u << bits) +
+           (size_t)threads * items * key_bytes;
 }
 
-template <typename K, int T, int I>
-void launch_one(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n, int shift,
+template <typename K>
+int sort_variant(int bits)
+{
+    const int64_t v = tune_get(sizeof(K) == 4 ? TUNE_SORT_VARIANT32 : TUNE_SORT_VARIANT64);
+    const int var = (v >= 0 && v < kSortShapeCount) ? (int)v : 0;
+    const SortShape sh = kSortShapes[var];
+    const bool fits = sh.threads * sh.items >= radix_min_tile(bits) &&
+                      sort_lds_bytes(sizeof(K), sh.threads, sh.items, bits) <= 150 * 1024;
+    return fits ? var : (sizeof(K) == 4 ? 4 : 3);   // 512 x 16 / 512 x 8 fit every width
+}
+
+template <typename K, int T, int I, int B>
+void launch_one(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n, int shift, int nbits,
                 const uint32_t *hist, uint32_t *st, uint32_t *st_next, uint32_t *ctr, uint32_t *err,
                 hipStream_t s)
 {
-    const unsigned tiles = (unsigned)(((int64_t)n + T * I - 1) / (T * I));
-    const SortSegs one{nullptr, nullptr, 1, 0};
-    hipLaunchKernelGGL((k_onesweep<K, T, I>), dim3(tiles), dim3(T), 0, s, kin, kout, vin, vout,
-                       (int64_t)n, one, shift, hist, st, st_next, ctr, err);
+    if constexpr (sort_lds_bytes(sizeof(K), T, I, B) > 150 * 1024) {
+        return;   // never selected (sort_variant)
+    } else {
+        const unsigned tiles = (unsigned)(((int64_t)n + T * I - 1) / (T * I));
+        const SortSegs one{nullptr, nullptr, 1, 0};
+        hipLaunchKernelGGL((k_onesweep<K, T, I, B>), dim3(tiles), dim3(T), 0, s, kin, kout, vin, vout,
+                           (int64_t)n, one, shift, nbits, hist, st, st_next, ctr, err);
+    }
 }
 
-template <typename K>
-void launch_onesweep(int variant, const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n,
-                     int shift, const uint32_t *hist, uint32_t *st, uint32_t *st_next, uint32_t *ctr,
-                     uint32_t *err, hipStream_t s)
+template <typename K, int B>
+void launch_onesweep_b(int variant, const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n,
+                       int shift, int nbits, const uint32_t *hist, uint32_t *st, uint32_t *st_next,
+                       uint32_t *ctr, uint32_t *err, hipStream_t s)
 {
+#define LBVH_SORT_ARGS kin, kout, vin, vout, n, shift, nbits, hist, st, st_next, ctr, err, s
     switch (variant) {
-    case 1: launch_one<K, 256, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
-    case 2: launch_one<K, 256, 24>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
-    case 3: launch_one<K, 512, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
-    case 4: launch_one<K, 512, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
-    case 5: launch_one<K, 1024, 8>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
-    case 6: launch_one<K, 768, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
-    default: launch_one<K, 256, 16>(kin, kout, vin, vout, n, shift, hist, st, st_next, ctr, err, s); break;
+    case 1: launch_one<K, 256, 8, B>(LBVH_SORT_ARGS); break;
+    case 2: launch_one<K, 256, 24, B>(LBVH_SORT_ARGS); break;
+    case 3: launch_one<K, 512, 8, B>(LBVH_SORT_ARGS); break;
+    case 4: launch_one<K, 512, 16, B>(LBVH_SORT_ARGS); break;
+    case 5: launch_one<K, 1024, 8, B>(LBVH_SORT_ARGS); break;
+    case 6: launch_one<K, 768, 16, B>(LBVH_SORT_ARGS); break;
+    default: launch_one<K, 256, 16, B>(LBVH_SORT_ARGS); break;
+    }
+#undef LBVH_SORT_ARGS
+}
+
+// The digit width's Morton kernel and radix passes.  Ping-pong: the Morton
+// kernel writes the codes to the buffer that makes the last pass end in
+// tree->codes (keys_alt for an odd number of passes); the last pass writes
+// the permutation to leaf_perm.
+template <int KIND, typename K, int B>
+void run_sort(const float *prims, int n, int code_bits, K *codes, int32_t *leaf_perm,
+              const float4 *scene, uint32_t *ctrl, uint32_t *hist, uint32_t *status[2], K *keys_alt,
+              int32_t *vals[2], hipStream_t s)
+{
+    using P = Prims<KIND>;
+    const int passes = radix_passes(code_bits, B);
+    const int variant = sort_variant<K>(B);
+    const int tile = kSortShapes[variant].threads * kSortShapes[variant].items;
+    const int64_t tiles = ((int64_t)n + tile - 1) / tile;
+    K *first = (passes & 1) ? keys_alt : codes;
+    K *second = (passes & 1) ? codes : keys_alt;
+
+    const int64_t groups = (int64_t)n / P::G;
+    int nm = (int)((groups + 4 * kBlock - 1) / (4 * kBlock));
+    // fewer, longer blocks for wide digits: each block adds its whole
+    // histogram table to the global one
+    const int nm_max = B <= 8 ? kMortonBlocksMax : (B <= 10 ? kMortonBlocksMax / 2 : kMortonBlocksMax / 4);
+    nm = nm < 1 ? 1 : (nm > nm_max ? nm_max : nm);
+    prof_begin(K_MORTON, s);
+    hipLaunchKernelGGL((k_morton<KIND, K, B>), dim3(nm), dim3(kBlock), 0, s, prims, n, scene, first,
+                       hist, status[0], tiles << B);
+    prof_end(K_MORTON, s);
+
+    for (int p = 0; p < passes; ++p) {
+        const K *kin = (p & 1) ? second : first;
+        K *kout = (p & 1) ? first : second;
+        const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
+        int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
+        uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
+        const int nbits = std::min(B, code_bits - p * B);
+        prof_begin(K_SORT, s);
+        launch_onesweep_b<K, B>(variant, kin, kout, vin, vout, n, p * B, nbits, hist + ((int64_t)p << B),
+                                status[p & 1], st_next, ctrl + kCtrlTileCounter + p, ctrl + kCtrlError, s);
+        prof_end(K_SORT, s);
     }
 }
 
@@ -196,7 +260,7 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
                         reinterpret_cast<int32_t *>(ws + L.vals[1])};
     int32_t *store = reinterpret_cast<int32_t *>(ws + L.store);
     float4 *nodes = reinterpret_cast<float4 *>(nodes_);
-    const int passes = L.passes;
+    const int bits = radix_bits(code_bits);
 
     const int64_t groups = (int64_t)n / P::G;
     int nb = (int)((groups + 4 * kBlock - 1) / (4 * kBlock));
@@ -206,30 +270,26 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     prof_end(K_BOUNDS, s);
     prof_begin(K_BOUNDS_FINAL, s);
     hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(kBlock), 0, s, partials, nb, code_bits / 3,
-                       scene, ctrl, hist, passes * kRadix);
+                       scene, ctrl, hist, (int)((int64_t)radix_passes(code_bits, bits) << bits));
     prof_end(K_BOUNDS_FINAL, s);
 
-    int nm = (int)((groups + 4 * kBlock - 1) / (4 * kBlock));
-    nm = nm < 1 ? 1 : (nm > kMortonBlocksMax ? kMortonBlocksMax : nm);
-    prof_begin(K_MORTON, s);
-    hipLaunchKernelGGL((k_morton<KIND, K>), dim3(nm), dim3(kBlock), 0, s, prims, n, scene, codes,
-                       hist, passes, status[0], L.ntiles * kRadix);
-    prof_end(K_MORTON, s);
-
-    // ping-pong: even passes read tree->codes, odd passes write it back;
-    // the pass count is even for both code widths, so the sorted codes end
-    // in tree->codes; the last pass writes the permutation to leaf_perm
-    for (int p = 0; p < passes; ++p) {
-        const K *kin = (p & 1) ? keys_alt : codes;
-        K *kout = (p & 1) ? codes : keys_alt;
-        const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
-        int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
-        uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
-        prof_begin(K_SORT, s);
-        launch_onesweep<K>(sort_variant<K>(), kin, kout, vin, vout, n, p * kRadixBits,
-                           hist + p * kRadix, status[p & 1], st_next, ctrl + kCtrlTileCounter + p,
-                           ctrl + kCtrlError, s);
-        prof_end(K_SORT, s);
+    if constexpr (sizeof(K) == 4) {
+        if (bits == 10)
+            run_sort<KIND, K, 10>(prims, n, code_bits, codes, leaf_perm, scene, ctrl, hist, status,
+                                  keys_alt, vals, s);
+        else
+            run_sort<KIND, K, 8>(prims, n, code_bits, codes, leaf_perm, scene, ctrl, hist, status,
+                                 keys_alt, vals, s);
+    } else {
+        if (bits == 11)
+            run_sort<KIND, K, 11>(prims, n, code_bits, codes, leaf_perm, scene, ctrl, hist, status,
+                                  keys_alt, vals, s);
+        else if (bits == 9)
+            run_sort<KIND, K, 9>(prims, n, code_bits, codes, leaf_perm, scene, ctrl, hist, status,
+                                 keys_alt, vals, s);
+        else
+            run_sort<KIND, K, 8>(prims, n, code_bits, codes, leaf_perm, scene, ctrl, hist, status,
+                                 keys_alt, vals, s);
     }
 
     prof_begin(K_BOTTOMUP, s);

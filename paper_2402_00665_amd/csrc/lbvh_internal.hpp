@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lbvh.h"
 
 namespace lbvh {
@@ -14,9 +16,8 @@ namespace lbvh {
 // ------------------------------------------------------------ constants
 
 constexpr int kBlock = 256;           // threads per block of the simple kernels
-constexpr int kRadixBits = 8;         // digit width of the LSD radix sort
+constexpr int kRadixBits = 8;         // digit width of the query-order sort (16-bit keys)
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kMinSortTile = 2048;    // smallest radix tile (sizes the look-back buffers)
 constexpr int kBoundsBlocksMax = 1024;
 constexpr int kMortonBlocksMax = 2048;
 constexpr int kChunk = 256;           // leaves per level-0 block of the bottom-up pass
@@ -24,7 +25,6 @@ constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
 constexpr int kBUThreads = 2 * kFanout;  // one thread per handed-over climb
 constexpr int kMaxBatchLevels = 3;    // kChunk * kFanout^3 >= LBVH_MAX_PRIMS
-constexpr int kMinBatchTile = 2048;     // smallest radix tile of the batched build
 constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // default: query walks cut by aligned blocks of 2^12 leaves
 constexpr int kSplit2 = 7;            // default: ... then by blocks of 2^7 leaves
@@ -36,6 +36,11 @@ constexpr int kMaskLeaves = 256;     // widest level-2 piece that gets a leaf-hi
 constexpr int kMaskWords = kMaskLeaves / 64;
 constexpr int kScanTile = kBlock * kScanItems;
 
+// the error word of a query call: byte offset in the query workspace's ctrl
+// area (single tree and batched); nonzero after a count call means its
+// results are not to be trusted (lbvh_query_check)
+constexpr int kQueryErrorByte = 24;
+
 // ctrl words at the start of the build workspace
 constexpr int kCtrlTileCounter = 0;   // [0, 8): one per sort pass
 constexpr int kCtrlError = 8;         // non-zero: a kernel flagged an error
@@ -46,7 +51,40 @@ constexpr uint32_t kFlagAggregate = 1u << 30;
 constexpr uint32_t kFlagInclusive = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1u;
 
-inline int radix_passes(int code_bits) { return (code_bits + kRadixBits - 1) / kRadixBits; }
+// Digit widths of the build's LSD radix sort (knobs radix_bits32 and
+// radix_bits64): 8 or 10 bits for 30-bit codes, 8, 9 or 11 for 63-bit.
+// Wider digits mean fewer passes over the keys, larger per-tile digit
+// tables.  A pass's tile holds at least radix_min_tile(bits) keys, which
+// bounds the look-back tables at half a status word per key.
+inline bool radix_bits_ok(int code_bits, int bits)
+{
+    return code_bits <= 32 ? (bits == 8 || bits == 10) : (bits == 8 || bits == 9 || bits == 11);
+}
+inline int radix_passes(int code_bits, int bits) { return (code_bits + bits - 1) / bits; }
+inline int radix_min_tile(int bits) { return bits >= 11 ? 4096 : 2048; }
+// words of the digit histograms of all passes, the largest over the widths
+// a code width allows (so a workspace fits every width)
+inline int64_t radix_hist_words(int code_bits)
+{
+    int64_t w = 0;
+    for (int b = 8; b <= 11; ++b)
+        if (radix_bits_ok(code_bits, b)) w = std::max<int64_t>(w, (int64_t)radix_passes(code_bits, b) << b);
+    return w;
+}
+// words of one look-back table for `tiles(min_tile)` tiles, the largest
+// over the allowed widths; `extra_tiles` partial tiles (one per scene of a
+// batch) on top
+inline int64_t radix_status_words(int64_t n, int code_bits, int64_t extra_tiles)
+{
+    int64_t w = 0;
+    for (int b = 8; b <= 11; ++b)
+        if (radix_bits_ok(code_bits, b)) {
+            const int64_t t = (n + radix_min_tile(b) - 1) / radix_min_tile(b) + extra_tiles;
+            w = std::max<int64_t>(w, t << b);
+        }
+    return w;
+}
+int radix_bits(int code_bits);   // the knob's current width for this code width
 inline int key_bytes(int code_bits) { return code_bits <= 32 ? 4 : 8; }
 
 // --------------------------------------------------- workspace layout
@@ -55,15 +93,13 @@ struct BuildLayout {
     size_t scene;      // float4 lo, hi, scale (48 B)
     size_t partials;   // kBoundsBlocksMax x 8 floats
     size_t ctrl;       // kCtrlWords uint32
-    size_t hist;       // passes x kRadix uint32 (global digit counts)
-    size_t status[2];  // ntiles x kRadix uint32 each (ping-pong look-back)
+    size_t hist;       // radix_hist_words uint32 (global digit counts of every pass)
+    size_t status[2];  // radix_status_words uint32 each (ping-pong look-back)
     size_t keys_alt;   // n keys (sort ping-pong partner of tree->codes)
     size_t vals[2];    // n int32 each (sort values: input indices)
     size_t store;      // n int32 (Alg. 4 arrival flags / parked range ends)
     size_t pend[2];    // handed-over climb states between bottom-up levels (int4)
     size_t total;
-    int passes;
-    int64_t ntiles;
 };
 
 BuildLayout build_layout(int64_t n, int code_bits);
@@ -84,7 +120,7 @@ struct QueryLayout {
     size_t hcache;     // batched: m x 64 int32, each query's first hits
     size_t hoff;       // cap2+1 int64
     size_t partials;   // scan tile sums
-    size_t ctrl;       // overflow flags, piece counts, query-order flag and sort counters
+    size_t ctrl;       // overflow flags, piece counts, query-order flag, sort counters, error word
     // query order (single tree): the reordered copy of the queries, each
     // reordered position's caller index, and the offsets in reordered order
     size_t qsorted;    // m x 6 float
@@ -106,16 +142,14 @@ struct BatchLayout {
     size_t scene_box;  // S x 3 float4 (lo, hi, scale)
     size_t tile_off;   // S+1 int32
     size_t blk_off;    // (levels+1) x (S+1) int32
-    size_t hist;       // S x passes x kRadix uint32
-    size_t status[2];  // tiles_max x kRadix uint32
+    size_t hist;       // S x radix_hist_words uint32
+    size_t status[2];  // radix_status_words(N, bits, S) uint32 each
     size_t keys_alt;   // N keys
     size_t vals[2];    // N int32
     size_t store;      // N int32
     size_t pend[2];    // 2 x blocks_max[0] int4
     size_t total;
-    int passes;
     int levels;
-    int64_t tiles_max;                       // upper bound of radix tiles
     int64_t blocks_max[kMaxBatchLevels + 1]; // upper bound of bottom-up blocks per level
 };
 
@@ -127,6 +161,7 @@ int batch_levels(int64_t max_scene);
 
 enum TuneKnob {
     TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_QORDER,
+    TUNE_RADIX_BITS32, TUNE_RADIX_BITS64, TUNE_QBUDGET,
     TUNE_NUM
 };
 int64_t tune_get(int knob);

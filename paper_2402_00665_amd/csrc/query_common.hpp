@@ -69,10 +69,21 @@ struct QBox {
     }
 };
 
+// Error word values of a query call (the count call's workspace).
+constexpr uint32_t kQErrWalkBudget = 5;   // a walk ran out of its node-visit budget
+
 struct Tree {
     const float4 *nodes;
     const int32_t *perm;   // leaf k -> primitive
     int n;
+    uint32_t *err = nullptr;   // count calls: where a walk that ran out of budget is flagged
+    int64_t budget = 0;        // node visits allowed per walk; 0: 2n (every node once)
+    __device__ int64_t walk_budget() const { return budget > 0 ? budget : 2 * (int64_t)n; }
+    // a walk stopped with its budget spent: its count is short; report it
+    __device__ void budget_spent() const
+    {
+        if (err) __hip_atomic_store(err, kQErrWalkBudget, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ int leaf0() const { return n - 1; }
     __device__ int index(int v) const { return v >= n - 1 ? v - (n - 1) : v; }
     __device__ void load(int v, float4 &a, float4 &b) const
@@ -242,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
             q.load(queries, it.x);
             int v = it.y, i = it.z;
             const int hi = it.w;
-            int64_t budget = 2 * (int64_t)tr.n;   // a walk visits each node at most once
+            int64_t budget = tr.walk_budget();   // a walk visits each node at most once
             while (v != -1 && i < hi && --budget >= 0) {
                 float4 a, b;
                 tr.load(v, a, b);
@@ -269,6 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
                 }
                 v = __float_as_int(a.w);   // multi-block node: descend
             }
+            if (budget < 0) tr.budget_spent();
         }
         counts[t] = cnt;
     }
@@ -349,16 +361,18 @@ struct LeafMask {
 };
 
 // Alg. 1 restricted to the leaves [i, hi) from node v, by one lane: counts
-// the hits, and writes them from slot pos of out (FILL) or sets them in
-// *mask (count pass, pieces at most kMaskLeaves wide).
+// the hits, and writes them from slot pos of out (FILL; at most `limit`,
+// the count the count call found for the piece, so a fill never writes
+// past the piece's slots) or sets them in *mask (count pass, pieces at most
+// kMaskLeaves wide).
 template <class Q, bool FILL>
 __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, int32_t *out,
-                              int64_t pos, LeafMask *mask = nullptr)
+                              int64_t pos, LeafMask *mask = nullptr, int64_t limit = 0)
 {
     const int leaf0 = tr.leaf0();
     const int i0 = i;
     int64_t cnt = 0;
-    int64_t budget = 2 * (int64_t)tr.n;
+    int64_t budget = tr.walk_budget();
     while (v != -1 && i < hi && --budget >= 0) {
         float4 a, b;
         tr.load(v, a, b);
@@ -366,13 +380,16 @@ __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, 
         const int j = tr.right_bound(b);
         if (q.test(a, b)) {
             if (v >= leaf0) {
-                if (FILL) out[pos + cnt] = left;
-                else if (mask) mask->set(i - i0, i - i0 + 1);
+                if (FILL) {
+                    if (cnt < limit) out[pos + cnt] = left;
+                } else if (mask) {
+                    mask->set(i - i0, i - i0 + 1);
+                }
                 ++cnt;
             } else if (q.contains(a, b)) {
                 const int e = j + 1 < hi ? j + 1 : hi;
                 if (FILL)
-                    for (int k = i; k < e; ++k) out[pos + cnt + (k - i)] = tr.perm[k];
+                    for (int k = i; k < e && cnt + (k - i) < limit; ++k) out[pos + cnt + (k - i)] = tr.perm[k];
                 else if (mask)
                     mask->set(i - i0, e - i0);
                 cnt += e - i;
@@ -384,6 +401,7 @@ __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, 
         v = __float_as_int(b.w);
         i = j + 1;
     }
+    if (budget < 0) tr.budget_spent();
     return cnt;
 }
 
@@ -408,11 +426,12 @@ __device__ bool dense_piece(const Q &q, float4 a, float4 b)
 
 // One wave tests the leaves [lo, hi) of a piece, 64 consecutive leaf
 // records per step (two steps in flight), and returns the hit count; with
-// FILL it writes the hits from slot pos of out, else, for a piece at most
-// kMaskLeaves wide, it stores the ballots as the piece's mask.
+// FILL it writes the hits from slot pos of out (at most `limit` of them),
+// else, for a piece at most kMaskLeaves wide, it stores the ballots as the
+// piece's mask.
 template <class Q, bool FILL>
 __device__ int64_t scan_piece(const Tree &tr, const Q &q, int lo, int hi, int32_t *out, int64_t pos,
-                              uint64_t *mask)
+                              uint64_t *mask, int64_t limit = 0)
 {
     const int lane = threadIdx.x & 63;
     const bool keep = !FILL && hi - lo <= kMaskLeaves;
@@ -426,8 +445,9 @@ __device__ int64_t scan_piece(const Tree &tr, const Q &q, int lo, int hi, int32_
         const bool h2 = k2 < hi && q.test(e, f);
         const uint64_t m = __ballot(h), m2 = __ballot(h2);
         if (FILL) {
-            if (h) out[pos + c + lanes_below(m)] = __float_as_int(a.w);   // leaf: its primitive
-            if (h2) out[pos + c + __popcll(m) + lanes_below(m2)] = __float_as_int(e.w);
+            const int64_t r1 = c + lanes_below(m), r2 = c + __popcll(m) + lanes_below(m2);
+            if (h && r1 < limit) out[pos + r1] = __float_as_int(a.w);   // leaf: its primitive
+            if (h2 && r2 < limit) out[pos + r2] = __float_as_int(e.w);
         } else if (keep && lane == 0) {
             const int w = (k0 - lo) >> 6;
             mask[w] = m;
@@ -746,13 +766,14 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float 
     for (int64_t t0 = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); t0 < T; t0 += stride) {
         const int64_t t = t0 + lane;
         int4 it = make_int4(0, kAllHits, 0, 0);
-        int64_t pos = 0;
+        int64_t pos = 0, limit = 0;
         bool scan = false;
         if (t < T) {
             it = in[t];
             const int64_t h0 = hit_off[t];
             pos = h0 + (reordered ? qm.shift[it.x] : 0);
-            if (it.y != kAllHits && it.w - it.z > kMaskLeaves && hit_off[t + 1] > h0) {
+            limit = hit_off[t + 1] - h0;
+            if (it.y != kAllHits && it.w - it.z > kMaskLeaves && limit > 0) {
                 Q q;
                 q.load(queries, it.x);
                 bool walk = true;
@@ -761,7 +782,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float 
                     tr.load(it.y, a, b);
                     walk = !dense_piece(q, a, b);
                 }
-                if (walk) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos);
+                if (walk) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos, nullptr, limit);
                 else scan = true;
             }
         }
@@ -774,9 +795,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float 
             const int hi = __builtin_amdgcn_readlane(it.w, L);
             const int plo = __builtin_amdgcn_readlane((int)(pos & 0xffffffff), L);
             const int phi = __builtin_amdgcn_readlane((int)(pos >> 32), L);
+            const int64_t lim = (int64_t)shfl64((uint64_t)limit, L);
             Q q;
             q.load(queries, qi);
-            scan_piece<Q, true>(tr, q, lo, hi, out, ((int64_t)phi << 32) | (uint32_t)plo, nullptr);
+            scan_piece<Q, true>(tr, q, lo, hi, out, ((int64_t)phi << 32) | (uint32_t)plo, nullptr, lim);
         }
     }
 }
@@ -892,10 +914,13 @@ __device__ __forceinline__ HitStage wave_stage(WaveStageLds &lds, int32_t *out, 
     return HitStage{lds.hits[w], lds.jobs[w], &lds.njobs[w], out, perm, base};
 }
 
-__global__ void k_zero_i64(int64_t *p, int64_t count)
+// Offsets of a count call with nothing to walk: all zero; and the call's
+// error word cleared.
+__global__ void k_zero_i64(int64_t *p, int64_t count, uint32_t *err)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < count) p[i] = 0;
+    if (i == 0) *err = 0u;
 }
 
 // -------------------------------------------------------------- scan

@@ -131,13 +131,16 @@ __global__ __launch_bounds__(kBlock) void k_qorder_shift(const int64_t *__restri
 }
 
 // start of a count call: the split levels' append counters, the order
-// flag the fill reads, and (when reordering) the sort's tile counters and
-// histograms
+// flag the fill reads, the call's error word, and (when reordering) the
+// sort's tile counters and histograms
 __global__ void k_query_reset(unsigned long long *app_count, int32_t *order_flag, int order,
-                              uint32_t *tile_counters, uint32_t *hist)
+                              uint32_t *tile_counters, uint32_t *hist, uint32_t *err)
 {
     if (threadIdx.x < 2) app_count[threadIdx.x] = 0ull;
-    if (threadIdx.x == 0) *order_flag = order;
+    if (threadIdx.x == 0) {
+        *order_flag = order;
+        *err = 0u;
+    }
     if (order) {
         if (threadIdx.x < kQOrderPasses) tile_counters[threadIdx.x] = 0u;
         for (int j = threadIdx.x; j < kQOrderPasses * kRadix; j += blockDim.x) hist[j] = 0u;
@@ -153,7 +156,8 @@ struct Scratch {
     unsigned long long *app_count;
     uint64_t *hmask;
     int32_t *order_flag;     // nonzero: this count call reordered the queries
-    uint32_t *sort_ctr;      // the order sort's tile counters, then its error word
+    uint32_t *sort_ctr;      // the order sort's tile counters [0], [1]
+    uint32_t *err;           // the count call's error word (order sort, walk budgets)
     float *qsorted;
     int32_t *qperm;
     int64_t *qoff;
@@ -181,7 +185,8 @@ Scratch carve(char *ws, const QueryLayout &L)
     S.count = reinterpret_cast<int64_t *>(ws + L.ctrl + 64);       // [0] pieces 1, [1] pieces 2
     S.app_count = reinterpret_cast<unsigned long long *>(ws + L.ctrl + 96);   // [0] level 1, [1] level 2
     S.order_flag = reinterpret_cast<int32_t *>(ws + L.ctrl + 8);
-    S.sort_ctr = reinterpret_cast<uint32_t *>(ws + L.ctrl + 16);   // [0], [1] tiles, [2] error
+    S.sort_ctr = reinterpret_cast<uint32_t *>(ws + L.ctrl + 16);   // [0], [1] tiles
+    S.err = reinterpret_cast<uint32_t *>(ws + L.ctrl + kQueryErrorByte);
     S.qsorted = reinterpret_cast<float *>(ws + L.qsorted);
     S.qperm = reinterpret_cast<int32_t *>(ws + L.qperm);
     S.qoff = reinterpret_cast<int64_t *>(ws + L.qoff);
@@ -202,16 +207,18 @@ unsigned grid_for(int64_t items)
 }
 
 template <class Q>
-hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, char *ws,
+hipError_t run_count(Tree tr, const float *q, int m, int64_t *offsets, char *ws,
                      const QueryLayout &L, hipStream_t s)
 {
     Scratch S = carve(ws, L);
+    tr.err = S.err;
+    tr.budget = tune_get(TUNE_QBUDGET);
     const unsigned gm = grid_for(m);
     const int split1 = (int)tune_get(TUNE_QSPLIT1), split2 = (int)tune_get(TUNE_QSPLIT2);
     const bool order = tune_get(TUNE_QORDER) != 0 && m > 1;
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL(k_query_reset, dim3(1), dim3(kBlock), 0, s, S.app_count, S.order_flag,
-                       order ? 1 : 0, S.sort_ctr, S.qhist);
+                       order ? 1 : 0, S.sort_ctr, S.qhist, S.err);
     prof_end(K_QSPLIT, s);
     int64_t *const caller_offsets = offsets;
     if (order) {
@@ -223,12 +230,12 @@ hipError_t run_count(const Tree &tr, const float *q, int m, int64_t *offsets, ch
         hipLaunchKernelGGL((k_qorder_keys<Q>), dim3(gk), dim3(kBlock), 0, s, tr, q, m, S.qkeys[0],
                            S.qhist, S.qstatus[0], qtiles * kRadix);
         const SortSegs one{nullptr, nullptr, 1, 0};
-        hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4>), dim3((unsigned)qtiles), dim3(512), 0, s,
-                           S.qkeys[0], S.qkeys[1], nullptr, S.qvals, (int64_t)m, one, 0, S.qhist,
-                           S.qstatus[0], S.qstatus[1], S.sort_ctr + 0, S.sort_ctr + 2);
-        hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4>), dim3((unsigned)qtiles), dim3(512), 0, s,
-                           S.qkeys[1], S.qkeys[0], S.qvals, S.qperm, (int64_t)m, one, kRadixBits,
-                           S.qhist + kRadix, S.qstatus[1], nullptr, S.sort_ctr + 1, S.sort_ctr + 2);
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4, kRadixBits>), dim3((unsigned)qtiles), dim3(512), 0, s,
+                           S.qkeys[0], S.qkeys[1], nullptr, S.qvals, (int64_t)m, one, 0, kRadixBits, S.qhist,
+                           S.qstatus[0], S.qstatus[1], S.sort_ctr + 0, S.err);
+        hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4, kRadixBits>), dim3((unsigned)qtiles), dim3(512), 0, s,
+                           S.qkeys[1], S.qkeys[0], S.qvals, S.qperm, (int64_t)m, one, kRadixBits, kRadixBits,
+                           S.qhist + kRadix, S.qstatus[1], nullptr, S.sort_ctr + 1, S.err);
         hipLaunchKernelGGL((k_qorder_gather<Q>), dim3(gm), dim3(kBlock), 0, s, q, S.qperm, m,
                            S.qsorted);
         prof_end(K_QORDER, s);
@@ -326,7 +333,7 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_p
         if (fill) return hipSuccess;
         const int64_t cnt = (int64_t)m + 1;
         hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           s, offsets, cnt);
+                           s, offsets, cnt, reinterpret_cast<uint32_t *>(ws + L.ctrl + kQueryErrorByte));
         return hipGetLastError();
     }
     Tree tr{reinterpret_cast<const float4 *>(nodes), leaf_perm, n};

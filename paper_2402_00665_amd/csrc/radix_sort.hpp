@@ -1,5 +1,5 @@
-// LSD radix pass (onesweep) over one 8-bit digit, for one key array or for
-// many independent segments of it (batched scenes).
+// LSD radix pass (onesweep) over one BITS-wide digit, for one key array or
+// for many independent segments of it (batched scenes).
 //
 // A block takes the next tile id from a counter (so every tile it waits for
 // is already running), ranks its THREADS*ITEMS keys stably with wave64
@@ -10,8 +10,16 @@
 // s, and the first tile of a segment starts its running totals at zero.  A
 // segment that fits one tile needs no histogram; otherwise `hist` holds the
 // segment's digit counts for this pass (written by the Morton kernel).
+//
+// Digit tables: with R = 2^BITS digits and THREADS threads, thread t owns
+// the DPT = ceil(R/THREADS) consecutive digits from t*DPT that are below R.
+// The per-wave digit counters are 32 bits wide up to 9-bit digits and 16
+// bits wide above (a tile holds fewer than 2^16 keys), so an 11-bit digit
+// costs 4 KiB of LDS per wave.
 #pragma once
 #pragma clang fp contract(off)
+
+#include <type_traits>
 
 #include "device_common.hpp"
 
@@ -22,7 +30,7 @@ struct SortSegs {
     const int64_t *seg_off;   // [S+1] segment starts; nullptr: one segment [0, n)
     const int32_t *tile_off;  // [S+1] first tile of each segment
     int S;
-    int hist_stride;          // words between consecutive segments' histograms
+    int64_t hist_stride;      // words between consecutive segments' histograms
 };
 
 __device__ __forceinline__ int upper_segment(const int32_t *off, int S, uint32_t x)
@@ -37,26 +45,50 @@ __device__ __forceinline__ int upper_segment(const int32_t *off, int S, uint32_t
     return lo;
 }
 
-template <typename K, int THREADS, int ITEMS>
+// Exclusive scan over the block of each thread's DPT values, in thread
+// order then item order (the digits a thread owns are consecutive).
+template <int THREADS, int DPT>
+__device__ __forceinline__ void digits_excl_scan(const uint32_t (&v)[DPT], uint32_t (&out)[DPT],
+                                                 uint32_t *sh /* [THREADS/64] */)
+{
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) sum += v[k];
+    uint32_t run = block_excl_scan<THREADS>(sum, sh);
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+        out[k] = run;
+        run += v[k];
+    }
+}
+
+// One pass over digit `shift .. shift+nbits` (nbits <= BITS: the last digit
+// of a code can be narrower).
+template <typename K, int THREADS, int ITEMS, int BITS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, const int32_t *__restrict__ vals_in,
-    int32_t *__restrict__ vals_out, int64_t n, SortSegs seg, int shift,
+    int32_t *__restrict__ vals_out, int64_t n, SortSegs seg, int shift, int nbits,
     const uint32_t *__restrict__ hist, uint32_t *status, uint32_t *__restrict__ status_next,
     uint32_t *tile_counter, uint32_t *err)
 {
-    static_assert(THREADS >= kRadix && THREADS % 64 == 0, "one thread per digit");
+    constexpr int R = 1 << BITS;
     constexpr int W = THREADS / 64;
     constexpr int TILE = THREADS * ITEMS;
+    constexpr int DPT = (R + THREADS - 1) / THREADS;   // digits per owning thread
+    static_assert(THREADS % 64 == 0, "whole waves");
+    static_assert(TILE < 65536, "16-bit per-wave digit counters");
+    using Cnt = typename std::conditional<(BITS <= 9), uint32_t, uint16_t>::type;
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_wcnt[W][kRadix];
-    __shared__ uint32_t s_start[kRadix];     // tile-local start of each digit run
-    __shared__ uint32_t s_gbase[kRadix];     // segment-local position of that run
+    __shared__ __align__(16) Cnt s_wcnt[W][R];   // per-wave digit counts, then exclusive offsets
+    __shared__ uint32_t s_start[R];          // tile-local start of each digit run
+    __shared__ uint32_t s_gbase[R];          // segment-local position of that run
     __shared__ uint32_t s_scan[2][W];
     __shared__ K s_buf[TILE];                // keys, then values
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (int j = tid; j < W * kRadix; j += THREADS) (&s_wcnt[0][0])[j] = 0u;
+    constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
+    for (int j = tid; j < kZeroWords; j += THREADS) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
     __syncthreads();
     const uint32_t tile = s_tile;
 
@@ -74,7 +106,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
     const uint32_t lt = tile - t0;           // tile index within the segment
     const int64_t base = (int64_t)lt * TILE; // segment-local
-    if (status_next && tid < kRadix) status_next[(int64_t)tile * kRadix + tid] = 0u;
+    if (status_next)
+        for (int d = tid; d < R; d += THREADS) status_next[(int64_t)tile * R + d] = 0u;
 
     // wave w owns keys [base + w*64*ITEMS, ...); item k of lane l is key
     // base + w*64*ITEMS + k*64 + l, so (item, lane) order is input order
@@ -95,80 +128,118 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
 
     // stable rank within the wave: lanes holding the same digit find each
-    // other with 8 ballots; the lowest of them advances the wave's counter
+    // other with one ballot per digit bit; the lowest of them advances the
+    // wave's counter
     uint32_t rank[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const bool ok = lofs + k * 64 < rem;
-        const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+        const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
         // lanes whose digit differs from this lane's in some bit: for each
         // bit, the ballot of lanes that have it, flipped where this lane has
-        // it (a sign-extended bit as the xor mask)
+        // it (a sign-extended bit as the xor mask); bits at or above nbits
+        // are zero in every key
         uint64_t diff = 0;
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
-            diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
+        for (int b = 0; b < BITS; ++b) {
+            if (b < nbits) {
+                const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
+                diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
+            }
         }
         const uint64_t peers = __ballot(ok) & ~diff;
         const uint32_t below = count_below(peers);
         const uint32_t cnt = s_wcnt[wave][d];
         rank[k] = cnt + below;
-        if (ok && below == 0) s_wcnt[wave][d] = cnt + (uint32_t)__popcll(peers);
+        if (ok && below == 0) s_wcnt[wave][d] = (Cnt)(cnt + (uint32_t)__popcll(peers));
     }
     __syncthreads();
 
-    // threads d < 256: per-wave exclusive offsets of digit d and the total
-    const uint32_t d = tid;
-    uint32_t total = 0;
-    if (tid < kRadix) {
-        uint32_t c[W];
+    // owning threads: per-wave exclusive offsets of their digits and the
+    // tile's totals, published for later tiles
+    const int d0 = tid * DPT;
+    const bool owner = d0 < R;
+    auto owns = [&](int k) { return d0 + k < R; };
+    uint32_t total[DPT];
 #pragma unroll
-        for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
+    for (int k = 0; k < DPT; ++k) {
+        total[k] = 0;
+        if (owns(k)) {
+            const int d = d0 + k;
+            uint32_t c[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) { s_wcnt[w][d] = total; total += c[w]; }
-        if (nt > 1)
-            __hip_atomic_store(status + (int64_t)tile * kRadix + d,
-                               (lt == 0 ? kFlagInclusive : kFlagAggregate) | total,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
+#pragma unroll
+            for (int w = 0; w < W; ++w) { s_wcnt[w][d] = (Cnt)total[k]; total[k] += c[w]; }
+            if (nt > 1)
+                __hip_atomic_store(status + (int64_t)tile * R + d,
+                                   (lt == 0 ? kFlagInclusive : kFlagAggregate) | total[k],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
-    const uint32_t start = block_excl_scan<THREADS>(tid < kRadix ? total : 0u, s_scan[0]);
+    uint32_t start[DPT], hoff[DPT], hv[DPT];
+    digits_excl_scan<THREADS, DPT>(total, start, s_scan[0]);
     const uint32_t *hs = hist + (int64_t)s * seg.hist_stride;
-    const uint32_t hoff =
-        block_excl_scan<THREADS>((tid < kRadix && nt > 1) ? hs[d] : 0u, s_scan[1]);
-    if (tid < kRadix) {
-        s_start[d] = start;
-        uint32_t excl = 0;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) hv[k] = (owns(k) && nt > 1) ? hs[d0 + k] : 0u;
+    digits_excl_scan<THREADS, DPT>(hv, hoff, s_scan[1]);
+    if (owner) {
+        // decoupled look-back, all of this thread's digits in flight together
+        uint32_t excl[DPT];
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) excl[k] = 0;
         if (nt > 1 && lt > 0) {
-            int64_t j = (int64_t)tile - 1;
+            int64_t j[DPT];
+            bool done[DPT];
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) { j[k] = (int64_t)tile - 1; done[k] = !owns(k); }
             uint32_t spins = 0;
             while (true) {
-                const uint32_t sv = __hip_atomic_load(status + j * kRadix + d, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t flag = sv & ~kValueMask;
-                if (flag == 0u) {
+                uint32_t sv[DPT];
+#pragma unroll
+                for (int k = 0; k < DPT; ++k)
+                    sv[k] = done[k] ? 0u
+                                    : __hip_atomic_load(status + j[k] * R + d0 + k, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                bool all = true, waiting = false;
+#pragma unroll
+                for (int k = 0; k < DPT; ++k) {
+                    if (done[k]) continue;
+                    const uint32_t flag = sv[k] & ~kValueMask;
+                    if (flag == 0u) { waiting = true; all = false; continue; }
+                    excl[k] += sv[k] & kValueMask;
+                    if (flag == kFlagInclusive || j[k] == (int64_t)t0) done[k] = true;
+                    else { --j[k]; all = false; }
+                }
+                if (all) break;
+                if (waiting) {
                     if (++spins > (1u << 24)) {   // never expected: bounded wait
                         __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += sv & kValueMask;
-                if (flag == kFlagInclusive || j == (int64_t)t0) break;
-                --j;
             }
-            __hip_atomic_store(status + (int64_t)tile * kRadix + d, kFlagInclusive | (excl + total),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (owns(k))
+                    __hip_atomic_store(status + (int64_t)tile * R + d0 + k,
+                                       kFlagInclusive | (excl[k] + total[k]), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_gbase[d] = (nt > 1 ? hoff : 0u) + excl + (nt > 1 ? 0u : start);
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            if (!owns(k)) continue;
+            s_start[d0 + k] = start[k];
+            s_gbase[d0 + k] = nt > 1 ? hoff[k] + excl[k] : start[k];
+        }
     }
     __syncthreads();
 
     uint32_t pos[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t dk = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+        const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
         pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
     }
     // keys: into LDS in tile-sorted order, then out in runs (segment-local
@@ -187,7 +258,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
         dst[k] = ~0u;
         if (p < rem) {
             const K kk = s_buf[p];
-            const uint32_t dk = (uint32_t)(kk >> shift) & (kRadix - 1);
+            const uint32_t dk = (uint32_t)(kk >> shift) & (R - 1);
             const uint32_t out = s_gbase[dk] + (uint32_t)p - s_start[dk];
             if (out < nsu) {
                 ko[out] = kk;

@@ -115,6 +115,18 @@ def test_tune_knobs():
         assert lb.lbvh_tune(name) == hi
         assert lb.lbvh_tune(name, old) == hi
         assert lb.lbvh_tune(name, hi + 1) == lb.LBVH_EINVAL
+    # digit widths: only the widths each code width allows
+    for name, ok in (("radix_bits32", (8, 10)), ("radix_bits64", (8, 9, 11))):
+        old = lb.lbvh_tune(name)
+        assert old in ok
+        for v in range(7, 13):
+            rc = lb.lbvh_tune(name, v)
+            if v in ok:
+                assert rc in ok
+            else:
+                assert rc == lb.LBVH_EINVAL
+        lb.lbvh_tune(name, old)
+        assert lb.lbvh_tune(name) == old
     assert lb.lbvh_tune("no_such_knob", 0) == lb.LBVH_EINVAL
 
 

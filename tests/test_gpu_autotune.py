@@ -22,7 +22,8 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     defaults = {k: lb.lbvh_tune(k) for k in autotune.KNOB_CANDIDATES}
     r = autotune.tune(p, 63, reps=3, verbose=True)
     say(f"single: {r}")
-    assert r["knob"] == "sort_variant64" and set(r["times_ms"]) == set(range(7))
+    assert set(r["knobs"]) == {"radix_bits64", "sort_variant64"}
+    assert set(r["times_ms"]) == {f"{b}/{v}" for b in (8, 9, 11) for v in range(7)}
     assert {k: lb.lbvh_tune(k) for k in defaults} == defaults   # tuning restores the defaults
     sizes = np.array([3000, 70000, 1, 0, 40000], np.int64)
     seg = np.zeros(len(sizes) + 1, np.int64)
@@ -30,13 +31,15 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     pb = torch.from_numpy(rng.random((int(seg[-1]), 3), dtype=np.float32)).cuda()
     rb = autotune.tune(pb, 30, seg_off=torch.from_numpy(seg).cuda(), max_scene=70000, reps=3)
     say(f"batched: {rb}")
-    assert rb["knob"] == "batch_sort_variant" and set(rb["times_ms"]) == set(range(4))
+    assert set(rb["knobs"]) == {"radix_bits32", "batch_sort_variant"}
+    assert set(rb["times_ms"]) == {f"{b}/{v}" for b in (8, 10) for v in range(4)}
     cache = json.loads((tmp_path / "tuning.json").read_text())
     assert len(cache) == 2
     try:
-        assert autotune.apply(1 << 18, 63, 0) == {"sort_variant64": r["value"]}
-        assert lb.lbvh_tune("sort_variant64") == r["value"]
-        assert autotune.apply(int(seg[-1]), 30, 0, batched=True) == {"batch_sort_variant": rb["value"]}
+        assert autotune.apply(1 << 18, 63, 0) == r["knobs"]
+        assert lb.lbvh_tune("sort_variant64") == r["knobs"]["sort_variant64"]
+        assert lb.lbvh_tune("radix_bits64") == r["knobs"]["radix_bits64"]
+        assert autotune.apply(int(seg[-1]), 30, 0, batched=True) == rb["knobs"]
         assert autotune.apply(1 << 10, 63, 0) == {}   # other size bucket: nothing cached
     finally:
         for k, v in defaults.items():

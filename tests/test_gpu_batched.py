@@ -241,16 +241,69 @@ def test_batched_workload_full_size():
 
 @pytest.mark.parametrize("variant", range(4))
 def test_batched_tile_variants(variant):
-    """Every segmented radix tile shape gives the same trees (tolerance 0)."""
+    """Every segmented radix tile shape, with every digit width, gives the
+    same trees (tolerance 0)."""
     import paper_2402_00665_amd as lb
-    old = lb.lbvh_tune("batch_sort_variant", variant)
+    old = {k: lb.lbvh_tune(k) for k in ("batch_sort_variant", "radix_bits32", "radix_bits64")}
+    lb.lbvh_tune("batch_sort_variant", variant)
     try:
         rng = np.random.default_rng([23, variant])
-        sizes = np.array([4097, 1, 2048, 0, 100003, 6000, 2047, 16384], np.int64)
+        sizes = np.array([4097, 1, 2048, 0, 100003, 6000, 2047, 16384, 8193, 4095], np.int64)
         seg = np.zeros(len(sizes) + 1, np.int64)
         np.cumsum(sizes, out=seg[1:])
         pts = rng.random((int(seg[-1]), 3), dtype=np.float32)
-        for bits in (30, 63):
-            batched_parity(pts, seg, bits, 0)
+        for b32, b64 in ((8, 8), (10, 9), (10, 11)):
+            lb.lbvh_tune("radix_bits32", b32)
+            lb.lbvh_tune("radix_bits64", b64)
+            for bits in (30, 63):
+                say(f"  batched digits {b32 if bits == 30 else b64} bits")
+                batched_parity(pts, seg, bits, 0)
     finally:
-        lb.lbvh_tune("batch_sort_variant", old)
+        for k, v in old.items():
+            lb.lbvh_tune(k, v)
+
+
+def test_batched_query_error_word():
+    """The batched count call clears its error word; a capped walk budget is
+    reported, and the fill stays inside the counted slots."""
+    import torch
+    import paper_2402_00665_amd as lb
+    rng = np.random.default_rng(77)
+    sizes = np.array([5000, 300, 70000, 1], np.int64)
+    seg = np.zeros(len(sizes) + 1, np.int64)
+    np.cumsum(sizes, out=seg[1:])
+    pts = torch.from_numpy(rng.random((int(seg[-1]), 3), dtype=np.float32)).cuda()
+    dseg = torch.from_numpy(seg).cuda()
+    b = lb.build_batched(pts, dseg, 63, int(sizes.max()))
+    lb.check_batched(b)
+    qn = np.array([100, 100, 100, 100], np.int64)
+    qseg = np.zeros(5, np.int64)
+    np.cumsum(qn, out=qseg[1:])
+    q = np.empty((400, 4), np.float32)
+    q[:, :3] = rng.random((400, 3), dtype=np.float32)
+    q[:, 3] = 0.2
+    dq, dqs = torch.from_numpy(q).cuda(), torch.from_numpy(qseg).cuda()
+    qws = lb.Workspace()
+    old = lb.lbvh_tune("query_walk_budget")
+    try:
+        off, idx = lb.query_batched(b, dq, dqs, 0, workspace=qws)
+        lb.check_query(qws, 400, batched=True)
+        lb.lbvh_tune("query_walk_budget", 5)
+        off = lb.query_batched_count(b, dq, dqs, 0, qws)
+        with pytest.raises(lb.LbvhError) as e:
+            lb.check_query(qws, 400, batched=True)
+        assert e.value.status == lb.LBVH_EDEVICE
+        total = int(off[-1].item())
+        buf = torch.full((total + 4096,), -7, dtype=torch.int32, device="cuda")
+        lb.query_batched_fill(b, dq, dqs, 0, off, buf, qws)
+        torch.cuda.synchronize()
+        assert bool((buf[total:] == -7).all()), "fill wrote past the counted hits"
+        lb.lbvh_tune("query_walk_budget", 0)
+        off2, idx2 = lb.query_batched(b, dq, dqs, 0, workspace=qws)
+        lb.check_query(qws, 400, batched=True)
+        # uncapped again: the same answers as the first clean call
+        first_off, first_idx = lb.query_batched(b, dq, dqs, 0)
+        assert torch.equal(off2, first_off) and torch.equal(idx2, first_idx)
+        assert torch.equal(idx2, idx)
+    finally:
+        lb.lbvh_tune("query_walk_budget", old)

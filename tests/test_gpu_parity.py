@@ -163,18 +163,19 @@ def test_full_size_autotuned(name, ws):
     from paper_2402_00665_amd import autotune
     w = workloads.by_name(name)
     knobs = ("sort_variant32", "sort_variant64", "query_split1", "query_split2", "query_leaf_mode",
-             "query_order")
+             "query_order", "radix_bits32", "radix_bits64")
     old = {k: lb.lbvh_tune(k) for k in knobs}
     try:
         p = torch.from_numpy(w.prims).cuda()
         t = autotune.tune(p, w.code_bits, kind=w.kind, reps=2, save=False)
-        lb.lbvh_tune(t["knob"], t["value"])
+        for k, v in t["knobs"].items():
+            lb.lbvh_tune(k, v)
         tree = lb.build(p, w.code_bits, kind=w.kind)
         tq = autotune.tune_query(tree, torch.from_numpy(w.queries).cuda(), w.qkind, reps=1,
                                  save=False)
-        for k, v in zip(knobs[2:], tq["value"]):
+        for k, v in zip(knobs[2:6], tq["value"]):
             lb.lbvh_tune(k, v)
-        say(f"full-size {name}, tuned: {t['knob']}={t['value']} query={tq['value']}")
+        say(f"full-size {name}, tuned: {t['knobs']} query={tq['value']}")
         del tree, p
         _parity(w, ws)
     finally:
@@ -225,20 +226,51 @@ def test_piece_capacity_overflow_passes_through(ws):
 
 @pytest.mark.parametrize("variant", range(7))
 def test_sort_tile_variants(variant, ws):
-    """Every radix-pass tile shape gives the same tree (tolerance 0)."""
+    """Every radix-pass tile shape, with every digit width (8 or 10 bits for
+    30-bit codes, 8, 9 or 11 for 63-bit), gives the same tree (tolerance 0).
+    Sizes span one tile, several tiles with a ragged tail, and odd and even
+    pass counts."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng([18, variant])
-    old32 = lb.lbvh_tune("sort_variant32", variant)
-    old64 = lb.lbvh_tune("sort_variant64", variant)
+    old = {k: lb.lbvh_tune(k) for k in ("sort_variant32", "sort_variant64", "radix_bits32",
+                                        "radix_bits64")}
+    lb.lbvh_tune("sort_variant32", variant)
+    lb.lbvh_tune("sort_variant64", variant)
     try:
-        for n, bits in [(100003, 30), (100003, 63), (4097, 30), (300, 63), (1 << 18, 30)]:
-            p = rng.random((n, 3), dtype=np.float32)
-            ref = oracle.build(0, p, bits)
-            tree, _ = gpu_build(p, 0, bits, ws)
-            assert_tree_equal(tree, ref)
+        cases = [(100003, 30), (100003, 63), (4097, 30), (300, 63), (1 << 18, 30), (40000, 63)]
+        pts = {n: rng.random((n, 3), dtype=np.float32) for n, _ in cases}
+        refs = {(n, b): oracle.build(0, pts[n], b) for n, b in cases}
+        for b32, b64 in ((8, 8), (10, 9), (10, 11)):
+            lb.lbvh_tune("radix_bits32", b32)
+            lb.lbvh_tune("radix_bits64", b64)
+            for n, bits in cases:
+                say(f"  digits {b32 if bits == 30 else b64} bits")
+                tree, _ = gpu_build(pts[n], 0, bits, ws)
+                assert_tree_equal(tree, refs[(n, bits)])
     finally:
-        lb.lbvh_tune("sort_variant32", old32)
-        lb.lbvh_tune("sort_variant64", old64)
+        for k, v in old.items():
+            lb.lbvh_tune(k, v)
+
+
+def test_sort_digit_widths_duplicates_and_clusters(ws):
+    """Clustered boxes with heavy duplicate codes and all-equal codes sort
+    stably under every digit width."""
+    import paper_2402_00665_amd as lb
+    old = {k: lb.lbvh_tune(k) for k in ("radix_bits32", "radix_bits64")}
+    try:
+        rng = workloads._rng(3, 0)
+        boxes = workloads.clustered_boxes(150000, rng)
+        same = np.repeat(rng.random((1, 3), dtype=np.float32), 9000, axis=0)
+        refs = {(k, b): oracle.build(k, p, b) for k, p in ((1, boxes), (0, same)) for b in (30, 63)}
+        for b32, b64 in ((8, 8), (10, 9), (10, 11)):
+            lb.lbvh_tune("radix_bits32", b32)
+            lb.lbvh_tune("radix_bits64", b64)
+            for (k, b), ref in refs.items():
+                tree, _ = gpu_build(boxes if k == 1 else same, k, b, ws)
+                assert_tree_equal(tree, ref)
+    finally:
+        for k, v in old.items():
+            lb.lbvh_tune(k, v)
 
 
 @pytest.mark.parametrize("split1,split2,leaf_mode,order", [
@@ -426,3 +458,49 @@ def _graph_capture_single_tree():
         x = torch.rand(1000, device="cuda").sum()   # eager work between replays
         x.item()
     lb.check_build(tree)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_query_error_word(order, ws):
+    """A count call clears its error word (lbvh_query_check is OK after a
+    clean call, also after a flagged one); a walk budget capped from the
+    host (knob query_walk_budget) is reported as LBVH_EDEVICE, and the fill
+    that follows still writes only inside the counted slots."""
+    import torch
+    import paper_2402_00665_amd as lb
+    w = workloads.by_name("clustered_boxes", 1 / 256)
+    ref = oracle.build(w.kind, w.prims, w.code_bits)
+    tree, _ = gpu_build(w.prims, w.kind, w.code_bits, ws)
+    q = torch.from_numpy(w.queries[:20000]).cuda()
+    qws = lb.Workspace()
+    old = {k: lb.lbvh_tune(k) for k in ("query_order", "query_walk_budget")}
+    lb.lbvh_tune("query_order", order)
+    try:
+        off = lb.query_count(tree, q, w.qkind, qws)
+        lb.check_query(qws, q.shape[0])
+        say("  capped walk budget: expect the error word")
+        lb.lbvh_tune("query_walk_budget", 3)
+        off = lb.query_count(tree, q, w.qkind, qws)
+        with pytest.raises(lb.LbvhError) as e:
+            lb.check_query(qws, q.shape[0])
+        assert e.value.status == lb.LBVH_EDEVICE
+        total = int(off[-1].item())
+        guard = 4096
+        buf = torch.full((total + guard,), -7, dtype=torch.int32, device="cuda")
+        lb.query_fill(tree, q, w.qkind, buf, qws)
+        torch.cuda.synchronize()
+        assert bool((buf[total:] == -7).all()), "fill wrote past the counted hits"
+        lb.lbvh_tune("query_walk_budget", 0)
+        roff, ridx, _ = oracle.query_traverse(w.qkind, w.queries[:20000], ref)
+        off2, idx2 = lb.query(tree, q, w.qkind, workspace=qws)
+        lb.check_query(qws, q.shape[0])
+        assert_query_equal(off2.cpu().numpy(), idx2.cpu().numpy(), roff, ridx)
+        # an empty query set clears the word too
+        lb.lbvh_tune("query_walk_budget", 3)
+        lb.query_count(tree, q, w.qkind, qws)
+        lb.lbvh_tune("query_walk_budget", 0)
+        lb.query_count(tree, q[:0], w.qkind, qws)
+        lb.check_query(qws, 0)
+    finally:
+        for k, v in old.items():
+            lb.lbvh_tune(k, v)
