@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liblbvh_oracle.so")
 
 POINTS, BOXES = 0, 1
-SPHERES, QBOXES = 0, 1
+SPHERES, QBOXES, RAYS = 0, 1, 2
 
 _lib = None
 
@@ -52,6 +52,10 @@ def _load():
         lib.orc_query_traverse.argtypes = [i32, P, i64, i64, P, P, P, P, P, P]
         lib.orc_query_traverse.restype = i64
         lib.orc_query_fill.argtypes = [i32, P, i64, i64, P, P, P, P, P, P]
+        lib.orc_pred_ray.argtypes = [P, P, P]
+        lib.orc_ray_first_brute.argtypes = [P, i64, i32, P, P, i64, P]
+        lib.orc_ray_first_brute.restype = C.c_int32
+        lib.orc_ray_first_traverse.argtypes = [P, i64, i64, P, P, P, P, P, P, P]
         lib.orc_threads.argtypes = [i32]
         lib.orc_threads.restype = None
         lib.orc_threads(1)
@@ -206,10 +210,23 @@ def pred_box(box, q) -> bool:
     return bool(_load().orc_pred_box(_p(box), _p(q)))
 
 
+def _qwidth(qkind: int) -> int:
+    return {SPHERES: 4, QBOXES: 6, RAYS: 8}[qkind]
+
+
+def pred_ray(box, q):
+    """Ray / segment q = (o.xyz, tmin, d.xyz, tmax) against a box:
+    (hit, entry parameter or None)."""
+    box = np.ascontiguousarray(box, np.float32); q = np.ascontiguousarray(q, np.float32)
+    e = np.zeros(1, np.float32)
+    hit = bool(_load().orc_pred_ray(_p(box), _p(q), _p(e)))
+    return hit, (float(e[0]) if hit else None)
+
+
 def query_brute(qkind: int, queries: np.ndarray, j: int, kind: int, prims: np.ndarray,
                 perm: np.ndarray) -> np.ndarray:
     """All primitives satisfying query j's predicate, in ascending leaf order."""
-    queries = _f32(queries, 4 if qkind == SPHERES else 6)
+    queries = _f32(queries, _qwidth(qkind))
     prims = _f32(prims, _kind_width(kind))
     perm = np.ascontiguousarray(perm, np.int32)
     n = prims.shape[0]
@@ -221,7 +238,7 @@ def query_brute(qkind: int, queries: np.ndarray, j: int, kind: int, prims: np.nd
 def query_traverse(qkind: int, queries: np.ndarray, tree: Tree):
     """Alg. 1 on the oracle tree for every query: (offsets[m+1] int64,
     indices int32 in traversal order, total node visits)."""
-    queries = _f32(queries, 4 if qkind == SPHERES else 6)
+    queries = _f32(queries, _qwidth(qkind))
     m = queries.shape[0]
     lib = _load()
     offsets = np.zeros(m + 1, np.int64)
@@ -232,6 +249,30 @@ def query_traverse(qkind: int, queries: np.ndarray, tree: Tree):
     lib.orc_query_fill(qkind, _p(queries), m, tree.n, _p(tree.left), _p(tree.rope),
                        _p(tree.aabb), _p(tree.perm), _p(offsets), _p(idx))
     return offsets, idx[:total].copy(), int(vis[0])
+
+
+def ray_first_brute(rays: np.ndarray, j: int, kind: int, prims: np.ndarray, perm: np.ndarray):
+    """First hit of ray j by brute force over all primitives in leaf order:
+    (primitive id or -1, entry parameter; +inf if none)."""
+    rays = _f32(rays, 8)
+    prims = _f32(prims, _kind_width(kind))
+    perm = np.ascontiguousarray(perm, np.int32)
+    t = np.zeros(1, np.float32)
+    h = _load().orc_ray_first_brute(_p(rays), j, kind, _p(prims), _p(perm), prims.shape[0], _p(t))
+    return int(h), float(t[0])
+
+
+def ray_first_traverse(rays: np.ndarray, tree: Tree):
+    """First hit of every ray by Alg. 1 with pruning on the oracle tree:
+    (hit int32 [m] primitive or -1, t float32 [m], total node visits)."""
+    rays = _f32(rays, 8)
+    m = rays.shape[0]
+    hit = np.zeros(m, np.int32)
+    t = np.zeros(m, np.float32)
+    vis = np.zeros(1, np.int64)
+    _load().orc_ray_first_traverse(_p(rays), m, tree.n, _p(tree.left), _p(tree.rope),
+                                   _p(tree.aabb), _p(tree.perm), _p(hit), _p(t), _p(vis))
+    return hit, t, int(vis[0])
 
 
 def threads(t: int):

@@ -49,7 +49,18 @@
  *   - Sphere predicate: per axis d = max(max(lo - c, c - hi), 0);
  *     hit iff (dx*dx + dy*dy) + dz*dz <= r*r.  Box predicate: closed-interval
  *     overlap on every axis.
+ *   - Ray / segment predicate (Sec. 1 names the primitives a ray meets as a
+ *     range search): a query is o.xyz, tmin, d.xyz, tmax, the points
+ *     o + t*d with tmin <= t <= tmax (a segment from a to b is o = a,
+ *     d = b - a, [0, 1]; a ray has tmax = +inf).  Closed slab test in
+ *     binary32: per axis, inv = 1/d (correctly rounded); if d = 0 or inv
+ *     overflows, the axis passes iff lo <= o <= hi; else t1 = (lo - o)*inv,
+ *     t2 = (hi - o)*inv.  enter = max(tmin, min(t1,t2) of each axis),
+ *     exit = min(tmax, max(t1,t2) of each axis), hit iff enter <= exit.
+ *     First hit of a ray: among the primitives it meets, the smallest
+ *     enter, ties to the smallest leaf position (Morton order).
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -62,6 +73,7 @@
 #define ORC_BOXES 1
 #define ORC_SPHERES 0
 #define ORC_QBOXES 1
+#define ORC_RAYS 2
 
 /* ---------------------------------------------------------------- boxes */
 
@@ -364,10 +376,40 @@ int orc_pred_box(const float box[6], const float q[6])
     return 1;
 }
 
+/* Ray / segment q = (o.xyz, tmin, d.xyz, tmax) against a box: 1 if some
+ * t in [tmin, tmax] has o + t*d in the closed box; then *enter (if
+ * non-NULL) receives the entry parameter, the largest lower end of the
+ * per-axis slab intervals and tmin. */
+int orc_pred_ray(const float box[6], const float q[8], float *enter)
+{
+    float t_in = q[3], t_out = q[7];
+    for (int a = 0; a < 3; ++a) {
+        const float o = q[a], d = q[4 + a];
+        const float inv = 1.0f / d;
+        if (d == 0.0f || inv == INFINITY || inv == -INFINITY) {
+            /* parallel to the slab: in it for every t, or never */
+            if (!(box[a] <= o && o <= box[3 + a])) return 0;
+            continue;
+        }
+        const float t1 = (box[a] - o) * inv;
+        const float t2 = (box[3 + a] - o) * inv;
+        const float near_ = t1 < t2 ? t1 : t2;
+        const float far_ = t1 < t2 ? t2 : t1;
+        if (near_ > t_in) t_in = near_;
+        if (far_ < t_out) t_out = far_;
+    }
+    if (!(t_in <= t_out)) return 0;
+    if (enter) *enter = t_in;
+    return 1;
+}
+
 static int pred(int qkind, const float *box, const float *q)
 {
+    if (qkind == ORC_RAYS) return orc_pred_ray(box, q, NULL);
     return qkind == ORC_SPHERES ? orc_pred_sphere(box, q) : orc_pred_box(box, q);
 }
+
+static int query_width(int qkind) { return qkind == ORC_SPHERES ? 4 : (qkind == ORC_QBOXES ? 6 : 8); }
 
 /* Brute force for query j: every primitive whose box satisfies the
  * predicate, listed in ascending leaf position (perm is the sorted order).
@@ -376,7 +418,7 @@ int64_t orc_query_brute(int qkind, const float *queries, int64_t j, int kind,
                         const float *prims, const int32_t *perm, int64_t n,
                         int32_t *out, int64_t cap)
 {
-    int qw = qkind == ORC_SPHERES ? 4 : 6;
+    int qw = query_width(qkind);
     const float *q = queries + qw * j;
     float box[6];
     int64_t h = 0;
@@ -430,7 +472,7 @@ int64_t orc_query_traverse(int qkind, const float *queries, int64_t m, int64_t n
                            const float *aabb, const int32_t *perm,
                            int64_t *offsets, int64_t *visits)
 {
-    int qw = qkind == ORC_SPHERES ? 4 : 6;
+    int qw = query_width(qkind);
     int64_t nvis = 0;
     offsets[0] = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : nvis)
@@ -451,11 +493,85 @@ int orc_query_fill(int qkind, const float *queries, int64_t m, int64_t n,
                    const int32_t *left, const int32_t *rope, const float *aabb,
                    const int32_t *perm, const int64_t *offsets, int32_t *indices)
 {
-    int qw = qkind == ORC_SPHERES ? 4 : 6;
+    int qw = query_width(qkind);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t j = 0; j < m; ++j) {
         int64_t v = 0;
         walk_one(qkind, queries + qw * j, n, left, rope, aabb, perm, indices + offsets[j], &v);
     }
+    return 0;
+}
+
+/* ------------------------------------------------------ first hit (rays) */
+
+/* First hit of ray j by brute force: every primitive in ascending leaf
+ * position; keep the one with the smallest entry parameter (a later leaf
+ * replaces it only if strictly smaller).  Returns the primitive id or -1;
+ * *t receives its entry parameter (+inf if none). */
+int32_t orc_ray_first_brute(const float *rays, int64_t j, int kind, const float *prims,
+                            const int32_t *perm, int64_t n, float *t)
+{
+    const float *q = rays + 8 * j;
+    float box[6], best = INFINITY, e;
+    int32_t hit = -1;
+    for (int64_t k = 0; k < n; ++k) {
+        prim_box(kind, prims, perm[k], box);
+        if (orc_pred_ray(box, q, &e) && (hit < 0 || e < best)) {
+            hit = perm[k];
+            best = e;
+        }
+    }
+    *t = best;
+    return hit;
+}
+
+/* First hit of one ray with Alg. 1 and pruning: a node is entered only if
+ * the ray meets its box with an entry parameter below the best hit found
+ * so far (any entry while none is found).  Boxes of a subtree contain the
+ * boxes below them, so a pruned subtree holds no leaf that would win, and
+ * Alg. 1 reaches leaves in ascending position, so on equal entries the
+ * first leaf found stays. */
+static int32_t first_walk(const float *q, int64_t n, const int32_t *left, const int32_t *rope,
+                          const float *aabb, const int32_t *perm, float *t, int64_t *visits)
+{
+    int64_t ni = n - 1, nvis = 0;
+    int32_t hit = -1;
+    float best = INFINITY, e;
+    if (n > 0) {
+        int32_t node = 0;
+        do {
+            ++nvis;
+            if (orc_pred_ray(aabb + 6 * (int64_t)node, q, &e) && (hit < 0 || e < best)) {
+                if (node >= ni) {
+                    hit = perm[node - ni];
+                    best = e;
+                    node = rope[node];
+                } else {
+                    node = left[node];
+                }
+            } else {
+                node = rope[node];
+            }
+        } while (node != -1);
+    }
+    *t = best;
+    *visits += nvis;
+    return hit;
+}
+
+/* First hits of rays [0, m) on the oracle tree: hit[j] (primitive or -1),
+ * t[j]; visits, if non-NULL, the total node visits.  One walk per ray. */
+int orc_ray_first_traverse(const float *rays, int64_t m, int64_t n, const int32_t *left,
+                           const int32_t *rope, const float *aabb, const int32_t *perm,
+                           int32_t *hit, float *t, int64_t *visits)
+{
+    int64_t nvis = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nvis)
+    for (int64_t j = 0; j < m; ++j) {
+        int64_t v = 0;
+        hit[j] = first_walk(rays + 8 * j, n, left, rope, aabb, perm, t + j, &v);
+        nvis += v;
+    }
+    if (visits) *visits = nvis;
     return 0;
 }
