@@ -13,6 +13,10 @@ answer of m sphere queries against it.  The loop
     formed while others run overlap on the device;
   * keeps finished trees resident (least recently finished evicted first
     when admission needs the memory) so they can be queried again;
+  * keeps each finished batch's results (CSR offsets and indices, on the
+    device) with its tree, counted in the budget and evicted with it, or
+    hands them to an ``on_done`` callback as each request finishes and
+    drops them (``keep_results=False``);
   * reports every request's latency (completion - arrival), hits, status.
 
 The executor does the work; ``GpuExecutor`` drives the batched entry points
@@ -81,7 +85,8 @@ class Response:
 
     def csr(self):
         """(offsets [m+1] from 0, indices [hits]) of this request, as the
-        executor's arrays (device tensors for the GPU executors)."""
+        executor's arrays (device tensors for the GPU executors).  KeyError
+        once the server has dropped them (evicted, or not kept)."""
         if self.status != LBVH_OK:
             raise RuntimeError(f"request {self.rid} has no result (status {self.status})")
         return self._handle.csr(self._k)
@@ -134,12 +139,18 @@ class _InFlight:
 
 class Server:
     """The request loop.  ``budget_bytes`` bounds in-flight plus resident
-    device memory; ``max_batch`` and ``max_batch_points`` cap a batch."""
+    device memory; ``max_batch`` and ``max_batch_points`` cap a batch.
+    A finished batch stays resident with its tree (``keep_resident``) and
+    its results (``keep_results``), both counted in the budget and evicted
+    together; ``on_done(response)`` is called for each finished request
+    while its results are still on the device."""
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 64,
                  max_batch_points: int = 1 << 25, clock=None, keep_resident: bool = True,
-                 pause_gc: bool | None = None):
+                 pause_gc: bool | None = None, keep_results: bool = True, on_done=None):
         self.ex = executor
+        self.keep_results = keep_results
+        self.on_done = on_done
         # Python's cyclic collector, when it walks a heap holding tens of
         # thousands of responses and tensors, stalls the loop for tens of
         # milliseconds (it set the latency tail); run() collects once and
@@ -170,12 +181,13 @@ class Server:
                 del self.where[r.rid]
         self.resident_bytes -= b.resident_bytes
         self.ex.evict(b.handle)
+        self.ex.drop_results(b.handle)
 
     def _used(self) -> int:
         return self.inflight_bytes + self.resident_bytes
 
     def evict_all(self):
-        """Drop every resident tree (results already delivered stay valid)."""
+        """Drop every resident tree and the results kept with it."""
         while self.resident:
             self._evict_one()
 
@@ -213,6 +225,7 @@ class Server:
             try:
                 self.ex.release(b.handle)
                 self.ex.evict(b.handle)
+                self.ex.drop_results(b.handle)
             except Exception:   # noqa: BLE001  (a failed batch may not release cleanly)
                 pass
             if len(b.reqs) == 1:
@@ -253,18 +266,32 @@ class Server:
                     o = out[r.rid]
                     o.done, o.hits, o._handle, o._k = t, int(hits[k]), b.handle, k
                     o.status = LBVH_OK
+                if self.on_done is not None:
+                    for r in b.reqs:
+                        self.on_done(out[r.rid])
                 self.ex.release(b.handle)
                 self.inflight_bytes -= b.bytes
                 slots.append(b.slot)
+                # what stays on the device: the trees and/or the results
+                keep = 0
                 if self.keep_resident:
-                    self.resident[b.bid] = (b, {r.rid: k for k, r in enumerate(b.reqs)})
-                    for r in b.reqs:
-                        self.where[r.rid] = b.bid
-                    self.resident_bytes += b.resident_bytes
-                    while self.resident and self._used() > self.budget:
-                        self._evict_one()
+                    keep += b.resident_bytes
                 else:
                     self.ex.evict(b.handle)
+                if self.keep_results:
+                    keep += self.ex.result_bytes(b.handle)
+                else:
+                    self.ex.drop_results(b.handle)
+                if keep:
+                    b.resident_bytes = keep
+                    self.resident[b.bid] = (b, {r.rid: k for k, r in enumerate(b.reqs)})
+                    if self.keep_resident:
+                        for r in b.reqs:
+                            self.where[r.rid] = b.bid
+                    self.resident_bytes += keep
+                    while self.resident and self._used() > self.budget:
+                        self._evict_one()
+                self.peak_bytes = max(self.peak_bytes, self._used())
             # deadlines
             now = self.clock.now()
             for q in (waiting, retry_alone):
@@ -343,7 +370,8 @@ class Server:
     def query_resident(self, rid: int, centres, radius: float):
         """Query the resident tree of finished request ``rid`` with spheres
         (executor-side arrays).  Returns (offsets, indices); KeyError if the
-        tree was evicted.  The tree becomes the most recently used."""
+        tree was evicted.  The tree becomes the most recently used.  These
+        answers are the caller's: the budget does not count them."""
         bid = self.where[rid]
         b, ks = self.resident[bid]
         self.resident.move_to_end(bid)
@@ -459,9 +487,21 @@ class _Handle:
         self.hits = None
 
     def csr(self, k):
+        if self.indices is None:
+            raise KeyError("results dropped (evicted or not kept)")
         a, b = self.qbase[k], self.qbase[k + 1]
         h0, h1 = int(self.hit_base[k]), int(self.hit_base[k + 1])
         return self.offsets[a:b + 1] - h0, self.indices[h0:h1]
+
+    def result_bytes(self) -> int:
+        n = 0
+        for t in (self.offsets, self.indices):
+            if t is not None:
+                n += t.numel() * t.element_size()
+        return n
+
+    def drop_results(self):
+        self.offsets = self.indices = None
 
 
 class GpuExecutor(_GpuBase):
@@ -562,6 +602,12 @@ class GpuExecutor(_GpuBase):
     def evict(self, h):
         h.batch = None
 
+    def result_bytes(self, h) -> int:
+        return h.result_bytes()
+
+    def drop_results(self, h):
+        h.drop_results()
+
     def query_resident(self, h, k, centres, radius):
         torch, lb = self.torch, self.lb
         if h.batch is None:
@@ -646,6 +692,12 @@ class PlainExecutor(_GpuBase):
 
     def evict(self, h):
         h.tree = None
+
+    def result_bytes(self, h) -> int:
+        return h.result_bytes()
+
+    def drop_results(self, h):
+        h.drop_results()
 
     def query_resident(self, h, k, centres, radius):
         torch, lb = self.torch, self.lb

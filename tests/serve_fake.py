@@ -13,6 +13,8 @@ class FakeHandle:
         self.released = False
 
     def csr(self, k):
+        if self.indices is None:
+            raise KeyError("results dropped")
         a, b = self.qbase[k], self.qbase[k + 1]
         h0, h1 = int(self.offsets[a]), int(self.offsets[b])
         return self.offsets[a:b + 1] - h0, self.indices[h0:h1]
@@ -100,6 +102,12 @@ class FakeExecutor:
         if not h.evicted:
             self.evictions += 1
         h.evicted = True
+
+    def result_bytes(self, h):
+        return 0 if h.indices is None else h.offsets.nbytes + h.indices.nbytes
+
+    def drop_results(self, h):
+        h.offsets = h.indices = None
 
     def query_resident(self, h, k, centres, radius):
         if h.evicted:

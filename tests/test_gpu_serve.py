@@ -84,19 +84,71 @@ def test_tight_budget_and_resident_queries(pools):
     _, ref = serve_run(pools, reqs)
     ex = serve.GpuExecutor(pools[2], pools[3], slots=2)
     big = max(ex.footprint([r])[0] for r in reqs)
-    srv = serve.Server(ex, 2 * big)
+    got = {}
+
+    def done(o):   # results as they finish (the server may evict its copy)
+        off, idx = o.csr()
+        got[o.rid] = (off.cpu(), idx.cpu())
+
+    srv = serve.Server(ex, 2 * big, on_done=done)
     out = srv.run(reqs)
     torch.cuda.synchronize()
     say(f"  tight budget {2 * big >> 20} MiB: peak {srv.peak_bytes >> 20} MiB, "
         f"{len(srv.batches)} batches, resident {len(srv.resident)}")
     assert all(o.status == serve.LBVH_OK for o in out)
     assert srv.peak_bytes <= 2 * big
-    assert all(same(a, b) for a, b in zip(ref, out))
+    for a in ref:
+        ao, ai = a.csr()
+        go, gi = got[a.rid]
+        assert torch.equal(ao.cpu(), go) and torch.equal(ai.cpu(), gi), f"request {a.rid}"
+    # results kept on the device count in the budget: only resident batches
+    # still hold theirs
+    kept = {r.rid for b, _ in srv.resident.values() for r in b.reqs}
+    for o in out:
+        if o.rid not in kept:
+            with pytest.raises(KeyError):
+                o.csr()
     # the last request's tree is resident: its own queries give its answer again
     r = reqs[-1]
     centres = pools[3][r.q_off:r.q_off + r.m]
     o, i = srv.query_resident(r.rid, centres, r.radius)
-    go, gi = out[r.rid].csr()
-    assert torch.equal(o, go) and torch.equal(i, gi)
+    go, gi = got[r.rid]
+    assert torch.equal(o.cpu(), go) and torch.equal(i.cpu(), gi)
     with pytest.raises(KeyError):
         srv.query_resident(reqs[0].rid, centres, r.radius)
+
+
+def test_oracle_sample_across_the_size_range(pools):
+    """A seeded set of requests whose sizes span the serving stream's whole
+    range (log-uniform in [1e3, 4e6] points, 10^4 spheres with about 8
+    expected neighbours each), served together; every answer equals the
+    oracle's."""
+    import math
+    from paper_2402_00665_amd import serve
+    rng = np.random.default_rng([5, 77])
+    k = 16
+    ns = np.floor(np.exp(np.linspace(math.log(1e3), math.log(4e6), k))).astype(np.int64)
+    ns = rng.permutation(ns)
+    reqs = []
+    for j, n in enumerate(ns):
+        p_off = int(rng.integers(0, (POOL_P - int(n)) // 4 + 1)) * 4
+        q_off = int(rng.integers(0, POOL_Q - 10000 + 1))
+        reqs.append(serve.Request(j, 0.0, int(n), 10000, p_off, q_off,
+                                  workloads.neighbour_radius(int(n), 8.0)))
+    say(f"serving: {k} requests, n from {ns.min()} to {ns.max()}")
+    srv, out = serve_run(pools, reqs)
+    assert all(o.status == serve.LBVH_OK for o in out), [o.error for o in out if o.status][:3]
+    pts, ctr = pools[0], pools[1]
+    oracle.threads(16)
+    try:
+        for r in reqs:
+            t = oracle.build(0, pts[r.p_off:r.p_off + r.n], 63)
+            q = np.concatenate([ctr[r.q_off:r.q_off + r.m],
+                                np.full((r.m, 1), r.radius, np.float32)], 1)
+            eo, ei, _ = oracle.query_traverse(0, q, t)
+            go, gi = out[r.rid].csr()
+            assert np.array_equal(go.cpu().numpy(), eo) and np.array_equal(gi.cpu().numpy(), ei), \
+                f"request {r.rid} (n={r.n}) differs from the oracle"
+            assert out[r.rid].hits == len(ei)
+    finally:
+        oracle.threads(1)

@@ -32,7 +32,8 @@ def run(pools, reqs, budget=1 << 40, slots=2, max_batch=64, **kw):
                                                      if k in ("fixed", "per_point", "per_query",
                                                               "fail_submit", "fail_advance")})
     srv = serve.Server(ex, budget, max_batch=max_batch, clock=clock,
-                       **{k: v for k, v in kw.items() if k in ("keep_resident", "max_batch_points")})
+                       **{k: v for k, v in kw.items() if k in ("keep_resident", "max_batch_points",
+                                                               "keep_results", "on_done")})
     return srv, ex, srv.run(reqs)
 
 
@@ -102,16 +103,59 @@ def test_budget_is_never_exceeded_and_trees_are_evicted(pools):
     reqs = plan_requests(seed=5)
     big = max(FakeExecutor(None, *pools).footprint([r])[0] for r in reqs)
     budget = 3 * big
-    srv, ex, out = run(pools, reqs, budget=budget)
+    got = {}
+    used = []
+    clock = serve.VirtualClock()
+    ex = FakeExecutor(clock, *pools, slots=2)
+
+    def done(o):
+        used.append(srv._used())
+        got[o.rid] = tuple(a.copy() for a in o.csr())
+
+    srv = serve.Server(ex, budget, max_batch=64, clock=clock, on_done=done)
+    out = srv.run(reqs)
     assert all(o.status == serve.LBVH_OK for o in out)
-    assert srv.peak_bytes <= budget
+    assert srv.peak_bytes <= budget and max(used) <= budget
     assert ex.evictions > 0
     assert srv.resident_bytes + srv.inflight_bytes <= budget
-    # results stay valid after their trees are evicted
+    # results handed to on_done are the requests' answers; the server's own
+    # copy went with the evicted tree
     r = reqs[0]
     do, di = direct(pools, r)
-    mo, mi = out[0].csr()
-    assert np.array_equal(mo, do) and np.array_equal(mi, di)
+    assert np.array_equal(got[r.rid][0], do) and np.array_equal(got[r.rid][1], di)
+    with pytest.raises(KeyError):
+        out[0].csr()
+
+
+def test_kept_results_count_in_the_budget(pools):
+    """Results kept on the device are counted with their tree: resident
+    bytes are the trees plus the results of the resident batches, never
+    above the budget; an evicted batch's results are gone, a resident one's
+    are the oracle's.  Without keeping results, only the trees count."""
+    reqs = plan_requests(seed=8)
+    fx = FakeExecutor(None, *pools)
+    big = max(fx.footprint([r])[0] for r in reqs)
+    for keep_results, keep_resident in ((True, True), (True, False), (False, True)):
+        budget = 2 * big
+        srv, ex, out = run(pools, reqs, budget=budget, keep_results=keep_results,
+                           keep_resident=keep_resident)
+        assert all(o.status == serve.LBVH_OK for o in out)
+        assert srv.peak_bytes <= budget
+        total = 0
+        for bid, (b, ks) in srv.resident.items():
+            tree = b.resident_bytes - (ex.result_bytes(b.handle) if keep_results else 0)
+            assert tree == (fx.footprint(b.reqs)[1] if keep_resident else 0)
+            total += b.resident_bytes
+        assert total == srv.resident_bytes <= budget
+        resident = {r.rid for b, _ in srv.resident.values() for r in b.reqs}
+        for r, o in zip(reqs, out):
+            if keep_results and r.rid in resident:
+                mo, mi = o.csr()
+                do, di = direct(pools, r)
+                assert np.array_equal(mo, do) and np.array_equal(mi, di)
+            else:
+                with pytest.raises(KeyError):
+                    o.csr()
 
 
 def test_resident_tree_can_be_queried_again(pools):
