@@ -187,6 +187,42 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m,
                           int32_t *indices, const void *workspace,
                           int64_t workspace_bytes, void *stream);
 
+/* Rays and segments (Sec. 1 lists the primitives a ray meets among the
+ * range searches a hierarchy answers; Alg. 1 walks them like any other
+ * query).  Ray j is rays[j] = (o.x, o.y, o.z, tmin, d.x, d.y, d.z, tmax):
+ * the points o + t*d with tmin <= t <= tmax.  A segment from a to b is
+ * o = a, d = b - a, [0, 1]; a ray has tmax = +inf.  Closed slab test in
+ * binary32, no fused multiply-add: per axis inv = 1/d (correctly rounded);
+ * an axis with d = 0, or whose inv overflows, passes iff lo <= o <= hi;
+ * otherwise t1 = (lo - o)*inv and t2 = (hi - o)*inv.  The entry parameter
+ * is the largest of tmin and the per-axis min(t1, t2), the exit the
+ * smallest of tmax and the per-axis max(t1, t2); a box B matches iff every
+ * parallel axis passes and entry <= exit.
+ *   rays : device, float [m][8], 16-byte aligned.
+ * All hits: the count and fill calls behave as the sphere and box calls
+ * (same workspace, CSR offsets, hits in ascending Morton-order position). */
+int lbvh_query_rays_count(const lbvh_tree *tree, const float *rays, int64_t m,
+                          int64_t *offsets, void *workspace,
+                          int64_t workspace_bytes, void *stream);
+int lbvh_query_rays_fill(const lbvh_tree *tree, const float *rays, int64_t m,
+                         int32_t *indices, const void *workspace,
+                         int64_t workspace_bytes, void *stream);
+
+/* First hit of each ray: among the primitives it matches, the one with the
+ * smallest entry parameter, ties to the smallest Morton-order position.
+ * One pruned Alg. 1 walk per ray: a node is entered only if the ray meets
+ * its box with an entry parameter below the best hit so far (a box inside
+ * another never has a smaller entry parameter, so nothing is lost).
+ *   hit       : device int32 [m]: input index of the primitive, -1 if none.
+ *   t         : device float [m]: its entry parameter, +inf if none.
+ *   workspace : device, at least lbvh_query_workspace_bytes(m) bytes,
+ *               256-byte aligned; only its error word is used, and
+ *               lbvh_query_check reads it as after a count call.
+ * m = 0 enqueues nothing. */
+int lbvh_query_rays_first(const lbvh_tree *tree, const float *rays, int64_t m,
+                          int32_t *hit, float *t, void *workspace,
+                          int64_t workspace_bytes, void *stream);
+
 /* Synchronise the stream and report an error that the last count call over
  * m queries flagged in `workspace` (LBVH_EDEVICE), else LBVH_OK.  Flagged:
  * a walk that spent its node-visit budget before the sentinel (never for a
@@ -345,6 +381,10 @@ const char *lbvh_last_hip_error(void);
  *   "query_walk_budget": for tests of the error path: caps the node visits
  *       of each walk of a count call (0 = no cap beyond 2n, the default).
  *       A walk that hits the cap stops; lbvh_query_check then reports it.
+ *   "morton_order": 1 = the single-tree build's Morton-code kernel sweeps
+ *       the primitives from the end of the array to its start (the
+ *       opposite of the scene-box pass before it), 0 = from the start
+ *       (default).
  * Results never depend on the knobs other than query_walk_budget; only
  * speed does.  Calls already enqueued keep the shapes they were enqueued
  * with. */

@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(_HERE, "liblbvh.so")
 
 LBVH_OK, LBVH_EINVAL, LBVH_ENOSPACE, LBVH_EHIP, LBVH_EDEVICE = 0, -1, -2, -3, -4
 LBVH_POINTS, LBVH_BOXES = 0, 1
-SPHERES, QBOXES = 0, 1
+SPHERES, QBOXES, RAYS = 0, 1, 2
+QUERY_WIDTH = {SPHERES: 4, QBOXES: 6, RAYS: 8}
 LBVH_MAX_PRIMS = (1 << 30) - 1
 NODE_BYTES = 32
 
@@ -95,6 +96,9 @@ def lib() -> C.CDLL:
             "lbvh_query_boxes_count": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_query_spheres_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_query_boxes_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
+            "lbvh_query_rays_count": (C.c_int, [T, P, i64, P, P, i64, P]),
+            "lbvh_query_rays_fill": (C.c_int, [T, P, i64, P, P, i64, P]),
+            "lbvh_query_rays_first": (C.c_int, [T, P, i64, P, P, P, i64, P]),
             "lbvh_strerror": (C.c_char_p, [C.c_int]),
             "lbvh_last_hip_error": (C.c_char_p, []),
             "lbvh_tune": (i64, [C.c_char_p, i64]),
@@ -157,6 +161,19 @@ def lbvh_query_spheres_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -
 
 def lbvh_query_boxes_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> int:
     return lib().lbvh_query_boxes_fill(C.byref(tree), q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_query_rays_count(tree, q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_rays_count(C.byref(tree), q_ptr, m, offsets_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_query_rays_fill(tree, q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_rays_fill(C.byref(tree), q_ptr, m, idx_ptr, ws_ptr, ws_bytes, stream)
+
+
+def lbvh_query_rays_first(tree, q_ptr, m, hit_ptr, t_ptr, ws_ptr, ws_bytes, stream) -> int:
+    return lib().lbvh_query_rays_first(C.byref(tree), q_ptr, m, hit_ptr, t_ptr, ws_ptr, ws_bytes,
+                                       stream)
 
 
 def lbvh_query_check(ws_ptr, m, stream) -> int:
@@ -353,14 +370,15 @@ def query_count(tree: Tree, queries, qkind: int, workspace: Workspace, offsets=N
     """First call: CSR offsets (int64 [m+1]) on the device; the workspace
     keeps what the fill call needs."""
     torch = _torch()
-    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    q = _dev_f32(queries, QUERY_WIDTH[qkind], "queries")
     m = int(q.shape[0])
     if offsets is None:
         offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
     ws_bytes = lbvh_query_workspace_bytes(m)
     _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_query_workspace_bytes")
     ws = workspace.get(ws_bytes)
-    f = lbvh_query_spheres_count if qkind == SPHERES else lbvh_query_boxes_count
+    f = {SPHERES: lbvh_query_spheres_count, QBOXES: lbvh_query_boxes_count,
+         RAYS: lbvh_query_rays_count}[qkind]
     _check(f(tree.desc, q.data_ptr() if m else None, m, offsets.data_ptr(), ws.data_ptr(),
              ws.numel(), _stream(stream)), "query count")
     return offsets
@@ -375,10 +393,11 @@ def check_query(workspace: Workspace, m: int, batched: bool = False, stream=None
 
 def query_fill(tree: Tree, queries, qkind: int, indices, workspace: Workspace, stream=None):
     """Second call, with the count call's workspace."""
-    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    q = _dev_f32(queries, QUERY_WIDTH[qkind], "queries")
     m = int(q.shape[0])
     ws = workspace.buf
-    f = lbvh_query_spheres_fill if qkind == SPHERES else lbvh_query_boxes_fill
+    f = {SPHERES: lbvh_query_spheres_fill, QBOXES: lbvh_query_boxes_fill,
+         RAYS: lbvh_query_rays_fill}[qkind]
     _check(f(tree.desc, q.data_ptr() if m else None, m, indices.data_ptr(), ws.data_ptr(),
              ws.numel(), _stream(stream)), "query fill")
     return indices
@@ -397,7 +416,35 @@ def query(tree: Tree, queries, qkind: int, workspace: Workspace | None = None, s
     return offsets, buf[:total]
 
 
+def query_first(tree: Tree, rays, workspace: Workspace | None = None, hit=None, t=None,
+                stream=None):
+    """First hit of each ray (float32 CUDA [m, 8] = o.xyz, tmin, d.xyz,
+    tmax): (hit int32 [m], input index or -1; t float32 [m], entry
+    parameter or +inf) on the device; asynchronous."""
+    torch = _torch()
+    q = _dev_f32(rays, 8, "rays")
+    m = int(q.shape[0])
+    if hit is None:
+        hit = torch.empty(max(m, 1), dtype=torch.int32, device=q.device)[:m]
+    if t is None:
+        t = torch.empty(max(m, 1), dtype=torch.float32, device=q.device)[:m]
+    workspace = workspace or Workspace(q.device)
+    ws_bytes = lbvh_query_workspace_bytes(m)
+    _check(ws_bytes if ws_bytes < 0 else 0, "lbvh_query_workspace_bytes")
+    ws = workspace.get(ws_bytes)
+    _check(lbvh_query_rays_first(tree.desc, q.data_ptr() if m else None, m,
+                                 hit.data_ptr() if m else None, t.data_ptr() if m else None,
+                                 ws.data_ptr(), ws.numel(), _stream(stream)), "lbvh_query_rays_first")
+    return hit, t
+
+
 # ------------------------------------------------------------- batched
+
+def _batched_width(qkind: int) -> int:
+    if qkind not in (SPHERES, QBOXES):
+        raise ValueError("batched queries are spheres or boxes")
+    return QUERY_WIDTH[qkind]
+
 
 @dataclass
 class Batch:
@@ -473,7 +520,7 @@ def query_batched_count(batch: Batch, queries, qseg_off, qkind: int, workspace: 
                         offsets=None, stream=None):
     """First batched call, asynchronous: CSR offsets int64 [m+1]."""
     torch = _torch()
-    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    q = _dev_f32(queries, _batched_width(qkind), "queries")
     m = int(q.shape[0])
     if offsets is None:
         offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
@@ -490,7 +537,7 @@ def query_batched_fill(batch: Batch, queries, qseg_off, qkind: int, offsets, ind
                        workspace: Workspace, stream=None):
     """Second batched call, asynchronous, with the count call's workspace:
     indices int32 [offsets[m]] (the tensor must hold at least one element)."""
-    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    q = _dev_f32(queries, _batched_width(qkind), "queries")
     m = int(q.shape[0])
     ws = workspace.buf
     fill = lbvh_query_batched_spheres_fill if qkind == SPHERES else lbvh_query_batched_boxes_fill
@@ -504,7 +551,7 @@ def query_batched(batch: Batch, queries, qseg_off, qkind: int, workspace: Worksp
     """Count, read the total, fill.  Returns (offsets int64 [m+1], indices
     int32 [total]) with scene-local primitive ids."""
     torch = _torch()
-    q = _dev_f32(queries, 4 if qkind == SPHERES else 6, "queries")
+    q = _dev_f32(queries, _batched_width(qkind), "queries")
     m = int(q.shape[0])
     offsets = torch.empty(m + 1, dtype=torch.int64, device=q.device)
     ws_bytes = lbvh_query_batched_workspace_bytes(m)

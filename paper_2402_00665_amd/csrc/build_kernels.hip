@@ -90,13 +90,17 @@ __global__ __launch_bounds__(kBlock) void k_bounds_final(const float *__restrict
 
 // Codes in input order, LDS digit histograms of every radix pass (BITS-wide
 // digits) folded into the global ones, and one side job that must precede
-// the sort: clear the look-back status of the first sort pass.
+// the sort: clear the look-back status of the first sort pass.  With
+// `reverse` the grid sweeps the primitives from the end of the array to its
+// start, the opposite of the scene-box pass just before it, so its first
+// reads find the lines that pass touched last (still in the last-level
+// cache when the array is larger than that cache); the codes are the same.
 template <int KIND, typename K, int BITS>
 __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ prims, int n,
                                                    const float4 *__restrict__ scene,
                                                    K *__restrict__ codes, uint32_t *__restrict__ hist,
                                                    uint32_t *__restrict__ status0,
-                                                   int64_t status_words)
+                                                   int64_t status_words, int reverse)
 {
     using P = Prims<KIND>;
     constexpr int R = 1 << BITS;
@@ -111,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
 
     const float4 slo = scene[0], sc = scene[2];
     const int64_t ng = n / P::G;
-    for (int64_t g = tid; g < ng; g += stride) {
+    for (int64_t g0 = tid; g0 < ng; g0 += stride) {
+        const int64_t g = reverse ? ng - 1 - g0 : g0;
         float lo[P::G][3], hi[P::G][3];
         P::group(prims, g, lo, hi);
         K c[P::G];
@@ -227,7 +232,7 @@ void run_sort(const float *prims, int n, int code_bits, K *codes, int32_t *leaf_
     nm = nm < 1 ? 1 : (nm > nm_max ? nm_max : nm);
     prof_begin(K_MORTON, s);
     hipLaunchKernelGGL((k_morton<KIND, K, B>), dim3(nm), dim3(kBlock), 0, s, prims, n, scene, first,
-                       hist, status[0], tiles << B);
+                       hist, status[0], tiles << B, (int)tune_get(TUNE_MORTON_ORDER));
     prof_end(K_MORTON, s);
 
     for (int p = 0; p < passes; ++p) {

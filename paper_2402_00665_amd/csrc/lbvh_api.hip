@@ -60,7 +60,7 @@ QueryLayout query_layout(int64_t m)
     L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
     L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
     L.ctrl = take(128);
-    L.qsorted = take((size_t)m * 6 * sizeof(float));
+    L.qsorted = take((size_t)m * 8 * sizeof(float));   // widest query: a ray
     L.qperm = take((size_t)m * sizeof(int32_t));
     L.qoff = take((size_t)(m + 1) * sizeof(int64_t));
     L.total = off;
@@ -131,13 +131,14 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 namespace {
 // defaults measured on MI355X: 8-bit digits and 512 x 16 tiles for 30-bit
 // keys, 9-bit digits and 768 x 16 tiles for 63-bit keys
-std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {6}, {0}, {kSplit1}, {kSplit2}, {0}, {0}, {8}, {9}, {0}};
+std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {6}, {0}, {kSplit1}, {kSplit2}, {0}, {0}, {8}, {9}, {0},
+                                         {0}};
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
                                     "query_split1", "query_split2", "query_leaf_mode",
                                     "query_order", "radix_bits32", "radix_bits64",
-                                    "query_walk_budget"};
-const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0};   // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1, 1, 10, 11, INT32_MAX};
+                                    "query_walk_budget", "morton_order"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0, 0};   // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1, 1, 10, 11, INT32_MAX, 1};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
@@ -491,6 +492,40 @@ int lbvh_query_boxes_fill(const lbvh_tree *tree, const float *lohi, int64_t m, i
                           const void *workspace, int64_t workspace_bytes, void *stream)
 {
     return query_fill(1, tree, lohi, m, indices, workspace, workspace_bytes, stream);
+}
+
+int lbvh_query_rays_count(const lbvh_tree *tree, const float *rays, int64_t m, int64_t *offsets,
+                          void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return query_count(2, tree, rays, m, offsets, workspace, workspace_bytes, stream);
+}
+
+int lbvh_query_rays_fill(const lbvh_tree *tree, const float *rays, int64_t m, int32_t *indices,
+                         const void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return query_fill(2, tree, rays, m, indices, workspace, workspace_bytes, stream);
+}
+
+int lbvh_query_rays_first(const lbvh_tree *tree, const float *rays, int64_t m, int32_t *hit,
+                          float *t, void *workspace, int64_t workspace_bytes, void *stream)
+{
+    if (!tree || m < 0 || m > INT32_MAX || tree->n < 0 || tree->n > LBVH_MAX_PRIMS) return LBVH_EINVAL;
+    if (m == 0) return LBVH_OK;
+    if (!rays || !aligned(rays, 16) || !hit || !t || !aligned(hit, 4) || !aligned(t, 4))
+        return LBVH_EINVAL;
+    if (tree->n > 0 && (!tree->nodes || !aligned(tree->nodes, 16))) return LBVH_EINVAL;
+    const QueryLayout L = query_layout(m);
+    if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
+    if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
+    hipError_t e;
+    if (tree->n == 0) {
+        // nothing to meet: hit -1, t = +inf, and a cleared error word
+        e = launch_ray_none(m, hit, t, static_cast<char *>(workspace), L, (hipStream_t)stream);
+    } else {
+        e = launch_ray_first(tree->nodes, (int)tree->n, rays, (int)m, hit, t,
+                             static_cast<char *>(workspace), L, (hipStream_t)stream);
+    }
+    return hip_status(e);
 }
 
 static int query_check(const void *workspace, size_t ctrl, void *stream)

@@ -123,7 +123,7 @@ struct QueryLayout {
     size_t ctrl;       // overflow flags, piece counts, query-order flag, sort counters, error word
     // query order (single tree): the reordered copy of the queries, each
     // reordered position's caller index, and the offsets in reordered order
-    size_t qsorted;    // m x 6 float
+    size_t qsorted;    // m x 8 float (the widest query, a ray)
     size_t qperm;      // m int32
     size_t qoff;       // m+1 int64
     // the order's radix sort, inside `hmask` (unused until the leaf level)
@@ -161,7 +161,7 @@ int batch_levels(int64_t max_scene);
 
 enum TuneKnob {
     TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_QORDER,
-    TUNE_RADIX_BITS32, TUNE_RADIX_BITS64, TUNE_QBUDGET,
+    TUNE_RADIX_BITS32, TUNE_RADIX_BITS64, TUNE_QBUDGET, TUNE_MORTON_ORDER,
     TUNE_NUM
 };
 int64_t tune_get(int knob);
@@ -191,6 +191,13 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_p
 
 hipError_t launch_build_batched(int kind, const float *prims, const lbvh_batch *b, int levels,
                                 char *ws, const BatchLayout &L, hipStream_t s);
+
+// first hit of each ray (Alg. 1 pruned on the entry parameter)
+hipError_t launch_ray_first(const lbvh_node *nodes, int n, const float *rays, int m, int32_t *hit,
+                            float *t, char *ws, const QueryLayout &L, hipStream_t s);
+// ... on an empty tree: every ray misses
+hipError_t launch_ray_none(int64_t m, int32_t *hit, float *t, char *ws, const QueryLayout &L,
+                           hipStream_t s);
 
 hipError_t launch_query_batched(int qkind, const lbvh_batch *b, const float *q,
                                 const int64_t *qseg_off, int64_t m, int64_t *offsets,

@@ -69,6 +69,77 @@ struct QBox {
     }
 };
 
+// Ray or segment: the points o + t*d with tmin <= t <= tmax (a segment from
+// a to b is o = a, d = b - a, [0, 1]; a ray has tmax = +inf).  Sec. 1 counts
+// the primitives a ray meets among the range searches a BVH answers.  Closed
+// slab test in binary32: per axis, inv = 1/d correctly rounded; an axis with
+// d = 0, or whose reciprocal overflows, passes iff o lies in the slab
+// [lo, hi]; otherwise its parameter interval has the ends (lo - o)*inv and
+// (hi - o)*inv.  enter = the largest of tmin and the intervals' lower ends,
+// exit = the smallest of tmax and their upper ends; hit iff enter <= exit.
+// Each step is a monotone function of lo (non-increasing) and hi
+// (non-decreasing), also after rounding, so a box inside a passing box can
+// only fail or pass with an entry parameter at least as large: Alg. 1's
+// pruning is exact, and so is the first-hit walk's pruning on the entry.
+struct Ray {
+    static constexpr int kFloats = 8;   // o.xyz, tmin, d.xyz, tmax
+    float o[3], d[3], inv[3], tmin, tmax;
+    bool par[3];
+    __device__ void load(const float *q, int j)
+    {
+        const float4 *p = reinterpret_cast<const float4 *>(q) + 2 * (int64_t)j;
+        const float4 a = p[0], b = p[1];
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; tmin = a.w;
+        d[0] = b.x; d[1] = b.y; d[2] = b.z; tmax = b.w;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            inv[k] = __fdiv_rn(1.0f, d[k]);
+            par[k] = d[k] == 0.0f || inv[k] == INFINITY || inv[k] == -INFINITY;
+        }
+    }
+    // the entry parameter in *enter when the ray meets the box
+    __device__ bool enter(float4 lo4, float4 hi4, float *enter) const
+    {
+        const float lo[3] = {lo4.x, lo4.y, lo4.z}, hi[3] = {hi4.x, hi4.y, hi4.z};
+        float t_in = tmin, t_out = tmax;
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (par[k]) {
+                ok = ok && lo[k] <= o[k] && o[k] <= hi[k];
+            } else {
+                const float t1 = (lo[k] - o[k]) * inv[k];
+                const float t2 = (hi[k] - o[k]) * inv[k];
+                const float nr = t1 < t2 ? t1 : t2;
+                const float fr = t1 < t2 ? t2 : t1;
+                t_in = nr > t_in ? nr : t_in;
+                t_out = fr < t_out ? fr : t_out;
+            }
+        }
+        *enter = t_in;
+        return ok && t_in <= t_out;
+    }
+    __device__ bool test(float4 lo, float4 hi) const
+    {
+        float e;
+        return enter(lo, hi, &e);
+    }
+    // A thin set contains no box of positive volume; claiming none only
+    // forgoes a shortcut.
+    __device__ bool contains(float4, float4) const { return false; }
+    // the start point as a degenerate box: it keys the query order by where
+    // the ray starts, and makes the mixed leaf schedule walk (not scan) a
+    // ray's pieces
+    __device__ void bounds(float lo[3], float hi[3]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float t = (tmin == -INFINITY || d[k] == 0.0f) ? 0.0f : tmin;
+            lo[k] = hi[k] = o[k] + t * d[k];
+        }
+    }
+};
+
 // Error word values of a query call (the count call's workspace).
 constexpr uint32_t kQErrWalkBudget = 5;   // a walk ran out of its node-visit budget
 

@@ -147,6 +147,63 @@ __global__ void k_query_reset(unsigned long long *app_count, int32_t *order_flag
     }
 }
 
+// ---------------------------------------------------------- first hit
+//
+// First hit of each ray: among the primitives it meets, the one with the
+// smallest entry parameter, ties to the smallest leaf position (Morton
+// order).  One lane walks Alg. 1 from the root and enters a node only if the
+// ray meets its box with an entry parameter below the best hit so far (any
+// entry while there is none).  A box inside a node's box never has a smaller
+// entry parameter (the slab test is monotone under box inclusion), so a
+// pruned subtree holds no better hit; Alg. 1 reaches leaves in ascending
+// position, so on equal entries the first leaf found stays.  An n = 0 tree
+// gives every ray hit -1 and t = +inf (n = 0 never reaches here: the caller
+// fills those).
+__global__ __launch_bounds__(kBlock) void k_ray_first(Tree tr, const float *__restrict__ rays, int m,
+                                                      int32_t *__restrict__ hit, float *__restrict__ t)
+{
+    const int leaf0 = tr.leaf0();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < m; j += stride) {
+        Ray q;
+        q.load(rays, (int)j);
+        int best_hit = -1, v = 0;
+        float best = INFINITY;
+        int64_t budget = tr.walk_budget();
+        while (v != -1 && --budget >= 0) {
+            float4 a, b;
+            tr.load(v, a, b);
+            float e;
+            if (q.enter(a, b, &e) && (best_hit < 0 || e < best)) {
+                if (v >= leaf0) {
+                    best_hit = __float_as_int(a.w);
+                    best = e;
+                    v = __float_as_int(b.w);
+                } else {
+                    v = __float_as_int(a.w);
+                }
+            } else {
+                v = __float_as_int(b.w);
+            }
+        }
+        if (budget < 0) tr.budget_spent();
+        hit[j] = best_hit;
+        t[j] = best;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ray_none(int64_t m, int32_t *__restrict__ hit,
+                                                     float *__restrict__ t, uint32_t *err)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t j0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j0 == 0) *err = 0u;
+    for (int64_t j = j0; j < m; j += stride) {
+        hit[j] = -1;
+        t[j] = INFINITY;
+    }
+}
+
 struct Scratch {
     int32_t *cnt1, *cnt2, *hcnt, *ovf;
     int64_t *off1, *off2, *hoff, *partials, *count;
@@ -337,11 +394,36 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_p
         return hipGetLastError();
     }
     Tree tr{reinterpret_cast<const float4 *>(nodes), leaf_perm, n};
-    if (fill)
+    if (fill) {
+        if (qkind == 2) return run_fill<Ray>(tr, q, indices, ws, L, s);
         return qkind == 0 ? run_fill<Sphere>(tr, q, indices, ws, L, s)
                           : run_fill<QBox>(tr, q, indices, ws, L, s);
+    }
+    if (qkind == 2) return run_count<Ray>(tr, q, m, offsets, ws, L, s);
     return qkind == 0 ? run_count<Sphere>(tr, q, m, offsets, ws, L, s)
                       : run_count<QBox>(tr, q, m, offsets, ws, L, s);
+}
+
+hipError_t launch_ray_none(int64_t m, int32_t *hit, float *t, char *ws, const QueryLayout &L,
+                           hipStream_t s)
+{
+    Scratch S = carve(ws, L);
+    hipLaunchKernelGGL(k_ray_none, dim3(grid_for(m)), dim3(kBlock), 0, s, m, hit, t, S.err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ray_first(const lbvh_node *nodes, int n, const float *rays, int m, int32_t *hit,
+                            float *t, char *ws, const QueryLayout &L, hipStream_t s)
+{
+    if (m == 0) return hipSuccess;
+    Scratch S = carve(ws, L);
+    Tree tr{reinterpret_cast<const float4 *>(nodes), nullptr, n, S.err, tune_get(TUNE_QBUDGET)};
+    prof_begin(K_QCOUNT, s);
+    hipLaunchKernelGGL(k_query_reset, dim3(1), dim3(kBlock), 0, s, S.app_count, S.order_flag, 0,
+                       S.sort_ctr, S.qhist, S.err);
+    hipLaunchKernelGGL(k_ray_first, dim3(grid_for(m)), dim3(kBlock), 0, s, tr, rays, m, hit, t);
+    prof_end(K_QCOUNT, s);
+    return hipGetLastError();
 }
 
 }  // namespace lbvh

@@ -160,3 +160,19 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_ray_calls_reject_bad_arguments_up_front():
+    """The ray entry points validate before enqueuing anything (no pointer
+    here is ever dereferenced)."""
+    t = lb.lbvh_tree(0, 30, 0, None, None, None)
+    assert lb.lbvh_query_rays_first(t, None, -1, None, None, None, 0, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_rays_first(t, None, 0, None, None, None, 0, None) == lb.LBVH_OK   # m = 0
+    assert lb.lbvh_query_rays_first(t, None, 10, 16, 16, 256, 0, None) == lb.LBVH_EINVAL  # no rays
+    assert lb.lbvh_query_rays_first(t, 8, 10, 16, 16, 256, 1 << 20, None) == lb.LBVH_EINVAL  # align
+    assert lb.lbvh_query_rays_first(t, 16, 10, None, 16, 256, 1 << 20, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_rays_first(t, 16, 10, 16, 16, 256, 0, None) == lb.LBVH_ENOSPACE
+    assert lb.lbvh_query_rays_first(t, 16, 10, 16, 16, 128, 1 << 20, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_rays_count(t, None, -1, 16, 256, 1 << 20, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_rays_count(t, 8, 10, 16, 256, 1 << 20, None) == lb.LBVH_EINVAL
+    assert lb.lbvh_query_rays_fill(t, 16, 10, None, 256, 0, None) == lb.LBVH_ENOSPACE

@@ -9,6 +9,9 @@ Every array is float32 and C-contiguous:
   boxes   : [n, 6]  (lo.x, lo.y, lo.z, hi.x, hi.y, hi.z)
   spheres : [m, 4]  (c.x, c.y, c.z, r)
   qboxes  : [m, 6]  same layout as boxes
+  rays    : [m, 8]  (o.x, o.y, o.z, tmin, d.x, d.y, d.z, tmax): the points
+            o + t*d for tmin <= t <= tmax (a segment is [0, 1] with d its
+            end minus its start; a ray has tmax = +inf)
 
 Random streams come from ``numpy.random.default_rng([cfg_id, stream])`` with
 stream 0 for primitives and stream 1 for queries, so a reduced-size variant of
@@ -30,6 +33,7 @@ POINTS = 0
 BOXES = 1
 SPHERES = 0
 QBOXES = 1
+RAYS = 2
 
 
 def _rng(cfg_id: int, stream: int) -> np.random.Generator:
@@ -81,6 +85,42 @@ def query_boxes(m: int, side: float, rng: np.random.Generator) -> np.ndarray:
     out = np.empty((m, 6), dtype=np.float32)
     out[:, :3] = c - 0.5 * side
     out[:, 3:] = c + 0.5 * side
+    return out
+
+
+def points_in_boxes(boxes: np.ndarray, m: int, rng: np.random.Generator) -> np.ndarray:
+    """m points, each uniform inside a box drawn uniformly from ``boxes``
+    (float64 lo + u * (hi - lo), then rounded to float32)."""
+    pick = rng.integers(0, boxes.shape[0], size=m)
+    lo = boxes[pick, :3].astype(np.float64)
+    hi = boxes[pick, 3:].astype(np.float64)
+    return (lo + rng.random((m, 3)) * (hi - lo)).astype(np.float32)
+
+
+def rays_toward(targets: np.ndarray, rng: np.random.Generator) -> np.ndarray:
+    """Rays [0, +inf) from origins uniform in [0,1)^3 through the given
+    targets (d = target - origin, so t = 1 reaches the target)."""
+    m = targets.shape[0]
+    o = rng.random((m, 3))
+    out = np.empty((m, 8), dtype=np.float32)
+    out[:, :3] = o
+    out[:, 3] = 0.0
+    out[:, 4:7] = targets.astype(np.float64) - o
+    out[:, 7] = np.inf
+    return out
+
+
+def segments_from(starts: np.ndarray, length: float, rng: np.random.Generator) -> np.ndarray:
+    """Segments of a fixed length from the given starts in directions
+    uniform on the sphere (o = start, d = length * unit direction, [0, 1])."""
+    m = starts.shape[0]
+    u = rng.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    out = np.empty((m, 8), dtype=np.float32)
+    out[:, :3] = starts
+    out[:, 3] = 0.0
+    out[:, 4:7] = length * u
+    out[:, 7] = 1.0
     return out
 
 
@@ -161,6 +201,21 @@ def clustered(n: int = 1 << 24, m: int = 1 << 20) -> Workload:
     return Workload("clustered_boxes", BOXES, b, 30, QBOXES, q)
 
 
+def clustered_rays(n: int = 1 << 24, m: int = 1 << 20, segments: bool = False,
+                   length: float = 0.002) -> Workload:
+    """Rays and segments on the clustered boxes (the same 2^24 boxes as
+    ``clustered``).  Rays (first hit): from origins uniform in [0,1)^3
+    through a random point of a random box, [0, +inf).  Segments (all
+    hits): from a random point of a random box, ``length`` long, uniform
+    direction.  Both aim at the boxes, so most of them meet some."""
+    b = clustered_boxes(n, _rng(3, 0))
+    rng = _rng(3, 3 if segments else 4)
+    p = points_in_boxes(b, m, rng)
+    q = segments_from(p, length, rng) if segments else rays_toward(p, rng)
+    name = "clustered_segments" if segments else "clustered_rays"
+    return Workload(name, BOXES, b, 30, RAYS, q, {"length": length} if segments else {})
+
+
 def batched_scene_sizes(S: int = 4096, lo: int = 32, hi: int = 65536,
                         rng: np.random.Generator | None = None) -> np.ndarray:
     """Scene sizes floor(exp(U(ln lo, ln hi)))."""
@@ -219,6 +274,9 @@ def by_name(name: str, scale: float = 1.0) -> Workload:
     if name == "clustered_boxes":
         return clustered(max(1, int((1 << 24) * scale)),
                          max(1, int((1 << 20) * scale)))
+    if name in ("clustered_rays", "clustered_segments"):
+        return clustered_rays(max(1, int((1 << 24) * scale)), max(1, int((1 << 20) * scale)),
+                              segments=name == "clustered_segments")
     raise KeyError(name)
 
 
