@@ -48,6 +48,7 @@ extern "C" {
 #define LBVH_ENOSPACE (-2)   /* workspace smaller than *_workspace_bytes */
 #define LBVH_EHIP (-3)       /* a HIP launch or runtime call failed */
 #define LBVH_EDEVICE (-4)    /* a kernel flagged an internal error */
+#define LBVH_ELIMIT (-5)     /* n above what lbvh_build_noalloc's fixed scratch holds */
 
 #define LBVH_POINTS 0        /* primitives: float [n][3] = x, y, z */
 #define LBVH_BOXES 1         /* primitives: float [n][6] = lo.xyz, hi.xyz */
@@ -137,6 +138,29 @@ int lbvh_build_boxes(const float *lohi, int64_t n, int32_t code_bits,
  * and debugging; the build itself never synchronises. */
 int lbvh_build_check(const void *workspace, int64_t n, int32_t code_bits,
                      int32_t kind, void *stream);
+
+/* lbvh_build for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops or harnesses that forbid hipMalloc):
+ * the same build, with no workspace argument.  Its scratch is a fixed
+ * array of LBVH_NOALLOC_SCRATCH_BYTES bytes in device memory, one per GPU,
+ * which each GPU the library runs on holds until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the caller still allocates the tree's arrays.
+ *   n         : 0 <= n <= LBVH_NOALLOC_MAX_PRIMS; a larger n returns
+ *               LBVH_ELIMIT and enqueues nothing.
+ *   error_out : NULL, or caller-owned device or pinned host memory (4-byte
+ *               aligned) that receives the build's error word once the
+ *               stream has passed the call: nonzero means what
+ *               lbvh_build_check reports as LBVH_EDEVICE.  Nothing is
+ *               written for n = 0.
+ * Other arguments, results and errors as lbvh_build.  The current device
+ * (hipSetDevice) must be the stream's.  Every call on one GPU shares that
+ * GPU's scratch, and each call overwrites it: calls that overlap on one GPU
+ * (different streams or host threads) race, so the caller orders them. */
+#define LBVH_NOALLOC_MAX_PRIMS ((int64_t)1 << 20)
+#define LBVH_NOALLOC_SCRATCH_BYTES ((int64_t)25 << 20)
+int lbvh_build_noalloc(int32_t kind, const float *prims, int64_t n, int32_t code_bits,
+                       lbvh_tree *tree, uint32_t *error_out, void *stream);
 
 
 /* ------------------------------------------------------------- queries */

@@ -23,7 +23,9 @@ from dataclasses import dataclass
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbvh.so")
 
-LBVH_OK, LBVH_EINVAL, LBVH_ENOSPACE, LBVH_EHIP, LBVH_EDEVICE = 0, -1, -2, -3, -4
+LBVH_OK, LBVH_EINVAL, LBVH_ENOSPACE, LBVH_EHIP, LBVH_EDEVICE, LBVH_ELIMIT = 0, -1, -2, -3, -4, -5
+LBVH_NOALLOC_MAX_PRIMS = 1 << 20
+LBVH_NOALLOC_SCRATCH_BYTES = 25 << 20
 LBVH_POINTS, LBVH_BOXES = 0, 1
 SPHERES, QBOXES, RAYS = 0, 1, 2
 QUERY_WIDTH = {SPHERES: 4, QBOXES: 6, RAYS: 8}
@@ -91,6 +93,7 @@ def lib() -> C.CDLL:
             "lbvh_build_points": (C.c_int, [P, i64, i32, T, P, i64, P]),
             "lbvh_build_boxes": (C.c_int, [P, i64, i32, T, P, i64, P]),
             "lbvh_build_check": (C.c_int, [P, i64, i32, i32, P]),
+            "lbvh_build_noalloc": (C.c_int, [i32, P, i64, i32, T, P, P]),
             "lbvh_query_workspace_bytes": (i64, [i64]),
             "lbvh_query_spheres_count": (C.c_int, [T, P, i64, P, P, i64, P]),
             "lbvh_query_boxes_count": (C.c_int, [T, P, i64, P, P, i64, P]),
@@ -137,6 +140,10 @@ def lbvh_build_points(xyz_ptr, n, code_bits, tree: lbvh_tree, ws_ptr, ws_bytes, 
 
 def lbvh_build_boxes(lohi_ptr, n, code_bits, tree: lbvh_tree, ws_ptr, ws_bytes, stream) -> int:
     return lib().lbvh_build_boxes(lohi_ptr, n, code_bits, C.byref(tree), ws_ptr, ws_bytes, stream)
+
+
+def lbvh_build_noalloc(kind, prims_ptr, n, code_bits, tree: lbvh_tree, err_ptr, stream) -> int:
+    return lib().lbvh_build_noalloc(kind, prims_ptr, n, code_bits, C.byref(tree), err_ptr, stream)
 
 
 def lbvh_build_check(ws_ptr, n, code_bits, kind, stream) -> int:
@@ -354,6 +361,27 @@ def build(prims, code_bits: int, kind: int | None = None, workspace: Workspace |
     _check(rc, "lbvh_build")
     tree.kind = kind
     tree.last_workspace = ws
+    return tree
+
+
+def build_noalloc(prims, code_bits: int, kind: int | None = None, tree: Tree | None = None,
+                  error=None, stream=None) -> Tree:
+    """``build`` through lbvh_build_noalloc: no workspace, the library's
+    fixed per-GPU scratch (n <= LBVH_NOALLOC_MAX_PRIMS).  ``error``: an
+    optional int32 CUDA tensor of one element that receives the build's
+    error word.  Pass a preallocated ``tree`` for a call that allocates
+    nothing at all."""
+    if kind is None:
+        kind = LBVH_POINTS if prims.shape[1] == 3 else LBVH_BOXES
+    prims = _dev_f32(prims, 3 if kind == LBVH_POINTS else 6, "prims")
+    n = int(prims.shape[0])
+    if tree is None or tree.n != n or tree.code_bits != code_bits:
+        tree = alloc_tree(n, code_bits, prims.device)
+    rc = lbvh_build_noalloc(kind, prims.data_ptr() if n else None, n, code_bits, tree.desc,
+                            error.data_ptr() if error is not None else None, _stream(stream))
+    _check(rc, "lbvh_build_noalloc")
+    tree.kind = kind
+    tree.last_workspace = None
     return tree
 
 

@@ -219,6 +219,40 @@ using namespace lbvh;
 
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// ------------------------------------------------ allocation-free build
+//
+// Scratch of lbvh_build_noalloc: a fixed array in device memory, one copy
+// per GPU at its own address, held until the process ends.  In host code
+// `scratch` names a host-side stand-in, not device memory: the device
+// address is taken once per device, with that device current, through
+// hipGetSymbolAddress, and only that address is ever handed to kernels.
+static __device__ __align__(256) char scratch[LBVH_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+
+// the current device's scratch address (looked up on its first use)
+hipError_t noalloc_scratch(char **out)
+{
+    int dev = 0;
+    if (hipError_t e = hipGetDevice(&dev); e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)); e != hipSuccess) return e;
+        g_scratch_addr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+// the build's error word to the caller's flag
+__global__ void k_copy_word(const uint32_t *src, uint32_t *dst) { *dst = *src; }
+}  // namespace
+
 // HIP error behind the last LBVH_EHIP returned on this thread.
 static thread_local hipError_t t_last_hip = hipSuccess;
 
@@ -239,6 +273,7 @@ const char *lbvh_strerror(int status)
     case LBVH_ENOSPACE: return "workspace too small";
     case LBVH_EHIP: return "HIP launch or runtime error";
     case LBVH_EDEVICE: return "device-side error flagged by a kernel";
+    case LBVH_ELIMIT: return "n exceeds the allocation-free build's fixed scratch (LBVH_NOALLOC_MAX_PRIMS)";
     default: return "unknown status";
     }
 }
@@ -275,6 +310,40 @@ int lbvh_build(int32_t kind, const float *prims, int64_t n, int32_t code_bits, l
     hipError_t e = launch_build(kind, prims, (int)n, code_bits, tree->nodes, tree->codes,
                                 tree->leaf_perm, static_cast<char *>(workspace), L,
                                 (hipStream_t)stream);
+    return hip_status(e);
+}
+
+int lbvh_build_noalloc(int32_t kind, const float *prims, int64_t n, int32_t code_bits,
+                       lbvh_tree *tree, uint32_t *error_out, void *stream)
+{
+    if (!tree || n < 0 || n > LBVH_MAX_PRIMS || (code_bits != 30 && code_bits != 63) ||
+        (kind != LBVH_POINTS && kind != LBVH_BOXES))
+        return LBVH_EINVAL;
+    if (n > LBVH_NOALLOC_MAX_PRIMS) return LBVH_ELIMIT;
+    if (error_out && !aligned(error_out, 4)) return LBVH_EINVAL;
+    if (n == 0) {
+        tree->n = 0;
+        tree->code_bits = code_bits;
+        tree->kind = kind;
+        return LBVH_OK;
+    }
+    if (!prims || !tree->nodes || !tree->codes || !tree->leaf_perm || !aligned(prims, 16) ||
+        !aligned(tree->nodes, 16) || !aligned(tree->codes, 16) || !aligned(tree->leaf_perm, 16))
+        return LBVH_EINVAL;
+    const BuildLayout L = build_layout(n, code_bits);
+    if ((int64_t)L.total > LBVH_NOALLOC_SCRATCH_BYTES) return LBVH_ELIMIT;   // not for n within the limit
+    char *ws = nullptr;
+    if (hipError_t e = noalloc_scratch(&ws); e != hipSuccess) return hip_status(e);
+    tree->n = n;
+    tree->code_bits = code_bits;
+    tree->kind = kind;
+    hipError_t e = launch_build(kind, prims, (int)n, code_bits, tree->nodes, tree->codes,
+                                tree->leaf_perm, ws, L, (hipStream_t)stream);
+    if (e == hipSuccess && error_out) {
+        hipLaunchKernelGGL(k_copy_word, dim3(1), dim3(1), 0, (hipStream_t)stream,
+                           reinterpret_cast<const uint32_t *>(ws + L.ctrl) + kCtrlError, error_out);
+        e = hipGetLastError();
+    }
     return hip_status(e);
 }
 
