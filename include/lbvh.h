@@ -169,6 +169,9 @@ int lbvh_build_noalloc(int32_t kind, const float *prims, int64_t n, int32_t code
 int64_t lbvh_query_workspace_bytes(int64_t m);
 
 /* Range queries, first of two calls: Alg. 1 per query, counting hits.
+ * The tree descriptor is the one its build filled in (its kind included:
+ * for LBVH_POINTS every leaf box has hi == lo, so the leaf test reads only
+ * the lower corner of each leaf record).
  * Sphere j is xyzr[j] = (x, y, z, r), r >= 0: a node or primitive box B
  * matches if d = per-axis max(B.lo - c, c - B.hi, 0) gives
  * (dx*dx + dy*dy) + dz*dz <= r*r in binary32 (closed ball, no fused
@@ -376,13 +379,17 @@ const char *lbvh_last_hip_error(void);
  *       default 9).  Other values are refused.
  *   "sort_variant32", "sort_variant64": tile shape of the radix passes for
  *       30-bit / 63-bit codes: 0 = 256 threads x 16 keys, 1 = 256 x 8,
- *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8, 6 = 768 x 16
- *       (defaults 4 and 6).  A shape whose tile holds fewer keys than the
- *       digit width needs (4096 for 11-bit digits) or whose tables do not
+ *       2 = 256 x 24, 3 = 512 x 8, 4 = 512 x 16, 5 = 1024 x 8, 6 = 768 x 16,
+ *       7 = 1024 x 16, 8 = 512 x 24 (defaults 4 and 6).  A shape whose tile
+ *       holds fewer keys than the digit width needs (4096 for 11-bit digits) or whose tables do not
  *       fit the LDS runs as 512 x 16 (30-bit) or 512 x 8 (63-bit).
  *   "batch_sort_variant": tile shape of the batched build's segmented
  *       radix passes: 0 = 256 x 16 (default), 1 = 256 x 8, 2 = 512 x 8,
  *       3 = 512 x 16 (1 runs as 0 with 11-bit digits).
+ *   "batch_sort_mode": how the batched build sorts: 0 = segmented radix
+ *       passes over all scenes (default), 1 = one block per scene, which
+ *       computes the scene's box and codes and runs every pass over the
+ *       scene itself (no look-back between blocks).
  *   "query_split1", "query_split2": the single-tree count call cuts each
  *       query's Alg. 1 walk into pieces at aligned blocks of 2^split1
  *       leaves, then cuts those at blocks of 2^split2 leaves, and walks the
@@ -406,9 +413,10 @@ const char *lbvh_last_hip_error(void);
  *       of each walk of a count call (0 = no cap beyond 2n, the default).
  *       A walk that hits the cap stops; lbvh_query_check then reports it.
  *   "morton_order": 1 = the single-tree build's Morton-code kernel sweeps
- *       the primitives from the end of the array to its start (the
- *       opposite of the scene-box pass before it), 0 = from the start
- *       (default).
+ *       the primitives from the end of the array to its start, the
+ *       opposite of the scene-box pass before it, so its first reads find
+ *       that pass's last lines in the last-level cache (default); 0 = from
+ *       the start.
  * Results never depend on the knobs other than query_walk_budget; only
  * speed does.  Calls already enqueued keep the shapes they were enqueued
  * with. */

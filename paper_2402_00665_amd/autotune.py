@@ -24,16 +24,18 @@ from . import (LBVH_POINTS, Workspace, alloc_tree, build, build_batched, check_b
                lbvh_tune, query_count, query_fill)
 
 KNOB_CANDIDATES = {
-    "sort_variant32": list(range(7)),
-    "sort_variant64": list(range(7)),
+    "sort_variant32": list(range(9)),
+    "sort_variant64": list(range(9)),
     "batch_sort_variant": list(range(4)),
+    "batch_sort_mode": [0, 1],
     "radix_bits32": [8, 10],
     "radix_bits64": [8, 9, 11],
 }
 # (query_split1, query_split2, query_leaf_mode, query_order): each split
 # schedule with the queries as given and in Morton order
+# (blocks larger than the tree: each query one plain Alg. 1 walk by one lane)
 _SPLITS = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (12, 6, 0), (13, 7, 0), (11, 6, 0),
-           (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1)]
+           (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1), (24, 24, 0)]
 QUERY_CANDIDATES = [s + (o,) for o in (0, 1) for s in _SPLITS]
 _QUERY_KNOBS = ("query_split1", "query_split2", "query_leaf_mode", "query_order")
 
@@ -129,9 +131,16 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
         kind = LBVH_POINTS if prims.shape[1] == 3 else 1
     batched = seg_off is not None
     wk, sk = sort_knobs(code_bits, batched)
-    default = (lbvh_tune(wk), lbvh_tune(sk))
+    # batched builds also choose between the segmented passes (mode 0, each
+    # tile shape) and one block per scene (mode 1, no tile shape): the shape
+    # slot then holds -1
+    mode0 = lbvh_tune("batch_sort_mode") if batched else 0
+    default = (lbvh_tune(wk), lbvh_tune(sk) if mode0 == 0 else -1)
     cands = [(b, v) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
+    if batched:
+        cands += [(b, -1) for b in KNOB_CANDIDATES[wk]]
     order = [default] + [c for c in cands if c != default]
+    shape0 = lbvh_tune(sk)
     ws = Workspace(prims.device)
     n = int(prims.shape[0])
     if batched:
@@ -143,7 +152,10 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
     try:
         for b, v in order:
             lbvh_tune(wk, b)
-            lbvh_tune(sk, v)
+            if batched:
+                lbvh_tune("batch_sort_mode", 1 if v < 0 else 0)
+            if v >= 0:
+                lbvh_tune(sk, v)
             t = (_time_batched(prims, seg_off, code_bits, kind, max_scene, ws, obj, reps) if batched
                  else _time_single(prims, code_bits, kind, ws, obj, reps))
             out = torch.cat([obj.nodes.flatten(), obj.leaf_perm]).clone()
@@ -156,9 +168,16 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
                 print(f"[autotune] {wk}={b} {sk}={v}: {t * 1e3:.1f} us per build", flush=True)
     finally:
         lbvh_tune(wk, default[0])
-        lbvh_tune(sk, default[1])
+        lbvh_tune(sk, shape0)
+        if batched:
+            lbvh_tune("batch_sort_mode", mode0)
     best = min(times, key=times.get)
-    knobs = dict(zip((wk, sk), (int(x) for x in best.split("/"))))
+    b_best, v_best = (int(x) for x in best.split("/"))
+    if batched:
+        knobs = {wk: b_best, "batch_sort_mode": 1 if v_best < 0 else 0,
+                 sk: v_best if v_best >= 0 else shape0}
+    else:
+        knobs = {wk: b_best, sk: v_best}
     if save:
         cache = _load()
         cache[_key(sk, code_bits, kind, n)] = {"knobs": knobs, "times_ms": times}

@@ -25,6 +25,8 @@ namespace {
 
 constexpr int kPlanThreads = 1024;
 constexpr int kSceneThreads = 512;
+constexpr int kSceneSortThreads = 256;   // one-block-per-scene sort: tile of 256 x 16 keys
+constexpr int kSceneSortItems = 16;
 
 __device__ __forceinline__ int64_t scene_size(const int64_t *seg_off, int s)
 {
@@ -39,10 +41,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t *__re
                                                              int S, int levels, int tile,
                                                              int32_t *__restrict__ tile_off,
                                                              int32_t *__restrict__ blk_off,
-                                                             uint32_t *__restrict__ ctrl)
+                                                             uint32_t *__restrict__ ctrl,
+                                                             int32_t *__restrict__ order)
 {
     __shared__ uint32_t sh[kPlanThreads / 64];
     __shared__ uint32_t s_total;
+    __shared__ uint32_t s_len[32];   // scenes per bit length of their size, then cursors
+    if (threadIdx.x < 32) s_len[threadIdx.x] = 0u;
     for (int w = threadIdx.x; w < kCtrlWords; w += kPlanThreads) ctrl[w] = 0u;
     uint32_t carry_t = 0;
     uint32_t carry_b[kMaxBatchLevels + 1] = {};
@@ -69,6 +74,25 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t *__re
         tile_off[S] = (int32_t)carry_t;
         for (int L = 0; L <= levels; ++L) blk_off[L * (S + 1) + S] = (int32_t)carry_b[L];
     }
+    // the scenes in decreasing bit length of their size (for the one-block-
+    // per-scene sort: the longest blocks start first); any order within a
+    // length
+    auto len_of = [&](int s) {
+        const uint64_t n = (uint64_t)scene_size(seg_off, s);
+        return n ? 64 - __clzll(n) : 0;   // 0 .. 31
+    };
+    for (int s = threadIdx.x; s < S; s += kPlanThreads) atomicAdd(&s_len[len_of(s)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t at = 0;
+        for (int l = 31; l >= 0; --l) {
+            const uint32_t c = s_len[l];
+            s_len[l] = at;
+            at += c;
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < S; s += kPlanThreads) order[atomicAdd(&s_len[len_of(s)], 1u)] = s;
 }
 
 // One block per scene: scene box (min/max), scale 2^b / extent, Morton codes
@@ -135,6 +159,211 @@ __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
     for (int j = threadIdx.x; j < PASSES * R; j += kSceneThreads) hs[j] = lh[j];
     const int64_t w0 = (int64_t)tile_off[s] * R, w1 = (int64_t)tile_off[s + 1] * R;
     for (int64_t w = w0 + threadIdx.x; w < w1; w += kSceneThreads) status0[w] = 0u;
+}
+
+// ------------------------------------------------- one block per scene
+//
+// The other sort schedule of the batched build ("batch_sort_mode" 1): one
+// block takes one whole scene (scenes in decreasing size, so the longest
+// blocks start first) and runs every step up to the sorted codes itself:
+// scene box and scale, the codes with every pass's digit histogram, then
+// each LSD pass over the scene in tiles of T*I keys.  A tile is ranked
+// stably with wave64 ballots (as in the onesweep pass) and scattered
+// through LDS so that global writes are runs of equal digits; the block's
+// running start of each digit carries over from tile to tile, so no tile
+// waits for another block (no look-back), and scenes need no tile plan.
+// Global writes of one pass are read by the next pass of the same block
+// after a workgroup barrier.
+template <int KIND, typename K, int BITS, int T, int I>
+__global__ __launch_bounds__(T) void k_scene_sort(
+    const float *__restrict__ prims, const int64_t *__restrict__ seg_off,
+    const int32_t *__restrict__ order, int code_bits, float4 *__restrict__ scene_box, K *key_a,
+    K *key_b, int32_t *val_a, int32_t *val_b, int32_t *__restrict__ perm_out, uint32_t *err)
+{
+    constexpr int R = 1 << BITS;
+    constexpr int W = T / 64;
+    constexpr int TILE = T * I;
+    constexpr int DPT = (R + T - 1) / T;
+    constexpr int PASSES = ((sizeof(K) == 4 ? 30 : 63) + BITS - 1) / BITS;
+    static_assert(TILE < 65536, "16-bit per-wave digit counters");
+    using Cnt = typename std::conditional<(BITS <= 9), uint32_t, uint16_t>::type;
+    using P = Prims<KIND>;
+    __shared__ __align__(16) Cnt s_wcnt[W][R];
+    __shared__ uint32_t s_start[R];   // tile-local start of each digit run
+    __shared__ uint32_t s_run[R];     // scene-local start of the digit's next run
+    __shared__ uint32_t s_hist[PASSES * R];
+    __shared__ uint32_t s_scan[2][W];
+    __shared__ K s_buf[TILE];
+    __shared__ float sh[W * 6];
+    __shared__ float4 s_box[3];
+
+    const int s = order[blockIdx.x];
+    const int64_t b0 = seg_off[s];
+    const int64_t ns64 = seg_off[s + 1] - b0;
+    if (ns64 == 0) return;
+    const uint32_t ns = (uint32_t)ns64;   // a scene holds fewer than 2^30 primitives
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = tid; j < PASSES * R; j += T) s_hist[j] = 0u;
+
+    // scene box and scale (2^b / extent, correctly rounded; 0 when flat)
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (uint32_t i = tid; i < ns; i += T) {
+        float lo[3], hi[3];
+        P::one(prims, b0 + i, lo, hi);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { v[a] = fminf(v[a], lo[a]); v[3 + a] = fmaxf(v[3 + a], hi[a]); }
+    }
+    block_minmax6<T>(v, sh);
+    if (tid == 0) {
+        const float two_b = (float)(1u << (code_bits / 3));
+        float sc[3];
+        for (int a = 0; a < 3; ++a) {
+            const float ext = v[3 + a] - v[a];
+            sc[a] = ext > 0.0f ? __fdiv_rn(two_b, ext) : 0.0f;
+        }
+        s_box[0] = make_float4(v[0], v[1], v[2], 0.0f);
+        s_box[1] = make_float4(v[3], v[4], v[5], 0.0f);
+        s_box[2] = make_float4(sc[0], sc[1], sc[2], 0.0f);
+        scene_box[3 * s + 0] = s_box[0];
+        scene_box[3 * s + 1] = s_box[1];
+        scene_box[3 * s + 2] = s_box[2];
+    }
+    __syncthreads();
+    // codes in input order, and every pass's digit counts
+    {
+        const float4 slo = s_box[0], sc = s_box[2];
+        for (uint32_t i = tid; i < ns; i += T) {
+            float lo[3], hi[3];
+            P::one(prims, b0 + i, lo, hi);
+            const K c = code_of<KIND, K>(lo, hi, slo, sc);
+            key_a[b0 + i] = c;
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p)
+                atomicAdd(&s_hist[p * R + (uint32_t)((c >> (p * BITS)) & (R - 1))], 1u);
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    const int d0 = tid * DPT;
+    auto owns = [&](int k) { return d0 + k < R; };
+    for (int p = 0; p < PASSES; ++p) {
+        const K *kin = (p & 1) ? key_b : key_a;
+        K *kout = (p & 1) ? key_a : key_b;
+        const int32_t *vin = p == 0 ? nullptr : ((p & 1) ? val_a : val_b);
+        int32_t *vout = p + 1 == PASSES ? perm_out : ((p & 1) ? val_b : val_a);
+        const int shift = p * BITS;
+        const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
+        {   // the scene-local start of each digit in this pass
+            uint32_t h[DPT], st[DPT];
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) h[k] = owns(k) ? s_hist[p * R + d0 + k] : 0u;
+            digits_excl_scan<T, DPT>(h, st, s_scan[0]);
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (owns(k)) s_run[d0 + k] = st[k];
+        }
+        for (uint32_t base = 0; base < ns; base += TILE) {
+            constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
+            for (int j = tid; j < kZeroWords; j += T) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
+            __syncthreads();
+            const uint32_t rem = ns - base < (uint32_t)TILE ? ns - base : (uint32_t)TILE;
+            const uint32_t lofs = (uint32_t)(wave * 64 * I + lane);
+            K key[I];
+            int32_t val[I];
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                const bool ok = lofs + k * 64 < rem;
+                const int64_t at = b0 + base + lofs + k * 64;
+                key[k] = ok ? kin[at] : (K)0;
+                val[k] = vin ? (ok ? vin[at] : 0) : (int32_t)(base + lofs + k * 64);
+            }
+            // stable rank within the wave, as in the onesweep pass
+            uint32_t rank[I];
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                const bool ok = lofs + k * 64 < rem;
+                const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
+                uint64_t diff = 0;
+#pragma unroll
+                for (int b = 0; b < BITS; ++b) {
+                    if (b < nbits) {
+                        const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                        diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
+                    }
+                }
+                const uint64_t peers = __ballot(ok) & ~diff;
+                const uint32_t below = count_below(peers);
+                const uint32_t cnt = s_wcnt[wave][d];
+                rank[k] = cnt + below;
+                if (ok && below == 0) s_wcnt[wave][d] = (Cnt)(cnt + (uint32_t)__popcll(peers));
+            }
+            __syncthreads();
+            // per-wave exclusive offsets and the tile's digit totals
+            uint32_t total[DPT], start[DPT];
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) {
+                total[k] = 0;
+                if (owns(k)) {
+                    const int d = d0 + k;
+                    uint32_t c[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) { s_wcnt[w][d] = (Cnt)total[k]; total[k] += c[w]; }
+                }
+            }
+            digits_excl_scan<T, DPT>(total, start, s_scan[1]);
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (owns(k)) s_start[d0 + k] = start[k];
+            __syncthreads();
+            uint32_t pos[I];
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
+                pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
+            }
+#pragma unroll
+            for (int k = 0; k < I; ++k)
+                if (lofs + k * 64 < rem) s_buf[pos[k]] = key[k];
+            __syncthreads();
+            uint32_t dst[I];
+#pragma unroll
+            for (int k = 0; k < I; ++k) {
+                const uint32_t q = (uint32_t)(k * T + tid);
+                dst[k] = ~0u;
+                if (q < rem) {
+                    const K kk = s_buf[q];
+                    const uint32_t dk = (uint32_t)(kk >> shift) & (R - 1);
+                    const uint32_t out = s_run[dk] + q - s_start[dk];   // < ns by construction
+                    if (out < ns) {
+                        kout[b0 + out] = kk;
+                        dst[k] = out;
+                    } else {   // inconsistent counts: flag it rather than write outside
+                        __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+            }
+            __syncthreads();
+            int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
+#pragma unroll
+            for (int k = 0; k < I; ++k)
+                if (lofs + k * 64 < rem) s_vals[pos[k]] = val[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < I; ++k)
+                if (dst[k] != ~0u) vout[b0 + dst[k]] = s_vals[k * T + tid];
+            // the next tile's runs of each digit follow this tile's
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (owns(k)) s_run[d0 + k] += total[k];
+            __syncthreads();
+        }
+        // this pass's writes are the next pass's reads (same block)
+        __threadfence_block();
+        __syncthreads();
+    }
 }
 
 // Alg. 1 for query j on the tree of its scene (no splitting: batched
@@ -334,6 +563,23 @@ void run_batch_sort(const float *prims, const int64_t *seg_off, int S, int64_t N
     }
 }
 
+// The one-block-per-scene sort: codes go to the key buffer that makes the
+// last pass end in the batch's codes array.
+template <int KIND, typename K, int B>
+void run_scene_sort(const float *prims, const int64_t *seg_off, const int32_t *order, int S,
+                    int code_bits, K *codes, int32_t *leaf_perm, float4 *scene_box, K *keys_alt,
+                    int32_t *vals[2], uint32_t *err, hipStream_t s)
+{
+    constexpr int T = kSceneSortThreads, I = kSceneSortItems;
+    const int passes = radix_passes(code_bits, B);
+    K *ka = (passes & 1) ? keys_alt : codes;
+    K *kb = (passes & 1) ? codes : keys_alt;
+    prof_begin(K_SORT, s);
+    hipLaunchKernelGGL((k_scene_sort<KIND, K, B, T, I>), dim3(S), dim3(T), 0, s, prims, seg_off, order,
+                       code_bits, scene_box, ka, kb, vals[0], vals[1], leaf_perm, err);
+    prof_end(K_SORT, s);
+}
+
 template <int KIND, typename K>
 hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t N, int levels,
                      int code_bits, lbvh_node *nodes_, K *codes, int32_t *leaf_perm, char *ws,
@@ -350,43 +596,74 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
     int32_t *vals[2] = {reinterpret_cast<int32_t *>(ws + L.vals[0]),
                         reinterpret_cast<int32_t *>(ws + L.vals[1])};
     int32_t *store = reinterpret_cast<int32_t *>(ws + L.store);
-    int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
+    Climb *pend[2] = {reinterpret_cast<Climb *>(ws + L.pend[0]), reinterpret_cast<Climb *>(ws + L.pend[1])};
     float4 *nodes = reinterpret_cast<float4 *>(nodes_);
 
     const int bits = radix_bits(code_bits);
     const int variant = batch_sort_variant(bits);
     const int tile = kBatchShapes[variant].threads * kBatchShapes[variant].items;
+    int32_t *order = reinterpret_cast<int32_t *>(ws + L.order);
     prof_begin(K_BATCH_PREP, s);
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile,
-                       tile_off, blk_off, ctrl);
+                       tile_off, blk_off, ctrl, order);
+    if (tune_get(TUNE_BATCH_SORT_MODE) == 1) {
+        prof_end(K_BATCH_PREP, s);
+#define LBVH_SSORT_ARGS prims, seg_off, order, S, code_bits, codes, leaf_perm, scene_box, keys_alt, \
+                        vals, ctrl + kCtrlError, s
+        if constexpr (sizeof(K) == 4) {
+            if (bits == 10) run_scene_sort<KIND, K, 10>(LBVH_SSORT_ARGS);
+            else run_scene_sort<KIND, K, 8>(LBVH_SSORT_ARGS);
+        } else {
+            if (bits == 11) run_scene_sort<KIND, K, 11>(LBVH_SSORT_ARGS);
+            else if (bits == 9) run_scene_sort<KIND, K, 9>(LBVH_SSORT_ARGS);
+            else run_scene_sort<KIND, K, 8>(LBVH_SSORT_ARGS);
+        }
+#undef LBVH_SSORT_ARGS
+    } else {
 #define LBVH_BSORT_ARGS prims, seg_off, S, N, code_bits, codes, leaf_perm, tile_off, scene_box, ctrl, \
                         hist, status, keys_alt, vals, variant, s
-    if constexpr (sizeof(K) == 4) {
-        if (bits == 10) run_batch_sort<KIND, K, 10>(LBVH_BSORT_ARGS);
-        else run_batch_sort<KIND, K, 8>(LBVH_BSORT_ARGS);
-    } else {
-        if (bits == 11) run_batch_sort<KIND, K, 11>(LBVH_BSORT_ARGS);
-        else if (bits == 9) run_batch_sort<KIND, K, 9>(LBVH_BSORT_ARGS);
-        else run_batch_sort<KIND, K, 8>(LBVH_BSORT_ARGS);
-    }
+        if constexpr (sizeof(K) == 4) {
+            if (bits == 10) run_batch_sort<KIND, K, 10>(LBVH_BSORT_ARGS);
+            else run_batch_sort<KIND, K, 8>(LBVH_BSORT_ARGS);
+        } else {
+            if (bits == 11) run_batch_sort<KIND, K, 11>(LBVH_BSORT_ARGS);
+            else if (bits == 9) run_batch_sort<KIND, K, 9>(LBVH_BSORT_ARGS);
+            else run_batch_sort<KIND, K, 8>(LBVH_BSORT_ARGS);
+        }
 #undef LBVH_BSORT_ARGS
+    }
 
     prof_begin(K_BOTTOMUP, s);
     BatchLevel bl{seg_off, blk_off, nullptr, S, levels == 0};
     // delta* bytes for the upper levels: in the sort's other key buffer, free now
     uint8_t *dstar = reinterpret_cast<uint8_t *>(keys_alt);
-    hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3((unsigned)L.blocks_max[0]), dim3(kBU0Threads),
-                       0, s, codes, leaf_perm, prims, (int)N, store, nodes, pend[0], bl, dstar,
-                       ctrl + kCtrlError);
+    // packed store words when the levels cover at most 2^24 leaves per
+    // scene (a larger scene is flagged as beyond the cover, never built)
+    int64_t cover = kChunk;
+    for (int lv = 0; lv < levels; ++lv) cover *= kFanout;
+    const bool packed = cover <= kPackedMaxN;
+    if (packed)
+        hipLaunchKernelGGL((k_bottomup_l0<KIND, K, true>), dim3((unsigned)L.blocks_max[0]),
+                           dim3(kBU0Threads), 0, s, codes, leaf_perm, prims, (int)N, store, nodes,
+                           pend[0], bl, dstar, ctrl + kCtrlError);
+    else
+        hipLaunchKernelGGL((k_bottomup_l0<KIND, K, false>), dim3((unsigned)L.blocks_max[0]),
+                           dim3(kBU0Threads), 0, s, codes, leaf_perm, prims, (int)N, store, nodes,
+                           pend[0], bl, dstar, ctrl + kCtrlError);
     prof_end(K_BOTTOMUP, s);
     int64_t span = kChunk;
     for (int lv = 1; lv <= levels; ++lv) {
         const int64_t next = span * kFanout;
         BatchLevel up{seg_off, blk_off + lv * (S + 1), blk_off + (lv - 1) * (S + 1), S, lv == levels};
         prof_begin(K_BOTTOMUP_UP, s);
-        hipLaunchKernelGGL(k_bottomup_up, dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads), 0, s,
-                           dstar, (int)N, span, next, store, nodes, pend[(lv - 1) & 1], pend[lv & 1],
-                           up, ctrl + kCtrlError);
+        if (packed)
+            hipLaunchKernelGGL(k_bottomup_up<true>, dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads),
+                               0, s, dstar, (int)N, span, next, store, nodes, pend[(lv - 1) & 1],
+                               pend[lv & 1], up, ctrl + kCtrlError);
+        else
+            hipLaunchKernelGGL(k_bottomup_up<false>, dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads),
+                               0, s, dstar, (int)N, span, next, store, nodes, pend[(lv - 1) & 1],
+                               pend[lv & 1], up, ctrl + kCtrlError);
         prof_end(K_BOTTOMUP_UP, s);
         span = next;
     }

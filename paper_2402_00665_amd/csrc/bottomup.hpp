@@ -28,9 +28,24 @@ namespace {
 // the second thread to arrive, exactly as in Alg. 4.
 
 //
-// Level 0 computes delta* of its boundaries from the codes in LDS and also
-// stores them as one byte each (`dstar`, in a buffer the sort no longer
-// needs); the upper levels read those bytes instead of pairs of codes.
+// A climb handed to the level above carries its whole state (a Climb:
+// node, leaf range, rope, delta* at the range's two outer boundaries, box),
+// so the level above starts it without a load.  A climb that arrives first
+// at a split p parks there: `store[p]` gets its far end and, for trees of
+// at most 2^24 leaves (PACKED), delta* at its outer boundary on that side
+// in the same word.  The second arriver then learns both from its
+// compare-and-swap, and takes the parked sibling's box and rope from the
+// sibling's record, which it loads together with the CAS: the sibling is
+// node p+1 (or p) as a leaf or as an internal node, so both candidate
+// records are loaded and the CAS result picks one.  One global round trip
+// per climb step.  (A parent's rope is its right child's: Alg. 2 makes a
+// node's rope depend only on the right end of its range.)  Climbs that
+// meet within one upper-level launch exchange their state through LDS:
+// the first marks `store[p]` with its thread and leaves its state in its
+// LDS slot, and at the end of the launch every such mark becomes the
+// parked word for the levels above.  Larger trees keep the far end alone
+// in `store` and read delta* from one byte per boundary that level 0 writes
+// (`dstar`, in a buffer the sort no longer needs).
 //
 // Batched trees: every scene is its own problem (local leaf and node ids);
 // its leaves sit at seg_off[s] in the sorted arrays and its 2n_s-1 node
@@ -45,6 +60,43 @@ struct BatchLevel {
     int last;                  // top level: no climb may stop at a boundary
 };
 
+struct Climb {
+    int4 id;     // node, rl, rr, rope (node -1: empty slot)
+    float4 lo;   // lo.xyz; w: delta*(rl-1) | delta*(rr) << 8, as bits
+    float4 hi;   // hi.xyz; w: 0
+};
+
+__device__ __forceinline__ Climb make_climb(int node, int rl, int rr, int rope, int dl, int dr,
+                                            const float lo[3], const float hi[3])
+{
+    Climb c;
+    c.id = make_int4(node, rl, rr, rope);
+    c.lo = make_float4(lo[0], lo[1], lo[2], __int_as_float(dl | (dr << 8)));
+    c.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    return c;
+}
+
+__device__ __forceinline__ Climb empty_climb()
+{
+    Climb c;
+    c.id = make_int4(-1, 0, 0, 0);
+    c.lo = c.hi = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return c;
+}
+
+// Packed `store` word: far end in bits 0..23, delta* in bits 24..30.  delta*
+// ranks are at most 64 + 62 = 126 for codes and 29 for indices, so 127 can
+// stand for +inf (255); bit 31 stays clear, so no packed word is the empty
+// marker -1 or a same-launch mark (bit 31 set).
+constexpr int kPackedMaxN = 1 << 24;
+__device__ __forceinline__ int32_t pack_park(int far, int d) { return far | ((d > 127 ? 127 : d) << 24); }
+__device__ __forceinline__ int park_far(int32_t v) { return v & 0xFFFFFF; }
+__device__ __forceinline__ int park_delta(int32_t v)
+{
+    const int d = (v >> 24) & 127;
+    return d == 127 ? 255 : d;
+}
+
 __device__ __forceinline__ int scene_of(const int32_t *off, int S, int b)
 {
     int lo = 0, hi = S - 1;   // largest s with off[s] <= b
@@ -56,13 +108,13 @@ __device__ __forceinline__ int scene_of(const int32_t *off, int S, int b)
     return lo;
 }
 
-template <int KIND, typename K>
+template <int KIND, typename K, bool PACKED>
 __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict__ codes_all,
                                                              const int32_t *__restrict__ perm_all,
                                                              const float *__restrict__ prims_all,
                                                              int n_all, int32_t *__restrict__ store_all,
                                                              float4 *__restrict__ nodes_all,
-                                                             int4 *__restrict__ pend, BatchLevel bl,
+                                                             Climb *__restrict__ pend, BatchLevel bl,
                                                              uint8_t *__restrict__ dstar_all,
                                                              uint32_t *err)
 {
@@ -70,7 +122,7 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     __shared__ uint8_t s_delta[kChunk + 2];  // delta*(g) for g in [A-1, B]
     __shared__ int32_t s_store[kChunk];      // store[A .. B-1]
     __shared__ float s_box[6][2 * kChunk];   // internal A.. then leaves A..
-    __shared__ int4 s_pend[2];
+    __shared__ Climb s_pend[2];
 
     // this block's chunk: tree (codes, perm, ... of one scene), leaves [A, B)
     int64_t b0 = 0;
@@ -98,7 +150,7 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
         s_codes[t] = (g >= 0 && g < n) ? codes[g] : (K)0;
     }
     s_store[tid] = -1;
-    if (tid < 2) s_pend[tid] = make_int4(-1, 0, 0, 0);
+    if (tid < 2) s_pend[tid] = empty_climb();
     // this thread's leaf i: primitive id and box (a gather), loaded while
     // the codes arrive
     const int i = A + tid;
@@ -122,9 +174,10 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     };
     for (int t = tid; t < cn + 2; t += kBU0Threads) s_delta[t] = (uint8_t)delta_codes(A - 1 + t);
     // leaf record: box, primitive id, rope (Alg. 2 on the range [i, i])
+    int rope = -1;
     if (i < B) {
         const int dr = delta_codes(i);
-        const int rope = (i == n - 1) ? -1 : (dr < delta_codes(i + 1) ? leaf0 + i + 1 : i + 1);
+        rope = (i == n - 1) ? -1 : (dr < delta_codes(i + 1) ? leaf0 + i + 1 : i + 1);
         store_node(nodes, leaf0 + i, lo, prim, hi, rope);
         const int sl = kChunk + tid;
 #pragma unroll
@@ -136,8 +189,9 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     // child) run the same instructions with selects, so a wave whose lanes
     // disagree does not run both.
     auto delta = [&](int g) -> int { return s_delta[g - A + 1]; };
-    // this chunk's boundaries g in [A, B), g < n-1, for the upper levels
-    if (i < B && i < n - 1) dstar_all[b0 + i] = s_delta[tid + 1];
+    // this chunk's boundaries g in [A, B), g < n-1, for the upper levels of
+    // a tree whose store words cannot carry delta*
+    if (!PACKED && i < B && i < n - 1) dstar_all[b0 + i] = s_delta[tid + 1];
     if (n > 1 && i < B) {
         int rl = i, rr = i, cur = leaf0 + i;
         int dl = delta(i - 1), dr = delta(i);
@@ -149,17 +203,20 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
             const bool is_left = dr < dl;              // left child of its parent
             const int p = is_left ? rr : rl - 1;       // the parent's split
             if (p == (is_left ? B - 1 : A - 1)) {      // the parent is split at a chunk edge
-                s_pend[is_left ? 1 : 0] = make_int4(cur, rl, rr, 0);
+                s_pend[is_left ? 1 : 0] = make_climb(cur, rl, rr, rope, dl, dr, lo, hi);
                 break;
             }
             int other = -1;
-            if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, is_left ? rl : rr,
+            const int far_mine = is_left ? rl : rr;   // this node's far end, seen from p
+            const int32_t park = PACKED ? pack_park(far_mine, is_left ? dl : dr) : far_mine;
+            if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, park,
                                                      __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
                                                      __HIP_MEMORY_SCOPE_WORKGROUP))
                 break;                                 // first to arrive
-            // second to arrive: `other` is the sibling's far end
-            rr = is_left ? other : rr;
-            rl = is_left ? rl : other;
+            // second to arrive: `other` holds the sibling's far end
+            const int far = PACKED ? park_far(other) : other;
+            rr = is_left ? far : rr;
+            rl = is_left ? rl : far;
             const int dn = delta(is_left ? rr : rl - 1);
             dr = is_left ? dn : dr;
             dl = is_left ? dl : dn;
@@ -180,27 +237,33 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
 #pragma unroll
             for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
             cur = q;
+            rope = qrope;
             if (q == 0) break;
         }
     }
     __syncthreads();
     if (tid < cn) store[A + tid] = s_store[tid];
     if (tid < 2) {
-        const int4 st = s_pend[tid];
-        if (bl.last && st.x >= 0)   // a climb stopped below the root of its tree
+        const Climb st = s_pend[tid];
+        if (bl.last && st.id.x >= 0)   // a climb stopped below the root of its tree
             __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         pend[2 * blockIdx.x + tid] = st;
     }
 }
 
+template <bool PACKED>
 __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__restrict__ dstar_all,
                                                             int n_all, int64_t child_span, int64_t span,
                                                             int32_t *store_all, float4 *nodes_all,
-                                                            const int4 *__restrict__ pend_in,
-                                                            int4 *__restrict__ pend_out, BatchLevel bl,
+                                                            const Climb *__restrict__ pend_in,
+                                                            Climb *__restrict__ pend_out, BatchLevel bl,
                                                             uint32_t *err)
 {
-    __shared__ int4 s_pend[2];
+    // a climb parked in this launch: lo.xyz + far end (packed with delta*
+    // if PACKED), hi.xyz + rope; delta* apart otherwise
+    __shared__ float4 s_state[kBUThreads][2];
+    __shared__ uint8_t s_dfar[PACKED ? 1 : kBUThreads];
+    __shared__ Climb s_pend[2];
     // this block's span [A, B) of one tree and the handed-over slots of its
     // child blocks
     int64_t b0 = 0, slot_lo, slot_hi, A, B;
@@ -227,20 +290,23 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__res
     int32_t *store = store_all + b0;
     float4 *nodes = nodes_all + 4 * b0;
     const int leaf0 = n - 1;
+    const int tid = threadIdx.x;
     // delta*(g), +inf (255) outside [0, n-2], as level 0 stored it
     auto delta = [&](int g) -> int { return (g < 0 || g >= n - 1) ? 255 : (int)dstar[g]; };
-    if (threadIdx.x < 2) s_pend[threadIdx.x] = make_int4(-1, 0, 0, 0);
+    if (tid < 2) s_pend[tid] = empty_climb();
     __syncthreads();
 
-    for (int64_t slot = slot_lo + threadIdx.x; slot < slot_hi; slot += kBUThreads) {
-        const int4 P = pend_in[slot];
-        if (P.x < 0) continue;
-        int cur = P.x, rl = P.y, rr = P.z;
-        const float4 *own = nodes + 2 * (int64_t)cur;
-        const float4 o0 = own[0], o1 = own[1];
-        float lo[3] = {o0.x, o0.y, o0.z}, hi[3] = {o1.x, o1.y, o1.z};
-        int dl = delta(rl - 1), dr = delta(rr);
-        for (int level = 0;; ++level) {
+    int park_at = -1;      // the split this thread parked at in this launch
+    int32_t park_word = 0; // ... and the store word the levels above read
+    // at most kFanout child blocks, two slots each: one per thread
+    const int64_t slot = slot_lo + tid;
+    if (slot < slot_hi) {
+        const Climb c = pend_in[slot];
+        int cur = c.id.x, rl = c.id.y, rr = c.id.z, rope = c.id.w;
+        const int dd = __float_as_int(c.lo.w);
+        int dl = dd & 0xff, dr = (dd >> 8) & 0xff;
+        float lo[3] = {c.lo.x, c.lo.y, c.lo.z}, hi[3] = {c.hi.x, c.hi.y, c.hi.z};
+        for (int level = 0; cur >= 0; ++level) {
             if (level == kMaxDepth) {
                 __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
@@ -248,42 +314,69 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__res
             const bool is_left = dr < dl;              // left child of its parent
             const int p = is_left ? rr : rl - 1;       // the parent's split
             if (p == (is_left ? B - 1 : A - 1)) {      // split at this block's edge
-                s_pend[is_left ? 1 : 0] = make_int4(cur, rl, rr, 0);
+                s_pend[is_left ? 1 : 0] = make_climb(cur, rl, rr, rope, dl, dr, lo, hi);
                 break;
             }
+            // a sibling parked by a lower level is node ci (internal) or
+            // leaf ci: load both records while the CAS is in flight
+            const int ci = is_left ? p + 1 : p;        // <= n-1: in bounds either way
+            const float4 *ip = nodes + 2 * (int64_t)ci, *lp = nodes + 2 * (int64_t)(leaf0 + ci);
+            const float4 i0 = ip[0], i1 = ip[1], l0 = lp[0], l1 = lp[1];
+            // publish this climb's state for a sibling in this launch, then
+            // claim p with this thread's mark
+            const int far_mine = is_left ? rl : rr;
+            const int d_mine = is_left ? dl : dr;
+            const int32_t word = PACKED ? pack_park(far_mine, d_mine) : far_mine;
+            s_state[tid][0] = make_float4(lo[0], lo[1], lo[2], __int_as_float(word));
+            s_state[tid][1] = make_float4(hi[0], hi[1], hi[2], __int_as_float(rope));
+            if (!PACKED) s_dfar[PACKED ? 0 : tid] = (uint8_t)d_mine;
             int other = -1;
-            if (__hip_atomic_compare_exchange_strong(&store[p], &other, is_left ? rl : rr,
+            if (__hip_atomic_compare_exchange_strong(&store[p], &other, (int32_t)(0x80000000u | tid),
                                                      __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
-                break;                                 // first to arrive
-            rr = is_left ? other : rr;
-            rl = is_left ? rl : other;
-            const int sib = is_left ? ((p + 1 == rr) ? leaf0 + p + 1 : p + 1)
-                                    : ((rl == p) ? leaf0 + p : p);
-            // the sibling's box and the two delta* bytes the step needs are
-            // independent loads: issue them together
-            const float4 *sp = nodes + 2 * (int64_t)sib;
-            const float4 s0 = sp[0], s1 = sp[1];
-            const int dn = delta(is_left ? rr : rl - 1);
-            const int d_next = delta(rr + 1);   // 255 past the end
-            dr = is_left ? dn : dr;
-            dl = is_left ? dl : dn;
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                park_at = p;                           // first to arrive
+                park_word = word;
+                break;
+            }
+            int far, dfar;
+            float4 s0, s1;
+            if (other < 0) {                           // parked in this launch: LDS
+                const int t = other & 0x7fffffff;
+                s0 = s_state[t][0];
+                s1 = s_state[t][1];
+                const int w = __float_as_int(s0.w);
+                far = PACKED ? park_far(w) : w;
+                dfar = PACKED ? park_delta(w) : (int)s_dfar[PACKED ? 0 : t];
+            } else {                                   // parked by a lower level
+                far = PACKED ? park_far(other) : other;
+                dfar = PACKED ? park_delta(other) : delta(is_left ? far : far - 1);
+                const bool leaf_sib = is_left ? (far == p + 1) : (far == p);
+                s0 = leaf_sib ? l0 : i0;
+                s1 = leaf_sib ? l1 : i1;
+            }
+            rr = is_left ? far : rr;
+            rl = is_left ? rl : far;
+            dr = is_left ? dfar : dr;
+            dl = is_left ? dl : dfar;
+            rope = is_left ? __float_as_int(s1.w) : rope;   // the right child's
             lo[0] = fminf(lo[0], s0.x); lo[1] = fminf(lo[1], s0.y); lo[2] = fminf(lo[2], s0.z);
             hi[0] = fmaxf(hi[0], s1.x); hi[1] = fmaxf(hi[1], s1.y); hi[2] = fmaxf(hi[2], s1.z);
-            const int q = dr < dl ? rr : rl;
+            const int q = dr < dl ? rr : rl;           // Karras index of the parent
             const int left = (rl == p) ? leaf0 + p : p;
-            const int qrope = rr == n - 1 ? -1 : (dr < d_next ? leaf0 + rr + 1 : rr + 1);
-            store_node(nodes, q, lo, left, hi, qrope);
+            store_node(nodes, q, lo, left, hi, rope);
             cur = q;
             if (q == 0) break;
         }
     }
     __syncthreads();
-    if (threadIdx.x < 2) {
-        const int4 st = s_pend[threadIdx.x];
-        if (bl.last && st.x >= 0)
+    // every climb parked in this launch leaves its word for the levels
+    // above (a consumed one is never read again)
+    if (park_at >= 0) store[park_at] = park_word;
+    if (tid < 2) {
+        const Climb st = s_pend[tid];
+        if (bl.last && st.id.x >= 0)
             __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pend_out[2 * blockIdx.x + threadIdx.x] = st;
+        pend_out[2 * blockIdx.x + tid] = st;
     }
 }
 

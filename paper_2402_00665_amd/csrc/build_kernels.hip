@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float *__restrict__ pri
 // exceed the LDS, is replaced by the width's default shape.
 struct SortShape { int threads, items; };
 constexpr SortShape kSortShapes[] = {{256, 16}, {256, 8}, {256, 24}, {512, 8}, {512, 16}, {1024, 8},
-                                     {768, 16}};
+                                     {768, 16}, {1024, 16}, {512, 24}};
 constexpr int kSortShapeCount = sizeof(kSortShapes) / sizeof(kSortShapes[0]);
 
 constexpr size_t sort_lds_bytes(int key_bytes, int threads, int items, int bits)
@@ -202,6 +202,8 @@ void launch_onesweep_b(int variant, const K *kin, K *kout, const int32_t *vin, i
     case 4: launch_one<K, 512, 16, B>(LBVH_SORT_ARGS); break;
     case 5: launch_one<K, 1024, 8, B>(LBVH_SORT_ARGS); break;
     case 6: launch_one<K, 768, 16, B>(LBVH_SORT_ARGS); break;
+    case 7: launch_one<K, 1024, 16, B>(LBVH_SORT_ARGS); break;
+    case 8: launch_one<K, 512, 24, B>(LBVH_SORT_ARGS); break;
     default: launch_one<K, 256, 16, B>(LBVH_SORT_ARGS); break;
     }
 #undef LBVH_SORT_ARGS
@@ -298,13 +300,19 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
     }
 
     prof_begin(K_BOTTOMUP, s);
-    int4 *pend[2] = {reinterpret_cast<int4 *>(ws + L.pend[0]), reinterpret_cast<int4 *>(ws + L.pend[1])};
+    Climb *pend[2] = {reinterpret_cast<Climb *>(ws + L.pend[0]), reinterpret_cast<Climb *>(ws + L.pend[1])};
     int nbu = (n + kChunk - 1) / kChunk;
     BatchLevel one{nullptr, nullptr, nullptr, 1, nbu == 1};
-    // delta* bytes for the upper levels: in the sort's other key buffer, free now
+    // delta* bytes for the upper levels of a tree too large for packed
+    // store words: in the sort's other key buffer, free now
     uint8_t *dstar = reinterpret_cast<uint8_t *>(keys_alt);
-    hipLaunchKernelGGL((k_bottomup_l0<KIND, K>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
-                       leaf_perm, prims, n, store, nodes, pend[0], one, dstar, ctrl + kCtrlError);
+    const bool packed = n <= kPackedMaxN;
+    if (packed)
+        hipLaunchKernelGGL((k_bottomup_l0<KIND, K, true>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
+                           leaf_perm, prims, n, store, nodes, pend[0], one, dstar, ctrl + kCtrlError);
+    else
+        hipLaunchKernelGGL((k_bottomup_l0<KIND, K, false>), dim3(nbu), dim3(kBU0Threads), 0, s, codes,
+                           leaf_perm, prims, n, store, nodes, pend[0], one, dstar, ctrl + kCtrlError);
     prof_end(K_BOTTOMUP, s);
     int64_t span = kChunk;
     int in = 0;
@@ -313,8 +321,12 @@ hipError_t run_build(const float *prims, int n, int code_bits, lbvh_node *nodes_
         const int nbn = (int)((n + next - 1) / next);
         one.last = nbn == 1;
         prof_begin(K_BOTTOMUP_UP, s);
-        hipLaunchKernelGGL(k_bottomup_up, dim3(nbn), dim3(kBUThreads), 0, s, dstar, n, span,
-                           next, store, nodes, pend[in], pend[in ^ 1], one, ctrl + kCtrlError);
+        if (packed)
+            hipLaunchKernelGGL(k_bottomup_up<true>, dim3(nbn), dim3(kBUThreads), 0, s, dstar, n, span,
+                               next, store, nodes, pend[in], pend[in ^ 1], one, ctrl + kCtrlError);
+        else
+            hipLaunchKernelGGL(k_bottomup_up<false>, dim3(nbn), dim3(kBUThreads), 0, s, dstar, n, span,
+                               next, store, nodes, pend[in], pend[in ^ 1], one, ctrl + kCtrlError);
         prof_end(K_BOTTOMUP_UP, s);
         in ^= 1;
         span = next;

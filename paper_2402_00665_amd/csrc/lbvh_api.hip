@@ -33,8 +33,8 @@ BuildLayout build_layout(int64_t n, int code_bits)
     L.store = take((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
     const int64_t nb0 = (n + kChunk - 1) / kChunk;
     const int64_t nb1 = (n + (int64_t)kChunk * kFanout - 1) / ((int64_t)kChunk * kFanout);
-    L.pend[0] = take((size_t)(2 * nb0 + 2) * 16);
-    L.pend[1] = take((size_t)(2 * nb1 + 2) * 16);
+    L.pend[0] = take((size_t)(2 * nb0 + 2) * kClimbBytes);
+    L.pend[1] = take((size_t)(2 * nb1 + 2) * kClimbBytes);
     L.total = off;
     return L;
 }
@@ -111,6 +111,7 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
     L.ctrl = take(kCtrlWords * sizeof(uint32_t));
     L.scene_box = take((size_t)S * 3 * sizeof(float4));
     L.tile_off = take((size_t)(S + 1) * sizeof(int32_t));
+    L.order = take((size_t)(S > 0 ? S : 1) * sizeof(int32_t));
     L.blk_off = take((size_t)(L.levels + 1) * (S + 1) * sizeof(int32_t));
     L.hist = take((size_t)S * radix_hist_words(code_bits) * sizeof(uint32_t));
     const size_t status_words = (size_t)radix_status_words(N, code_bits, S);
@@ -120,8 +121,8 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
     L.vals[0] = take((size_t)N * sizeof(int32_t));
     L.vals[1] = take((size_t)N * sizeof(int32_t));
     L.store = take((size_t)(N > 0 ? N : 1) * sizeof(int32_t));
-    L.pend[0] = take((size_t)2 * L.blocks_max[0] * 16);
-    L.pend[1] = take((size_t)2 * L.blocks_max[0] * 16);
+    L.pend[0] = take((size_t)2 * L.blocks_max[0] * kClimbBytes);
+    L.pend[1] = take((size_t)2 * L.blocks_max[0] * kClimbBytes);
     L.total = off;
     return L;
 }
@@ -130,15 +131,16 @@ BatchLayout batch_layout(int64_t N, int S, int64_t max_scene, int code_bits)
 
 namespace {
 // defaults measured on MI355X: 8-bit digits and 512 x 16 tiles for 30-bit
-// keys, 9-bit digits and 768 x 16 tiles for 63-bit keys
+// keys, 9-bit digits and 768 x 16 tiles for 63-bit keys; the Morton kernel
+// sweeping backwards
 std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {6}, {0}, {kSplit1}, {kSplit2}, {0}, {0}, {8}, {9}, {0},
-                                         {0}};
+                                         {1}, {0}};
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
                                     "query_split1", "query_split2", "query_leaf_mode",
                                     "query_order", "radix_bits32", "radix_bits64",
-                                    "query_walk_budget", "morton_order"};
-const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0, 0};   // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {6, 6, 3, 24, 24, 1, 1, 10, 11, INT32_MAX, 1};
+                                    "query_walk_budget", "morton_order", "batch_sort_mode"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0, 0, 0};   // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {8, 8, 3, 24, 24, 1, 1, 10, 11, INT32_MAX, 1, 1};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }
@@ -514,7 +516,7 @@ static int query_count(int qkind, const lbvh_tree *tree, const float *q, int64_t
     const QueryLayout L = query_layout(m);
     if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
     if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
-    hipError_t e = launch_query(qkind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
+    hipError_t e = launch_query(qkind, tree->kind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
                                 offsets, nullptr, false,
                                 static_cast<char *>(workspace), L, (hipStream_t)stream);
     return hip_status(e);
@@ -532,7 +534,7 @@ static int query_fill(int qkind, const lbvh_tree *tree, const float *q, int64_t 
     const QueryLayout L = query_layout(m);
     if (!workspace || !aligned(workspace, 256)) return LBVH_EINVAL;
     if (workspace_bytes < (int64_t)L.total) return LBVH_ENOSPACE;
-    hipError_t e = launch_query(qkind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
+    hipError_t e = launch_query(qkind, tree->kind, tree->nodes, tree->leaf_perm, (int)tree->n, q, (int)m,
                                 nullptr, indices, true,
                                 static_cast<char *>(const_cast<void *>(workspace)), L,
                                 (hipStream_t)stream);

@@ -24,6 +24,7 @@ constexpr int kChunk = 256;           // leaves per level-0 block of the bottom-
 constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
 constexpr int kBUThreads = 2 * kFanout;  // one thread per handed-over climb
+constexpr int kClimbBytes = 48;       // a climb handed between bottom-up levels
 constexpr int kMaxBatchLevels = 3;    // kChunk * kFanout^3 >= LBVH_MAX_PRIMS
 constexpr int kScanItems = 8;         // values per thread in the query scan
 constexpr int kSplit1 = 12;           // default: query walks cut by aligned blocks of 2^12 leaves
@@ -98,7 +99,7 @@ struct BuildLayout {
     size_t keys_alt;   // n keys (sort ping-pong partner of tree->codes)
     size_t vals[2];    // n int32 each (sort values: input indices)
     size_t store;      // n int32 (Alg. 4 arrival flags / parked range ends)
-    size_t pend[2];    // handed-over climb states between bottom-up levels (int4)
+    size_t pend[2];    // handed-over climbs between bottom-up levels (kClimbBytes each)
     size_t total;
 };
 
@@ -141,13 +142,14 @@ struct BatchLayout {
     size_t ctrl;       // kCtrlWords uint32
     size_t scene_box;  // S x 3 float4 (lo, hi, scale)
     size_t tile_off;   // S+1 int32
+    size_t order;      // S int32: scenes in decreasing size class (one-block-per-scene sort)
     size_t blk_off;    // (levels+1) x (S+1) int32
     size_t hist;       // S x radix_hist_words uint32
     size_t status[2];  // radix_status_words(N, bits, S) uint32 each
     size_t keys_alt;   // N keys
     size_t vals[2];    // N int32
     size_t store;      // N int32
-    size_t pend[2];    // 2 x blocks_max[0] int4
+    size_t pend[2];    // 2 x blocks_max[0] handed-over climbs
     size_t total;
     int levels;
     int64_t blocks_max[kMaxBatchLevels + 1]; // upper bound of bottom-up blocks per level
@@ -161,7 +163,7 @@ int batch_levels(int64_t max_scene);
 
 enum TuneKnob {
     TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_QORDER,
-    TUNE_RADIX_BITS32, TUNE_RADIX_BITS64, TUNE_QBUDGET, TUNE_MORTON_ORDER,
+    TUNE_RADIX_BITS32, TUNE_RADIX_BITS64, TUNE_QBUDGET, TUNE_MORTON_ORDER, TUNE_BATCH_SORT_MODE,
     TUNE_NUM
 };
 int64_t tune_get(int knob);
@@ -184,7 +186,9 @@ hipError_t launch_build(int kind, const float *prims, int n, int code_bits,
                         lbvh_node *nodes, void *codes, int32_t *leaf_perm, char *ws,
                         const BuildLayout &L, hipStream_t s);
 
-hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_perm, int n,
+// kind: the tree's primitives (LBVH_POINTS lets the leaf scan read half of
+// each leaf record)
+hipError_t launch_query(int qkind, int kind, const lbvh_node *nodes, const int32_t *leaf_perm, int n,
                         const float *q, int m, int64_t *offsets,
                         int32_t *indices, bool fill, char *ws,
                         const QueryLayout &L, hipStream_t s);

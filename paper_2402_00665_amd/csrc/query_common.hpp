@@ -149,6 +149,7 @@ struct Tree {
     int n;
     uint32_t *err = nullptr;   // count calls: where a walk that ran out of budget is flagged
     int64_t budget = 0;        // node visits allowed per walk; 0: 2n (every node once)
+    bool points = false;       // a tree of points: every leaf box has hi == lo
     __device__ int64_t walk_budget() const { return budget > 0 ? budget : 2 * (int64_t)n; }
     // a walk stopped with its budget spent: its count is short; report it
     __device__ void budget_spent() const
@@ -162,6 +163,15 @@ struct Tree {
         const float4 *p = nodes + 2 * (int64_t)v;
         a = p[0];
         b = p[1];
+    }
+    // the box of leaf record v for a test: in a tree of points the upper
+    // corner equals the lower one, so only the record's first half is read
+    // (b.w, the rope, is then not loaded)
+    __device__ void load_leaf_box(int v, float4 &a, float4 &b) const
+    {
+        const float4 *p = nodes + 2 * (int64_t)v;
+        a = p[0];
+        b = points ? make_float4(a.x, a.y, a.z, 0.0f) : p[1];
     }
     // right bound of node v whose record half `b` holds the rope
     __device__ int right_bound(float4 b) const
@@ -510,8 +520,8 @@ __device__ int64_t scan_piece(const Tree &tr, const Q &q, int lo, int hi, int32_
     for (int k0 = lo; k0 < hi; k0 += 128) {
         const int k = k0 + lane, k2 = k + 64;
         float4 a, b, e, f;
-        if (k < hi) tr.load(tr.leaf0() + k, a, b);
-        if (k2 < hi) tr.load(tr.leaf0() + k2, e, f);
+        if (k < hi) tr.load_leaf_box(tr.leaf0() + k, a, b);
+        if (k2 < hi) tr.load_leaf_box(tr.leaf0() + k2, e, f);
         const bool h = k < hi && q.test(a, b);
         const bool h2 = k2 < hi && q.test(e, f);
         const uint64_t m = __ballot(h), m2 = __ballot(h2);

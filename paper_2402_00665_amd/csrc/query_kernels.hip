@@ -382,7 +382,7 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
 
 }  // namespace
 
-hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_perm, int n,
+hipError_t launch_query(int qkind, int kind, const lbvh_node *nodes, const int32_t *leaf_perm, int n,
                         const float *q, int m, int64_t *offsets, int32_t *indices, bool fill,
                         char *ws, const QueryLayout &L, hipStream_t s)
 {
@@ -394,6 +394,7 @@ hipError_t launch_query(int qkind, const lbvh_node *nodes, const int32_t *leaf_p
         return hipGetLastError();
     }
     Tree tr{reinterpret_cast<const float4 *>(nodes), leaf_perm, n};
+    tr.points = kind == LBVH_POINTS;
     if (fill) {
         if (qkind == 2) return run_fill<Ray>(tr, q, indices, ws, L, s);
         return qkind == 0 ? run_fill<Sphere>(tr, q, indices, ws, L, s)

@@ -137,7 +137,15 @@ def alg4_blocked(delta, n, chunk, fanout, leaf_boxes=None, policy="random", seed
     (p = A-1 or p = B-1) stops and hands its state (node, range) to the
     level above.  Blocks of one level run one after another here (they touch
     disjoint parts of `store`); threads inside a block interleave under the
-    given schedule.  Returns (left, rope, boxes) like ``alg4``."""
+    given schedule.  Returns (left, rope, boxes) like ``alg4``.
+
+    Level 0 climbs as Alg. 4 does, with delta* looked up.  The levels above
+    climb the way the upper-level kernel does: a climb carries delta* at
+    its two outer boundaries and its rope; a first arrival parks its far
+    end together with delta* at its outer boundary on that side, so the
+    second arrival takes the parent's new outer delta* from the parked word
+    and looks none up; and a parent's rope is its right child's (Alg. 2
+    depends only on the range's right end)."""
     D = _Delta(delta, n)
     ni = n - 1
     left = [None] * max(ni, 0)
@@ -151,38 +159,44 @@ def alg4_blocked(delta, n, chunk, fanout, leaf_boxes=None, policy="random", seed
     def union(a, b):
         return tuple(min(a[x], b[x]) for x in range(3)) + tuple(max(a[3 + x], b[3 + x]) for x in range(3))
 
-    def climb(cur, rl, rr, A, B, out):
-        dl, dr = D(rl - 1), D(rr)
+    def climb(cur, rl, rr, A, B, out, carried=None):
+        # carried (upper levels): (dl, dr) handed over with the climb
+        dl, dr = carried if carried is not None else (D(rl - 1), D(rr))
+        upper = carried is not None
         while True:
             if dr < dl:
                 p = rr
                 if p == B - 1:
-                    out[1] = (cur, rl, rr)
+                    out[1] = (cur, rl, rr, dl, dr)
                     return
                 yield
                 old = store[p]
                 if old is None:
-                    store[p] = rl
+                    store[p] = (rl, dl)          # far end, delta* beyond it
                     return
-                rr = old
-                dr = D(rr)
+                rr, d_far = old
+                dr = d_far if upper else D(rr)
                 sib = leaf(p + 1) if p + 1 == rr else p + 1
+                right = sib
             else:
                 p = rl - 1
                 if p == A - 1:
-                    out[0] = (cur, rl, rr)
+                    out[0] = (cur, rl, rr, dl, dr)
                     return
                 yield
                 old = store[p]
                 if old is None:
-                    store[p] = rr
+                    store[p] = (rr, dr)
                     return
-                rl = old
-                dl = D(rl - 1)
+                rl, d_far = old
+                dl = d_far if upper else D(rl - 1)
                 sib = leaf(p) if rl == p else p
+                right = cur
             q = rr if dr < dl else rl
             left[q] = leaf(p) if rl == p else p
-            if rr == n - 1:
+            if upper:
+                rope[q] = rope[right]
+            elif rr == n - 1:
                 rope[q] = SENTINEL
             else:
                 r = rr + 1
@@ -219,7 +233,7 @@ def alg4_blocked(delta, n, chunk, fanout, leaf_boxes=None, policy="random", seed
             A, B = b * span, min((b + 1) * span, n)
             j0, j1 = A // child_span, (B + child_span - 1) // child_span
             out = [None, None]
-            gens = [climb(s[0], s[1], s[2], A, B, out)
+            gens = [climb(s[0], s[1], s[2], A, B, out, carried=(s[3], s[4]))
                     for j in range(j0, j1) for s in pend[j] if s is not None]
             _schedule(gens, policy, rng)
             nxt.append(out)

@@ -23,7 +23,7 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     r = autotune.tune(p, 63, reps=3, verbose=True)
     say(f"single: {r}")
     assert set(r["knobs"]) == {"radix_bits64", "sort_variant64"}
-    assert set(r["times_ms"]) == {f"{b}/{v}" for b in (8, 9, 11) for v in range(7)}
+    assert set(r["times_ms"]) == {f"{b}/{v}" for b in (8, 9, 11) for v in range(9)}
     assert {k: lb.lbvh_tune(k) for k in defaults} == defaults   # tuning restores the defaults
     sizes = np.array([3000, 70000, 1, 0, 40000], np.int64)
     seg = np.zeros(len(sizes) + 1, np.int64)
@@ -31,8 +31,9 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     pb = torch.from_numpy(rng.random((int(seg[-1]), 3), dtype=np.float32)).cuda()
     rb = autotune.tune(pb, 30, seg_off=torch.from_numpy(seg).cuda(), max_scene=70000, reps=3)
     say(f"batched: {rb}")
-    assert set(rb["knobs"]) == {"radix_bits32", "batch_sort_variant"}
-    assert set(rb["times_ms"]) == {f"{b}/{v}" for b in (8, 10) for v in range(4)}
+    assert set(rb["knobs"]) == {"radix_bits32", "batch_sort_mode", "batch_sort_variant"}
+    assert set(rb["times_ms"]) == ({f"{b}/{v}" for b in (8, 10) for v in range(4)}
+                                   | {f"{b}/-1" for b in (8, 10)})
     cache = json.loads((tmp_path / "tuning.json").read_text())
     assert len(cache) == 2
     try:

@@ -178,7 +178,17 @@ def test_max_scene_below_size_within_cover_is_exact():
         check_scene(b, s, seg, ref, nodes_h, codes_h, perm_h)
 
 
-def test_graph_capture_replays_identically():
+@pytest.fixture(params=[0, 1], ids=["segmented", "per_scene"])
+def sort_mode(request):
+    """Both sort schedules of the batched build: segmented onesweep passes
+    over all scenes, and one block per scene."""
+    import paper_2402_00665_amd as lb
+    old = lb.lbvh_tune("batch_sort_mode", request.param)
+    yield request.param
+    lb.lbvh_tune("batch_sort_mode", old)
+
+
+def test_graph_capture_replays_identically(sort_mode):
     """The batched build and count enqueue kernels only, so they can be
     captured in a HIP graph; every replay must reproduce the eager bits."""
     import torch
@@ -230,13 +240,44 @@ def test_graph_capture_replays_identically():
 
 
 @pytest.mark.timeout(900)
-def test_batched_workload_full_size():
+def test_batched_workload_full_size(sort_mode):
     """4096 scenes, sizes log-uniform in [32, 65536] (35M points), 63-bit
-    codes, 64 spheres per scene: every 16th scene checked against the
-    oracle, all scenes' query counts checked against per-scene oracles."""
-    say("full batched workload: generating")
+    codes, 64 spheres per scene: every scene's tree and query results
+    checked against the oracle run on that scene alone."""
+    say(f"full batched workload (sort mode {sort_mode}): generating")
     pts, off, q, qoff = workloads.batched()
-    batched_parity(pts, off, 63, 0, q, qoff, 0, check_every=16)
+    oracle.threads(16)
+    try:
+        batched_parity(pts, off, 63, 0, q, qoff, 0, check_every=1)
+    finally:
+        oracle.threads(1)
+
+
+@pytest.mark.parametrize("bits", [30, 63])
+def test_scene_sort_widths_and_sizes(bits):
+    """The one-block-per-scene sort with every digit width: empty and
+    one-point scenes, scenes around its 4096-key tile, a scene above
+    65536 points, duplicate codes; every tree equals the oracle's."""
+    import paper_2402_00665_amd as lb
+    old = {k: lb.lbvh_tune(k) for k in ("batch_sort_mode", "radix_bits32", "radix_bits64")}
+    lb.lbvh_tune("batch_sort_mode", 1)
+    try:
+        rng = np.random.default_rng([29, bits])
+        sizes = np.array([4097, 1, 4096, 0, 100003, 6000, 4095, 16384, 8193, 2, 0, 3], np.int64)
+        seg = np.zeros(len(sizes) + 1, np.int64)
+        np.cumsum(sizes, out=seg[1:])
+        pts = rng.random((int(seg[-1]), 3), dtype=np.float32)
+        pts[seg[5]:seg[6]] = pts[seg[5]]                     # one scene of equal points
+        pts[seg[7]:seg[8]:3] = pts[seg[7]]                    # duplicates in another
+        for width in ((8, 10) if bits == 30 else (8, 9, 11)):
+            lb.lbvh_tune("radix_bits32" if bits == 30 else "radix_bits64", width)
+            say(f"  per-scene sort, {width}-bit digits, {bits}-bit codes")
+            batched_parity(pts, seg, bits, 0)
+            boxes = np.concatenate([pts, pts + 1e-3], 1).astype(np.float32)
+            batched_parity(boxes, seg, bits, 1)
+    finally:
+        for k, v in old.items():
+            lb.lbvh_tune(k, v)
 
 
 @pytest.mark.parametrize("variant", range(4))

@@ -224,7 +224,7 @@ def test_piece_capacity_overflow_passes_through(ws):
     assert_query_equal(off, idx, roff, ridx)
 
 
-@pytest.mark.parametrize("variant", range(7))
+@pytest.mark.parametrize("variant", range(9))
 def test_sort_tile_variants(variant, ws):
     """Every radix-pass tile shape, with every digit width (8 or 10 bits for
     30-bit codes, 8, 9 or 11 for 63-bit), gives the same tree (tolerance 0).
