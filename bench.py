@@ -144,6 +144,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-plain comparison (4096 scenes)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--no-rays", action="store_true",
+                    help="skip the ray leg (clustered boxes only: first hits of 2^20 rays, all "
+                         "hits of 2^20 segments, on the same tree)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default launch shapes instead of autotuned ones")
     ap.add_argument("--knobs", default="",
@@ -427,6 +430,10 @@ def main():
                  "note": "node bytes counted once per visit; upper tree levels stay in cache, "
                          "so this can exceed what HBM alone would allow"}
 
+    rays = None
+    if not args.no_rays and w.name == "clustered_boxes" and not args.build_only:
+        rays = bench_rays(args, w, tree)
+
     batched = None if args.no_batched else bench_batched(args)
     serving = None if args.no_serving else bench_serving(args)
 
@@ -462,10 +469,59 @@ def main():
                     for k, v in kernels.items()},
         "tuning": tuning,
         "cpu_baseline": cpu,
+        "rays": rays,
         "batched": batched,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------- rays
+
+def bench_rays(args, w, tree, reps: int = 10):
+    """Rays and segments on the built tree (the clustered boxes): first
+    hits of 2^20 rays through random points of random boxes, and all hits
+    of 2^20 segments of length 0.002 from such points (the clustered_rays /
+    clustered_segments workloads).  Median of ``reps`` timed calls after
+    two warm-ups (their parity with the oracle is the GPU tests' job)."""
+    import torch
+    import paper_2402_00665_amd as lb
+    import workloads
+    t0 = time.time()
+    rays = workloads.clustered_ray_queries(w.prims, w.m, segments=False)
+    segs = workloads.clustered_ray_queries(w.prims, w.m, segments=True)
+    log(f"[bench] rays: {w.m} rays, {w.m} segments (generated in {time.time() - t0:.1f}s)")
+    dr, dsg = torch.from_numpy(rays).cuda(), torch.from_numpy(segs).cuda()
+    ws = lb.Workspace()
+    hit = torch.empty(w.m, dtype=torch.int32, device="cuda")
+    tt = torch.empty(w.m, dtype=torch.float32, device="cuda")
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    first_ms, all_ms = [], []
+    for r in range(reps + 2):
+        e[0].record()
+        lb.query_first(tree, dr, workspace=ws, hit=hit, t=tt)
+        e[1].record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            first_ms.append(e[0].elapsed_time(e[1]))
+    lb.check_query(ws, w.m)
+    for r in range(reps + 2):
+        e[0].record()
+        off, idx = lb.query(tree, dsg, lb.RAYS, workspace=ws)
+        e[1].record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            all_ms.append(e[0].elapsed_time(e[1]))
+    lb.check_query(ws, w.m)
+    hit_h = hit.cpu().numpy()
+    off_h = off.cpu().numpy()
+    fm, am = float(np.median(first_ms)), float(np.median(all_ms))
+    return {"workload": "clustered_rays / clustered_segments", "m": w.m,
+            "first_hit_ms": round(fm, 4), "first_hit_mrays_per_s": round(w.m / (fm * 1e-3) / 1e6, 1),
+            "rays_hit": int((hit_h >= 0).sum()),
+            "segments_ms": round(am, 4),
+            "segments_mqueries_per_s": round(w.m / (am * 1e-3) / 1e6, 1),
+            "segment_hits": int(off_h[-1])}
 
 
 # ---------------------------------------------------------------- batched
@@ -630,12 +686,8 @@ def bench_serving(args):
                       generator=gen)
 
     def digest_into(store):
-        cur = torch.cuda.current_stream()
-
-        def done(o):
+        def done(o):   # runs on the batch's stream (the server makes it current)
             off, idx = o.csr()
-            off.record_stream(cur)   # read on this stream, freed by the executor's
-            idx.record_stream(cur)
             d = (off * W[:off.numel()]).sum()
             i64 = idx.long()
             for a in range(0, i64.numel(), W.numel()):
@@ -702,7 +754,7 @@ KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name (first 
     "k_split": "query_split", "k_leaf_scan_count": "query_count", "k_leaf_count_wide": "query_count",
     "k_leaf_mixed_count": "query_count", "k_leaf_fill": "query_fill", "copyBuffer": "copy",
     "k_batch_plan": "batch_plan", "k_batch_morton": "morton", "k_batch_count": "query_count",
-    "k_batch_fill": "query_fill",
+    "k_batch_fill": "query_fill", "k_scene_sort": "scene_sort", "k_ray_first": "ray_first",
 }
 
 

@@ -143,7 +143,9 @@ class Server:
     A finished batch stays resident with its tree (``keep_resident``) and
     its results (``keep_results``), both counted in the budget and evicted
     together; ``on_done(response)`` is called for each finished request
-    while its results are still on the device."""
+    while its results are still on the device, with the executor's stream
+    for that batch current (GPU executors), so device work it enqueues on
+    the results runs before their memory can be reused."""
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 64,
                  max_batch_points: int = 1 << 25, clock=None, keep_resident: bool = True,
@@ -267,8 +269,11 @@ class Server:
                     o.done, o.hits, o._handle, o._k = t, int(hits[k]), b.handle, k
                     o.status = LBVH_OK
                 if self.on_done is not None:
-                    for r in b.reqs:
-                        self.on_done(out[r.rid])
+                    # on the batch's own stream: work the callback enqueues
+                    # on the results is ordered before their memory is reused
+                    with self.ex.stream_context(b.handle):
+                        for r in b.reqs:
+                            self.on_done(out[r.rid])
                 self.ex.release(b.handle)
                 self.inflight_bytes -= b.bytes
                 slots.append(b.slot)
@@ -458,6 +463,10 @@ class _GpuBase:
 
     def ready_time(self, h):
         return None
+
+    def stream_context(self, h):
+        """The batch's stream as torch's current stream."""
+        return self.torch.cuda.stream(h.stream)
 
     def _stage(self, reqs, prims, queries, radius_dev, ms_dev, M):
         """Copy each request's payload rows into the packed arrays."""

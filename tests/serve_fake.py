@@ -92,6 +92,10 @@ class FakeExecutor:
     def ready_time(self, h):
         return h.done_at
 
+    def stream_context(self, h):
+        import contextlib
+        return contextlib.nullcontext()
+
     def hits(self, h):
         return [int(h.offsets[h.qbase[k + 1]] - h.offsets[h.qbase[k]]) for k in range(len(h.reqs))]
 

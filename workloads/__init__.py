@@ -209,11 +209,17 @@ def clustered_rays(n: int = 1 << 24, m: int = 1 << 20, segments: bool = False,
     hits): from a random point of a random box, ``length`` long, uniform
     direction.  Both aim at the boxes, so most of them meet some."""
     b = clustered_boxes(n, _rng(3, 0))
-    rng = _rng(3, 3 if segments else 4)
-    p = points_in_boxes(b, m, rng)
-    q = segments_from(p, length, rng) if segments else rays_toward(p, rng)
+    q = clustered_ray_queries(b, m, segments, length)
     name = "clustered_segments" if segments else "clustered_rays"
     return Workload(name, BOXES, b, 30, RAYS, q, {"length": length} if segments else {})
+
+
+def clustered_ray_queries(boxes: np.ndarray, m: int, segments: bool,
+                          length: float = 0.002) -> np.ndarray:
+    """The queries of ``clustered_rays`` for the given boxes."""
+    rng = _rng(3, 3 if segments else 4)
+    p = points_in_boxes(boxes, m, rng)
+    return segments_from(p, length, rng) if segments else rays_toward(p, rng)
 
 
 def batched_scene_sizes(S: int = 4096, lo: int = 32, hi: int = 65536,
