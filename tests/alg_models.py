@@ -387,3 +387,88 @@ def split_walk(n, left, rope, perm, test, S1, S2, contains=None, leaf_scan=None)
         for (b, i2, hi2) in split(a, i, hi, S2):
             hits += walk(b, i2, hi2)
     return hits
+
+
+def split_levels_capped(n, left, rope, perm, tests, S1, S2, cap1, cap2, seed=0):
+    """Both split levels over a batch of queries with bounded append lists,
+    the way the count kernels fill them: every piece of every item is
+    appended in an arbitrary interleaving (seeded shuffle); the first
+    ``cap`` appended are kept; an item that lost any of its pieces passes
+    through its level unsplit, as one piece (a query: the walk from the
+    root over [0, n); a level-1 piece: itself).  Returns each query's hits
+    in order.  ``tests[q]`` is query q's node predicate."""
+    import random as _random
+    rng = _random.Random(seed)
+    if n == 0:
+        return [[] for _ in tests]
+
+    def level(items, S, cap):
+        # items: list of (query, v, i, hi); returns the next level's items
+        pieces = []
+        for t, (q, v, i, hi) in enumerate(items):
+            got = _split_pieces(n, left, rope, tests[q], v, i, hi, S)
+            pieces.append([(q,) + pc for pc in got])
+        order = [(t, r) for t, ps in enumerate(pieces) for r in range(len(ps))]
+        rng.shuffle(order)
+        kept = set(order[:cap])
+        out = []
+        for t, ps in enumerate(pieces):
+            if all((t, r) in kept for r in range(len(ps))):
+                out += ps
+            else:
+                out.append(items[t])      # unsplit
+        return out
+
+    items = [(q, 0, 0, n) for q in range(len(tests))]
+    items = level(items, S1, cap1)
+    items = level(items, S2, cap2)
+    hits = [[] for _ in tests]
+    for (q, v, i, hi) in items:
+        hits[q] += _walk_range(n, left, rope, perm, tests[q], v, i, hi)
+    return hits
+
+
+def _split_pieces(n, left, rope, test, v, i, hi, S):
+    """One split level of one item (no containment): pieces (v, i, hi)."""
+    ni = n - 1
+    idx = (lambda x: x - ni if x >= ni else x)
+    jend = (lambda x: n - 1 if rope[x] == -1 else idx(rope[x]) - 1)
+
+    def first_at(r):
+        if r <= n - 2 and idx(left[r]) >= r:
+            return r
+        return ni + r
+    out = []
+    while v != -1 and i < hi:
+        j = jend(v)
+        if not test(v):
+            v, i = rope[v], j + 1
+            continue
+        if (i >> S) == (j >> S):
+            blk = i >> S
+            out.append((v, i, min((blk + 1) << S, hi)))
+            r = (blk + 1) << S
+            if r >= hi or r > n - 1:
+                break
+            v, i = first_at(r), r
+            continue
+        v = left[v]
+    return out
+
+
+def _walk_range(n, left, rope, perm, test, v, i, hi):
+    """Alg. 1 restricted to the leaves [i, hi) from node v."""
+    ni = n - 1
+    idx = (lambda x: x - ni if x >= ni else x)
+    jend = (lambda x: n - 1 if rope[x] == -1 else idx(rope[x]) - 1)
+    out = []
+    while v != -1 and i < hi:
+        j = jend(v)
+        if test(v):
+            if v >= ni:
+                out.append(int(perm[v - ni]))
+            else:
+                v = left[v]
+                continue
+        v, i = rope[v], j + 1
+    return out

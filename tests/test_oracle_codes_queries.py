@@ -305,3 +305,25 @@ def test_split_walk_degenerate():
             got = split_walk(n, left, t.rope.tolist(), t.perm,
                              lambda v: oracle.pred_sphere(t.aabb[v], q), 3, 1)
             assert got == idx.tolist()
+
+
+@pytest.mark.parametrize("cap1,cap2,seed", [(10**9, 10**9, 0), (40, 120, 1), (5, 30, 2), (0, 0, 3),
+                                            (60, 8, 4)])
+def test_split_levels_with_bounded_lists(cap1, cap2, seed):
+    """Both split levels over a batch of queries whose pieces exceed the
+    append lists: whatever subset of pieces fits (arbitrary append order),
+    an item that lost one passes through its level unsplit and every query
+    still gets the plain walk's hits in order (the GPU count kernels' rule
+    for a full list)."""
+    from alg_models import split_levels_capped
+    w = workloads.by_name("clustered_boxes", 1 / 256)
+    t = oracle.build(w.kind, w.prims, w.code_bits)
+    qs = w.queries[:40].copy()
+    qs[::5, 3:] += 0.2                                  # some large queries: many pieces
+    off, idx, _ = oracle.query_traverse(1, qs, t)
+    left = np.concatenate([t.left, t.perm]).tolist()
+    rope = t.rope.tolist()
+    tests = [(lambda v, q=q: oracle.pred_box(t.aabb[v], q)) for q in qs]
+    hits = split_levels_capped(t.n, left, rope, t.perm, tests, 9, 5, cap1, cap2, seed)
+    for j in range(len(qs)):
+        assert hits[j] == idx[off[j]:off[j + 1]].tolist(), f"query {j}"
