@@ -33,9 +33,13 @@ KNOB_CANDIDATES = {
 }
 # (query_split1, query_split2, query_leaf_mode, query_order): each split
 # schedule with the queries as given and in Morton order
-# (blocks larger than the tree: each query one plain Alg. 1 walk by one lane)
+# Coarse blocks suit thin queries (rays, segments), whose hits fall in few
+# Morton ranges but whose finer pieces would exceed the split levels'
+# capacity; (24, 24): blocks larger than the tree, each query one plain
+# Alg. 1 walk by one lane.
 _SPLITS = [(12, 7, 0), (13, 8, 0), (12, 8, 0), (12, 6, 0), (13, 7, 0), (11, 6, 0),
-           (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1), (24, 24, 0)]
+           (12, 7, 1), (11, 6, 1), (13, 7, 1), (11, 5, 1), (14, 10, 1), (16, 10, 1),
+           (14, 9, 1), (15, 10, 0), (24, 24, 0)]
 QUERY_CANDIDATES = [s + (o,) for o in (0, 1) for s in _SPLITS]
 _QUERY_KNOBS = ("query_split1", "query_split2", "query_leaf_mode", "query_order")
 
@@ -132,13 +136,13 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
     batched = seg_off is not None
     wk, sk = sort_knobs(code_bits, batched)
     # batched builds also choose between the segmented passes (mode 0, each
-    # tile shape) and one block per scene (mode 1, no tile shape): the shape
-    # slot then holds -1
+    # tile shape) and one block per scene (mode 1, each block shape): a
+    # mode-1 candidate's shape slot holds -1 - shape
     mode0 = lbvh_tune("batch_sort_mode") if batched else 0
-    default = (lbvh_tune(wk), lbvh_tune(sk) if mode0 == 0 else -1)
+    default = (lbvh_tune(wk), lbvh_tune(sk) if mode0 == 0 else -1 - lbvh_tune(sk))
     cands = [(b, v) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
     if batched:
-        cands += [(b, -1) for b in KNOB_CANDIDATES[wk]]
+        cands += [(b, -1 - v) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
     order = [default] + [c for c in cands if c != default]
     shape0 = lbvh_tune(sk)
     ws = Workspace(prims.device)
@@ -154,8 +158,7 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
             lbvh_tune(wk, b)
             if batched:
                 lbvh_tune("batch_sort_mode", 1 if v < 0 else 0)
-            if v >= 0:
-                lbvh_tune(sk, v)
+            lbvh_tune(sk, v if v >= 0 else -1 - v)
             t = (_time_batched(prims, seg_off, code_bits, kind, max_scene, ws, obj, reps) if batched
                  else _time_single(prims, code_bits, kind, ws, obj, reps))
             out = torch.cat([obj.nodes.flatten(), obj.leaf_perm]).clone()
@@ -175,7 +178,7 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
     b_best, v_best = (int(x) for x in best.split("/"))
     if batched:
         knobs = {wk: b_best, "batch_sort_mode": 1 if v_best < 0 else 0,
-                 sk: v_best if v_best >= 0 else shape0}
+                 sk: v_best if v_best >= 0 else -1 - v_best}
     else:
         knobs = {wk: b_best, sk: v_best}
     if save:

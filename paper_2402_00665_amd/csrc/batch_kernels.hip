@@ -25,8 +25,6 @@ namespace {
 
 constexpr int kPlanThreads = 1024;
 constexpr int kSceneThreads = 512;
-constexpr int kSceneSortThreads = 256;   // one-block-per-scene sort: tile of 256 x 16 keys
-constexpr int kSceneSortItems = 16;
 
 __device__ __forceinline__ int64_t scene_size(const int64_t *seg_off, int s)
 {
@@ -564,19 +562,48 @@ void run_batch_sort(const float *prims, const int64_t *seg_off, int S, int64_t N
 }
 
 // The one-block-per-scene sort: codes go to the key buffer that makes the
-// last pass end in the batch's codes array.
+// last pass end in the batch's codes array.  Block shapes (threads x keys
+// per thread, the knob "batch_sort_variant" in this mode): wider blocks take
+// a large scene in fewer tiles per pass; a shape whose tables and tile do
+// not fit the LDS runs as 256 x 16.
+constexpr size_t scene_sort_lds(int key_bytes, int threads, int items, int bits, int passes)
+{
+    return (size_t)(threads / 64) * ((bits <= 9 ? 4u : 2u) << bits) + (8u << bits) +
+           ((size_t)passes << bits) * 4 + (size_t)threads * items * key_bytes;
+}
+
+template <int KIND, typename K, int B, int T, int I>
+void launch_scene_sort(const float *prims, const int64_t *seg_off, const int32_t *order, int S,
+                       int code_bits, K *ka, K *kb, int32_t *vals[2], int32_t *leaf_perm,
+                       float4 *scene_box, uint32_t *err, hipStream_t s)
+{
+    constexpr int P = ((sizeof(K) == 4 ? 30 : 63) + B - 1) / B;
+    if constexpr (scene_sort_lds(sizeof(K), T, I, B, P) > 150 * 1024) {
+        launch_scene_sort<KIND, K, B, 256, 16>(prims, seg_off, order, S, code_bits, ka, kb, vals,
+                                               leaf_perm, scene_box, err, s);
+    } else {
+        hipLaunchKernelGGL((k_scene_sort<KIND, K, B, T, I>), dim3(S), dim3(T), 0, s, prims, seg_off,
+                           order, code_bits, scene_box, ka, kb, vals[0], vals[1], leaf_perm, err);
+    }
+}
+
 template <int KIND, typename K, int B>
 void run_scene_sort(const float *prims, const int64_t *seg_off, const int32_t *order, int S,
                     int code_bits, K *codes, int32_t *leaf_perm, float4 *scene_box, K *keys_alt,
                     int32_t *vals[2], uint32_t *err, hipStream_t s)
 {
-    constexpr int T = kSceneSortThreads, I = kSceneSortItems;
     const int passes = radix_passes(code_bits, B);
     K *ka = (passes & 1) ? keys_alt : codes;
     K *kb = (passes & 1) ? codes : keys_alt;
     prof_begin(K_SORT, s);
-    hipLaunchKernelGGL((k_scene_sort<KIND, K, B, T, I>), dim3(S), dim3(T), 0, s, prims, seg_off, order,
-                       code_bits, scene_box, ka, kb, vals[0], vals[1], leaf_perm, err);
+#define LBVH_SCENE_ARGS prims, seg_off, order, S, code_bits, ka, kb, vals, leaf_perm, scene_box, err, s
+    switch (tune_get(TUNE_BATCH_SORT)) {
+    case 1: launch_scene_sort<KIND, K, B, 512, 8>(LBVH_SCENE_ARGS); break;
+    case 2: launch_scene_sort<KIND, K, B, 1024, 8>(LBVH_SCENE_ARGS); break;
+    case 3: launch_scene_sort<KIND, K, B, 512, 16>(LBVH_SCENE_ARGS); break;
+    default: launch_scene_sort<KIND, K, B, 256, 16>(LBVH_SCENE_ARGS); break;
+    }
+#undef LBVH_SCENE_ARGS
     prof_end(K_SORT, s);
 }
 
@@ -606,7 +633,10 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
     prof_begin(K_BATCH_PREP, s);
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile,
                        tile_off, blk_off, ctrl, order);
-    if (tune_get(TUNE_BATCH_SORT_MODE) == 1) {
+    // one block per scene only while every scene is small (at most one
+    // upper level: 65536 primitives); a block alone on a scene of millions
+    // would set the whole batch's time
+    if (tune_get(TUNE_BATCH_SORT_MODE) == 1 && levels <= 1) {
         prof_end(K_BATCH_PREP, s);
 #define LBVH_SSORT_ARGS prims, seg_off, order, S, code_bits, codes, leaf_perm, scene_box, keys_alt, \
                         vals, ctrl + kCtrlError, s

@@ -44,21 +44,23 @@ QueryLayout query_layout(int64_t m)
     QueryLayout L{};
     L.cap1 = 2 * m + 1024;
     L.cap2 = 6 * m + 4096;
+    L.out1 = L.cap1 + m;        // an unsplit query adds one piece
+    L.out2 = L.cap2 + L.out1;   // an unsplit level-1 piece adds one
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align256(off + bytes); return at; };
     L.cnt1 = take((size_t)(m + 1) * sizeof(int32_t));
     L.off1 = take((size_t)(m + 1) * sizeof(int64_t));
-    L.items1 = take((size_t)L.cap1 * 16);
-    L.cnt2 = take((size_t)L.cap1 * sizeof(int32_t));
-    L.off2 = take((size_t)(L.cap1 + 1) * sizeof(int64_t));
-    L.items2 = take((size_t)L.cap2 * 16);
+    L.items1 = take((size_t)L.out1 * 16);
+    L.cnt2 = take((size_t)L.out1 * sizeof(int32_t));
+    L.off2 = take((size_t)(L.out1 + 1) * sizeof(int64_t));
+    L.items2 = take((size_t)L.out2 * 16);
     L.app_piece = take((size_t)L.cap2 * 16);   // shared by both levels (cap2 >= cap1)
     L.app_item = take((size_t)L.cap2 * sizeof(int64_t));
     L.app_rank = take((size_t)L.cap2 * sizeof(int32_t));
-    L.hcnt = take((size_t)L.cap2 * sizeof(int32_t));
-    L.hmask = take((size_t)L.cap2 * kMaskWords * sizeof(uint64_t));
-    L.hoff = take((size_t)(L.cap2 + 1) * sizeof(int64_t));
-    L.partials = take((size_t)((L.cap2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
+    L.hcnt = take((size_t)L.out2 * sizeof(int32_t));
+    L.hmask = take((size_t)L.out2 * kMaskWords * sizeof(uint64_t));
+    L.hoff = take((size_t)(L.out2 + 1) * sizeof(int64_t));
+    L.partials = take((size_t)((L.out2 + kScanTile - 1) / kScanTile + 1) * sizeof(int64_t));
     L.ctrl = take(128);
     L.qsorted = take((size_t)m * 8 * sizeof(float));   // widest query: a ray
     L.qperm = take((size_t)m * sizeof(int32_t));
@@ -75,7 +77,7 @@ QueryLayout query_layout(int64_t m)
     L.qstatus[0] = inner(qtiles * kRadix * sizeof(uint32_t));
     L.qstatus[1] = inner(qtiles * kRadix * sizeof(uint32_t));
     L.qhist = inner((size_t)kQOrderPasses * kRadix * sizeof(uint32_t));
-    // hmask holds 32 * cap2 >= 192 m + 131072 bytes: more than the above
+    // hmask holds 32 * out2 >= 288 m + 163840 bytes: more than the above
     return L;
 }
 

@@ -106,20 +106,21 @@ struct BuildLayout {
 BuildLayout build_layout(int64_t n, int code_bits);
 
 struct QueryLayout {
-    int64_t cap1, cap2;  // capacities of level-1 and level-2 pieces
+    int64_t cap1, cap2;  // capacities of the level-1 and level-2 append lists
+    int64_t out1, out2;  // pieces each level can emit: its list plus one per unsplit item
     size_t cnt1;       // m int32: level-1 pieces per query
     size_t off1;       // m+1 int64
-    size_t items1;     // cap1 int4 (query, node, left bound, range end)
-    size_t cnt2;       // cap1 int32: level-2 pieces per level-1 piece
-    size_t off2;       // cap1+1 int64
-    size_t items2;     // cap2 int4
+    size_t items1;     // out1 int4 (query, node, left bound, range end)
+    size_t cnt2;       // out1 int32: level-2 pieces per level-1 piece
+    size_t off2;       // out1+1 int64
+    size_t items2;     // out2 int4
     size_t app_piece;  // cap2 int4: pieces appended by a split level's count pass
     size_t app_item;   // cap2 int64: ... the item each came from
     size_t app_rank;   // cap2 int32: ... and its rank among that item's pieces
-    size_t hcnt;       // cap2 int32: hits per level-2 piece
-    size_t hmask;      // cap2 x kMaskWords uint64: leaf-hit mask of each level-2 piece
+    size_t hcnt;       // out2 int32: hits per level-2 piece
+    size_t hmask;      // out2 x kMaskWords uint64: leaf-hit mask of each level-2 piece
     size_t hcache;     // batched: m x 64 int32, each query's first hits
-    size_t hoff;       // cap2+1 int64
+    size_t hoff;       // out2+1 int64
     size_t partials;   // scan tile sums
     size_t ctrl;       // overflow flags, piece counts, query-order flag, sort counters, error word
     // query order (single tree): the reordered copy of the queries, each

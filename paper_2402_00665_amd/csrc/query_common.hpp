@@ -221,8 +221,11 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 // among that item's pieces.  After the scan of the counts, k_split_scatter
 // puts each piece at its item's offset plus its rank: the order a second
 // walk would emit them in, so no item is walked twice.  Past `cap` pieces
-// the list stops growing; the level then overflows and passes its items
-// through.
+// the list stops growing; an item one of whose pieces did not fit is
+// marked (kDropBit in its count) and passes through the level unsplit, as
+// one piece, while every other item is split as usual.  The counts are
+// accumulated atomically (the mark can come from another lane's flush at
+// any time), so each level's count array starts at zero.
 //
 // Appends go to the wave's LDS stage.  After each append step the wave's
 // active lanes check the stage and, once it holds kAppendStage - 64 or more
@@ -231,6 +234,7 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 // execute together, so the active ones can do this from inside their
 // diverged walks.
 constexpr int kAppendStage = 256;
+constexpr int32_t kDropBit = 1 << 30;   // an item of a split level left unsplit
 
 struct AppendLds {
     int4 piece[kWavesPerBlock][kAppendStage];
@@ -249,6 +253,7 @@ struct WaveAppend {
     int4 *g_piece;
     int64_t *g_item;
     int32_t *g_rank;
+    int32_t *counts;   // per-item piece counts of the level (kDropBit: left unsplit)
 
     __device__ void to_list(unsigned long long slot, int4 pc, int64_t t, int32_t r) const
     {
@@ -256,6 +261,8 @@ struct WaveAppend {
             g_piece[slot] = pc;
             g_item[slot] = t;
             g_rank[slot] = r;
+        } else {
+            atomicOr(&counts[t], kDropBit);
         }
     }
     // by the wave's active lanes, all with the same view of the stage
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
     __shared__ AppendLds lds;
     const int wv = threadIdx.x >> 6;
     const WaveAppend ap{lds.piece[wv], lds.item[wv], lds.rank[wv], &lds.n[wv], app_count, cap,
-                        app_piece, app_item, app_rank};
+                        app_piece, app_item, app_rank, counts};
     if ((threadIdx.x & 63) == 0) lds.n[wv] = 0u;
     wave_sync();
     const int64_t T = FIRST ? (int64_t)m : *in_count;
@@ -363,33 +370,41 @@ __global__ __launch_bounds__(kBlock) void k_split(Tree tr, const float *__restri
             }
             if (budget < 0) tr.budget_spent();
         }
-        counts[t] = cnt;
+        atomicAdd(&counts[t], cnt);   // the count array starts at zero
     }
     ap.flush();   // every lane of the wave
 }
 
-// A split level's output: each appended piece to slot out_off[item] + rank,
-// or, when the level overflowed, its items passed through unchanged.
+// A split level's output: each appended piece of an item that was split to
+// slot out_off[item] + rank, and each item left unsplit (kDropBit) to its
+// own slot out_off[item], unchanged.  Also clears the next level's counts
+// (`next_counts`, next_n entries) before that level accumulates into them.
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_split_scatter(int n, int m, const int4 *__restrict__ in,
                                                           const int64_t *in_count,
                                                           const int64_t *__restrict__ out_off,
-                                                          const int32_t *__restrict__ overflow,
+                                                          const int32_t *__restrict__ counts,
                                                           const unsigned long long *app_count,
+                                                          int64_t cap,
                                                           const int4 *__restrict__ app_piece,
                                                           const int64_t *__restrict__ app_item,
                                                           const int32_t *__restrict__ app_rank,
-                                                          int4 *__restrict__ out)
+                                                          int4 *__restrict__ out,
+                                                          int32_t *__restrict__ next_counts,
+                                                          int64_t next_n)
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (*overflow) {
-        const int64_t T = FIRST ? (int64_t)m : *in_count;
-        for (int64_t t = t0; t < T; t += stride) out[t] = FIRST ? piece((int)t, 0, 0, n) : in[t];
-        return;
+    const int64_t T = FIRST ? (int64_t)m : *in_count;
+    for (int64_t t = t0; t < T; t += stride)
+        if (counts[t] & kDropBit) out[out_off[t]] = FIRST ? piece((int)t, 0, 0, n) : in[t];
+    const unsigned long long a = *app_count;
+    const int64_t A = a < (unsigned long long)cap ? (int64_t)a : cap;   // pieces kept in the list
+    for (int64_t k = t0; k < A; k += stride) {
+        const int64_t t = app_item[k];
+        if (!(counts[t] & kDropBit)) out[out_off[t] + app_rank[k]] = app_piece[k];
     }
-    const int64_t A = (int64_t)*app_count;   // no overflow: every piece was kept
-    for (int64_t k = t0; k < A; k += stride) out[out_off[app_item[k]] + app_rank[k]] = app_piece[k];
+    for (int64_t j = t0; j < next_n; j += stride) next_counts[j] = 0;
 }
 
 // The leaf level.  A level-2 piece covers the leaves [i, hi) of one aligned
@@ -1036,6 +1051,11 @@ __device__ __forceinline__ int64_t count_of(int64_t cap, const int64_t *m_dev)
     return m_dev ? *m_dev : cap;
 }
 
+// a split level's count of an item: its pieces, or 1 if it is left unsplit.
+// The scans also run over hit counts, which stay below kDropBit: a piece
+// covers at most LBVH_MAX_PRIMS < 2^30 leaves.
+__device__ __forceinline__ int32_t piece_count(int32_t c) { return (c & kDropBit) ? 1 : c; }
+
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ counts, int64_t cap,
                                                         const int64_t *m_dev, int64_t *__restrict__ partials)
 {
@@ -1046,7 +1066,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restric
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < m) s += counts[base + k];
+        if (base + k < m) s += piece_count(counts[base + k]);
     int64_t total;
     block_excl_scan_total<int64_t>(s, sh, &total);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -1087,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t *__restrict
     int64_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        c[k] = base + k < m ? counts[base + k] : 0;
+        c[k] = base + k < m ? piece_count(counts[base + k]) : 0;
         s += c[k];
     }
     int64_t total;
@@ -1100,17 +1120,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(const int32_t *__restrict
     }
 }
 
-// After a level's scan: does the number of pieces fit?  If not, the level
-// passes its parents through unchanged.
+// The number of pieces a split level emits (its output always holds them:
+// split items' pieces are at most the list capacity, and each unsplit item
+// adds one).  The overflow word stays 0 (every level's offsets are valid).
 __global__ void k_level_check(const int64_t *__restrict__ off, const int64_t *parent_dev,
-                              int64_t parent_host, int64_t cap, int32_t *__restrict__ overflow,
+                              int64_t parent_host, int32_t *__restrict__ overflow,
                               int64_t *__restrict__ count)
 {
     const int64_t parents = parent_dev ? *parent_dev : parent_host;
-    const int64_t total = off[parents];
-    const bool over = total > cap;
-    *overflow = over ? 1 : 0;
-    *count = over ? parents : total;
+    *overflow = 0;
+    *count = off[parents];
 }
 
 // offsets[q] = hit offset of query q's first leaf-walk piece.  With `perm`

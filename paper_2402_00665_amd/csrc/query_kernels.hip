@@ -131,20 +131,26 @@ __global__ __launch_bounds__(kBlock) void k_qorder_shift(const int64_t *__restri
 }
 
 // start of a count call: the split levels' append counters, the order
-// flag the fill reads, the call's error word, and (when reordering) the
-// sort's tile counters and histograms
+// flag the fill reads, the call's error word, (when reordering) the sort's
+// tile counters and histograms, and the first split level's per-query
+// counts (cnt1, m entries), which that level accumulates into
 __global__ void k_query_reset(unsigned long long *app_count, int32_t *order_flag, int order,
-                              uint32_t *tile_counters, uint32_t *hist, uint32_t *err)
+                              uint32_t *tile_counters, uint32_t *hist, uint32_t *err,
+                              int32_t *cnt1, int64_t m)
 {
-    if (threadIdx.x < 2) app_count[threadIdx.x] = 0ull;
-    if (threadIdx.x == 0) {
-        *order_flag = order;
-        *err = 0u;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 2) app_count[threadIdx.x] = 0ull;
+        if (threadIdx.x == 0) {
+            *order_flag = order;
+            *err = 0u;
+        }
+        if (order) {
+            if (threadIdx.x < kQOrderPasses) tile_counters[threadIdx.x] = 0u;
+            for (int j = threadIdx.x; j < kQOrderPasses * kRadix; j += blockDim.x) hist[j] = 0u;
+        }
     }
-    if (order) {
-        if (threadIdx.x < kQOrderPasses) tile_counters[threadIdx.x] = 0u;
-        for (int j = threadIdx.x; j < kQOrderPasses * kRadix; j += blockDim.x) hist[j] = 0u;
-    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) cnt1[j] = 0;
 }
 
 // ---------------------------------------------------------- first hit
@@ -274,8 +280,8 @@ hipError_t run_count(Tree tr, const float *q, int m, int64_t *offsets, char *ws,
     const int split1 = (int)tune_get(TUNE_QSPLIT1), split2 = (int)tune_get(TUNE_QSPLIT2);
     const bool order = tune_get(TUNE_QORDER) != 0 && m > 1;
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL(k_query_reset, dim3(1), dim3(kBlock), 0, s, S.app_count, S.order_flag,
-                       order ? 1 : 0, S.sort_ctr, S.qhist, S.err);
+    hipLaunchKernelGGL(k_query_reset, dim3(gm), dim3(kBlock), 0, s, S.app_count, S.order_flag,
+                       order ? 1 : 0, S.sort_ctr, S.qhist, S.err, S.cnt1, (int64_t)m);
     prof_end(K_QSPLIT, s);
     int64_t *const caller_offsets = offsets;
     if (order) {
@@ -306,33 +312,34 @@ hipError_t run_count(Tree tr, const float *q, int m, int64_t *offsets, char *ws,
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
     scan(S.cnt1, m, nullptr, S.partials, S.off1, s);
-    hipLaunchKernelGGL(k_level_check, dim3(1), dim3(1), 0, s, S.off1, nullptr, (int64_t)m, L.cap1,
+    hipLaunchKernelGGL(k_level_check, dim3(1), dim3(1), 0, s, S.off1, nullptr, (int64_t)m,
                        S.ovf + 0, S.count + 0);
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL(k_split_scatter<true>, dim3(grid_for(L.cap1)), dim3(kBlock), 0, s, tr.n, m,
-                       nullptr, nullptr, S.off1, S.ovf + 0, S.app_count + 0, S.app_piece, S.app_item,
-                       S.app_rank, S.items1);
+    // (also clears the level-2 counts)
+    hipLaunchKernelGGL(k_split_scatter<true>, dim3(grid_for(L.out1)), dim3(kBlock), 0, s, tr.n, m,
+                       nullptr, nullptr, S.off1, S.cnt1, S.app_count + 0, L.cap1, S.app_piece,
+                       S.app_item, S.app_rank, S.items1, S.cnt2, L.out1);
     prof_end(K_QSPLIT, s);
     // level 2: pieces -> pieces of 2^split2 leaves
-    const unsigned g1 = grid_for(L.cap1);
+    const unsigned g1 = grid_for(L.out1);
     prof_begin(K_QSPLIT, s);
     hipLaunchKernelGGL((k_split<Q, false>), dim3(g1), dim3(kBlock), 0, s, tr, q, m, S.items1,
                        S.count + 0, split2, S.cnt2, S.app_count + 1, L.cap2, S.app_piece, S.app_item,
                        S.app_rank);
     prof_end(K_QSPLIT, s);
     prof_begin(K_SCAN, s);
-    scan(S.cnt2, L.cap1, S.count + 0, S.partials, S.off2, s);
-    hipLaunchKernelGGL(k_level_check, dim3(1), dim3(1), 0, s, S.off2, S.count + 0, (int64_t)0, L.cap2,
+    scan(S.cnt2, L.out1, S.count + 0, S.partials, S.off2, s);
+    hipLaunchKernelGGL(k_level_check, dim3(1), dim3(1), 0, s, S.off2, S.count + 0, (int64_t)0,
                        S.ovf + 1, S.count + 1);
     prof_end(K_SCAN, s);
     prof_begin(K_QSPLIT, s);
-    hipLaunchKernelGGL(k_split_scatter<false>, dim3(grid_for(L.cap2)), dim3(kBlock), 0, s, tr.n, m,
-                       S.items1, S.count + 0, S.off2, S.ovf + 1, S.app_count + 1, S.app_piece,
-                       S.app_item, S.app_rank, S.items2);
+    hipLaunchKernelGGL(k_split_scatter<false>, dim3(grid_for(L.out2)), dim3(kBlock), 0, s, tr.n, m,
+                       S.items1, S.count + 0, S.off2, S.cnt2, S.app_count + 1, L.cap2, S.app_piece,
+                       S.app_item, S.app_rank, S.items2, nullptr, (int64_t)0);
     prof_end(K_QSPLIT, s);
     // leaf level: count hits per piece, scan, per-query offsets
-    const unsigned g2 = grid_for(L.cap2);
+    const unsigned g2 = grid_for(L.out2);
     prof_begin(K_QCOUNT, s);
     if (tune_get(TUNE_QLEAF) == 1)
         hipLaunchKernelGGL((k_leaf_mixed_count<Q>), dim3(g2), dim3(kBlock), 0, s, tr, q, S.items2,
@@ -345,7 +352,7 @@ hipError_t run_count(Tree tr, const float *q, int m, int64_t *offsets, char *ws,
     }
     prof_end(K_QCOUNT, s);
     prof_begin(K_SCAN, s);
-    scan(S.hcnt, L.cap2, S.count + 1, S.partials, S.hoff, s);
+    scan(S.hcnt, L.out2, S.count + 1, S.partials, S.hoff, s);
     // with the order: also the per-query counts in the caller's order (in
     // cnt1, free since level 1)
     hipLaunchKernelGGL(k_compose, dim3((unsigned)((m + kBlock) / kBlock)), dim3(kBlock), 0, s, S.off1,
@@ -370,7 +377,7 @@ hipError_t run_fill(const Tree &tr, const float *q, int32_t *indices, char *ws, 
 {
     Scratch S = carve(ws, L);
     prof_begin(K_QFILL, s);
-    const unsigned g2 = grid_for(L.cap2);
+    const unsigned g2 = grid_for(L.out2);
     const QueryMap qm{S.order_flag, S.qsorted, S.off1};
     hipLaunchKernelGGL((k_leaf_fill<Q>), dim3(g2), dim3(kBlock), 0, s, tr, S.items2, S.count + 1,
                        S.hoff, S.hmask, qm, indices);
@@ -421,7 +428,7 @@ hipError_t launch_ray_first(const lbvh_node *nodes, int n, const float *rays, in
     Tree tr{reinterpret_cast<const float4 *>(nodes), nullptr, n, S.err, tune_get(TUNE_QBUDGET)};
     prof_begin(K_QCOUNT, s);
     hipLaunchKernelGGL(k_query_reset, dim3(1), dim3(kBlock), 0, s, S.app_count, S.order_flag, 0,
-                       S.sort_ctr, S.qhist, S.err);
+                       S.sort_ctr, S.qhist, S.err, nullptr, (int64_t)0);
     hipLaunchKernelGGL(k_ray_first, dim3(grid_for(m)), dim3(kBlock), 0, s, tr, rays, m, hit, t);
     prof_end(K_QCOUNT, s);
     return hipGetLastError();

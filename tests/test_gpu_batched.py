@@ -253,17 +253,22 @@ def test_batched_workload_full_size(sort_mode):
         oracle.threads(1)
 
 
+@pytest.mark.parametrize("shape", range(4))
 @pytest.mark.parametrize("bits", [30, 63])
-def test_scene_sort_widths_and_sizes(bits):
-    """The one-block-per-scene sort with every digit width: empty and
-    one-point scenes, scenes around its 4096-key tile, a scene above
-    65536 points, duplicate codes; every tree equals the oracle's."""
+def test_scene_sort_widths_and_sizes(bits, shape):
+    """The one-block-per-scene sort with every block shape and digit
+    width: empty and one-point scenes, scenes around the 4096- and
+    8192-key tiles, a scene above 65536 points, duplicate codes; every
+    tree equals the oracle's."""
     import paper_2402_00665_amd as lb
-    old = {k: lb.lbvh_tune(k) for k in ("batch_sort_mode", "radix_bits32", "radix_bits64")}
+    old = {k: lb.lbvh_tune(k) for k in ("batch_sort_mode", "batch_sort_variant", "radix_bits32",
+                                        "radix_bits64")}
     lb.lbvh_tune("batch_sort_mode", 1)
+    lb.lbvh_tune("batch_sort_variant", shape)
     try:
         rng = np.random.default_rng([29, bits])
-        sizes = np.array([4097, 1, 4096, 0, 100003, 6000, 4095, 16384, 8193, 2, 0, 3], np.int64)
+        sizes = np.array([4097, 1, 4096, 0, 100003, 6000, 4095, 16384, 8193, 2, 0, 3, 8191, 8192],
+                         np.int64)
         seg = np.zeros(len(sizes) + 1, np.int64)
         np.cumsum(sizes, out=seg[1:])
         pts = rng.random((int(seg[-1]), 3), dtype=np.float32)
