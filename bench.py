@@ -493,6 +493,17 @@ def bench_rays(args, w, tree, reps: int = 10):
     log(f"[bench] rays: {w.m} rays, {w.m} segments (generated in {time.time() - t0:.1f}s)")
     dr, dsg = torch.from_numpy(rays).cuda(), torch.from_numpy(segs).cuda()
     ws = lb.Workspace()
+    # the segments' own query schedule (thin queries: walks beat scans)
+    qknobs = ("query_split1", "query_split2", "query_leaf_mode", "query_order")
+    saved = {k: lb.lbvh_tune(k) for k in qknobs}
+    tuned = None
+    if not args.no_autotune and not args.knobs:
+        from paper_2402_00665_amd import autotune
+        tq = autotune.tune_query(tree, dsg, lb.RAYS, reps=2, save=False)
+        tuned = dict(zip(qknobs, tq["value"]))
+        for k, v in tuned.items():
+            lb.lbvh_tune(k, v)
+        log(f"[bench] rays: segment schedule {tuned}")
     hit = torch.empty(w.m, dtype=torch.int32, device="cuda")
     tt = torch.empty(w.m, dtype=torch.float32, device="cuda")
     e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -513,6 +524,8 @@ def bench_rays(args, w, tree, reps: int = 10):
         if r >= 2:
             all_ms.append(e[0].elapsed_time(e[1]))
     lb.check_query(ws, w.m)
+    for k, v in saved.items():
+        lb.lbvh_tune(k, v)
     hit_h = hit.cpu().numpy()
     off_h = off.cpu().numpy()
     fm, am = float(np.median(first_ms)), float(np.median(all_ms))
@@ -521,7 +534,7 @@ def bench_rays(args, w, tree, reps: int = 10):
             "rays_hit": int((hit_h >= 0).sum()),
             "segments_ms": round(am, 4),
             "segments_mqueries_per_s": round(w.m / (am * 1e-3) / 1e6, 1),
-            "segment_hits": int(off_h[-1])}
+            "segment_hits": int(off_h[-1]), "segment_tuning": tuned}
 
 
 # ---------------------------------------------------------------- batched
@@ -654,9 +667,12 @@ def bench_serving(args):
     codes, and answers 10^4 spheres with about 8 expected neighbours),
     served twice on the same trace in real time: FIFO one request at a time
     through the single-tree entry points, and continuous batching through
-    the batched ones on 3 streams.  Latency = completion - arrival; every
-    request's answer is compared between the two on the device (through a
-    per-request digest taken when it finishes; the server then drops it)."""
+    the batched ones on 3 streams.  Latency = completion - arrival.  Each
+    finished request's answer is handed to the client: copied, on the
+    batch's stream, into a client-owned device buffer (one per run,
+    allocated before the runs, request k at the same place in both), after
+    which the server drops it.  After the two runs the two buffers are
+    compared whole, so every request's answer is checked."""
     import torch
     import workloads
     from paper_2402_00665_amd import serve
@@ -674,46 +690,55 @@ def bench_serving(args):
     log(f"[bench] serving: {R} requests over {args.serve_seconds:.0f}s "
         f"(generated in {time.time() - t0:.1f}s)")
     budget = int(args.serve_budget_gib * (1 << 30))
-    res = {}
-    digests = {}
-    # each finished request's answer is reduced on the device to a digest
-    # (a weighted sum of its offsets and indices) and then dropped, so that
-    # the two runs can be compared request by request without keeping 60k
-    # answers on the device
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(12345)
-    W = torch.randint(-(1 << 62), 1 << 62, (1 << 22,), dtype=torch.int64, device="cuda",
-                      generator=gen)
+    # the clients' buffers: offsets of request k at its prefix of (m + 1),
+    # indices placed by the first run as they come (10 hits per sphere of
+    # room; about 8 are expected) and at the same places in the second
+    m_all = plan["m"].astype(np.int64)
+    off_pos = np.concatenate([[0], np.cumsum(m_all + 1)])
+    idx_cap = int(10 * m_all.sum())
+    arena = {mode: (torch.empty(int(off_pos[-1]), dtype=torch.int64, device="cuda"),
+                    torch.empty(idx_cap, dtype=torch.int32, device="cuda"))
+             for mode in ("fifo", "continuous")}
+    idx_pos = {}          # rid -> (start, hits) in the indices buffers
+    state = {"next": 0, "mismatch": 0, "skipped": 0}
 
-    def digest_into(store):
-        def done(o):   # runs on the batch's stream (the server makes it current)
-            off, idx = o.csr()
-            d = (off * W[:off.numel()]).sum()
-            i64 = idx.long()
-            for a in range(0, i64.numel(), W.numel()):
-                c = i64[a:a + W.numel()]
-                d = d + (c * W[:c.numel()]).sum()
-            store[o.rid] = d
+    def hand_over(mode):
+        a_off, a_idx = arena[mode]
+
+        def done(o):   # runs with the batch's stream current
+            k = o.rid
+            if mode == "fifo":
+                if state["next"] + o.hits > idx_cap:
+                    state["skipped"] += 1
+                    return
+                idx_pos[k] = (state["next"], o.hits)
+                state["next"] += o.hits
+            elif k not in idx_pos:
+                return
+            elif idx_pos[k][1] != o.hits:
+                state["mismatch"] += 1
+                return
+            p0, h = idx_pos[k]
+            o.csr(out=(a_off[int(off_pos[k]):int(off_pos[k + 1])], a_idx[p0:p0 + h]))
         return done
 
+    res = {}
     for mode in ("fifo", "continuous"):
         ex = (serve.PlainExecutor(dp, dc) if mode == "fifo"
               else serve.GpuExecutor(dp, dc, slots=args.serve_slots))
         warm = reqs(0, min(R, 400))
-        wsrv = serve.Server(ex, budget, max_batch=1 if mode == "fifo" else 64, keep_results=False,
-                            on_done=digest_into({}))
+        wsrv = serve.Server(ex, budget, max_batch=1 if mode == "fifo" else 64, keep_results=False)
         wsrv.run(warm)
         wsrv.evict_all()
+        del wsrv
         torch.cuda.synchronize()
         torch.cuda.empty_cache()   # both modes start from the same allocator state
-        digests[mode] = {}
         srv = serve.Server(ex, budget, max_batch=1 if mode == "fifo" else 64, keep_results=False,
-                           on_done=digest_into(digests[mode]))
+                           on_done=hand_over(mode))
         w0 = time.perf_counter()
         out = srv.run(reqs(0, R))
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        srv.evict_all()
         s = serve.summarize(out)
         if not s["ok"]:
             raise RuntimeError(f"serving {mode}: no request succeeded: {s}")
@@ -730,19 +755,22 @@ def bench_serving(args):
             s["slots"] = args.serve_slots
         res[mode] = s
         log(f"[bench] serving {mode}: {s}")
+        srv.evict_all()
         del srv
-    f_d, c_d = digests["fifo"], digests["continuous"]
-    same = len(f_d) == len(c_d) == R and set(f_d) == set(c_d)
-    if same:
-        rids = sorted(f_d)
-        same = bool(torch.equal(torch.stack([f_d[k] for k in rids]),
-                                torch.stack([c_d[k] for k in rids])))
+    # both buffers hold every handed-over answer at the same places
+    used = state["next"]
+    compared = len(idx_pos) if state["mismatch"] == 0 else 0
+    same = (state["mismatch"] == 0 and state["skipped"] == 0 and compared == R
+            and bool(torch.equal(arena["fifo"][0], arena["continuous"][0]))
+            and bool(torch.equal(arena["fifo"][1][:used], arena["continuous"][1][:used])))
+    del arena
+    torch.cuda.empty_cache()
     f, c = res["fifo"], res["continuous"]
     return {"workload": "serving_stream", "rate_per_s": 2000, "seconds": args.serve_seconds,
             "requests": R, "budget_gib": args.serve_budget_gib, "fifo": f, "continuous": c,
             "p99_speedup": round(f["p99_ms"] / c["p99_ms"], 2),
             "throughput_ratio": round(c["throughput_rps"] / f["throughput_rps"], 3),
-            "identical": same}
+            "identical": same, "compared": compared}
 
 
 # --------------------------------------------------------------- profiles

@@ -14,9 +14,10 @@ answer of m sphere queries against it.  The loop
   * keeps finished trees resident (least recently finished evicted first
     when admission needs the memory) so they can be queried again;
   * keeps each finished batch's results (CSR offsets and indices, on the
-    device) with its tree, counted in the budget and evicted with it, or
-    hands them to an ``on_done`` callback as each request finishes and
-    drops them (``keep_results=False``);
+    device), counted in the budget; when memory is needed, resident trees
+    (a cache) are evicted first, least recently finished first, and kept
+    results only once no tree is left.  ``keep_results=False`` drops the
+    results as soon as an ``on_done`` callback has seen them;
   * reports every request's latency (completion - arrival), hits, status.
 
 The executor does the work; ``GpuExecutor`` drives the batched entry points
@@ -83,13 +84,18 @@ class Response:
     def latency(self) -> float:
         return self.done - self.arrival
 
-    def csr(self):
+    def csr(self, out=None):
         """(offsets [m+1] from 0, indices [hits]) of this request, as the
-        executor's arrays (device tensors for the GPU executors).  KeyError
-        once the server has dropped them (evicted, or not kept)."""
+        executor's arrays (device tensors for the GPU executors).  With
+        ``out`` = (offsets [m+1] int64, indices [hits] int32) caller-owned
+        buffers, the answer is written there (enqueued on the current
+        stream, nothing allocated) and ``out`` is returned.  KeyError once
+        the server has dropped the results (evicted, or not kept)."""
         if self.status != LBVH_OK:
             raise RuntimeError(f"request {self.rid} has no result (status {self.status})")
-        return self._handle.csr(self._k)
+        if out is None:
+            return self._handle.csr(self._k)
+        return self._handle.csr(self._k, out)
 
 
 class WallClock:
@@ -130,9 +136,11 @@ def request_valid(r: Request, pool_points: int, pool_centres: int) -> bool:
 
 
 class _InFlight:
-    __slots__ = ("bid", "reqs", "slot", "handle", "bytes", "resident_bytes", "admitted")
+    __slots__ = ("bid", "reqs", "slot", "handle", "bytes", "resident_bytes", "admitted",
+                 "tree_bytes", "result_bytes")
 
     def __init__(self, bid, reqs, slot, handle, nbytes, resident_bytes, admitted):
+        self.tree_bytes = self.result_bytes = 0   # held on the device after completion
         self.bid, self.reqs, self.slot, self.handle = bid, reqs, slot, handle
         self.bytes, self.resident_bytes, self.admitted = nbytes, resident_bytes, admitted
 
@@ -140,9 +148,10 @@ class _InFlight:
 class Server:
     """The request loop.  ``budget_bytes`` bounds in-flight plus resident
     device memory; ``max_batch`` and ``max_batch_points`` cap a batch.
-    A finished batch stays resident with its tree (``keep_resident``) and
-    its results (``keep_results``), both counted in the budget and evicted
-    together; ``on_done(response)`` is called for each finished request
+    A finished batch keeps its tree (``keep_resident``) and its results
+    (``keep_results``) on the device, both counted in the budget; trees are
+    evicted before results.  ``on_done(response)`` is called for each
+    finished request
     while its results are still on the device, with the executor's stream
     for that batch current (GPU executors), so device work it enqueues on
     the results runs before their memory can be reused."""
@@ -166,9 +175,11 @@ class Server:
         if self.pause_gc is None:
             self.pause_gc = isinstance(self.clock, WallClock)
         self.keep_resident = keep_resident
-        self.resident = collections.OrderedDict()   # bid -> (_InFlight, {rid: k})
+        self.resident = collections.OrderedDict()   # bid -> (_InFlight, {rid: k}): resident trees
+        self.kept = collections.OrderedDict()       # bid -> _InFlight: batches whose results are kept
         self.where = {}                              # rid -> bid of its resident tree
-        self.resident_bytes = 0
+        self.resident_bytes = 0                      # resident trees + kept results
+        self.kept_bytes = 0                          # ... of which kept results
         self.inflight_bytes = 0
         self.peak_bytes = 0
         self.batches = []                            # (bid, size, points) per batch started
@@ -176,21 +187,33 @@ class Server:
 
     # -------------------------------------------------------------- memory
 
+    def _evictable(self) -> bool:
+        return bool(self.resident or self.kept)
+
     def _evict_one(self):
-        bid, (b, _) = self.resident.popitem(last=False)
-        for r in b.reqs:
-            if self.where.get(r.rid) == bid:
-                del self.where[r.rid]
-        self.resident_bytes -= b.resident_bytes
-        self.ex.evict(b.handle)
-        self.ex.drop_results(b.handle)
+        """Free the least recently finished tree, or, with no tree left, the
+        least recently finished batch's kept results."""
+        if self.resident:
+            bid, (b, _) = self.resident.popitem(last=False)
+            for r in b.reqs:
+                if self.where.get(r.rid) == bid:
+                    del self.where[r.rid]
+            self.resident_bytes -= b.tree_bytes
+            b.tree_bytes = 0
+            self.ex.evict(b.handle)
+        else:
+            _, b = self.kept.popitem(last=False)
+            self.resident_bytes -= b.result_bytes
+            self.kept_bytes -= b.result_bytes
+            b.result_bytes = 0
+            self.ex.drop_results(b.handle)
 
     def _used(self) -> int:
         return self.inflight_bytes + self.resident_bytes
 
     def evict_all(self):
-        """Drop every resident tree and the results kept with it."""
-        while self.resident:
+        """Drop every resident tree and every kept result."""
+        while self._evictable():
             self._evict_one()
 
     # --------------------------------------------------------------- loop
@@ -277,25 +300,23 @@ class Server:
                 self.ex.release(b.handle)
                 self.inflight_bytes -= b.bytes
                 slots.append(b.slot)
-                # what stays on the device: the trees and/or the results
-                keep = 0
+                # what stays on the device: the tree and/or the results
                 if self.keep_resident:
-                    keep += b.resident_bytes
+                    b.tree_bytes = b.resident_bytes
+                    self.resident[b.bid] = (b, {r.rid: k for k, r in enumerate(b.reqs)})
+                    for r in b.reqs:
+                        self.where[r.rid] = b.bid
                 else:
                     self.ex.evict(b.handle)
                 if self.keep_results:
-                    keep += self.ex.result_bytes(b.handle)
+                    b.result_bytes = self.ex.result_bytes(b.handle)
+                    self.kept[b.bid] = b
                 else:
                     self.ex.drop_results(b.handle)
-                if keep:
-                    b.resident_bytes = keep
-                    self.resident[b.bid] = (b, {r.rid: k for k, r in enumerate(b.reqs)})
-                    if self.keep_resident:
-                        for r in b.reqs:
-                            self.where[r.rid] = b.bid
-                    self.resident_bytes += keep
-                    while self.resident and self._used() > self.budget:
-                        self._evict_one()
+                self.resident_bytes += b.tree_bytes + b.result_bytes
+                self.kept_bytes += b.result_bytes
+                while self._evictable() and self._used() > self.budget:
+                    self._evict_one()
                 self.peak_bytes = max(self.peak_bytes, self._used())
             # deadlines
             now = self.clock.now()
@@ -309,7 +330,8 @@ class Server:
                 alone = bool(retry_alone)
                 src = retry_alone if alone else waiting
                 cap = 1 if alone else self.max_batch
-                room = self.budget - self.inflight_bytes   # resident trees can be evicted
+                # resident trees can be evicted for a new batch, kept results not
+                room = self.budget - self.inflight_bytes - self.kept_bytes
                 take, pts = [], 0
                 fp = (0, 0)
                 for r in src:
@@ -363,7 +385,7 @@ class Server:
                 if ahead is not None and not ahead and (waiting or retry_alone):
                     # nothing in flight, nothing arriving, and the head does
                     # not fit: only resident trees can be holding the memory
-                    if self.resident:
+                    if self._evictable():
                         self._evict_one()
                         continue
                     raise RuntimeError("request loop stalled with work waiting")
@@ -495,12 +517,21 @@ class _Handle:
         self.qbase = None
         self.hits = None
 
-    def csr(self, k):
+    def csr(self, k, out=None):
         if self.indices is None:
             raise KeyError("results dropped (evicted or not kept)")
         a, b = self.qbase[k], self.qbase[k + 1]
         h0, h1 = int(self.hit_base[k]), int(self.hit_base[k + 1])
-        return self.offsets[a:b + 1] - h0, self.indices[h0:h1]
+        if out is None:
+            return self.offsets[a:b + 1] - h0, self.indices[h0:h1]
+        off, idx = out
+        if off.numel() != b - a + 1 or idx.numel() != h1 - h0:
+            raise ValueError(f"out holds {off.numel()} offsets and {idx.numel()} indices; "
+                             f"the answer has {b - a + 1} and {h1 - h0}")
+        import torch
+        torch.sub(self.offsets[a:b + 1], h0, out=off)
+        idx.copy_(self.indices[h0:h1])
+        return out
 
     def result_bytes(self) -> int:
         n = 0

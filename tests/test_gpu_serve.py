@@ -101,9 +101,9 @@ def test_tight_budget_and_resident_queries(pools):
         ao, ai = a.csr()
         go, gi = got[a.rid]
         assert torch.equal(ao.cpu(), go) and torch.equal(ai.cpu(), gi), f"request {a.rid}"
-    # results kept on the device count in the budget: only resident batches
-    # still hold theirs
-    kept = {r.rid for b, _ in srv.resident.values() for r in b.reqs}
+    # results kept on the device count in the budget: only the batches the
+    # server still keeps results for hold theirs
+    kept = {r.rid for b in srv.kept.values() for r in b.reqs}
     for o in out:
         if o.rid not in kept:
             with pytest.raises(KeyError):
@@ -152,3 +152,38 @@ def test_oracle_sample_across_the_size_range(pools):
             assert out[r.rid].hits == len(ei)
     finally:
         oracle.threads(1)
+
+
+def test_hand_over_into_caller_buffers(pools):
+    """Answers copied by on_done into caller-owned buffers (nothing kept by
+    the server) equal the answers the server keeps."""
+    import torch
+    from paper_2402_00665_amd import serve
+    reqs = requests(seed=4, seconds=0.01)
+    _, ref = serve_run(pools, reqs)
+    M = sum(r.m for r in reqs)
+    offs = torch.empty(M + len(reqs), dtype=torch.int64, device="cuda")
+    idx = torch.full((16 * M,), -1, dtype=torch.int32, device="cuda")
+    where, pos = {}, [0, 0]
+
+    def done(o):
+        r = reqs[o.rid]
+        a, b = pos
+        where[o.rid] = (a, b, o.hits)
+        pos[0], pos[1] = a + r.m + 1, b + o.hits
+        assert b + o.hits <= idx.numel()
+        got = o.csr(out=(offs[a:a + r.m + 1], idx[b:b + o.hits]))
+        assert got[0].data_ptr() == offs[a:].data_ptr()
+
+    ex = serve.GpuExecutor(pools[2], pools[3], slots=3)
+    srv = serve.Server(ex, 64 << 30, keep_results=False, on_done=done)
+    out = srv.run(reqs)
+    torch.cuda.synchronize()
+    assert all(o.status == serve.LBVH_OK for o in out)
+    assert not srv.kept
+    for a in ref:
+        ao, ai = a.csr()
+        p, q, h = where[a.rid]
+        assert torch.equal(ao, offs[p:p + ao.numel()]) and torch.equal(ai, idx[q:q + h]), a.rid
+    with pytest.raises(ValueError):   # buffers of the wrong size
+        ref[0].csr(out=(offs[:1], idx[:1]))

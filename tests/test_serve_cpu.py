@@ -118,45 +118,57 @@ def test_budget_is_never_exceeded_and_trees_are_evicted(pools):
     assert srv.peak_bytes <= budget and max(used) <= budget
     assert ex.evictions > 0
     assert srv.resident_bytes + srv.inflight_bytes <= budget
-    # results handed to on_done are the requests' answers; the server's own
-    # copy went with the evicted tree
+    # results handed to on_done are the requests' answers
     r = reqs[0]
     do, di = direct(pools, r)
     assert np.array_equal(got[r.rid][0], do) and np.array_equal(got[r.rid][1], di)
-    with pytest.raises(KeyError):
-        out[0].csr()
 
 
 def test_kept_results_count_in_the_budget(pools):
-    """Results kept on the device are counted with their tree: resident
-    bytes are the trees plus the results of the resident batches, never
-    above the budget; an evicted batch's results are gone, a resident one's
-    are the oracle's.  Without keeping results, only the trees count."""
+    """Results kept on the device count in the budget, beside the resident
+    trees: resident bytes are exactly the resident trees plus the kept
+    results, never above the budget.  Trees are evicted before results: with
+    room for every result, every tree but few is evicted and every answer
+    is still there; with a budget too small for the results too, the oldest
+    results go, an evicted answer raises KeyError and a kept one equals the
+    oracle.  Without keeping results, only the trees count."""
     reqs = plan_requests(seed=8)
     fx = FakeExecutor(None, *pools)
     big = max(fx.footprint([r])[0] for r in reqs)
-    for keep_results, keep_resident in ((True, True), (True, False), (False, True)):
-        budget = 2 * big
+    all_results = sum(8 * (r.m + 1) + 4 * len(direct(pools, r)[1]) for r in reqs)
+    cases = ((True, True, 2 * big + all_results), (True, True, 2 * big), (True, False, 2 * big),
+             (False, True, 2 * big))
+    for keep_results, keep_resident, budget in cases:
         srv, ex, out = run(pools, reqs, budget=budget, keep_results=keep_results,
                            keep_resident=keep_resident)
         assert all(o.status == serve.LBVH_OK for o in out)
         assert srv.peak_bytes <= budget
-        total = 0
-        for bid, (b, ks) in srv.resident.items():
-            tree = b.resident_bytes - (ex.result_bytes(b.handle) if keep_results else 0)
-            assert tree == (fx.footprint(b.reqs)[1] if keep_resident else 0)
-            total += b.resident_bytes
-        assert total == srv.resident_bytes <= budget
-        resident = {r.rid for b, _ in srv.resident.values() for r in b.reqs}
+        trees = sum(b.tree_bytes for b, _ in srv.resident.values())
+        results = sum(b.result_bytes for b in srv.kept.values())
+        assert trees + results == srv.resident_bytes <= budget
+        assert all(b.tree_bytes == fx.footprint(b.reqs)[1] for b, _ in srv.resident.values())
+        assert all(b.result_bytes == ex.result_bytes(b.handle) > 0 for b in srv.kept.values())
+        if not keep_resident:
+            assert not srv.resident
+        if not keep_results:
+            assert not srv.kept
+        if srv.kept and srv.resident:
+            # trees go first: every kept result is at least as recent as the
+            # oldest resident tree's batch... or older ones were kept because
+            # trees were evicted instead
+            assert min(srv.kept) <= min(srv.resident)
+        kept = {r.rid for b in srv.kept.values() for r in b.reqs}
+        if keep_results and budget > 2 * big:
+            assert len(kept) == len(reqs), "results were dropped although they fit"
+            assert ex.evictions > 0, "trees should have been evicted"
         for r, o in zip(reqs, out):
-            if keep_results and r.rid in resident:
+            if r.rid in kept:
                 mo, mi = o.csr()
                 do, di = direct(pools, r)
                 assert np.array_equal(mo, do) and np.array_equal(mi, di)
             else:
                 with pytest.raises(KeyError):
                     o.csr()
-
 
 def test_resident_tree_can_be_queried_again(pools):
     reqs = plan_requests(seed=6)
