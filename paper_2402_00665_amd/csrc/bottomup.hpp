@@ -244,10 +244,16 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     __syncthreads();
     if (tid < cn) store[A + tid] = s_store[tid];
     if (tid < 2) {
-        const Climb st = s_pend[tid];
-        if (bl.last && st.id.x >= 0)   // a climb stopped below the root of its tree
+        // field by field: a whole-struct copy around the atomic goes through
+        // scratch memory, and scratch in any part of a kernel costs every wave
+        const int4 id = s_pend[tid].id;
+        const float4 slo = s_pend[tid].lo, shi = s_pend[tid].hi;
+        if (bl.last && id.x >= 0)   // a climb stopped below the root of its tree
             __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pend[2 * blockIdx.x + tid] = st;
+        Climb *o = pend + 2 * (int64_t)blockIdx.x + tid;
+        o->id = id;
+        o->lo = slo;
+        o->hi = shi;
     }
 }
 
@@ -373,10 +379,14 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__res
     // above (a consumed one is never read again)
     if (park_at >= 0) store[park_at] = park_word;
     if (tid < 2) {
-        const Climb st = s_pend[tid];
-        if (bl.last && st.id.x >= 0)
+        const int4 id = s_pend[tid].id;
+        const float4 slo = s_pend[tid].lo, shi = s_pend[tid].hi;
+        if (bl.last && id.x >= 0)
             __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pend_out[2 * blockIdx.x + tid] = st;
+        Climb *o = pend_out + 2 * (int64_t)blockIdx.x + tid;
+        o->id = id;
+        o->lo = slo;
+        o->hi = shi;
     }
 }
 

@@ -459,11 +459,12 @@ struct LeafMask {
 // Alg. 1 restricted to the leaves [i, hi) from node v, by one lane: counts
 // the hits, and writes them from slot pos of out (FILL; at most `limit`,
 // the count the count call found for the piece, so a fill never writes
-// past the piece's slots) or sets them in *mask (count pass, pieces at most
-// kMaskLeaves wide).
+// past the piece's slots) or, with `keep`, sets them in `mask` (count
+// pass, pieces at most kMaskLeaves wide).  The mask is a reference with a
+// flag, not a pointer that may be null: that keeps it in registers.
 template <class Q, bool FILL>
 __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, int32_t *out,
-                              int64_t pos, LeafMask *mask = nullptr, int64_t limit = 0)
+                              int64_t pos, LeafMask &mask, bool keep, int64_t limit = 0)
 {
     const int leaf0 = tr.leaf0();
     const int i0 = i;
@@ -478,16 +479,16 @@ __device__ int64_t walk_piece(const Tree &tr, const Q &q, int v, int i, int hi, 
             if (v >= leaf0) {
                 if (FILL) {
                     if (cnt < limit) out[pos + cnt] = left;
-                } else if (mask) {
-                    mask->set(i - i0, i - i0 + 1);
+                } else if (keep) {
+                    mask.set(i - i0, i - i0 + 1);
                 }
                 ++cnt;
             } else if (q.contains(a, b)) {
                 const int e = j + 1 < hi ? j + 1 : hi;
                 if (FILL)
                     for (int k = i; k < e && cnt + (k - i) < limit; ++k) out[pos + cnt + (k - i)] = tr.perm[k];
-                else if (mask)
-                    mask->set(i - i0, e - i0);
+                else if (keep)
+                    mask.set(i - i0, e - i0);
                 cnt += e - i;
             } else {
                 v = left;
@@ -593,7 +594,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_count_wide(Tree tr, const float
         if (it.y == kAllHits || it.w - it.z <= kLeafScanMax) continue;
         Q q;
         q.load(queries, it.x);
-        counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0);
+        LeafMask none;
+        counts[t] = (int32_t)walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0, none, false);
     }
 }
 
@@ -633,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_mixed_count(Tree tr, const floa
                 if (walk) {
                     const bool keep = it.w - it.z <= kMaskLeaves;
                     LeafMask mk;
-                    cnt = walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0, keep ? &mk : nullptr);
+                    cnt = walk_piece<Q, false>(tr, q, it.y, it.z, it.w, nullptr, 0, mk, keep);
                     if (keep) mk.store(masks + t * kMaskWords, it.w - it.z);
                 } else {
                     scan = true;
@@ -878,7 +880,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_fill_wide(Tree tr, const float 
                     tr.load(it.y, a, b);
                     walk = !dense_piece(q, a, b);
                 }
-                if (walk) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos, nullptr, limit);
+                LeafMask none;
+                if (walk) walk_piece<Q, true>(tr, q, it.y, it.z, it.w, out, pos, none, false, limit);
                 else scan = true;
             }
         }

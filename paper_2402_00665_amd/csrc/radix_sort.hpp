@@ -119,12 +119,10 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K *kp = keys_in + b0 + base + lofs;
     const int32_t *vp = vals_in ? vals_in + b0 + base + lofs : nullptr;
     K key[ITEMS];
-    int32_t val[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const bool ok = lofs + k * 64 < rem;
         key[k] = ok ? kp[k * 64] : (K)0;
-        val[k] = vp ? (ok ? vp[k * 64] : 0) : (int32_t)(base + lofs + k * 64);
     }
 
     // stable rank within the wave: lanes holding the same digit find each
@@ -241,6 +239,14 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
         pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
+    }
+    // the values, loaded only now (they are needed last; loading them with
+    // the keys made the widest tiles spill registers to scratch memory)
+    int32_t val[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const bool ok = lofs + k * 64 < rem;
+        val[k] = vp ? (ok ? vp[k * 64] : 0) : (int32_t)(base + lofs + k * 64);
     }
     // keys: into LDS in tile-sorted order, then out in runs (segment-local
     // positions fit 32 bits: a segment holds at most 2^30 keys)
