@@ -119,10 +119,18 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K *kp = keys_in + b0 + base + lofs;
     const int32_t *vp = vals_in ? vals_in + b0 + base + lofs : nullptr;
     K key[ITEMS];
+    uint32_t dig[ITEMS];   // this pass's digit of each key
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const bool ok = lofs + k * 64 < rem;
         key[k] = ok ? kp[k * 64] : (K)0;
+        dig[k] = (uint32_t)(key[k] >> shift) & (R - 1);
+    }
+    // 64-bit keys wait in LDS (input order) while the tile is ranked: kept
+    // in registers, the widest tiles spilled to scratch memory
+    if constexpr (sizeof(K) == 8) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) s_buf[lofs + k * 64] = key[k];
     }
 
     // stable rank within the wave: lanes holding the same digit find each
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const bool ok = lofs + k * 64 < rem;
-        const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
+        const uint32_t d = dig[k];
         // lanes whose digit differs from this lane's in some bit: for each
         // bit, the ballot of lanes that have it, flipped where this lane has
         // it (a sign-extended bit as the xor mask); bits at or above nbits
@@ -237,8 +245,14 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     uint32_t pos[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
+        const uint32_t dk = dig[k];
         pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
+    }
+    if constexpr (sizeof(K) == 8) {
+        // the keys back from LDS before their slots are reused
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) key[k] = s_buf[lofs + k * 64];
+        __syncthreads();
     }
     // the values, loaded only now (they are needed last; loading them with
     // the keys made the widest tiles spill registers to scratch memory)
