@@ -783,6 +783,7 @@ KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name (first 
     "k_leaf_mixed_count": "query_count", "k_leaf_fill": "query_fill", "copyBuffer": "copy",
     "k_batch_plan": "batch_plan", "k_batch_morton": "morton", "k_batch_count": "query_count",
     "k_batch_fill": "query_fill", "k_scene_sort": "scene_sort", "k_ray_first": "ray_first",
+    "k_radix_count": "sort_count",
 }
 
 

@@ -421,6 +421,12 @@ const char *lbvh_last_hip_error(void);
  *       opposite of the scene-box pass before it, so its first reads find
  *       that pass's last lines in the last-level cache (default); 0 = from
  *       the start.
+ *   "radix_mode": how the single-tree build runs each radix pass: 0 = one
+ *       onesweep kernel whose tiles find their output positions by a
+ *       decoupled look-back over the earlier tiles (default); 1 = a count
+ *       kernel over chunks of 8 tiles (the look-back runs over the
+ *       chunks' totals) and then the scatter kernel, which reads each
+ *       tile's positions and waits for no other tile.
  * Results never depend on the knobs other than query_walk_budget; only
  * speed does.  Calls already enqueued keep the shapes they were enqueued
  * with. */

@@ -29,6 +29,7 @@ KNOB_CANDIDATES = {
     "batch_sort_variant": list(range(4)),
     "batch_sort_mode": [0, 1],
     "radix_bits32": [8, 10],
+    "radix_mode": [0, 1],
     "radix_bits64": [8, 9, 11],
 }
 # (query_split1, query_split2, query_leaf_mode, query_order): each split
@@ -125,11 +126,11 @@ def sort_knobs(code_bits: int, batched: bool):
 def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene: int | None = None,
          reps: int = 5, save: bool = True, verbose: bool = False) -> dict:
     """Tune the radix digit width and tile shape for this workload (a single
-    tree, or a batch when ``seg_off`` is given): each (width, shape) pair is
-    timed as the codes kernel plus all radix passes of a build.  Returns
-    {"knobs": {width knob: bits, shape knob: shape}, "times_ms": {"bits/shape":
-    ms per build}}; every candidate is checked to give the same tree, bit for
-    bit, as the first (current) one."""
+    tree, or a batch when ``seg_off`` is given), and for a single tree the
+    pass form ("radix_mode"): each candidate is timed as the codes kernel
+    plus all radix passes of a build.  Returns {"knobs": {knob: value},
+    "times_ms": {"bits/shape[/mode]": ms per build}}; every candidate is
+    checked to give the same tree, bit for bit, as the first (current) one."""
     import torch
     if kind is None:
         kind = LBVH_POINTS if prims.shape[1] == 3 else 1
@@ -139,10 +140,14 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
     # tile shape) and one block per scene (mode 1, each block shape): a
     # mode-1 candidate's shape slot holds -1 - shape
     mode0 = lbvh_tune("batch_sort_mode") if batched else 0
-    default = (lbvh_tune(wk), lbvh_tune(sk) if mode0 == 0 else -1 - lbvh_tune(sk))
-    cands = [(b, v) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
+    rmode0 = 0 if batched else lbvh_tune("radix_mode")
+    default = (lbvh_tune(wk), lbvh_tune(sk) if mode0 == 0 else -1 - lbvh_tune(sk), rmode0)
     if batched:
-        cands += [(b, -1 - v) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
+        cands = [(b, v, 0) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
+        cands += [(b, -1 - v, 0) for b in KNOB_CANDIDATES[wk] for v in KNOB_CANDIDATES[sk]]
+    else:
+        cands = [(b, v, m) for m in KNOB_CANDIDATES["radix_mode"] for b in KNOB_CANDIDATES[wk]
+                 for v in KNOB_CANDIDATES[sk]]
     order = [default] + [c for c in cands if c != default]
     shape0 = lbvh_tune(sk)
     ws = Workspace(prims.device)
@@ -154,10 +159,12 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
         obj = alloc_tree(n, code_bits, prims.device)
     times, ref = {}, None
     try:
-        for b, v in order:
+        for b, v, m in order:
             lbvh_tune(wk, b)
             if batched:
                 lbvh_tune("batch_sort_mode", 1 if v < 0 else 0)
+            else:
+                lbvh_tune("radix_mode", m)
             lbvh_tune(sk, v if v >= 0 else -1 - v)
             t = (_time_batched(prims, seg_off, code_bits, kind, max_scene, ws, obj, reps) if batched
                  else _time_single(prims, code_bits, kind, ws, obj, reps))
@@ -166,21 +173,25 @@ def tune(prims, code_bits: int, kind: int | None = None, seg_off=None, max_scene
                 ref = out
             elif not torch.equal(out, ref):
                 raise RuntimeError(f"{wk}={b}, {sk}={v} changed the tree; refusing to tune with it")
-            times[f"{b}/{v}"] = t
+            times[f"{b}/{v}" if batched else f"{b}/{v}/{m}"] = t
             if verbose:
-                print(f"[autotune] {wk}={b} {sk}={v}: {t * 1e3:.1f} us per build", flush=True)
+                print(f"[autotune] {wk}={b} {sk}={v}" + ("" if batched else f" radix_mode={m}")
+                      + f": {t * 1e3:.1f} us per build", flush=True)
     finally:
         lbvh_tune(wk, default[0])
         lbvh_tune(sk, shape0)
         if batched:
             lbvh_tune("batch_sort_mode", mode0)
+        else:
+            lbvh_tune("radix_mode", rmode0)
     best = min(times, key=times.get)
-    b_best, v_best = (int(x) for x in best.split("/"))
+    got = [int(x) for x in best.split("/")]
+    b_best, v_best = got[0], got[1]
     if batched:
         knobs = {wk: b_best, "batch_sort_mode": 1 if v_best < 0 else 0,
                  sk: v_best if v_best >= 0 else -1 - v_best}
     else:
-        knobs = {wk: b_best, sk: v_best}
+        knobs = {wk: b_best, sk: v_best, "radix_mode": got[2]}
     if save:
         cache = _load()
         cache[_key(sk, code_bits, kind, n)] = {"knobs": knobs, "times_ms": times}

@@ -509,7 +509,8 @@ void launch_seg(int64_t grid, const K *kin, K *kout, const int32_t *vin, int32_t
                 uint32_t *st_next, uint32_t *ctr, uint32_t *err, hipStream_t s)
 {
     hipLaunchKernelGGL((k_onesweep<K, T, I, B>), dim3((unsigned)grid), dim3(T), 0, s, kin, kout, vin,
-                       vout, N, segs, shift, nbits, hist, st, st_next, ctr, err);
+                       vout, N, segs, shift, nbits, hist, st, st_next, (uint32_t)grid, ctr, err,
+                       (const uint32_t *)nullptr);
 }
 
 template <typename K, int B>

@@ -174,27 +174,42 @@ int sort_variant(int bits)
     return fits ? var : (sizeof(K) == 4 ? 4 : 3);   // 512 x 16 / 512 x 8 fit every width
 }
 
+// One radix pass: the onesweep kernel alone, or (toff given: the
+// reduce-then-scan form) the count kernel over chunks of tiles and then the
+// scatter, which reads its tiles' offsets from toff.  `st` is the pass's
+// look-back table (per tile, or per chunk), `st_next` the next pass's,
+// cleared by this pass's scatter.
 template <typename K, int T, int I, int B>
 void launch_one(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n, int shift, int nbits,
                 const uint32_t *hist, uint32_t *st, uint32_t *st_next, uint32_t *ctr, uint32_t *err,
-                hipStream_t s)
+                uint32_t *toff, hipStream_t s)
 {
     if constexpr (sort_lds_bytes(sizeof(K), T, I, B) > 150 * 1024) {
         return;   // never selected (sort_variant)
     } else {
         const unsigned tiles = (unsigned)(((int64_t)n + T * I - 1) / (T * I));
         const SortSegs one{nullptr, nullptr, 1, 0};
-        hipLaunchKernelGGL((k_onesweep<K, T, I, B>), dim3(tiles), dim3(T), 0, s, kin, kout, vin, vout,
-                           (int64_t)n, one, shift, nbits, hist, st, st_next, ctr, err);
+        if (toff) {
+            const unsigned chunks = (tiles + kCountChunk - 1) / kCountChunk;
+            hipLaunchKernelGGL((k_radix_count<K, B, T * I>), dim3(chunks), dim3(kCountThreads), 0, s, kin,
+                               (int64_t)n, shift, hist, st, toff, ctr, err);
+            hipLaunchKernelGGL((k_onesweep<K, T, I, B>), dim3(tiles), dim3(T), 0, s, kin, kout, vin, vout,
+                               (int64_t)n, one, shift, nbits, hist, st, st_next, chunks, ctr, err,
+                               (const uint32_t *)toff);
+        } else {
+            hipLaunchKernelGGL((k_onesweep<K, T, I, B>), dim3(tiles), dim3(T), 0, s, kin, kout, vin, vout,
+                               (int64_t)n, one, shift, nbits, hist, st, st_next, tiles, ctr, err,
+                               (const uint32_t *)nullptr);
+        }
     }
 }
 
 template <typename K, int B>
 void launch_onesweep_b(int variant, const K *kin, K *kout, const int32_t *vin, int32_t *vout, int n,
                        int shift, int nbits, const uint32_t *hist, uint32_t *st, uint32_t *st_next,
-                       uint32_t *ctr, uint32_t *err, hipStream_t s)
+                       uint32_t *ctr, uint32_t *err, uint32_t *toff, hipStream_t s)
 {
-#define LBVH_SORT_ARGS kin, kout, vin, vout, n, shift, nbits, hist, st, st_next, ctr, err, s
+#define LBVH_SORT_ARGS kin, kout, vin, vout, n, shift, nbits, hist, st, st_next, ctr, err, toff, s
     switch (variant) {
     case 1: launch_one<K, 256, 8, B>(LBVH_SORT_ARGS); break;
     case 2: launch_one<K, 256, 24, B>(LBVH_SORT_ARGS); break;
@@ -212,7 +227,9 @@ void launch_onesweep_b(int variant, const K *kin, K *kout, const int32_t *vin, i
 // The digit width's Morton kernel and radix passes.  Ping-pong: the Morton
 // kernel writes the codes to the buffer that makes the last pass end in
 // tree->codes (keys_alt for an odd number of passes); the last pass writes
-// the permutation to leaf_perm.
+// the permutation to leaf_perm.  Look-back tables: the two status buffers
+// in turn (onesweep), or status[0] for the chunks of every pass and
+// status[1] for the tiles' offsets (reduce-then-scan, "radix_mode" 1).
 template <int KIND, typename K, int B>
 void run_sort(const float *prims, int n, int code_bits, K *codes, int32_t *leaf_perm,
               const float4 *scene, uint32_t *ctrl, uint32_t *hist, uint32_t *status[2], K *keys_alt,
@@ -237,16 +254,19 @@ void run_sort(const float *prims, int n, int code_bits, K *codes, int32_t *leaf_
                        hist, status[0], tiles << B, (int)tune_get(TUNE_MORTON_ORDER));
     prof_end(K_MORTON, s);
 
+    const bool rts = tune_get(TUNE_RADIX_MODE) == 1;
     for (int p = 0; p < passes; ++p) {
         const K *kin = (p & 1) ? second : first;
         K *kout = (p & 1) ? first : second;
         const int32_t *vin = p == 0 ? nullptr : vals[(p - 1) & 1];
         int32_t *vout = p + 1 == passes ? leaf_perm : vals[p & 1];
-        uint32_t *st_next = (p + 1 < passes) ? status[(p + 1) & 1] : nullptr;
+        uint32_t *st = rts ? status[0] : status[p & 1];
+        uint32_t *st_next = (p + 1 < passes) ? (rts ? status[0] : status[(p + 1) & 1]) : nullptr;
         const int nbits = std::min(B, code_bits - p * B);
         prof_begin(K_SORT, s);
         launch_onesweep_b<K, B>(variant, kin, kout, vin, vout, n, p * B, nbits, hist + ((int64_t)p << B),
-                                status[p & 1], st_next, ctrl + kCtrlTileCounter + p, ctrl + kCtrlError, s);
+                                st, st_next, ctrl + kCtrlTileCounter + p, ctrl + kCtrlError,
+                                rts ? status[1] : nullptr, s);
         prof_end(K_SORT, s);
     }
 }

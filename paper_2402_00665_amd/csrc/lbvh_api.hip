@@ -136,13 +136,14 @@ namespace {
 // keys, 9-bit digits and 768 x 16 tiles for 63-bit keys; the Morton kernel
 // sweeping backwards
 std::atomic<int64_t> g_tune[TUNE_NUM] = {{4}, {6}, {0}, {kSplit1}, {kSplit2}, {0}, {0}, {8}, {9}, {0},
-                                         {1}, {0}};
+                                         {1}, {0}, {0}};
 const char *kTuneNames[TUNE_NUM] = {"sort_variant32", "sort_variant64", "batch_sort_variant",
                                     "query_split1", "query_split2", "query_leaf_mode",
                                     "query_order", "radix_bits32", "radix_bits64",
-                                    "query_walk_budget", "morton_order", "batch_sort_mode"};
-const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0, 0, 0};   // accepted values: min .. max
-const int64_t kTuneMax[TUNE_NUM] = {8, 8, 3, 24, 24, 1, 1, 10, 11, INT32_MAX, 1, 1};
+                                    "query_walk_budget", "morton_order", "batch_sort_mode",
+                                    "radix_mode"};
+const int64_t kTuneMin[TUNE_NUM] = {0, 0, 0, 2, 2, 0, 0, 8, 8, 0, 0, 0, 0};   // accepted values: min .. max
+const int64_t kTuneMax[TUNE_NUM] = {8, 8, 3, 24, 24, 1, 1, 10, 11, INT32_MAX, 1, 1, 1};
 }  // namespace
 
 int64_t tune_get(int knob) { return g_tune[knob].load(std::memory_order_relaxed); }

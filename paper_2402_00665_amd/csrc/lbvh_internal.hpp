@@ -165,6 +165,7 @@ int batch_levels(int64_t max_scene);
 enum TuneKnob {
     TUNE_SORT_VARIANT32 = 0, TUNE_SORT_VARIANT64, TUNE_BATCH_SORT, TUNE_QSPLIT1, TUNE_QSPLIT2, TUNE_QLEAF, TUNE_QORDER,
     TUNE_RADIX_BITS32, TUNE_RADIX_BITS64, TUNE_QBUDGET, TUNE_MORTON_ORDER, TUNE_BATCH_SORT_MODE,
+    TUNE_RADIX_MODE,
     TUNE_NUM
 };
 int64_t tune_get(int knob);

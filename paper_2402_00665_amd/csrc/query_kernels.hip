@@ -295,10 +295,12 @@ hipError_t run_count(Tree tr, const float *q, int m, int64_t *offsets, char *ws,
         const SortSegs one{nullptr, nullptr, 1, 0};
         hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4, kRadixBits>), dim3((unsigned)qtiles), dim3(512), 0, s,
                            S.qkeys[0], S.qkeys[1], nullptr, S.qvals, (int64_t)m, one, 0, kRadixBits, S.qhist,
-                           S.qstatus[0], S.qstatus[1], S.sort_ctr + 0, S.err);
+                           S.qstatus[0], S.qstatus[1], (uint32_t)qtiles, S.sort_ctr + 0, S.err,
+                           (const uint32_t *)nullptr);
         hipLaunchKernelGGL((k_onesweep<uint32_t, 512, 4, kRadixBits>), dim3((unsigned)qtiles), dim3(512), 0, s,
                            S.qkeys[1], S.qkeys[0], S.qvals, S.qperm, (int64_t)m, one, kRadixBits, kRadixBits,
-                           S.qhist + kRadix, S.qstatus[1], nullptr, S.sort_ctr + 1, S.err);
+                           S.qhist + kRadix, S.qstatus[1], nullptr, 0u, S.sort_ctr + 1, S.err,
+                           (const uint32_t *)nullptr);
         hipLaunchKernelGGL((k_qorder_gather<Q>), dim3(gm), dim3(kBlock), 0, s, q, S.qperm, m,
                            S.qsorted);
         prof_end(K_QORDER, s);

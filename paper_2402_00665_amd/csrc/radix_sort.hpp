@@ -62,14 +62,191 @@ __device__ __forceinline__ void digits_excl_scan(const uint32_t (&v)[DPT], uint3
     }
 }
 
+// Decoupled look-back for the DPT digits from d0 that this thread owns:
+// sums the counts earlier tiles published (row j of `status`, R words a
+// row) back from tile-1 until an inclusive prefix or the segment's first
+// tile t0, then publishes this tile's inclusive prefix.  All of the
+// thread's digits are in flight together.  A wait that never ends (not
+// expected: every earlier tile is already running) is cut and flagged.
+template <int DPT>
+__device__ __forceinline__ void look_back(uint32_t *status, int R, uint32_t tile, uint32_t t0, int d0,
+                                          const uint32_t (&total)[DPT], uint32_t (&excl)[DPT],
+                                          uint32_t *err)
+{
+    auto owns = [&](int k) { return d0 + k < R; };
+    int64_t j[DPT];
+    bool done[DPT];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) { excl[k] = 0; j[k] = (int64_t)tile - 1; done[k] = !owns(k); }
+    uint32_t spins = 0;
+    while (true) {
+        uint32_t sv[DPT];
+#pragma unroll
+        for (int k = 0; k < DPT; ++k)
+            sv[k] = done[k] ? 0u
+                            : __hip_atomic_load(status + j[k] * R + d0 + k, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        bool all = true, waiting = false;
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            if (done[k]) continue;
+            const uint32_t flag = sv[k] & ~kValueMask;
+            if (flag == 0u) { waiting = true; all = false; continue; }
+            excl[k] += sv[k] & kValueMask;
+            if (flag == kFlagInclusive || j[k] == (int64_t)t0) done[k] = true;
+            else { --j[k]; all = false; }
+        }
+        if (all) break;
+        if (waiting) {
+            if (++spins > (1u << 24)) {   // never expected: bounded wait
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DPT; ++k)
+        if (owns(k))
+            __hip_atomic_store(status + (int64_t)tile * R + d0 + k, kFlagInclusive | (excl[k] + total[k]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reduce-then-scan form of a pass over one key array: the tiles' digit
+// offsets are worked out before the scatter, so the scatter (k_onesweep
+// with `toff`) waits for no other tile.  Measured on 2^24 keys, the
+// look-back inside the scatter cost 30-110 us per pass (it touches R
+// status words per tile); here it runs once per chunk of kCountChunk
+// tiles, over the chunks' digit totals.
+//
+// One block per chunk (taken in order from a counter, so every chunk it
+// waits for is already running): counts the digits of all the chunk's keys
+// in one sweep, per tile, in LDS; turns them into running counts over the
+// chunk's tiles; then the chunk's totals go through the look-back, and each
+// tile's first output position per digit,
+//   toff[t][d] = (keys of digits < d) + (digit d in earlier chunks)
+//              + (digit d in earlier tiles of the chunk),
+// is written for the scatter.
+constexpr int kCountThreads = 1024;   // 16 waves: the digit matching is latency-bound
+constexpr int kCountChunk = 8;       // tiles per chunk
+
+template <typename K, int BITS, int TILE>
+__global__ __launch_bounds__(kCountThreads) void k_radix_count(
+    const K *__restrict__ keys, int64_t n, int shift, const uint32_t *__restrict__ hist,
+    uint32_t *status, uint32_t *__restrict__ toff, uint32_t *chunk_counter, uint32_t *err)
+{
+    constexpr int R = 1 << BITS;
+    constexpr int DPT = (R + kCountThreads - 1) / kCountThreads;   // digits per owning thread
+    constexpr int kLoads = 4;                // 16-byte loads per thread in flight
+    __shared__ uint32_t s_cnt[kCountChunk][R];   // per tile: digit counts, then the chunk's running counts
+    __shared__ uint32_t s_scan[kCountThreads / 64];
+    __shared__ uint32_t s_chunk;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_chunk = atomicAdd(chunk_counter, 1u);
+    for (int w = tid; w < kCountChunk * R; w += kCountThreads) (&s_cnt[0][0])[w] = 0u;
+    __syncthreads();
+    const uint32_t c = s_chunk;
+    const int64_t tiles = (n + TILE - 1) / TILE;
+    const int64_t tb = (int64_t)c * kCountChunk;
+    const int nct = (int)(tiles - tb < kCountChunk ? tiles - tb : kCountChunk);   // >= 1: grid = chunks
+    const int d0 = tid * DPT;
+    auto owns = [&](int k) { return d0 + k < R; };
+    // every key of the chunk's tiles in one sweep, counted under its tile
+    const int64_t cb = tb * TILE;
+    const int len = n - cb < (int64_t)nct * TILE ? (int)(n - cb) : nct * TILE;
+    // 16-byte loads (the chunk starts 16-byte aligned: TILE is a multiple of
+    // 256 keys), kLoads of them in flight per thread, then the ragged tail.
+    // The lanes holding one digit find each other with one ballot per digit
+    // bit and the lowest adds their number: one LDS atomic per distinct
+    // digit of a wave's 64 keys, not one per key (equal codes, frequent in
+    // clustered scenes, sit together after the first passes and would
+    // serialize the atomics).  A wave's 64 keys (lanes in order) never
+    // straddle a tile: the loads of a wave cover 64 * V consecutive keys
+    // from a multiple of that.
+    const K *kp = keys + cb;
+    constexpr int V = 16 / (int)sizeof(K);   // keys per load
+    const int nvec = len / V;
+    const uint4 *vp = reinterpret_cast<const uint4 *>(kp);
+    auto count = [&](bool ok, int i, K key) {   // all lanes together
+        const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
+        uint64_t diff = 0;
+#pragma unroll
+        for (int b = 0; b < BITS; ++b) {
+            const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
+            diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
+        }
+        const uint64_t peers = __ballot(ok) & ~diff;
+        if (ok && count_below(peers) == 0u) atomicAdd(&s_cnt[i / TILE][d], (uint32_t)__popcll(peers));
+    };
+    for (int i0 = 0; i0 < nvec; i0 += kLoads * kCountThreads) {
+        uint4 vv[kLoads];
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int iv = i0 + u * kCountThreads + tid;
+            vv[u] = iv < nvec ? vp[iv] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoads; ++u) {
+            const int iv = i0 + u * kCountThreads + tid;
+            const bool ok = iv < nvec;
+            if constexpr (sizeof(K) == 4) {
+                count(ok, iv * 4, (K)vv[u].x);
+                count(ok, iv * 4 + 1, (K)vv[u].y);
+                count(ok, iv * 4 + 2, (K)vv[u].z);
+                count(ok, iv * 4 + 3, (K)vv[u].w);
+            } else {
+                count(ok, iv * 2, (K)(((uint64_t)vv[u].y << 32) | vv[u].x));
+                count(ok, iv * 2 + 1, (K)(((uint64_t)vv[u].w << 32) | vv[u].z));
+            }
+        }
+    }
+    for (int i = nvec * V + tid; i < len; i += kCountThreads)   // fewer than V keys
+        atomicAdd(&s_cnt[i / TILE][(uint32_t)(kp[i] >> shift) & (R - 1)], 1u);
+    __syncthreads();
+    // per digit: the running count over the chunk's tiles, and the total
+    uint32_t run[DPT];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+        run[k] = 0u;
+        if (!owns(k)) continue;
+        for (int j = 0; j < nct; ++j) {
+            const uint32_t v = s_cnt[j][d0 + k];
+            s_cnt[j][d0 + k] = run[k];
+            run[k] += v;
+        }
+    }
+    // the chunk's totals: published, then the earlier chunks' summed
+    uint32_t excl[DPT];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+        excl[k] = 0u;
+        if (owns(k))
+            __hip_atomic_store(status + (int64_t)c * R + d0 + k,
+                               (c == 0 ? kFlagInclusive : kFlagAggregate) | run[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (c > 0 && d0 < R) look_back<DPT>(status, R, c, 0u, d0, run, excl, err);
+    uint32_t hv[DPT], hoff[DPT];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) hv[k] = owns(k) ? hist[d0 + k] : 0u;
+    digits_excl_scan<kCountThreads, DPT>(hv, hoff, s_scan);
+    for (int j = 0; j < nct; ++j)
+#pragma unroll
+        for (int k = 0; k < DPT; ++k)
+            if (owns(k)) toff[(tb + j) * R + d0 + k] = hoff[k] + excl[k] + s_cnt[j][d0 + k];
+}
+
 // One pass over digit `shift .. shift+nbits` (nbits <= BITS: the last digit
-// of a code can be narrower).
+// of a code can be narrower).  With `toff` (one key array, reduce-then-scan
+// form): block b is tile b and takes its digits' output positions from
+// toff[b] instead of the look-back; `next_rows` rows of `status_next` are
+// cleared (by the tiles of those numbers) for the next pass either way.
 template <typename K, int THREADS, int ITEMS, int BITS>
 __global__ __launch_bounds__(THREADS) void k_onesweep(
     const K *__restrict__ keys_in, K *__restrict__ keys_out, const int32_t *__restrict__ vals_in,
     int32_t *__restrict__ vals_out, int64_t n, SortSegs seg, int shift, int nbits,
     const uint32_t *__restrict__ hist, uint32_t *status, uint32_t *__restrict__ status_next,
-    uint32_t *tile_counter, uint32_t *err)
+    uint32_t next_rows, uint32_t *tile_counter, uint32_t *err, const uint32_t *__restrict__ toff)
 {
     constexpr int R = 1 << BITS;
     constexpr int W = THREADS / 64;
@@ -86,7 +263,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     __shared__ K s_buf[TILE];                // keys, then values
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    if (tid == 0) s_tile = toff ? blockIdx.x : atomicAdd(tile_counter, 1u);
     constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
     for (int j = tid; j < kZeroWords; j += THREADS) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
     __syncthreads();
@@ -106,7 +283,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     }
     const uint32_t lt = tile - t0;           // tile index within the segment
     const int64_t base = (int64_t)lt * TILE; // segment-local
-    if (status_next)
+    if (status_next && tile < next_rows)
         for (int d = tid; d < R; d += THREADS) status_next[(int64_t)tile * R + d] = 0u;
 
     // wave w owns keys [base + w*64*ITEMS, ...); item k of lane l is key
@@ -177,7 +354,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
             for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
 #pragma unroll
             for (int w = 0; w < W; ++w) { s_wcnt[w][d] = (Cnt)total[k]; total[k] += c[w]; }
-            if (nt > 1)
+            if (nt > 1 && !toff)
                 __hip_atomic_store(status + (int64_t)tile * R + d,
                                    (lt == 0 ? kFlagInclusive : kFlagAggregate) | total[k],
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -187,57 +364,19 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     digits_excl_scan<THREADS, DPT>(total, start, s_scan[0]);
     const uint32_t *hs = hist + (int64_t)s * seg.hist_stride;
 #pragma unroll
-    for (int k = 0; k < DPT; ++k) hv[k] = (owns(k) && nt > 1) ? hs[d0 + k] : 0u;
+    for (int k = 0; k < DPT; ++k) hv[k] = (owns(k) && nt > 1 && !toff) ? hs[d0 + k] : 0u;
     digits_excl_scan<THREADS, DPT>(hv, hoff, s_scan[1]);
     if (owner) {
         // decoupled look-back, all of this thread's digits in flight together
         uint32_t excl[DPT];
 #pragma unroll
         for (int k = 0; k < DPT; ++k) excl[k] = 0;
-        if (nt > 1 && lt > 0) {
-            int64_t j[DPT];
-            bool done[DPT];
-#pragma unroll
-            for (int k = 0; k < DPT; ++k) { j[k] = (int64_t)tile - 1; done[k] = !owns(k); }
-            uint32_t spins = 0;
-            while (true) {
-                uint32_t sv[DPT];
-#pragma unroll
-                for (int k = 0; k < DPT; ++k)
-                    sv[k] = done[k] ? 0u
-                                    : __hip_atomic_load(status + j[k] * R + d0 + k, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-                bool all = true, waiting = false;
-#pragma unroll
-                for (int k = 0; k < DPT; ++k) {
-                    if (done[k]) continue;
-                    const uint32_t flag = sv[k] & ~kValueMask;
-                    if (flag == 0u) { waiting = true; all = false; continue; }
-                    excl[k] += sv[k] & kValueMask;
-                    if (flag == kFlagInclusive || j[k] == (int64_t)t0) done[k] = true;
-                    else { --j[k]; all = false; }
-                }
-                if (all) break;
-                if (waiting) {
-                    if (++spins > (1u << 24)) {   // never expected: bounded wait
-                        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < DPT; ++k)
-                if (owns(k))
-                    __hip_atomic_store(status + (int64_t)tile * R + d0 + k,
-                                       kFlagInclusive | (excl[k] + total[k]), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (nt > 1 && lt > 0 && !toff) look_back<DPT>(status, R, tile, t0, d0, total, excl, err);
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
             if (!owns(k)) continue;
             s_start[d0 + k] = start[k];
-            s_gbase[d0 + k] = nt > 1 ? hoff[k] + excl[k] : start[k];
+            s_gbase[d0 + k] = toff ? toff[(int64_t)tile * R + d0 + k] : (nt > 1 ? hoff[k] + excl[k] : start[k]);
         }
     }
     __syncthreads();

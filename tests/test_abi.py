@@ -107,6 +107,7 @@ def test_tune_knobs():
     """Every knob reads back, takes a value in range and refuses one out of
     range (no GPU needed: knobs are host state)."""
     ranges = {"sort_variant32": 8, "sort_variant64": 8, "batch_sort_variant": 3, "morton_order": 1,
+              "radix_mode": 1, "batch_sort_mode": 1,
               "query_split1": 24, "query_split2": 24, "query_leaf_mode": 1, "query_order": 1}
     for name, hi in ranges.items():
         old = lb.lbvh_tune(name)

@@ -163,7 +163,7 @@ def test_full_size_autotuned(name, ws):
     from paper_2402_00665_amd import autotune
     w = workloads.by_name(name)
     knobs = ("sort_variant32", "sort_variant64", "query_split1", "query_split2", "query_leaf_mode",
-             "query_order", "radix_bits32", "radix_bits64")
+             "query_order", "radix_bits32", "radix_bits64", "radix_mode")
     old = {k: lb.lbvh_tune(k) for k in knobs}
     try:
         p = torch.from_numpy(w.prims).cuda()
@@ -227,26 +227,30 @@ def test_piece_capacity_overflow_passes_through(ws):
 @pytest.mark.parametrize("variant", range(9))
 def test_sort_tile_variants(variant, ws):
     """Every radix-pass tile shape, with every digit width (8 or 10 bits for
-    30-bit codes, 8, 9 or 11 for 63-bit), gives the same tree (tolerance 0).
-    Sizes span one tile, several tiles with a ragged tail, and odd and even
-    pass counts."""
+    30-bit codes, 8, 9 or 11 for 63-bit), in both pass forms (onesweep, and
+    count + scatter), gives the same tree (tolerance 0).  Sizes span one
+    tile, several tiles (and chunks of tiles) with a ragged tail, and odd
+    and even pass counts."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng([18, variant])
     old = {k: lb.lbvh_tune(k) for k in ("sort_variant32", "sort_variant64", "radix_bits32",
-                                        "radix_bits64")}
+                                        "radix_bits64", "radix_mode")}
     lb.lbvh_tune("sort_variant32", variant)
     lb.lbvh_tune("sort_variant64", variant)
     try:
-        cases = [(100003, 30), (100003, 63), (4097, 30), (300, 63), (1 << 18, 30), (40000, 63)]
+        cases = [(100003, 30), (100003, 63), (4097, 30), (300, 63), (1 << 18, 30), (40000, 63),
+                 (1 << 20, 30)]
         pts = {n: rng.random((n, 3), dtype=np.float32) for n, _ in cases}
         refs = {(n, b): oracle.build(0, pts[n], b) for n, b in cases}
-        for b32, b64 in ((8, 8), (10, 9), (10, 11)):
-            lb.lbvh_tune("radix_bits32", b32)
-            lb.lbvh_tune("radix_bits64", b64)
-            for n, bits in cases:
-                say(f"  digits {b32 if bits == 30 else b64} bits")
-                tree, _ = gpu_build(pts[n], 0, bits, ws)
-                assert_tree_equal(tree, refs[(n, bits)])
+        for mode in (0, 1):
+            lb.lbvh_tune("radix_mode", mode)
+            for b32, b64 in ((8, 8), (10, 9), (10, 11)):
+                lb.lbvh_tune("radix_bits32", b32)
+                lb.lbvh_tune("radix_bits64", b64)
+                for n, bits in cases:
+                    say(f"  mode {mode}, digits {b32 if bits == 30 else b64} bits, n {n}")
+                    tree, _ = gpu_build(pts[n], 0, bits, ws)
+                    assert_tree_equal(tree, refs[(n, bits)])
     finally:
         for k, v in old.items():
             lb.lbvh_tune(k, v)
@@ -254,20 +258,22 @@ def test_sort_tile_variants(variant, ws):
 
 def test_sort_digit_widths_duplicates_and_clusters(ws):
     """Clustered boxes with heavy duplicate codes and all-equal codes sort
-    stably under every digit width."""
+    stably under every digit width, in both pass forms."""
     import paper_2402_00665_amd as lb
-    old = {k: lb.lbvh_tune(k) for k in ("radix_bits32", "radix_bits64")}
+    old = {k: lb.lbvh_tune(k) for k in ("radix_bits32", "radix_bits64", "radix_mode")}
     try:
         rng = workloads._rng(3, 0)
         boxes = workloads.clustered_boxes(150000, rng)
         same = np.repeat(rng.random((1, 3), dtype=np.float32), 9000, axis=0)
         refs = {(k, b): oracle.build(k, p, b) for k, p in ((1, boxes), (0, same)) for b in (30, 63)}
-        for b32, b64 in ((8, 8), (10, 9), (10, 11)):
-            lb.lbvh_tune("radix_bits32", b32)
-            lb.lbvh_tune("radix_bits64", b64)
-            for (k, b), ref in refs.items():
-                tree, _ = gpu_build(boxes if k == 1 else same, k, b, ws)
-                assert_tree_equal(tree, ref)
+        for mode in (0, 1):
+            lb.lbvh_tune("radix_mode", mode)
+            for b32, b64 in ((8, 8), (10, 9), (10, 11)):
+                lb.lbvh_tune("radix_bits32", b32)
+                lb.lbvh_tune("radix_bits64", b64)
+                for (k, b), ref in refs.items():
+                    tree, _ = gpu_build(boxes if k == 1 else same, k, b, ws)
+                    assert_tree_equal(tree, ref)
     finally:
         for k, v in old.items():
             lb.lbvh_tune(k, v)
