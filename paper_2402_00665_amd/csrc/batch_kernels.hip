@@ -245,6 +245,104 @@ __global__ __launch_bounds__(T) void k_scene_sort(
 
     const int d0 = tid * DPT;
     auto owns = [&](int k) { return d0 + k < R; };
+    // The tile ranking shared by both paths below: key k of this thread is
+    // the tile's key lofs + 64k (rem keys in the tile); returns each key's
+    // position in the tile's stable order by this pass's digit.
+    auto rank_tile = [&](const K (&key)[I], uint32_t rem, uint32_t lofs, int shift, int nbits,
+                         uint32_t (&pos)[I], uint32_t (&total)[DPT], uint32_t (&start)[DPT]) {
+        constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
+        for (int j = tid; j < kZeroWords; j += T) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
+        __syncthreads();
+        uint32_t rank[I];
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            const bool ok = lofs + k * 64 < rem;
+            const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
+            uint64_t diff = 0;
+#pragma unroll
+            for (int b = 0; b < BITS; ++b) {
+                if (b < nbits) {
+                    const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+                    diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
+                }
+            }
+            const uint64_t peers = __ballot(ok) & ~diff;
+            const uint32_t below = count_below(peers);
+            const uint32_t cnt = s_wcnt[wave][d];
+            rank[k] = cnt + below;
+            if (ok && below == 0) s_wcnt[wave][d] = (Cnt)(cnt + (uint32_t)__popcll(peers));
+        }
+        __syncthreads();
+        // per-wave exclusive offsets and the tile's digit totals
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            total[k] = 0;
+            if (owns(k)) {
+                const int d = d0 + k;
+                uint32_t c[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
+#pragma unroll
+                for (int w = 0; w < W; ++w) { s_wcnt[w][d] = (Cnt)total[k]; total[k] += c[w]; }
+            }
+        }
+        digits_excl_scan<T, DPT>(total, start, s_scan[1]);
+#pragma unroll
+        for (int k = 0; k < DPT; ++k)
+            if (owns(k)) s_start[d0 + k] = start[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
+            pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
+        }
+    };
+    if (ns <= (uint32_t)TILE) {
+        // the scene is one tile: its keys and values stay on chip through
+        // all passes (each pass reorders them through LDS), and only the
+        // last pass writes the sorted codes and the permutation
+        const uint32_t lofs = (uint32_t)(wave * 64 * I + lane);
+        K key[I];
+        int32_t val[I];
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            const bool ok = lofs + k * 64 < ns;
+            key[k] = ok ? key_a[b0 + lofs + k * 64] : (K)0;
+            val[k] = (int32_t)(lofs + k * 64);
+        }
+        int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
+        K *kfinal = ((PASSES - 1) & 1) ? key_a : key_b;
+        for (int p = 0; p < PASSES; ++p) {
+            const int shift = p * BITS;
+            const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
+            uint32_t pos[I], total[DPT], start[DPT];
+            rank_tile(key, ns, lofs, shift, nbits, pos, total, start);
+            if (p + 1 == PASSES) {
+#pragma unroll
+                for (int k = 0; k < I; ++k)
+                    if (lofs + k * 64 < ns) {
+                        kfinal[b0 + pos[k]] = key[k];
+                        perm_out[b0 + pos[k]] = val[k];
+                    }
+                break;
+            }
+#pragma unroll
+            for (int k = 0; k < I; ++k)
+                if (lofs + k * 64 < ns) s_buf[pos[k]] = key[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < I; ++k) key[k] = lofs + k * 64 < ns ? s_buf[lofs + k * 64] : (K)0;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < I; ++k)
+                if (lofs + k * 64 < ns) s_vals[pos[k]] = val[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < I; ++k) val[k] = lofs + k * 64 < ns ? s_vals[lofs + k * 64] : 0;
+            __syncthreads();
+        }
+        return;
+    }
     for (int p = 0; p < PASSES; ++p) {
         const K *kin = (p & 1) ? key_b : key_a;
         K *kout = (p & 1) ? key_a : key_b;
@@ -262,9 +360,6 @@ __global__ __launch_bounds__(T) void k_scene_sort(
                 if (owns(k)) s_run[d0 + k] = st[k];
         }
         for (uint32_t base = 0; base < ns; base += TILE) {
-            constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
-            for (int j = tid; j < kZeroWords; j += T) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
-            __syncthreads();
             const uint32_t rem = ns - base < (uint32_t)TILE ? ns - base : (uint32_t)TILE;
             const uint32_t lofs = (uint32_t)(wave * 64 * I + lane);
             K key[I];
@@ -277,51 +372,8 @@ __global__ __launch_bounds__(T) void k_scene_sort(
                 val[k] = vin ? (ok ? vin[at] : 0) : (int32_t)(base + lofs + k * 64);
             }
             // stable rank within the wave, as in the onesweep pass
-            uint32_t rank[I];
-#pragma unroll
-            for (int k = 0; k < I; ++k) {
-                const bool ok = lofs + k * 64 < rem;
-                const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
-                uint64_t diff = 0;
-#pragma unroll
-                for (int b = 0; b < BITS; ++b) {
-                    if (b < nbits) {
-                        const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-                        diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
-                    }
-                }
-                const uint64_t peers = __ballot(ok) & ~diff;
-                const uint32_t below = count_below(peers);
-                const uint32_t cnt = s_wcnt[wave][d];
-                rank[k] = cnt + below;
-                if (ok && below == 0) s_wcnt[wave][d] = (Cnt)(cnt + (uint32_t)__popcll(peers));
-            }
-            __syncthreads();
-            // per-wave exclusive offsets and the tile's digit totals
-            uint32_t total[DPT], start[DPT];
-#pragma unroll
-            for (int k = 0; k < DPT; ++k) {
-                total[k] = 0;
-                if (owns(k)) {
-                    const int d = d0 + k;
-                    uint32_t c[W];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) c[w] = s_wcnt[w][d];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) { s_wcnt[w][d] = (Cnt)total[k]; total[k] += c[w]; }
-                }
-            }
-            digits_excl_scan<T, DPT>(total, start, s_scan[1]);
-#pragma unroll
-            for (int k = 0; k < DPT; ++k)
-                if (owns(k)) s_start[d0 + k] = start[k];
-            __syncthreads();
-            uint32_t pos[I];
-#pragma unroll
-            for (int k = 0; k < I; ++k) {
-                const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
-                pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
-            }
+            uint32_t pos[I], total[DPT], start[DPT];
+            rank_tile(key, rem, lofs, shift, nbits, pos, total, start);
 #pragma unroll
             for (int k = 0; k < I; ++k)
                 if (lofs + k * 64 < rem) s_buf[pos[k]] = key[k];

@@ -22,8 +22,8 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
     defaults = {k: lb.lbvh_tune(k) for k in autotune.KNOB_CANDIDATES}
     r = autotune.tune(p, 63, reps=3, verbose=True)
     say(f"single: {r}")
-    assert set(r["knobs"]) == {"radix_bits64", "sort_variant64"}
-    assert set(r["times_ms"]) == {f"{b}/{v}" for b in (8, 9, 11) for v in range(9)}
+    assert set(r["knobs"]) == {"radix_bits64", "sort_variant64", "radix_mode"}
+    assert set(r["times_ms"]) == {f"{b}/{v}/{m}" for b in (8, 9, 11) for v in range(9) for m in (0, 1)}
     assert {k: lb.lbvh_tune(k) for k in defaults} == defaults   # tuning restores the defaults
     sizes = np.array([3000, 70000, 1, 0, 40000], np.int64)
     seg = np.zeros(len(sizes) + 1, np.int64)
@@ -39,6 +39,7 @@ def test_tune_single_and_batched(tmp_path, monkeypatch):
         assert autotune.apply(1 << 18, 63, 0) == r["knobs"]
         assert lb.lbvh_tune("sort_variant64") == r["knobs"]["sort_variant64"]
         assert lb.lbvh_tune("radix_bits64") == r["knobs"]["radix_bits64"]
+        assert lb.lbvh_tune("radix_mode") == r["knobs"]["radix_mode"]
         assert autotune.apply(int(seg[-1]), 30, 0, batched=True) == rb["knobs"]
         assert autotune.apply(1 << 10, 63, 0) == {}   # other size bucket: nothing cached
     finally:
