@@ -213,6 +213,14 @@ def main():
     import workloads
 
     torch.cuda.set_device(0)
+    # the library's knob values before any leg tunes them: each later leg
+    # starts from these (the batched leg tunes its own; serving runs on them)
+    knob_defaults = {k: lb.lbvh_tune(k) for k in KNOBS}
+
+    def reset_knobs():
+        for k, v in knob_defaults.items():
+            lb.lbvh_tune(k, v)
+
     if args.batched_only:
         for kv in filter(None, args.knobs.split(",")):
             k, v = kv.split("=")
@@ -434,8 +442,13 @@ def main():
     if not args.no_rays and w.name == "clustered_boxes" and not args.build_only:
         rays = bench_rays(args, w, tree)
 
+    tuned_here = {k: lb.lbvh_tune(k) for k in KNOBS}
+    reset_knobs()
     batched = None if args.no_batched else bench_batched(args)
+    reset_knobs()
     serving = None if args.no_serving else bench_serving(args)
+    for k, v in tuned_here.items():   # the single-tree workload's knobs again, for what follows
+        lb.lbvh_tune(k, v)
 
     out = {
         "metric": "rope-LBVH build Mprims/s + stackless Mqueries/s",
@@ -672,7 +685,9 @@ def bench_serving(args):
     batch's stream, into a client-owned device buffer (one per run,
     allocated before the runs, request k at the same place in both), after
     which the server drops it.  After the two runs the two buffers are
-    compared whole, so every request's answer is checked."""
+    compared whole, so every request's answer is checked.  Both servers run
+    with the library's default knobs (not the single-tree workload's tuned
+    ones)."""
     import torch
     import workloads
     from paper_2402_00665_amd import serve
@@ -774,6 +789,10 @@ def bench_serving(args):
 
 
 # --------------------------------------------------------------- profiles
+
+KNOBS = ("sort_variant32", "sort_variant64", "batch_sort_variant", "query_split1", "query_split2",
+         "query_leaf_mode", "query_order", "radix_bits32", "radix_bits64", "morton_order",
+         "batch_sort_mode", "radix_mode")
 
 KERNEL_GROUPS = {  # rocprofv3 kernel-name fragment -> bench kernel name (first match wins)
     "k_onesweep<unsigned int, 512, 4>": "query_order", "k_qorder": "query_order",
