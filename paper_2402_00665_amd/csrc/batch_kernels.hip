@@ -165,13 +165,16 @@ __global__ __launch_bounds__(kSceneThreads) void k_batch_morton(
 // block takes one whole scene (scenes in decreasing size, so the longest
 // blocks start first) and runs every step up to the sorted codes itself:
 // scene box and scale, the codes with every pass's digit histogram, then
-// each LSD pass over the scene in tiles of T*I keys.  A tile is ranked
-// stably with wave64 ballots (as in the onesweep pass) and scattered
-// through LDS so that global writes are runs of equal digits; the block's
-// running start of each digit carries over from tile to tile, so no tile
-// waits for another block (no look-back), and scenes need no tile plan.
-// Global writes of one pass are read by the next pass of the same block
-// after a workgroup barrier.
+// the sort.  A scene of one tile (T*I keys) is sorted on chip.  A larger
+// scene is partitioned by its top digit in one pass over global memory and
+// its runs of whole digit values, packed up to a tile, are sorted on chip;
+// if one top-digit value holds more than a tile, each LSD pass runs over
+// the scene in tiles instead.  A tile is ranked stably with wave64 ballots
+// (as in the onesweep pass) and scattered through LDS so that global
+// writes are runs of equal digits; the block's running start of each digit
+// carries over from tile to tile, so no tile waits for another block (no
+// look-back), and scenes need no tile plan.  Global writes of one pass are
+// read by the next step of the same block after a workgroup barrier.
 template <int KIND, typename K, int BITS, int T, int I>
 __global__ __launch_bounds__(T) void k_scene_sort(
     const float *__restrict__ prims, const int64_t *__restrict__ seg_off,
@@ -194,6 +197,8 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     __shared__ K s_buf[TILE];
     __shared__ float sh[W * 6];
     __shared__ float4 s_box[3];
+    __shared__ uint32_t s_flag;       // some top digit holds more than a tile
+    __shared__ uint32_t s_last[2];    // last digit of the current run group
 
     const int s = order[blockIdx.x];
     const int64_t b0 = seg_off[s];
@@ -202,6 +207,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     const uint32_t ns = (uint32_t)ns64;   // a scene holds fewer than 2^30 primitives
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int j = tid; j < PASSES * R; j += T) s_hist[j] = 0u;
+    if (tid == 0) { s_flag = 0u; s_last[0] = 0u; }
 
     // scene box and scale (2^b / extent, correctly rounded; 0 when flat)
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -227,17 +233,19 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         scene_box[3 * s + 2] = s_box[2];
     }
     __syncthreads();
-    // codes in input order, and every pass's digit counts
+    // codes in input order, and (scenes of several tiles) the top digit's
+    // counts; the other digits are counted only if the scene needs them
+    const int top = PASSES - 1;
+    const int top_shift = top * BITS;
     {
         const float4 slo = s_box[0], sc = s_box[2];
+        const bool count = ns > (uint32_t)TILE;
         for (uint32_t i = tid; i < ns; i += T) {
             float lo[3], hi[3];
             P::one(prims, b0 + i, lo, hi);
             const K c = code_of<KIND, K>(lo, hi, slo, sc);
             key_a[b0 + i] = c;
-#pragma unroll
-            for (int p = 0; p < PASSES; ++p)
-                atomicAdd(&s_hist[p * R + (uint32_t)((c >> (p * BITS)) & (R - 1))], 1u);
+            if (count) atomicAdd(&s_hist[top * R + (uint32_t)((c >> top_shift) & (R - 1))], 1u);
         }
     }
     __threadfence_block();
@@ -297,63 +305,63 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
         }
     };
-    if (ns <= (uint32_t)TILE) {
-        // the scene is one tile: its keys and values stay on chip through
-        // all passes (each pass reorders them through LDS), and only the
-        // last pass writes the sorted codes and the permutation
-        const uint32_t lofs = (uint32_t)(wave * 64 * I + lane);
+    const uint32_t lofs = (uint32_t)(wave * 64 * I + lane);
+    K *const kfinal = ((PASSES - 1) & 1) ? key_a : key_b;
+    // Keys [off, off + cnt) of kin (cnt <= TILE) sorted on chip: each pass
+    // reorders them through LDS and only the last pass writes, the sorted
+    // codes to kfinal and the permutation to perm_out at the same places.
+    // Values are vin's, or the scene-local index when vin is null.  kin may
+    // be kfinal: every key is in registers before the first barrier.
+    auto sort_on_chip = [&](const K *kin, const int32_t *vin, uint32_t off, uint32_t cnt) {
         K key[I];
         int32_t val[I];
 #pragma unroll
         for (int k = 0; k < I; ++k) {
-            const bool ok = lofs + k * 64 < ns;
-            key[k] = ok ? key_a[b0 + lofs + k * 64] : (K)0;
-            val[k] = (int32_t)(lofs + k * 64);
+            const bool ok = lofs + k * 64 < cnt;
+            const int64_t at = b0 + off + lofs + k * 64;
+            key[k] = ok ? kin[at] : (K)0;
+            val[k] = vin ? (ok ? vin[at] : 0) : (int32_t)(off + lofs + k * 64);
         }
         int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
-        K *kfinal = ((PASSES - 1) & 1) ? key_a : key_b;
         for (int p = 0; p < PASSES; ++p) {
             const int shift = p * BITS;
             const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
             uint32_t pos[I], total[DPT], start[DPT];
-            rank_tile(key, ns, lofs, shift, nbits, pos, total, start);
+            rank_tile(key, cnt, lofs, shift, nbits, pos, total, start);
             if (p + 1 == PASSES) {
 #pragma unroll
                 for (int k = 0; k < I; ++k)
-                    if (lofs + k * 64 < ns) {
-                        kfinal[b0 + pos[k]] = key[k];
-                        perm_out[b0 + pos[k]] = val[k];
+                    if (lofs + k * 64 < cnt) {
+                        kfinal[b0 + off + pos[k]] = key[k];
+                        perm_out[b0 + off + pos[k]] = val[k];
                     }
                 break;
             }
 #pragma unroll
             for (int k = 0; k < I; ++k)
-                if (lofs + k * 64 < ns) s_buf[pos[k]] = key[k];
+                if (lofs + k * 64 < cnt) s_buf[pos[k]] = key[k];
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < I; ++k) key[k] = lofs + k * 64 < ns ? s_buf[lofs + k * 64] : (K)0;
+            for (int k = 0; k < I; ++k) key[k] = lofs + k * 64 < cnt ? s_buf[lofs + k * 64] : (K)0;
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < I; ++k)
-                if (lofs + k * 64 < ns) s_vals[pos[k]] = val[k];
+                if (lofs + k * 64 < cnt) s_vals[pos[k]] = val[k];
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < I; ++k) val[k] = lofs + k * 64 < ns ? s_vals[lofs + k * 64] : 0;
+            for (int k = 0; k < I; ++k) val[k] = lofs + k * 64 < cnt ? s_vals[lofs + k * 64] : 0;
             __syncthreads();
         }
-        return;
-    }
-    for (int p = 0; p < PASSES; ++p) {
-        const K *kin = (p & 1) ? key_b : key_a;
-        K *kout = (p & 1) ? key_a : key_b;
-        const int32_t *vin = p == 0 ? nullptr : ((p & 1) ? val_a : val_b);
-        int32_t *vout = p + 1 == PASSES ? perm_out : ((p & 1) ? val_b : val_a);
-        const int shift = p * BITS;
-        const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
+    };
+    // One stable pass over the whole scene by digit `shift .. shift+nbits`
+    // (histogram row hp), tile after tile through global memory.  Afterwards
+    // s_run[d] is the scene-local end of digit d's run.
+    auto global_pass = [&](const K *kin, K *kout, const int32_t *vin, int32_t *vout, int hp, int shift,
+                           int nbits) {
         {   // the scene-local start of each digit in this pass
             uint32_t h[DPT], st[DPT];
 #pragma unroll
-            for (int k = 0; k < DPT; ++k) h[k] = owns(k) ? s_hist[p * R + d0 + k] : 0u;
+            for (int k = 0; k < DPT; ++k) h[k] = owns(k) ? s_hist[hp * R + d0 + k] : 0u;
             digits_excl_scan<T, DPT>(h, st, s_scan[0]);
 #pragma unroll
             for (int k = 0; k < DPT; ++k)
@@ -361,7 +369,6 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         }
         for (uint32_t base = 0; base < ns; base += TILE) {
             const uint32_t rem = ns - base < (uint32_t)TILE ? ns - base : (uint32_t)TILE;
-            const uint32_t lofs = (uint32_t)(wave * 64 * I + lane);
             K key[I];
             int32_t val[I];
 #pragma unroll
@@ -410,9 +417,69 @@ __global__ __launch_bounds__(T) void k_scene_sort(
                 if (owns(k)) s_run[d0 + k] += total[k];
             __syncthreads();
         }
-        // this pass's writes are the next pass's reads (same block)
+        // this pass's writes are the next reads (same block)
         __threadfence_block();
         __syncthreads();
+    };
+
+    if (ns <= (uint32_t)TILE) {   // one tile: all passes on chip
+        sort_on_chip(key_a, nullptr, 0u, ns);
+        return;
+    }
+    // Several tiles.  When no value of the top digit holds more than a
+    // tile's keys, one global pass partitions the scene by the top digit
+    // (most significant first), and runs of whole digit values, packed up to
+    // a tile, are then sorted on chip by the whole code: the final order of
+    // each run's keys lies inside the run, and both steps are stable, so
+    // equal codes keep their input order.  Two global passes instead of one
+    // per digit.  Otherwise every pass runs over the scene (least
+    // significant digit first).
+    const int top_bits = BITS < code_bits - top_shift ? BITS : code_bits - top_shift;
+#pragma unroll
+    for (int k = 0; k < DPT; ++k)
+        if (owns(k) && s_hist[top * R + d0 + k] > (uint32_t)TILE) s_flag = 1u;
+    __syncthreads();
+    if (s_flag == 0u && top_bits > 0) {
+        global_pass(key_a, key_b, nullptr, val_a, top, top_shift, top_bits);
+        // digit d's keys now lie in [end(d-1), end(d)) of key_b / val_a,
+        // with end(d) = s_run[d]; group g takes digits gb..last, the most
+        // that fit a tile (slot g & 1 of s_last holds gb before the max)
+        uint32_t gb = 0;
+        for (int g = 0;; ++g) {
+            const uint32_t gstart = gb == 0 ? 0u : s_run[gb - 1];
+            if (gb >= (uint32_t)R || gstart >= ns) break;
+#pragma unroll
+            for (int k = 0; k < DPT; ++k) {
+                const uint32_t d = (uint32_t)(d0 + k);
+                if (owns(k) && d >= gb && s_run[d] - gstart <= (uint32_t)TILE) atomicMax(&s_last[g & 1], d);
+            }
+            __syncthreads();
+            const uint32_t last = s_last[g & 1];
+            const uint32_t gend = s_run[last];
+            if (tid == 0) s_last[(g + 1) & 1] = last + 1;
+            if (gend <= gstart || gend > ns || gend - gstart > (uint32_t)TILE) {   // not expected
+                if (tid == 0) __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            sort_on_chip(key_b, val_a, gstart, gend - gstart);
+            gb = last + 1;
+        }
+        return;
+    }
+    for (uint32_t i = tid; i < ns; i += T) {   // the lower digits' counts
+        const K c = key_a[b0 + i];
+#pragma unroll
+        for (int p = 0; p < top; ++p) atomicAdd(&s_hist[p * R + (uint32_t)((c >> (p * BITS)) & (R - 1))], 1u);
+    }
+    __syncthreads();
+    for (int p = 0; p < PASSES; ++p) {
+        const K *kin = (p & 1) ? key_b : key_a;
+        K *kout = (p & 1) ? key_a : key_b;
+        const int32_t *vin = p == 0 ? nullptr : ((p & 1) ? val_a : val_b);
+        int32_t *vout = p + 1 == PASSES ? perm_out : ((p & 1) ? val_b : val_a);
+        const int shift = p * BITS;
+        const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
+        global_pass(kin, kout, vin, vout, p, shift, nbits);
     }
 }
 

@@ -258,8 +258,11 @@ def test_batched_workload_full_size(sort_mode):
 def test_scene_sort_widths_and_sizes(bits, shape):
     """The one-block-per-scene sort with every block shape and digit
     width: empty and one-point scenes, scenes around the 4096- and
-    8192-key tiles, a scene above 65536 points, duplicate codes; every
-    tree equals the oracle's."""
+    8192-key tiles, a 65536-point scene, scenes whose top digit value
+    holds exactly 4096 keys and 4097 keys (runs of whole digit values on
+    chip, and the pass-per-digit form), duplicate codes; every tree equals
+    the oracle's.  A batch with a scene above 65536 points, asked for in
+    this mode, is built by the segmented passes and is checked too."""
     import paper_2402_00665_amd as lb
     old = {k: lb.lbvh_tune(k) for k in ("batch_sort_mode", "batch_sort_variant", "radix_bits32",
                                         "radix_bits64")}
@@ -267,19 +270,32 @@ def test_scene_sort_widths_and_sizes(bits, shape):
     lb.lbvh_tune("batch_sort_variant", shape)
     try:
         rng = np.random.default_rng([29, bits])
-        sizes = np.array([4097, 1, 4096, 0, 100003, 6000, 4095, 16384, 8193, 2, 0, 3, 8191, 8192],
-                         np.int64)
+        sizes = np.array([4097, 1, 4096, 0, 65536, 6000, 4095, 16384, 8193, 2, 0, 3, 8191, 8192,
+                          28000, 28001], np.int64)
         seg = np.zeros(len(sizes) + 1, np.int64)
         np.cumsum(sizes, out=seg[1:])
         pts = rng.random((int(seg[-1]), 3), dtype=np.float32)
         pts[seg[5]:seg[6]] = pts[seg[5]]                     # one scene of equal points
         pts[seg[7]:seg[8]:3] = pts[seg[7]]                    # duplicates in another
+        for j, zeros in ((14, 4096), (15, 4097)):
+            # the origin's top digit value holds exactly `zeros` keys: the
+            # other points lie in [0.3, 1]^3, away from every axis' first
+            # quarter, and one at (1, 1, 1) fixes the scene box
+            a, e = int(seg[j]), int(seg[j + 1])
+            pts[a:e] = (np.float32(0.3) + np.float32(0.7) * pts[a:e]).astype(np.float32)
+            pts[a:a + zeros] = 0.0
+            pts[e - 1] = 1.0
         for width in ((8, 10) if bits == 30 else (8, 9, 11)):
             lb.lbvh_tune("radix_bits32" if bits == 30 else "radix_bits64", width)
             say(f"  per-scene sort, {width}-bit digits, {bits}-bit codes")
             batched_parity(pts, seg, bits, 0)
             boxes = np.concatenate([pts, pts + 1e-3], 1).astype(np.float32)
             batched_parity(boxes, seg, bits, 1)
+        if shape == 0:
+            big = np.concatenate([pts[:20000], rng.random((70000, 3), dtype=np.float32)])
+            bseg = np.array([0, 20000, 90000], np.int64)
+            say("  per-scene sort asked for with a 70000-point scene")
+            batched_parity(big, bseg, bits, 0)
     finally:
         for k, v in old.items():
             lb.lbvh_tune(k, v)
