@@ -191,10 +191,11 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     using P = Prims<KIND>;
     __shared__ __align__(16) Cnt s_wcnt[W][R];
     __shared__ uint32_t s_start[R];   // tile-local start of each digit run
-    __shared__ uint32_t s_run[R];     // scene-local start of the digit's next run
-    __shared__ uint32_t s_hist[PASSES * R];
+    __shared__ uint32_t s_run[2][R];  // scene-local start of the digit's next run
+    __shared__ uint32_t s_hist[R];    // one digit's counts over the scene
     __shared__ uint32_t s_scan[2][W];
     __shared__ K s_buf[TILE];
+    __shared__ int32_t s_val[TILE];
     __shared__ float sh[W * 6];
     __shared__ float4 s_box[3];
     __shared__ uint32_t s_flag;       // some top digit holds more than a tile
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     if (ns64 == 0) return;
     const uint32_t ns = (uint32_t)ns64;   // a scene holds fewer than 2^30 primitives
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int j = tid; j < PASSES * R; j += T) s_hist[j] = 0u;
+    for (int j = tid; j < R; j += T) s_hist[j] = 0u;
     if (tid == 0) { s_flag = 0u; s_last[0] = 0u; }
 
     // scene box and scale (2^b / extent, correctly rounded; 0 when flat)
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             P::one(prims, b0 + i, lo, hi);
             const K c = code_of<KIND, K>(lo, hi, slo, sc);
             key_a[b0 + i] = c;
-            if (count) atomicAdd(&s_hist[top * R + (uint32_t)((c >> top_shift) & (R - 1))], 1u);
+            if (count) atomicAdd(&s_hist[(uint32_t)((c >> top_shift) & (R - 1))], 1u);
         }
     }
     __threadfence_block();
@@ -253,14 +254,17 @@ __global__ __launch_bounds__(T) void k_scene_sort(
 
     const int d0 = tid * DPT;
     auto owns = [&](int k) { return d0 + k < R; };
+    constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
+    auto zero_counts = [&]() {
+        for (int j = tid; j < kZeroWords; j += T) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
+    };
     // The tile ranking shared by both paths below: key k of this thread is
     // the tile's key lofs + 64k (rem keys in the tile); returns each key's
-    // position in the tile's stable order by this pass's digit.
+    // position in the tile's stable order by this pass's digit.  The wave
+    // counters must be zero on entry (each caller clears them, after its
+    // last read of the previous ranking and before a barrier).
     auto rank_tile = [&](const K (&key)[I], uint32_t rem, uint32_t lofs, int shift, int nbits,
                          uint32_t (&pos)[I], uint32_t (&total)[DPT], uint32_t (&start)[DPT]) {
-        constexpr int kZeroWords = W * R * (int)sizeof(Cnt) / 4;
-        for (int j = tid; j < kZeroWords; j += T) reinterpret_cast<uint32_t *>(&s_wcnt[0][0])[j] = 0u;
-        __syncthreads();
         uint32_t rank[I];
 #pragma unroll
         for (int k = 0; k < I; ++k) {
@@ -311,10 +315,12 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     // reorders them through LDS and only the last pass writes, the sorted
     // codes to kfinal and the permutation to perm_out at the same places.
     // Values are vin's, or the scene-local index when vin is null.  kin may
-    // be kfinal: every key is in registers before the first barrier.
+    // be kfinal: every key is in registers before the first barrier.  The
+    // caller's last barrier must follow its last read of the wave counters.
     auto sort_on_chip = [&](const K *kin, const int32_t *vin, uint32_t off, uint32_t cnt) {
         K key[I];
         int32_t val[I];
+        zero_counts();
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             const bool ok = lofs + k * 64 < cnt;
@@ -322,7 +328,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             key[k] = ok ? kin[at] : (K)0;
             val[k] = vin ? (ok ? vin[at] : 0) : (int32_t)(off + lofs + k * 64);
         }
-        int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
+        __syncthreads();
         for (int p = 0; p < PASSES; ++p) {
             const int shift = p * BITS;
             const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
@@ -339,35 +345,41 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             }
 #pragma unroll
             for (int k = 0; k < I; ++k)
-                if (lofs + k * 64 < cnt) s_buf[pos[k]] = key[k];
+                if (lofs + k * 64 < cnt) {
+                    s_buf[pos[k]] = key[k];
+                    s_val[pos[k]] = val[k];
+                }
             __syncthreads();
+            zero_counts();   // every position is read
 #pragma unroll
-            for (int k = 0; k < I; ++k) key[k] = lofs + k * 64 < cnt ? s_buf[lofs + k * 64] : (K)0;
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < I; ++k)
-                if (lofs + k * 64 < cnt) s_vals[pos[k]] = val[k];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < I; ++k) val[k] = lofs + k * 64 < cnt ? s_vals[lofs + k * 64] : 0;
+            for (int k = 0; k < I; ++k) {
+                const bool ok = lofs + k * 64 < cnt;
+                key[k] = ok ? s_buf[lofs + k * 64] : (K)0;
+                val[k] = ok ? s_val[lofs + k * 64] : 0;
+            }
             __syncthreads();
         }
     };
     // One stable pass over the whole scene by digit `shift .. shift+nbits`
-    // (histogram row hp), tile after tile through global memory.  Afterwards
-    // s_run[d] is the scene-local end of digit d's run.
-    auto global_pass = [&](const K *kin, K *kout, const int32_t *vin, int32_t *vout, int hp, int shift,
-                           int nbits) {
+    // (its counts in s_hist), tile after tile through global memory.  The
+    // running start of each digit alternates between the two rows of s_run
+    // (tile t reads row t & 1 and its owner writes the next row), so no
+    // barrier guards it; returns the row that ends up holding the
+    // scene-local end of each digit's run.
+    auto global_pass = [&](const K *kin, K *kout, const int32_t *vin, int32_t *vout, int shift,
+                           int nbits) -> int {
+        zero_counts();
         {   // the scene-local start of each digit in this pass
             uint32_t h[DPT], st[DPT];
 #pragma unroll
-            for (int k = 0; k < DPT; ++k) h[k] = owns(k) ? s_hist[hp * R + d0 + k] : 0u;
+            for (int k = 0; k < DPT; ++k) h[k] = owns(k) ? s_hist[d0 + k] : 0u;
             digits_excl_scan<T, DPT>(h, st, s_scan[0]);
 #pragma unroll
             for (int k = 0; k < DPT; ++k)
-                if (owns(k)) s_run[d0 + k] = st[k];
+                if (owns(k)) s_run[0][d0 + k] = st[k];
         }
-        for (uint32_t base = 0; base < ns; base += TILE) {
+        int row = 0;
+        for (uint32_t base = 0; base < ns; base += TILE, row ^= 1) {
             const uint32_t rem = ns - base < (uint32_t)TILE ? ns - base : (uint32_t)TILE;
             K key[I];
             int32_t val[I];
@@ -381,45 +393,39 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             // stable rank within the wave, as in the onesweep pass
             uint32_t pos[I], total[DPT], start[DPT];
             rank_tile(key, rem, lofs, shift, nbits, pos, total, start);
+            // the next tile's runs of each digit follow this tile's
+#pragma unroll
+            for (int k = 0; k < DPT; ++k)
+                if (owns(k)) s_run[row ^ 1][d0 + k] = s_run[row][d0 + k] + total[k];
 #pragma unroll
             for (int k = 0; k < I; ++k)
-                if (lofs + k * 64 < rem) s_buf[pos[k]] = key[k];
+                if (lofs + k * 64 < rem) {
+                    s_buf[pos[k]] = key[k];
+                    s_val[pos[k]] = val[k];
+                }
             __syncthreads();
-            uint32_t dst[I];
+            zero_counts();
 #pragma unroll
             for (int k = 0; k < I; ++k) {
                 const uint32_t q = (uint32_t)(k * T + tid);
-                dst[k] = ~0u;
                 if (q < rem) {
                     const K kk = s_buf[q];
                     const uint32_t dk = (uint32_t)(kk >> shift) & (R - 1);
-                    const uint32_t out = s_run[dk] + q - s_start[dk];   // < ns by construction
+                    const uint32_t out = s_run[row][dk] + q - s_start[dk];   // < ns by construction
                     if (out < ns) {
                         kout[b0 + out] = kk;
-                        dst[k] = out;
+                        vout[b0 + out] = s_val[q];
                     } else {   // inconsistent counts: flag it rather than write outside
                         __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }
             __syncthreads();
-            int32_t *s_vals = reinterpret_cast<int32_t *>(s_buf);
-#pragma unroll
-            for (int k = 0; k < I; ++k)
-                if (lofs + k * 64 < rem) s_vals[pos[k]] = val[k];
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < I; ++k)
-                if (dst[k] != ~0u) vout[b0 + dst[k]] = s_vals[k * T + tid];
-            // the next tile's runs of each digit follow this tile's
-#pragma unroll
-            for (int k = 0; k < DPT; ++k)
-                if (owns(k)) s_run[d0 + k] += total[k];
-            __syncthreads();
         }
         // this pass's writes are the next reads (same block)
         __threadfence_block();
         __syncthreads();
+        return row;
     };
 
     if (ns <= (uint32_t)TILE) {   // one tile: all passes on chip
@@ -437,25 +443,25 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     const int top_bits = BITS < code_bits - top_shift ? BITS : code_bits - top_shift;
 #pragma unroll
     for (int k = 0; k < DPT; ++k)
-        if (owns(k) && s_hist[top * R + d0 + k] > (uint32_t)TILE) s_flag = 1u;
+        if (owns(k) && s_hist[d0 + k] > (uint32_t)TILE) s_flag = 1u;
     __syncthreads();
     if (s_flag == 0u && top_bits > 0) {
-        global_pass(key_a, key_b, nullptr, val_a, top, top_shift, top_bits);
-        // digit d's keys now lie in [end(d-1), end(d)) of key_b / val_a,
-        // with end(d) = s_run[d]; group g takes digits gb..last, the most
-        // that fit a tile (slot g & 1 of s_last holds gb before the max)
+        const uint32_t *end = s_run[global_pass(key_a, key_b, nullptr, val_a, top_shift, top_bits)];
+        // digit d's keys now lie in [end[d-1], end[d]) of key_b / val_a;
+        // group g takes digits gb..last, the most that fit a tile (slot
+        // g & 1 of s_last holds gb before the max)
         uint32_t gb = 0;
         for (int g = 0;; ++g) {
-            const uint32_t gstart = gb == 0 ? 0u : s_run[gb - 1];
+            const uint32_t gstart = gb == 0 ? 0u : end[gb - 1];
             if (gb >= (uint32_t)R || gstart >= ns) break;
 #pragma unroll
             for (int k = 0; k < DPT; ++k) {
                 const uint32_t d = (uint32_t)(d0 + k);
-                if (owns(k) && d >= gb && s_run[d] - gstart <= (uint32_t)TILE) atomicMax(&s_last[g & 1], d);
+                if (owns(k) && d >= gb && end[d] - gstart <= (uint32_t)TILE) atomicMax(&s_last[g & 1], d);
             }
             __syncthreads();
             const uint32_t last = s_last[g & 1];
-            const uint32_t gend = s_run[last];
+            const uint32_t gend = end[last];
             if (tid == 0) s_last[(g + 1) & 1] = last + 1;
             if (gend <= gstart || gend > ns || gend - gstart > (uint32_t)TILE) {   // not expected
                 if (tid == 0) __hip_atomic_store(err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -466,12 +472,6 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         }
         return;
     }
-    for (uint32_t i = tid; i < ns; i += T) {   // the lower digits' counts
-        const K c = key_a[b0 + i];
-#pragma unroll
-        for (int p = 0; p < top; ++p) atomicAdd(&s_hist[p * R + (uint32_t)((c >> (p * BITS)) & (R - 1))], 1u);
-    }
-    __syncthreads();
     for (int p = 0; p < PASSES; ++p) {
         const K *kin = (p & 1) ? key_b : key_a;
         K *kout = (p & 1) ? key_a : key_b;
@@ -479,7 +479,14 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         int32_t *vout = p + 1 == PASSES ? perm_out : ((p & 1) ? val_b : val_a);
         const int shift = p * BITS;
         const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
-        global_pass(kin, kout, vin, vout, p, shift, nbits);
+        // this digit's counts (the previous pass read s_hist before its
+        // last barrier)
+        for (int j = tid; j < R; j += T) s_hist[j] = 0u;
+        __syncthreads();
+        for (uint32_t i = tid; i < ns; i += T)
+            atomicAdd(&s_hist[(uint32_t)((kin[b0 + i] >> shift) & (R - 1))], 1u);
+        __syncthreads();
+        global_pass(kin, kout, vin, vout, shift, nbits);
     }
 }
 
@@ -686,10 +693,11 @@ void run_batch_sort(const float *prims, const int64_t *seg_off, int S, int64_t N
 // per thread, the knob "batch_sort_variant" in this mode): wider blocks take
 // a large scene in fewer tiles per pass; a shape whose tables and tile do
 // not fit the LDS runs as 256 x 16.
-constexpr size_t scene_sort_lds(int key_bytes, int threads, int items, int bits, int passes)
+constexpr size_t scene_sort_lds(int key_bytes, int threads, int items, int bits)
 {
-    return (size_t)(threads / 64) * ((bits <= 9 ? 4u : 2u) << bits) + (8u << bits) +
-           ((size_t)passes << bits) * 4 + (size_t)threads * items * key_bytes;
+    // wave counters; digit counts, starts and two rows of runs; keys and values
+    return (size_t)(threads / 64) * ((bits <= 9 ? 4u : 2u) << bits) + (16u << bits) +
+           (size_t)threads * items * (key_bytes + 4);
 }
 
 template <int KIND, typename K, int B, int T, int I>
@@ -697,8 +705,7 @@ void launch_scene_sort(const float *prims, const int64_t *seg_off, const int32_t
                        int code_bits, K *ka, K *kb, int32_t *vals[2], int32_t *leaf_perm,
                        float4 *scene_box, uint32_t *err, hipStream_t s)
 {
-    constexpr int P = ((sizeof(K) == 4 ? 30 : 63) + B - 1) / B;
-    if constexpr (scene_sort_lds(sizeof(K), T, I, B, P) > 150 * 1024) {
+    if constexpr (scene_sort_lds(sizeof(K), T, I, B) > 150 * 1024) {
         launch_scene_sort<KIND, K, B, 256, 16>(prims, seg_off, order, S, code_bits, ka, kb, vals,
                                                leaf_perm, scene_box, err, s);
     } else {
