@@ -811,7 +811,8 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
     int64_t span = kChunk;
     for (int lv = 1; lv <= levels; ++lv) {
         const int64_t next = span * kFanout;
-        BatchLevel up{seg_off, blk_off + lv * (S + 1), blk_off + (lv - 1) * (S + 1), S, lv == levels};
+        BatchLevel up{seg_off, blk_off + lv * (S + 1), blk_off + (lv - 1) * (S + 1), S, lv == levels,
+                      lv == levels ? order : nullptr};
         prof_begin(K_BOTTOMUP_UP, s);
         if (packed)
             hipLaunchKernelGGL(k_bottomup_up<true>, dim3((unsigned)L.blocks_max[lv]), dim3(kBUThreads),

@@ -58,6 +58,9 @@ struct BatchLevel {
     const int32_t *child_off;  // [S+1] first block of each scene one level down
     int S;
     int last;                  // top level: no climb may stop at a boundary
+    const int32_t *order;      // top level of a batch (at most one block per
+                               // scene): block b takes scene order[b], the
+                               // largest scenes first; nullptr: scene order
 };
 
 struct Climb {
@@ -274,12 +277,26 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__res
     // child blocks
     int64_t b0 = 0, slot_lo, slot_hi, A, B;
     int n = n_all;
+    int lb = blockIdx.x;   // this block's number at its level (its hand-over slots)
     if (bl.seg_off) {
-        if ((int)blockIdx.x >= bl.blk_off[bl.S]) return;
-        const int s = scene_of(bl.blk_off, bl.S, blockIdx.x);
+        int s;
+        if (bl.order) {
+            if ((int)blockIdx.x >= bl.S) return;
+            s = bl.order[blockIdx.x];
+            const int nb = bl.blk_off[s + 1] - bl.blk_off[s];
+            if (nb == 0) return;   // the scene's tree is complete below this level
+            if (nb > 1) {          // not expected: the top level has one block a scene
+                if (threadIdx.x == 0) __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            lb = bl.blk_off[s];
+        } else {
+            if ((int)blockIdx.x >= bl.blk_off[bl.S]) return;
+            s = scene_of(bl.blk_off, bl.S, blockIdx.x);
+        }
         b0 = bl.seg_off[s];
         n = (int)(bl.seg_off[s + 1] - b0);
-        const int g = blockIdx.x - bl.blk_off[s];
+        const int g = lb - bl.blk_off[s];
         const int nchild = bl.child_off[s + 1] - bl.child_off[s];
         const int c0 = g * kFanout, c1 = min(c0 + kFanout, nchild);
         A = (int64_t)c0 * child_span;
@@ -383,7 +400,7 @@ __global__ __launch_bounds__(kBUThreads) void k_bottomup_up(const uint8_t *__res
         const float4 slo = s_pend[tid].lo, shi = s_pend[tid].hi;
         if (bl.last && id.x >= 0)
             __hip_atomic_store(err, 4u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        Climb *o = pend_out + 2 * (int64_t)blockIdx.x + tid;
+        Climb *o = pend_out + 2 * (int64_t)lb + tid;
         o->id = id;
         o->lo = slo;
         o->hi = shi;
