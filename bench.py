@@ -102,8 +102,11 @@ def host_info() -> dict:
 
 
 KERNEL_SOURCES = ["paper_2402_00665_amd/csrc/build_kernels.hip",
+                  "paper_2402_00665_amd/csrc/batch_kernels.hip",
+                  "paper_2402_00665_amd/csrc/query_kernels.hip",
                   "paper_2402_00665_amd/csrc/bottomup.hpp",
                   "paper_2402_00665_amd/csrc/radix_sort.hpp",
+                  "paper_2402_00665_amd/csrc/query_common.hpp",
                   "paper_2402_00665_amd/csrc/device_common.hpp",
                   "paper_2402_00665_amd/csrc/lbvh_internal.hpp"]
 
