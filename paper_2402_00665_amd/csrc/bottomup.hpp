@@ -100,6 +100,24 @@ __device__ __forceinline__ int park_delta(int32_t v)
     return d == 127 ? 255 : d;
 }
 
+// min and max of two canonical floats (no signalling NaN): the hardware
+// instruction alone.  fminf / fmaxf first quiet both operands (one more
+// instruction each), which the merge loop below does not need: every box in
+// its LDS copy is either a leaf box quieted once on load or a result of
+// these operations.  Same results as fminf / fmaxf on such operands.
+__device__ __forceinline__ float min_canon(float a, float b)
+{
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float max_canon(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 __device__ __forceinline__ int scene_of(const int32_t *off, int S, int b)
 {
     int lo = 0, hi = S - 1;   // largest s with off[s] <= b
@@ -181,10 +199,15 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     if (i < B) {
         const int dr = delta_codes(i);
         rope = (i == n - 1) ? -1 : (dr < delta_codes(i + 1) ? leaf0 + i + 1 : i + 1);
-        store_node(nodes, leaf0 + i, lo, prim, hi, rope);
+        store_node(nodes, leaf0 + i, lo, prim, hi, rope);   // the box as given
         const int sl = kChunk + tid;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) { s_box[a][sl] = lo[a]; s_box[3 + a][sl] = hi[a]; }
+        for (int a = 0; a < 3; ++a) {   // merged from here on: quieted once
+            lo[a] = __builtin_canonicalizef(lo[a]);
+            hi[a] = __builtin_canonicalizef(hi[a]);
+            s_box[a][sl] = lo[a];
+            s_box[3 + a][sl] = hi[a];
+        }
     }
     __syncthreads();
 
@@ -223,14 +246,17 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
             const int dn = delta(is_left ? rr : rl - 1);
             dr = is_left ? dn : dr;
             dl = is_left ? dl : dn;
-            const int sib = is_left ? ((p + 1 == rr) ? leaf0 + p + 1 : p + 1)
-                                    : ((rl == p) ? leaf0 + p : p);
-            const int ss = sib >= leaf0 ? kChunk + (sib - leaf0 - A) : sib - A;
-            const int d_next = rr == n - 1 ? 255 : delta(rr + 1);
+            // the sibling: leaf or internal node at split-side index sp
+            // (selects, not branches); its LDS slot
+            const int sp = is_left ? p + 1 : p;
+            const bool sleaf = is_left ? (sp == rr) : (sp == rl);
+            const int ss = sleaf ? kChunk + (sp - A) : sp - A;
+            // delta*(rr + 1): rr + 1 <= B, in the LDS table (255 at n - 1)
+            const int d_next = delta(rr + 1);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                lo[a] = fminf(lo[a], s_box[a][ss]);
-                hi[a] = fmaxf(hi[a], s_box[3 + a][ss]);
+                lo[a] = min_canon(lo[a], s_box[a][ss]);
+                hi[a] = max_canon(hi[a], s_box[3 + a][ss]);
             }
             const int q = dr < dl ? rr : rl;   // Karras index of the parent
             const int left = (rl == p) ? leaf0 + p : p;
