@@ -221,54 +221,65 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
     if (n > 1 && i < B) {
         int rl = i, rr = i, cur = leaf0 + i;
         int dl = delta(i - 1), dr = delta(i);
-        for (int level = 0;; ++level) {
-            if (level == kMaxDepth) {
-                __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            const bool is_left = dr < dl;              // left child of its parent
-            const int p = is_left ? rr : rl - 1;       // the parent's split
-            if (p == (is_left ? B - 1 : A - 1)) {      // the parent is split at a chunk edge
-                s_pend[is_left ? 1 : 0] = make_climb(cur, rl, rr, rope, dl, dr, lo, hi);
-                break;
-            }
-            int other = -1;
-            const int far_mine = is_left ? rl : rr;   // this node's far end, seen from p
-            const int32_t park = PACKED ? pack_park(far_mine, is_left ? dl : dr) : far_mine;
-            if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, park,
-                                                     __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
-                break;                                 // first to arrive
-            // second to arrive: `other` holds the sibling's far end
-            const int far = PACKED ? park_far(other) : other;
-            rr = is_left ? far : rr;
-            rl = is_left ? rl : far;
-            const int dn = delta(is_left ? rr : rl - 1);
-            dr = is_left ? dn : dr;
-            dl = is_left ? dl : dn;
-            // the sibling: leaf or internal node at split-side index sp
-            // (selects, not branches); its LDS slot
-            const int sp = is_left ? p + 1 : p;
-            const bool sleaf = is_left ? (sp == rr) : (sp == rl);
-            const int ss = sleaf ? kChunk + (sp - A) : sp - A;
-            // delta*(rr + 1): rr + 1 <= B, in the LDS table (255 at n - 1)
-            const int d_next = delta(rr + 1);
+        // one exit for the whole wave (a lane stops when it parks at a
+        // chunk edge, is first at its parent, or reaches the root), so the
+        // loop keeps no per-exit lane masks
+        bool live = true, edge = false;
+        int level = 0;
+        do {
+            if (live) {
+                const bool is_left = dr < dl;              // left child of its parent
+                const int p = is_left ? rr : rl - 1;       // the parent's split
+                if (level == kMaxDepth) {
+                    __hip_atomic_store(err, 3u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    live = false;
+                } else if (p == (is_left ? B - 1 : A - 1)) {   // the parent is split at a chunk edge
+                    edge = true;
+                    live = false;
+                } else {
+                    int other = -1;
+                    const int far_mine = is_left ? rl : rr;   // this node's far end, seen from p
+                    const int32_t park = PACKED ? pack_park(far_mine, is_left ? dl : dr) : far_mine;
+                    if (__hip_atomic_compare_exchange_strong(&s_store[p - A], &other, park,
+                                                             __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        live = false;                          // first to arrive
+                    } else {
+                        // second to arrive: `other` holds the sibling's far end
+                        const int far = PACKED ? park_far(other) : other;
+                        rr = is_left ? far : rr;
+                        rl = is_left ? rl : far;
+                        const int dn = delta(is_left ? rr : rl - 1);
+                        dr = is_left ? dn : dr;
+                        dl = is_left ? dl : dn;
+                        // the sibling: leaf or internal node at split-side
+                        // index sp (selects, not branches); its LDS slot
+                        const int sp = is_left ? p + 1 : p;
+                        const bool sleaf = is_left ? (sp == rr) : (sp == rl);
+                        const int ss = sleaf ? kChunk + (sp - A) : sp - A;
+                        // delta*(rr + 1): rr + 1 <= B, in the LDS table (255 at n - 1)
+                        const int d_next = delta(rr + 1);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = min_canon(lo[a], s_box[a][ss]);
-                hi[a] = max_canon(hi[a], s_box[3 + a][ss]);
-            }
-            const int q = dr < dl ? rr : rl;   // Karras index of the parent
-            const int left = (rl == p) ? leaf0 + p : p;
-            const int qrope = rr == n - 1 ? -1 : (dr < d_next ? leaf0 + rr + 1 : rr + 1);
-            store_node(nodes, q, lo, left, hi, qrope);
-            const int qs = q - A;
+                        for (int a = 0; a < 3; ++a) {
+                            lo[a] = min_canon(lo[a], s_box[a][ss]);
+                            hi[a] = max_canon(hi[a], s_box[3 + a][ss]);
+                        }
+                        const int q = dr < dl ? rr : rl;   // Karras index of the parent
+                        const int left = (rl == p) ? leaf0 + p : p;
+                        const int qrope = rr == n - 1 ? -1 : (dr < d_next ? leaf0 + rr + 1 : rr + 1);
+                        store_node(nodes, q, lo, left, hi, qrope);
+                        const int qs = q - A;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
-            cur = q;
-            rope = qrope;
-            if (q == 0) break;
-        }
+                        for (int a = 0; a < 3; ++a) { s_box[a][qs] = lo[a]; s_box[3 + a][qs] = hi[a]; }
+                        cur = q;
+                        rope = qrope;
+                        live = q != 0;
+                    }
+                }
+                ++level;
+            }
+        } while (__ballot(live) != 0);
+        if (edge) s_pend[dr < dl ? 1 : 0] = make_climb(cur, rl, rr, rope, dl, dr, lo, hi);
     }
     __syncthreads();
     if (tid < cn) store[A + tid] = s_store[tid];
