@@ -194,27 +194,33 @@ __global__ __launch_bounds__(kBU0Threads) void k_bottomup_l0(const K *__restrict
         return highest_bit((uint32_t)(g ^ (g + 1)));
     };
     for (int t = tid; t < cn + 2; t += kBU0Threads) s_delta[t] = (uint8_t)delta_codes(A - 1 + t);
-    // leaf record: box, primitive id, rope (Alg. 2 on the range [i, i])
-    int rope = -1;
+    // the leaf's box as the merges below use it: quieted once
+    float clo[3], chi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        clo[a] = __builtin_canonicalizef(lo[a]);
+        chi[a] = __builtin_canonicalizef(hi[a]);
+    }
     if (i < B) {
-        const int dr = delta_codes(i);
-        rope = (i == n - 1) ? -1 : (dr < delta_codes(i + 1) ? leaf0 + i + 1 : i + 1);
-        store_node(nodes, leaf0 + i, lo, prim, hi, rope);   // the box as given
         const int sl = kChunk + tid;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {   // merged from here on: quieted once
-            lo[a] = __builtin_canonicalizef(lo[a]);
-            hi[a] = __builtin_canonicalizef(hi[a]);
-            s_box[a][sl] = lo[a];
-            s_box[3 + a][sl] = hi[a];
-        }
+        for (int a = 0; a < 3; ++a) { s_box[a][sl] = clo[a]; s_box[3 + a][sl] = chi[a]; }
     }
     __syncthreads();
+    auto delta = [&](int g) -> int { return s_delta[g - A + 1]; };
+    // leaf record: the box as given, primitive id, rope (Alg. 2 on the
+    // range [i, i]; delta*(i + 1) is in the table, i + 1 <= B)
+    int rope = -1;
+    if (i < B) {
+        rope = (i == n - 1) ? -1 : (delta(i) < delta(i + 1) ? leaf0 + i + 1 : i + 1);
+        store_node(nodes, leaf0 + i, lo, prim, hi, rope);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { lo[a] = clo[a]; hi[a] = chi[a]; }
 
     // Alg. 4's climb.  Both cases (the node is its parent's left or right
     // child) run the same instructions with selects, so a wave whose lanes
     // disagree does not run both.
-    auto delta = [&](int g) -> int { return s_delta[g - A + 1]; };
     // this chunk's boundaries g in [A, B), g < n-1, for the upper levels of
     // a tree whose store words cannot carry delta*
     if (!PACKED && i < B && i < n - 1) dstar_all[b0 + i] = s_delta[tid + 1];
