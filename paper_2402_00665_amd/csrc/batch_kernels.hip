@@ -263,22 +263,15 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     // position in the tile's stable order by this pass's digit.  The wave
     // counters must be zero on entry (each caller clears them, after its
     // last read of the previous ranking and before a barrier).
-    auto rank_tile = [&](const K (&key)[I], uint32_t rem, uint32_t lofs, int shift, int nbits,
+    auto rank_tile = [&](const K (&key)[I], uint32_t rem, uint32_t lofs, int shift,
                          uint32_t (&pos)[I], uint32_t (&total)[DPT], uint32_t (&start)[DPT]) {
         uint32_t rank[I];
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             const bool ok = lofs + k * 64 < rem;
             const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
-            uint64_t diff = 0;
-#pragma unroll
-            for (int b = 0; b < BITS; ++b) {
-                if (b < nbits) {
-                    const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
-                    diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
-                }
-            }
-            const uint64_t peers = __ballot(ok) & ~diff;
+            // bits of a narrower last digit are zero above it in every key
+            const uint64_t peers = __ballot(ok) & ~digit_diff<BITS>(d);
             const uint32_t below = count_below(peers);
             const uint32_t cnt = s_wcnt[wave][d];
             rank[k] = cnt + below;
@@ -331,9 +324,8 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         __syncthreads();
         for (int p = 0; p < PASSES; ++p) {
             const int shift = p * BITS;
-            const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
             uint32_t pos[I], total[DPT], start[DPT];
-            rank_tile(key, cnt, lofs, shift, nbits, pos, total, start);
+            rank_tile(key, cnt, lofs, shift, pos, total, start);
             if (p + 1 == PASSES) {
 #pragma unroll
                 for (int k = 0; k < I; ++k)
@@ -360,14 +352,13 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             __syncthreads();
         }
     };
-    // One stable pass over the whole scene by digit `shift .. shift+nbits`
-    // (its counts in s_hist), tile after tile through global memory.  The
+    // One stable pass over the whole scene by the digit at `shift` (its
+    // counts in s_hist), tile after tile through global memory.  The
     // running start of each digit alternates between the two rows of s_run
     // (tile t reads row t & 1 and its owner writes the next row), so no
     // barrier guards it; returns the row that ends up holding the
     // scene-local end of each digit's run.
-    auto global_pass = [&](const K *kin, K *kout, const int32_t *vin, int32_t *vout, int shift,
-                           int nbits) -> int {
+    auto global_pass = [&](const K *kin, K *kout, const int32_t *vin, int32_t *vout, int shift) -> int {
         zero_counts();
         {   // the scene-local start of each digit in this pass
             uint32_t h[DPT], st[DPT];
@@ -392,7 +383,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
             }
             // stable rank within the wave, as in the onesweep pass
             uint32_t pos[I], total[DPT], start[DPT];
-            rank_tile(key, rem, lofs, shift, nbits, pos, total, start);
+            rank_tile(key, rem, lofs, shift, pos, total, start);
             // the next tile's runs of each digit follow this tile's
 #pragma unroll
             for (int k = 0; k < DPT; ++k)
@@ -446,7 +437,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         if (owns(k) && s_hist[d0 + k] > (uint32_t)TILE) s_flag = 1u;
     __syncthreads();
     if (s_flag == 0u && top_bits > 0) {
-        const uint32_t *end = s_run[global_pass(key_a, key_b, nullptr, val_a, top_shift, top_bits)];
+        const uint32_t *end = s_run[global_pass(key_a, key_b, nullptr, val_a, top_shift)];
         // digit d's keys now lie in [end[d-1], end[d]) of key_b / val_a;
         // group g takes digits gb..last, the most that fit a tile (slot
         // g & 1 of s_last holds gb before the max)
@@ -478,7 +469,6 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         const int32_t *vin = p == 0 ? nullptr : ((p & 1) ? val_a : val_b);
         int32_t *vout = p + 1 == PASSES ? perm_out : ((p & 1) ? val_b : val_a);
         const int shift = p * BITS;
-        const int nbits = BITS < code_bits - shift ? BITS : code_bits - shift;
         // this digit's counts (the previous pass read s_hist before its
         // last barrier)
         for (int j = tid; j < R; j += T) s_hist[j] = 0u;
@@ -486,7 +476,7 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         for (uint32_t i = tid; i < ns; i += T)
             atomicAdd(&s_hist[(uint32_t)((kin[b0 + i] >> shift) & (R - 1))], 1u);
         __syncthreads();
-        global_pass(kin, kout, vin, vout, shift, nbits);
+        global_pass(kin, kout, vin, vout, shift);
     }
 }
 

@@ -47,6 +47,27 @@ __device__ __forceinline__ int upper_segment(const int32_t *off, int S, uint32_t
 
 // Exclusive scan over the block of each thread's DPT values, in thread
 // order then item order (the digits a thread owns are consecutive).
+// The lanes of the wave whose BITS-bit digit differs from this lane's d in
+// some bit: for each bit, the ballot of the lanes that have it, flipped
+// where this lane has it (its bit sign-extended to a 32-bit mask), or-ed in
+// with one three-input bit operation per half of the mask.  A bit that is
+// zero in every lane's digit (above a narrower last digit) adds nothing,
+// so no pass needs to skip it.
+template <int BITS>
+__device__ __forceinline__ uint64_t digit_diff(uint32_t d)
+{
+    uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+    for (int b = 0; b < BITS; ++b) {
+        const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
+        const uint64_t m = __ballot(rep != 0u);
+        // x | (y ^ z): the truth table is f(0xF0, 0xCC, 0xAA)
+        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, rep, 0xF6);
+        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), rep, 0xF6);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <int THREADS, int DPT>
 __device__ __forceinline__ void digits_excl_scan(const uint32_t (&v)[DPT], uint32_t (&out)[DPT],
                                                  uint32_t *sh /* [THREADS/64] */)
@@ -318,19 +339,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     for (int k = 0; k < ITEMS; ++k) {
         const bool ok = lofs + k * 64 < rem;
         const uint32_t d = dig[k];
-        // lanes whose digit differs from this lane's in some bit: for each
-        // bit, the ballot of lanes that have it, flipped where this lane has
-        // it (a sign-extended bit as the xor mask); bits at or above nbits
-        // are zero in every key
-        uint64_t diff = 0;
-#pragma unroll
-        for (int b = 0; b < BITS; ++b) {
-            if (b < nbits) {
-                const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
-                diff |= __ballot(rep != 0u) ^ (((uint64_t)rep << 32) | rep);
-            }
-        }
-        const uint64_t peers = __ballot(ok) & ~diff;
+        // bits at or above nbits are zero in every key
+        const uint64_t peers = __ballot(ok) & ~digit_diff<BITS>(d);
         const uint32_t below = count_below(peers);
         const uint32_t cnt = s_wcnt[wave][d];
         rank[k] = cnt + below;
