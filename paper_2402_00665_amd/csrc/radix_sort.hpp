@@ -60,7 +60,9 @@ __device__ __forceinline__ uint64_t digit_diff(uint32_t d)
 #pragma unroll
     for (int b = 0; b < BITS; ++b) {
         const uint32_t rep = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // 0 or ~0
-        const uint64_t m = __ballot(rep != 0u);
+        // the ballot of rep != 0 (33: not-equal), compared on rep itself
+        // rather than re-derived from d by a shift
+        const uint64_t m = __builtin_amdgcn_uicmp(rep, 0u, 33);
         // x | (y ^ z): the truth table is f(0xF0, 0xCC, 0xAA)
         lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)m, rep, 0xF6);
         hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(m >> 32), rep, 0xF6);
