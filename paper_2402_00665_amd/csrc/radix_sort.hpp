@@ -320,12 +320,16 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     const int32_t *vp = vals_in ? vals_in + b0 + base + lofs : nullptr;
     K key[ITEMS];
     uint32_t dig[ITEMS];   // this pass's digit of each key
+    const bool full = rem == TILE;   // every tile but a segment's last: no per-key test
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const bool ok = lofs + k * 64 < rem;
-        key[k] = ok ? kp[k * 64] : (K)0;
-        dig[k] = (uint32_t)(key[k] >> shift) & (R - 1);
+        for (int k = 0; k < ITEMS; ++k) key[k] = kp[k * 64];
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) key[k] = lofs + k * 64 < rem ? kp[k * 64] : (K)0;
     }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) dig[k] = (uint32_t)(key[k] >> shift) & (R - 1);
     // 64-bit keys wait in LDS (input order) while the tile is ranked: kept
     // in registers, the widest tiles spilled to scratch memory
     if constexpr (sizeof(K) == 8) {
@@ -408,10 +412,15 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(
     // the values, loaded only now (they are needed last; loading them with
     // the keys made the widest tiles spill registers to scratch memory)
     int32_t val[ITEMS];
+    if (vp && full) {
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const bool ok = lofs + k * 64 < rem;
-        val[k] = vp ? (ok ? vp[k * 64] : 0) : (int32_t)(base + lofs + k * 64);
+        for (int k = 0; k < ITEMS; ++k) val[k] = vp[k * 64];
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const bool ok = lofs + k * 64 < rem;
+            val[k] = vp ? (ok ? vp[k * 64] : 0) : (int32_t)(base + lofs + k * 64);
+        }
     }
     // keys: into LDS in tile-sorted order, then out in runs (segment-local
     // positions fit 32 bits: a segment holds at most 2^30 keys)
