@@ -266,8 +266,13 @@ __global__ __launch_bounds__(T) void k_scene_sort(
     auto rank_tile = [&](const K (&key)[I], uint32_t rem, uint32_t lofs, int shift,
                          uint32_t (&pos)[I], uint32_t (&total)[DPT], uint32_t (&start)[DPT]) {
         uint32_t rank[I];
+        // the wave's first key (a scalar: rows with no key in the tile are
+        // skipped by a branch of the whole wave)
+        const uint32_t wbase = (uint32_t)__builtin_amdgcn_readfirstlane((int)(lofs - lane));
 #pragma unroll
         for (int k = 0; k < I; ++k) {
+            rank[k] = 0u;
+            if (wbase + k * 64 >= rem) continue;
             const bool ok = lofs + k * 64 < rem;
             const uint32_t d = (uint32_t)(key[k] >> shift) & (R - 1);
             // bits of a narrower last digit are zero above it in every key
@@ -298,6 +303,8 @@ __global__ __launch_bounds__(T) void k_scene_sort(
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < I; ++k) {
+            pos[k] = 0u;
+            if (wbase + k * 64 >= rem) continue;
             const uint32_t dk = (uint32_t)(key[k] >> shift) & (R - 1);
             pos[k] = s_start[dk] + s_wcnt[wave][dk] + rank[k];
         }
