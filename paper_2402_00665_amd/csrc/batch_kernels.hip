@@ -758,7 +758,7 @@ hipError_t run_batch(const float *prims, const int64_t *seg_off, int S, int64_t 
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, seg_off, S, levels, tile,
                        tile_off, blk_off, ctrl, order);
     // one block per scene only while every scene is small (at most one
-    // upper level: 65536 primitives); a block alone on a scene of millions
+    // upper level: kChunk * kFanout primitives); a block alone on a scene of millions
     // would set the whole batch's time
     if (tune_get(TUNE_BATCH_SORT_MODE) == 1 && levels <= 1) {
         prof_end(K_BATCH_PREP, s);

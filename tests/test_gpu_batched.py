@@ -151,7 +151,7 @@ def test_batched_box_queries_and_duplicates():
 
 
 def test_max_scene_too_small_is_reported():
-    """max_scene = 100 launches no level above the 256-leaf blocks, so a
+    """max_scene = 100 launches no level above the 512-leaf blocks, so a
     scene of 3000 points cannot be finished: the check call reports it."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng(22)
@@ -164,8 +164,8 @@ def test_max_scene_too_small_is_reported():
 
 
 def test_max_scene_below_size_within_cover_is_exact():
-    """max_scene = 1000 launches one level above the 256-leaf blocks
-    (covering 65536 leaves), so a 3000-point scene is still built exactly."""
+    """max_scene = 1000 launches one level above the 512-leaf blocks
+    (covering 131072 leaves), so a 3000-point scene is still built exactly."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng(24)
     seg = np.array([0, 3000, 5000], np.int64)
@@ -261,7 +261,7 @@ def test_scene_sort_widths_and_sizes(bits, shape):
     8192-key tiles, a 65536-point scene, scenes whose top digit value
     holds exactly 4096 keys and 4097 keys (runs of whole digit values on
     chip, and the pass-per-digit form), duplicate codes; every tree equals
-    the oracle's.  A batch with a scene above 65536 points, asked for in
+    the oracle's.  A batch with a scene above 131072 points, asked for in
     this mode, is built by the segmented passes and is checked too."""
     import paper_2402_00665_amd as lb
     old = {k: lb.lbvh_tune(k) for k in ("batch_sort_mode", "batch_sort_variant", "radix_bits32",
@@ -292,9 +292,9 @@ def test_scene_sort_widths_and_sizes(bits, shape):
             boxes = np.concatenate([pts, pts + 1e-3], 1).astype(np.float32)
             batched_parity(boxes, seg, bits, 1)
         if shape == 0:
-            big = np.concatenate([pts[:20000], rng.random((70000, 3), dtype=np.float32)])
-            bseg = np.array([0, 20000, 90000], np.int64)
-            say("  per-scene sort asked for with a 70000-point scene")
+            big = np.concatenate([pts[:20000], rng.random((140000, 3), dtype=np.float32)])
+            bseg = np.array([0, 20000, 160000], np.int64)
+            say("  per-scene sort asked for with a 140000-point scene")
             batched_parity(big, bseg, bits, 0)
     finally:
         for k, v in old.items():
