@@ -393,7 +393,7 @@ const char *lbvh_last_hip_error(void);
  *       "batch_sort_variant" picks the block: 0 = 256 x 16, 1 = 512 x 8,
  *       2 = 1024 x 8, 3 = 512 x 16 (a block whose tables do not fit the LDS
  *       runs as 256 x 16).  Mode 1 applies to batches whose largest scene
- *       has at most 131072 primitives; larger batches run mode 0.
+ *       has at most 262144 primitives; larger batches run mode 0.
  *   "query_split1", "query_split2": the single-tree count call cuts each
  *       query's Alg. 1 walk into pieces at aligned blocks of 2^split1
  *       leaves, then cuts those at blocks of 2^split2 leaves, and walks the

@@ -20,7 +20,7 @@ constexpr int kRadixBits = 8;         // digit width of the query-order sort (16
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kBoundsBlocksMax = 1024;
 constexpr int kMortonBlocksMax = 2048;
-constexpr int kChunk = 512;           // leaves per level-0 block of the bottom-up pass
+constexpr int kChunk = 1024;          // leaves per level-0 block of the bottom-up pass
 constexpr int kBU0Threads = kChunk;     // one leaf per thread
 constexpr int kFanout = 256;          // level-(L-1) blocks per level-L block
 constexpr int kBUThreads = 2 * kFanout;  // one thread per handed-over climb

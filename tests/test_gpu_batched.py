@@ -151,7 +151,7 @@ def test_batched_box_queries_and_duplicates():
 
 
 def test_max_scene_too_small_is_reported():
-    """max_scene = 100 launches no level above the 512-leaf blocks, so a
+    """max_scene = 100 launches no level above the 1024-leaf blocks, so a
     scene of 3000 points cannot be finished: the check call reports it."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng(22)
@@ -164,13 +164,13 @@ def test_max_scene_too_small_is_reported():
 
 
 def test_max_scene_below_size_within_cover_is_exact():
-    """max_scene = 1000 launches one level above the 512-leaf blocks
-    (covering 131072 leaves), so a 3000-point scene is still built exactly."""
+    """max_scene = 1500 launches one level above the 1024-leaf blocks
+    (covering 262144 leaves), so a 3000-point scene is still built exactly."""
     import paper_2402_00665_amd as lb
     rng = np.random.default_rng(24)
     seg = np.array([0, 3000, 5000], np.int64)
     pts = rng.random((5000, 3), dtype=np.float32)
-    b, _, _ = run_batched(pts, seg, 30, 0, max_scene=1000)
+    b, _, _ = run_batched(pts, seg, 30, 0, max_scene=1500)
     lb.check_batched(b)
     nodes_h, codes_h, perm_h = host_arrays(b)
     for s in range(2):
@@ -261,7 +261,7 @@ def test_scene_sort_widths_and_sizes(bits, shape):
     8192-key tiles, a 65536-point scene, scenes whose top digit value
     holds exactly 4096 keys and 4097 keys (runs of whole digit values on
     chip, and the pass-per-digit form), duplicate codes; every tree equals
-    the oracle's.  A batch with a scene above 131072 points, asked for in
+    the oracle's.  A batch with a scene above 262144 points, asked for in
     this mode, is built by the segmented passes and is checked too."""
     import paper_2402_00665_amd as lb
     old = {k: lb.lbvh_tune(k) for k in ("batch_sort_mode", "batch_sort_variant", "radix_bits32",
@@ -292,9 +292,9 @@ def test_scene_sort_widths_and_sizes(bits, shape):
             boxes = np.concatenate([pts, pts + 1e-3], 1).astype(np.float32)
             batched_parity(boxes, seg, bits, 1)
         if shape == 0:
-            big = np.concatenate([pts[:20000], rng.random((140000, 3), dtype=np.float32)])
-            bseg = np.array([0, 20000, 160000], np.int64)
-            say("  per-scene sort asked for with a 140000-point scene")
+            big = np.concatenate([pts[:20000], rng.random((270000, 3), dtype=np.float32)])
+            bseg = np.array([0, 20000, 290000], np.int64)
+            say("  per-scene sort asked for with a 270000-point scene")
             batched_parity(big, bseg, bits, 0)
     finally:
         for k, v in old.items():
